@@ -1,0 +1,690 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test ties one part of the oracle to something other than itself: a
+dispersion relation or force factor the paper derives (Sec. III.A, Eqs.
+(10)-(15)), textbook closed forms (plane-wave orbit, exact Boris maps,
+betatron frequency Eq. (1)), conservation laws (Gauss's law with [k]_B, charge
+continuity, the work identity behind Eq. (16)), physical moments of the
+deposited charge and current, the published SplitMix64 test vector, brute
+force on tiny grids, and the worked numbers the paper prints (tests/golden).
+"""
+import functools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import coef
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+LAMBDA0 = 2.0 * math.pi
+
+
+@functools.lru_cache(maxsize=None)
+def setup_cached(N, M, dz, dr):
+    return coef.solver_setup(N, M, dz, dr)
+
+
+# --------------------------------------------------------------------------
+# random numbers
+
+
+def test_splitmix64_published_vector():
+    # First outputs of SplitMix64 seeded with 0 (the generator's published test vector).
+    assert oracle.splitmix64(0, 1) == 0xE220A8397B1DCDAF
+    assert oracle.splitmix64(0, 2) == 0x6E789E6AA1B965F4
+    assert oracle.splitmix64(0, 3) == 0x06C45D188009454F
+
+
+def test_loader_matches_independent_draws():
+    """Tiny load re-derived in Python from the generator's definition (brute force)."""
+    Nz, Nr, M, ppc, seed = 3, 4, 1, 2, 12345
+    dz, dr = 0.3, 1.1
+    o = oracle.Oracle(Nz, Nr, M, dz, dr, 0.1, [1.0], [1.0])
+    o.load_plasma(ppc, 0.02, seed=seed, n_tracked=3)
+    P = o.particles()
+    mask = 2**64 - 1
+
+    def mix(z):
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & mask
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & mask
+        return z ^ (z >> 31)
+
+    def U(pid, d):
+        return (mix((seed + (4 * pid + d + 1) * 0x9E3779B97F4A7C15) & mask) >> 11) * 2.0**-53
+
+    keys = []
+    for iz in range(Nz):
+        for ir in range(Nr - 1):
+            for s in range(ppc):
+                pid = (iz * (Nr - 1) + ir) * ppc + s
+                r = ir + U(pid, 1)
+                phi = 2.0 * math.pi * U(pid, 2)
+                assert P["z"][pid] == iz + U(pid, 0)
+                assert P["x"][pid] == r * math.cos(phi)
+                assert P["y"][pid] == r * math.sin(phi)
+                assert P["w"][pid] == 0.02 * (2.0 * math.pi) * (r * dr) * dr * dz / ppc
+                keys.append((U(pid, 3), pid))
+    tracked = sorted(p for _, p in sorted(keys)[:3])
+    assert list(o.tracked()["id"]) == tracked
+
+
+# --------------------------------------------------------------------------
+# coefficient fit (Sec. III.A, Eqs. (11), (15))
+
+
+def test_fit_meets_both_conditions_in_band():
+    nu = 0.75
+    CE, CB = coef.fit(16, nu)
+    kap = np.linspace(1e-3, 2.0 * np.pi / 3.0, 2000)
+    kE, kB = coef.symbol(CE, kap), coef.symbol(CB, kap)
+    # Eq. (11): [k]_B [k]_E = (sin(c k dt/2) / (c dt/2))^2   (dz = 1 units)
+    cond1 = kB * kE / (np.sin(0.5 * kap * nu) / (0.5 * nu)) ** 2 - 1.0
+    # Eq. (15): sqrt([k]_E/[k]_B) cos(c k dt / 2) = 1
+    cond2 = np.sqrt(kE / kB) * np.cos(0.5 * kap * nu) - 1.0
+    assert np.abs(cond1).max() < 1e-6
+    assert np.abs(cond2).max() < 1e-6
+    # consistency: both symbols -> k for small k
+    assert abs(np.sum((2 * np.arange(1, 17) - 1) * CE) - 1.0) < 1e-13
+    assert abs(np.sum((2 * np.arange(1, 17) - 1) * CB) - 1.0) < 1e-13
+
+
+def test_yee_is_one_coefficient_case():
+    CE, CB = coef.fit(1, 0.9)
+    assert list(CE) == [1.0] and list(CB) == [1.0]
+    kap = np.linspace(0.1, 3.0, 7)
+    assert np.allclose(coef.symbol(CE, kap), 2.0 * np.sin(kap / 2.0), rtol=0, atol=1e-15)
+
+
+def test_filter_factorises_dual_difference():
+    """D_B = D_Yee o P: the symbols agree and the taps sum to one."""
+    CE, CB = coef.fit(16, 0.8)
+    p = oracle.Oracle(8, 4, 0, 1.0, 1.0, 0.5, CE, CB).filter_taps()
+    assert p.size == 31 and abs(p.sum() - 1.0) < 1e-13
+    assert np.allclose(p, p[::-1], rtol=0, atol=0)
+    kap = np.linspace(0.01, np.pi, 300)
+    ls = np.arange(-15, 16)
+    Pk = (p[None, :] * np.cos(np.outer(kap, ls))).sum(axis=1)
+    assert np.abs(2.0 * np.sin(kap / 2.0) * Pk - coef.symbol(CB, kap)).max() < 1e-14
+
+
+# --------------------------------------------------------------------------
+# vacuum waves: P1 (Yee), P2 (dual dispersion), P3 (Lorentz-force factor)
+
+
+def _uniform_wave(N, nu, kappa_index, Nz=32, Nr=16, M=1, dz=LAMBDA0 / 16, nsteps=12, probe_row=1):
+    """Uniform-in-r x-polarised wave E_r^1 = E, E_phi^1 = iE, B_r^1 = -iB, B_phi^1 = B,
+    an exact discrete solution away from the wall.  Returns measured omega, the
+    forward-wave ratio Bbar/E and (k, dt, CE, CB)."""
+    CE, CB = coef.fit(N, nu)
+    dr = 4.0 * dz
+    dt = nu * dz
+    o = oracle.Oracle(Nz, Nr, M, dz, dr, dt, CE, CB)
+    k = 2.0 * np.pi * kappa_index / (Nz * dz)
+    zi = np.arange(Nz) * dz
+    zh = zi + 0.5 * dz
+    ones = np.ones((Nr + 1, 1))
+    E = ones * np.cos(k * zi)[None, :]
+    B = ones * np.cos(k * zh)[None, :]
+    o.set_field(oracle.ER, 1, E)
+    o.set_field(oracle.EP, 1, 1j * E)
+    o.set_field(oracle.BR, 1, -1j * B)
+    o.set_field(oracle.BP, 1, B)
+    o.start_fields()
+    a, b = [], []
+    for n in range(nsteps):
+        e = o.get_field(oracle.ER, 1)[probe_row]
+        bb = 0.5 * (o.get_field(oracle.BOP, 1)[probe_row] + o.get_field(oracle.BP, 1)[probe_row])
+        a.append(np.sum(e * np.exp(-1j * k * zi)) / Nz)
+        b.append(np.sum(bb * np.exp(-1j * k * zh)) / Nz)
+        o.field_step(1)
+    a, b = np.array(a), np.array(b)
+    # any mix of the +omega and -omega waves obeys a_{n+1} + a_{n-1} = 2 cos(omega dt) a_n
+    lhs = (a[2:] + a[:-2])
+    rhs = 2.0 * a[1:-1]
+    cw = np.real(np.vdot(rhs, lhs) / np.vdot(rhs, rhs))
+    omega = math.acos(cw) / dt
+    th = omega * dt
+
+    def forward(s):  # amplitude of the e^{-i omega t} (forward) component
+        return (s[1] - s[0] * np.exp(1j * th)) / (np.exp(-1j * th) - np.exp(1j * th))
+
+    return omega, forward(b) / forward(a), (k, dt, CE, CB)
+
+
+def test_P1_yee_dispersion_textbook():
+    nu = 0.9
+    omega, _, (k, dt, _, _) = _uniform_wave(1, nu, 2)
+    dz = LAMBDA0 / 16
+    expect = 2.0 / dt * math.asin(nu * math.sin(k * dz / 2.0))
+    assert abs(omega / expect - 1.0) < 1e-12
+
+
+def test_P2_dual_dispersion_eq10_and_light():
+    nu = 0.9341  # 0.95 of the M = 1 limit at dr = 4 dz
+    omega, _, (k, dt, CE, CB) = _uniform_wave(16, nu, 2)
+    dz = LAMBDA0 / 16
+    kE = coef.symbol(CE, k * dz) / dz
+    kB = coef.symbol(CB, k * dz) / dz
+    # Eq. (10): sin(omega dt/2)/(dt/2) = sqrt([k]_B [k]_E)
+    assert abs(math.sin(omega * dt / 2.0) / (dt / 2.0) / math.sqrt(kB * kE) - 1.0) < 1e-12
+    # the fitted solver propagates light at c
+    assert abs(omega / k - 1.0) < 1e-7
+
+
+def test_P2_yee_dispersion_error_is_large():
+    omega, _, (k, _, _, _) = _uniform_wave(1, 0.9341, 2)
+    assert abs(omega / k - 1.0) > 1e-4  # contrast with the dual solver
+
+
+def test_P3_lorentz_factor_dual_and_yee():
+    nu = 0.9341
+    omega, ratio, (k, dt, CE, CB) = _uniform_wave(16, nu, 2)
+    dz = LAMBDA0 / 16
+    kE = coef.symbol(CE, k * dz) / dz
+    kB = coef.symbol(CB, k * dz) / dz
+    # Eq. (14): Bbar / E = sqrt([k]_E/[k]_B) cos(omega dt/2) for the forward wave
+    assert abs(ratio / (math.sqrt(kE / kB) * math.cos(omega * dt / 2.0)) - 1.0) < 1e-11
+    # Eq. (15): the dual solver makes it one
+    assert abs(ratio - 1.0) < 1e-7
+    omega_y, ratio_y, (_, dt_y, _, _) = _uniform_wave(1, nu, 2)
+    assert abs(ratio_y - math.cos(omega_y * dt_y / 2.0)) < 1e-12
+    assert abs(ratio_y - 1.0) > 1e-3
+
+
+def test_P3_paper_worked_staggering_factor():
+    """Yee at the paper's App. A time step, the grid of 30 points per initial
+    laser wavelength, and the local frequency 12 omega_p used in Sec. IV.C:
+    the measured B/E factor is the printed 0.994."""
+    t1 = GOLDEN["table1"]
+    lam_m = t1["wavelength_nm"] * 1e-9
+    # critical density n_c = eps0 m omega^2 / e^2
+    eps0, me, e, c = 8.8541878128e-12, 9.1093837015e-31, 1.602176634e-19, 299792458.0
+    omega0 = 2.0 * math.pi * c / lam_m
+    nc_cm3 = eps0 * me * omega0**2 / e**2 * 1e-6
+    w0_over_wp = math.sqrt(nc_cm3 / t1["n0_cm3"])
+    assert abs(w0_over_wp - 10.83) < 0.01
+    dt = GOLDEN["appendix_dt_over_wp"]["yee_3d"] * w0_over_wp  # in 1/omega0 of the initial laser
+    ppl = GOLDEN["appendix_grid"]["points_per_lambda"]
+    Nz = 960
+    dz = LAMBDA0 / ppl
+    nu = dt / dz
+    kidx = round(12.0 / w0_over_wp * Nz / ppl)  # wavenumber of the 12 omega_p light
+    omega, ratio, (k, dtm, _, _) = _uniform_wave(1, nu, kidx, Nz=Nz, Nr=12, dz=dz, nsteps=8)
+    g = GOLDEN["yee_staggering_factor"]
+    assert round(ratio.real, g["digits"]) == g["value"]
+    assert abs(ratio.real - math.cos(omega * dtm / 2.0)) < 1e-12
+
+
+def test_P10_paper_cfl_ratio_arithmetic():
+    a = GOLDEN["appendix_dt_over_wp"]
+    assert abs(a["dual_3d"] / a["yee_3d"] - GOLDEN["yee_cfl_fraction"]["value"]) < 0.01
+
+
+# --------------------------------------------------------------------------
+# pusher: P4
+
+
+def _boris(u, E, B, dt):
+    u = np.array(u, dtype=np.float64)
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    oracle.lib().orc_boris(oracle._ptr(u), oracle._ptr(E), oracle._ptr(B), float(dt))
+    return u
+
+
+def test_P4_exact_boris_maps():
+    # uniform E alone: u changes by exactly -E dt (q/m = -1)
+    E = np.array([0.3, -0.2, 0.7])
+    u = _boris([0.1, 0.2, -0.3], E, [0, 0, 0], 0.37)
+    assert np.allclose(u, np.array([0.1, 0.2, -0.3]) - 0.37 * E, rtol=0, atol=1e-15)
+    # uniform B_z alone: rotation by 2 atan(Omega dt / 2), Omega = B/gamma, counter-clockwise for an electron
+    u0 = np.array([2.0, 0.0, 1.0])
+    g = math.sqrt(1.0 + u0 @ u0)
+    Bz, dt = 0.8, 0.5
+    u = _boris(u0, [0, 0, 0], [0, 0, Bz], dt)
+    ang = math.atan2(u[1], u[0])
+    assert abs(ang - 2.0 * math.atan(Bz / g * dt / 2.0)) < 1e-14
+    assert abs(np.hypot(u[0], u[1]) - 2.0) < 1e-14 and u[2] == 1.0
+
+
+def _plane_wave_orbit(dt, bscale=1.0, a0=1.0, tau=10 * LAMBDA0):
+    """Electron initially at rest in a vacuum plane wave E_x = B_y = -da/dxi,
+    a(xi) = a0 g(xi) sin(xi), xi = t - z (pusher only, analytic fields)."""
+    def a_of(xi):
+        g = math.exp(-2.0 * math.log(2.0) * (xi - 3 * tau) ** 2 / tau**2)
+        return a0 * g * math.sin(xi)
+
+    def E_of(xi, h=1e-5):
+        return -(a_of(xi + h) - a_of(xi - h)) / (2 * h)
+
+    u = np.zeros(3)
+    z = 0.0
+    t = 0.0
+    err_inv, err_ux = 0.0, 0.0
+    z += 0.5 * dt * 0.0  # positions at integer times, u at half times
+    while t < 6 * tau:
+        xi = t - z
+        Ex = E_of(xi)
+        u = _boris(u, [Ex, 0.0, 0.0], [0.0, bscale * Ex, 0.0], dt)
+        g = math.sqrt(1.0 + u @ u)
+        z += dt * u[2] / g
+        t += dt
+        err_inv = max(err_inv, abs(g - u[2] - 1.0))
+        err_ux = max(err_ux, abs(u[0] - a_of(t - dt / 2 - z)))
+    return err_inv, err_ux, u
+
+
+def test_P4_plane_wave_orbit_closed_form():
+    e1, x1, u1 = _plane_wave_orbit(0.32)
+    e2, x2, u2 = _plane_wave_orbit(0.16)
+    # gamma - u_z = 1 is conserved by the exact motion; the discrete error is second order
+    assert e1 < 2e-3
+    assert 3.5 < e1 / e2 < 4.5
+    # the electron is left at rest after the pulse (u_perp = a(xi) -> 0)
+    assert np.abs(u2).max() < 1e-3
+    # the Yee time-staggering factor on B (Eq. (13)) degrades the invariant several-fold
+    ey, _, _ = _plane_wave_orbit(0.32, bscale=math.cos(0.32 / 2))
+    assert ey > 3.0 * e1
+
+
+# --------------------------------------------------------------------------
+# gather: P8(c) -- fields linear in Cartesian coordinates are gathered exactly
+
+
+def test_gather_exact_for_linear_cartesian_fields():
+    Nz, Nr, M = 8, 6, 2
+    dz, dr = 0.5, 0.7
+    o = oracle.Oracle(Nz, Nr, M, dz, dr, 0.1, [1.0], [1.0])
+    zero = np.zeros((Nr + 1, Nz), dtype=complex)
+    for c in range(9):
+        for m in range(M + 1):
+            o.set_field(c, m, zero)
+    rows = np.arange(Nr + 1)[:, None] * np.ones((1, Nz))
+    # E_x = 1.5 (uniform): E_r^1 = 1.5, E_phi^1 = 1.5 i
+    o.set_field(oracle.ER, 1, 1.5 + 0 * rows)
+    o.set_field(oracle.EP, 1, 1.5j + 0 * rows)
+    # E_y = -0.4 (uniform): E_r^1 += -0.4*(-i), E_phi^1 += -0.4
+    o.set_field(oracle.ER, 1, (1.5 + 0.4j) + 0 * rows)
+    o.set_field(oracle.EP, 1, (1.5j - 0.4) + 0 * rows)
+    # E_z = 0.25 + 0.3 x  (m = 0 constant, m = 1: 0.3 r at integer rows)
+    o.set_field(oracle.EZ, 0, 0.25 + 0 * rows)
+    o.set_field(oracle.EZ, 1, 0.3 * rows * dr)
+    # B_z = -0.6 y: B_z^1 = 0.6 i r at half rows (r_{j+1/2})
+    for bc in (oracle.BOZ, oracle.BZ):
+        o.set_field(bc, 1, 0.6j * (rows + 0.5) * dr)
+    # B_x = 0.2 (uniform): B_r^1 = 0.2, B_phi^1 = 0.2 i
+    for bc, val in ((oracle.BOR, 0.2), (oracle.BR, 0.2), (oracle.BOP, 0.2j), (oracle.BP, 0.2j)):
+        o.set_field(bc, 1, val + 0 * rows)
+    # an m = 2 field x^2 - y^2 in E_z: E_z^2 = r^2 at integer rows (exact only on nodes in r)
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        zc = rng.uniform(0, Nz)
+        r = rng.uniform(0, Nr - 1.0)
+        ph = rng.uniform(0, 2 * np.pi)
+        xc, yc = r * math.cos(ph), r * math.sin(ph)
+        EB = o.gather(zc, xc, yc)
+        X, Y = xc * dr, yc * dr
+        assert np.allclose(EB, [1.5, -0.4, 0.25 + 0.3 * X, 0.2, 0.0, -0.6 * Y], rtol=0, atol=1e-13), (zc, xc, yc)
+
+
+# --------------------------------------------------------------------------
+# deposit: P6 and P8(b) -- continuity per particle, moments
+
+
+def _single_particle_run(p0, u, Nz=12, Nr=8, M=3, dz=0.4, dr=1.2, dt=0.3, N=16, q=-1.0):
+    nu = dt / dz
+    CE, CB = coef.fit(N, nu) if N > 1 else ([1.0], [1.0])
+    o = oracle.Oracle(Nz, Nr, M, dz, dr, dt, CE, CB)
+    z, x, y = p0
+    o.set_particles([z], [x], [y], [u[0]], [u[1]], [u[2]], [-q])
+    o.set_flags(deposit_rho=True)
+    o.deposit_rho()
+    G0 = [o.gauss_residual(m) for m in range(M + 1)]
+    o.step(1)
+    G1 = [o.gauss_residual(m) for m in range(M + 1)]
+    return o, G0, G1
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_P6_single_particle_gauss_invariant(seed):
+    """div_B E - P rho stays constant through a full step for one particle in
+    empty space (deposit + filter + Ampere), for every mode, near the axis,
+    across cell faces and across the periodic seam."""
+    rng = np.random.default_rng(seed)
+    Nz = 12
+    z = rng.choice([rng.uniform(0, Nz), rng.uniform(Nz - 0.3, Nz), rng.uniform(0, 0.3)])
+    r = rng.choice([rng.uniform(0, 0.8), rng.uniform(0.9, 1.1), rng.uniform(0, 5.0)])
+    ph = rng.uniform(0, 2 * np.pi)
+    u = rng.normal(size=3) * 3.0
+    o, G0, G1 = _single_particle_run((z, r * math.cos(ph), r * math.sin(ph)), u, Nz=Nz)
+    scale = max(np.abs(g).max() for g in G0)
+    for m in range(o.M + 1):
+        assert np.abs(G1[m] - G0[m]).max() < 1e-13 * scale, (m, np.abs(G1[m] - G0[m]).max(), scale)
+
+
+def test_P8_deposit_moments():
+    """Charge and dipole of rho, and the current's moments, equal those of a point particle."""
+    Nz, Nr, M = 10, 8, 2
+    dz, dr, dt = 0.4, 1.3, 0.35
+    o = oracle.Oracle(Nz, Nr, M, dz, dr, dt, [1.0], [1.0])
+    V = np.array([math.pi * dr * dr * dz / 4] + [2 * math.pi * j * dr * dr * dz for j in range(1, Nr + 1)])
+    rj = np.arange(Nr + 1) * dr
+    rng = np.random.default_rng(7)
+    q = -0.7
+    for _ in range(20):
+        z0 = rng.uniform(1, Nz - 2)
+        r0 = rng.uniform(0, Nr - 2.5)
+        ph0 = rng.uniform(0, 2 * math.pi)
+        x0, y0 = r0 * math.cos(ph0), r0 * math.sin(ph0)
+        o.set_particles([z0], [x0], [y0], [0.0], [0.0], [0.0], [-q])
+        o.deposit_rho()
+        rho0, rho1 = o.get_field(oracle.RHO, 0), o.get_field(oracle.RHO, 1)
+        assert abs(np.sum(rho0.real * V[:, None]) - q) < 1e-14
+        # dipole: int x rho dV = q x, int y rho dV = q y  ->  sum (V r/2) rho^1 = q (x - i y)
+        d = np.sum(rho1 * (V * rj / 2.0)[:, None])
+        assert abs(d - q * (x0 - 1j * y0) * dr) < 1e-13
+        # current moments of one move
+        dzc, dxc, dyc = rng.uniform(-0.9, 0.9), rng.uniform(-0.2, 0.2), rng.uniform(-0.2, 0.2)
+        z1, x1, y1 = z0 + dzc, x0 + dxc, y0 + dyc
+        vphi = rng.normal()
+        o.deposit_one(q, (z0, x0, y0), (z1, x1, y1), vphi)
+        Jz0 = o.get_field(oracle.JZ, 0)
+        Jr0 = o.get_field(oracle.JR, 0)
+        Jp0 = o.get_field(oracle.JP, 0)
+        r1 = math.hypot(x1, y1)
+        assert abs(np.sum(Jz0.real * V[:, None]) - q * dzc * dz / dt) < 1e-13
+        Ar = 2 * math.pi * (np.arange(Nr + 1) + 0.5) * dr * dz
+        assert abs(np.sum(Jr0.real * (Ar * dr)[:, None]) - q * (r1 - r0) * dr / dt) < 1e-13
+        assert abs(np.sum(Jp0.real * V[:, None]) - q * vphi) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# betatron: P5, Eq. (1)
+
+
+def test_P5_betatron_frequency():
+    """Ion-channel field E_r^0 = (omega_p^2/2) r (Gauss's law for uniform ions),
+    test electron with gamma >> 1: x oscillates at omega_beta = omega_p/sqrt(2 gamma)."""
+    Nz, Nr, M = 32, 8, 0
+    dz, dr, dt = LAMBDA0 / 16, 1.0, 0.36
+    n0 = 0.01
+    wp = math.sqrt(n0)
+    o = oracle.Oracle(Nz, Nr, M, dz, dr, dt, [1.0], [1.0])
+    rows = (np.arange(Nr + 1) + 0.5)[:, None] * dr * np.ones((1, Nz))
+    o.set_field(oracle.ER, 0, 0.5 * n0 * rows)
+    o.set_flags(freeze_fields=True)
+    gamma = 40.0
+    uz = math.sqrt(gamma**2 - 1.0)
+    o.set_particles([1.0], [0.6], [0.0], [0.0], [0.0], [uz], [0.0])
+    wb = wp / math.sqrt(2 * gamma)
+    nsteps = int(3.2 * 2 * math.pi / wb / dt)
+    xs = np.empty(nsteps)
+    for n in range(nsteps):
+        xs[n] = o.particles()["x"][0]
+        o.step(1)
+    s = np.sign(xs)
+    idx = np.where(s[:-1] * s[1:] < 0)[0]
+    tc = (idx + xs[idx] / (xs[idx] - xs[idx + 1])) * dt
+    period = 2.0 * np.mean(np.diff(tc))
+    assert abs(2 * math.pi / period / wb - 1.0) < 1e-3
+
+
+# --------------------------------------------------------------------------
+# plasma run: P6 (Gauss), P7 (work), P9 (stability)
+
+
+@functools.lru_cache(maxsize=None)
+def _small_plasma_run(nsteps=20):
+    Nz, Nr, M = 64, 12, 2
+    dz = LAMBDA0 / 16
+    dr = 4 * dz
+    dt, CE, CB, _ = setup_cached(16, M, dz, dr)
+    o = oracle.Oracle(Nz, Nr, M, dz, dr, dt, CE, CB)
+    o.load_plasma(2, 0.02, seed=99, n_tracked=64)
+    o.add_laser(1.5, 3 * LAMBDA0, 2 * LAMBDA0, 2 * LAMBDA0, taper=LAMBDA0)
+    o.start_fields()
+    o.set_flags(deposit_rho=True)
+    o.deposit_rho()
+    G0 = [o.gauss_residual(m) for m in range(M + 1)]
+    o.step(nsteps)
+    G1 = [o.gauss_residual(m) for m in range(M + 1)]
+    return o, G0, G1
+
+
+def test_P6_gauss_invariant_plasma_run():
+    o, G0, G1 = _small_plasma_run()
+    for m in range(o.M + 1):
+        divE = np.abs(G1[m]).max() + np.abs(G0[m]).max()
+        assert np.abs(G1[m] - G0[m]).max() < 1e-13 * divE
+
+
+def test_P7_modal_work_sums_to_energy_gain():
+    o, _, _ = _small_plasma_run()
+    tr = o.tracked()
+    gain = tr["gamma"] - 1.0
+    assert np.abs(tr["W"].sum(axis=1) - gain).max() < 1e-13 * max(1.0, np.abs(gain).max())
+    assert np.abs(tr["W"][:, 1]).max() > 1e-3  # the laser (m = 1) does work
+
+
+def test_P7_vacuum_laser_does_no_wake_work():
+    """Test electrons (w = 0) in a pure m = 1 laser: the m = 0 work is exactly 0."""
+    Nz, Nr, M = 64, 12, 1
+    dz = LAMBDA0 / 16
+    dr = 4 * dz
+    dt, CE, CB, _ = setup_cached(16, M, dz, dr)
+    o = oracle.Oracle(Nz, Nr, M, dz, dr, dt, CE, CB)
+    rng = np.random.default_rng(1)
+    n = 50
+    r = rng.uniform(0, 4, n)
+    ph = rng.uniform(0, 2 * np.pi, n)
+    o.set_particles(rng.uniform(0, Nz, n), r * np.cos(ph), r * np.sin(ph), np.zeros(n), np.zeros(n),
+                    np.zeros(n), np.zeros(n))
+    o.add_laser(2.0, 3 * LAMBDA0, 2 * LAMBDA0, 2 * LAMBDA0, taper=LAMBDA0)
+    o.start_fields()
+    o.step(15)
+    tr = o.tracked()
+    assert np.all(tr["W"][:, 0] == 0.0)
+    assert np.abs(tr["W"][:, 1]).max() > 1e-3
+
+
+@pytest.mark.slow
+def test_P9_vacuum_long_run_bounded():
+    Nz, Nr, M = 64, 12, 3
+    dz = LAMBDA0 / 16
+    dr = 4 * dz
+    dt, CE, CB, _ = setup_cached(16, M, dz, dr)
+    o = oracle.Oracle(Nz, Nr, M, dz, dr, dt, CE, CB)
+    o.add_laser(1.0, 3 * LAMBDA0, 2 * LAMBDA0, 2 * LAMBDA0, taper=LAMBDA0)
+    o.start_fields()
+    U0 = sum(o.field_energy(m) for m in range(M + 1))
+    o.field_step(3000)
+    U1 = sum(o.field_energy(m) for m in range(M + 1))
+    assert abs(U1 / U0 - 1.0) < 1e-2
+
+
+# --------------------------------------------------------------------------
+# stability: P8(a) -- dense one-step operator on a tiny grid
+
+
+def _one_step_matrix(Nz, Nr, m, dz, dr, dt, CE, CB):
+    o = oracle.Oracle(Nz, Nr, m, dz, dr, dt, CE, CB)
+    comps = [0, 1, 2, 6, 7, 8]
+    n = (Nr + 1) * Nz
+    T = np.zeros((6 * n, 6 * n), dtype=complex)
+    zero = np.zeros((Nr + 1, Nz), dtype=complex)
+    for col in range(6 * n):
+        for c in comps:
+            o.set_field(c, m, zero)
+        ci, k = divmod(col, n)
+        v = zero.reshape(-1).copy()
+        v[k] = 1.0
+        o.set_field(comps[ci], m, v.reshape(Nr + 1, Nz))
+        o.field_step(1)
+        T[:, col] = np.concatenate([o.get_field(c, m).reshape(-1) for c in comps])
+    return T
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("N,m", [(16, 1), (16, 3), (1, 2)])
+def test_P8_dense_operator_matches_stability_formula(N, m):
+    Nz, Nr = 16, 6
+    dz, dr = 1.0 / 16, 0.25
+    lam = coef.radial_lambda(m, nr=Nr)
+    kap = 2 * np.pi * np.arange(1, Nz // 2 + 1) / Nz
+
+    def measure(nu):
+        CE, CB = coef.fit(N, nu)
+        return 0.25 * nu * nu * ((coef.symbol(CB, kap) * coef.symbol(CE, kap)).max() + lam * (dz / dr) ** 2)
+
+    lo, hi = 0.0, 1.5
+    for _ in range(40):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if measure(mid) <= 1.0 else (lo, mid)
+    for f, stable in ((0.999, True), (1.001, False)):
+        CE, CB = coef.fit(N, f * lo)
+        T = _one_step_matrix(Nz, Nr, m, dz, dr, f * lo * dz, CE, CB)
+        rmax = np.abs(np.linalg.eigvals(T)).max()
+        if stable:
+            assert rmax < 1.0 + 1e-10
+        else:
+            assert rmax > 1.01
+
+
+# --------------------------------------------------------------------------
+# axis: the m = 1 field is single valued on the axis, F_phi^1 = i F_r^1
+
+
+@pytest.mark.parametrize("N", [1, 16])
+def test_m1_axis_values_single_valued(N):
+    """E_phi^1 and B_r^1 on the axis row are read only by the gather; the
+    Cartesian field there must be single valued, F_phi^1(0) = i F_r^1(0),
+    where F_r^1 (even in r for m = 1) is extrapolated from r = dr/2, 3dr/2.
+    A narrow beam (k w0^2 ~ 2) makes the radial terms of the axis rules large."""
+    Nz, Nr, M = 64, 24, 1
+    dz = dr = 0.25
+    nu = 0.5
+    CE, CB = coef.fit(N, nu)
+    o = oracle.Oracle(Nz, Nr, M, dz, dr, nu * dz, CE, CB)
+    o.add_laser(1.0, 6 * dr, 4.0, Nz * dz / 2, taper=2.0)
+    o.start_fields()
+    o.field_step(40)
+    Er, Ep = o.get_field(oracle.ER, 1), o.get_field(oracle.EP, 1)
+    Br = 0.5 * (o.get_field(oracle.BOR, 1) + o.get_field(oracle.BR, 1))
+    Bp = 0.5 * (o.get_field(oracle.BOP, 1) + o.get_field(oracle.BP, 1))
+    Er0 = (9 * Er[0] - Er[1]) / 8
+    Bp0 = (9 * Bp[0] - Bp[1]) / 8
+    assert np.abs(Ep[0] - 1j * Er0).max() < 0.1 * np.abs(Er0).max()
+    assert np.abs(Br[0] + 1j * Bp0).max() < 0.1 * np.abs(Bp0).max()
+
+
+# --------------------------------------------------------------------------
+# kinematics: free streaming and the wall
+
+
+def test_free_streaming_and_periodic_wrap():
+    Nz, Nr, M = 16, 8, 1
+    dz, dr, dt = 0.4, 1.1, 0.3
+    o = oracle.Oracle(Nz, Nr, M, dz, dr, dt, [1.0], [1.0])
+    u = np.array([0.3, -0.2, 2.5])
+    g = math.sqrt(1 + u @ u)
+    o.set_particles([15.5], [1.0], [0.5], [u[0]], [u[1]], [u[2]], [0.0])
+    n = 7
+    o.step(n)
+    P = o.particles()
+    zexp = (15.5 + n * dt * u[2] / g / dz) % Nz
+    assert abs(P["z"][0] - zexp) < 1e-12
+    assert abs(P["x"][0] - (1.0 + n * dt * u[0] / g / dr)) < 1e-12
+    assert abs(P["y"][0] - (0.5 + n * dt * u[1] / g / dr)) < 1e-12
+    assert abs(P["uz"][0] - u[2]) == 0.0
+
+
+def test_wall_reflection_is_specular():
+    Nz, Nr, M = 8, 6, 1
+    dz, dr, dt = 0.4, 1.0, 0.35
+    o = oracle.Oracle(Nz, Nr, M, dz, dr, dt, [1.0], [1.0])
+    u = np.array([3.0, 1.0, 0.5])
+    o.set_particles([2.0], [4.9], [0.1], [u[0]], [u[1]], [u[2]], [0.0])
+    o.step(1)
+    P = o.particles()
+    r = math.hypot(P["x"][0], P["y"][0])
+    assert r < Nr - 1
+    un = np.array([P["ux"][0], P["uy"][0], P["uz"][0]])
+    assert abs(np.linalg.norm(un) - np.linalg.norm(u)) < 1e-14
+    nx, ny = P["x"][0] / r, P["y"][0] / r
+    assert un[0] * nx + un[1] * ny < 0  # now moving inwards
+
+
+# --------------------------------------------------------------------------
+# P4 on the grid: gather of E^n and the Eq. (12) average of B, dual vs Yee
+
+
+def _grid_orbit(N, nsteps=190, a0=0.5):
+    Nz, Nr, M = 192, 64, 1
+    dz = LAMBDA0 / 16
+    dr = 4 * dz
+    nu = 0.9341
+    dt = nu * dz
+    CE, CB = coef.fit(N, nu)
+    o = oracle.Oracle(Nz, Nr, M, dz, dr, dt, CE, CB)
+    L = Nz * dz
+    tau = 2 * LAMBDA0
+    zc = L / 2 - 1.5 * tau
+
+    def a_env(z):
+        return np.exp(-2 * np.log(2) * (z - zc) ** 2 / tau**2)
+
+    zi = np.arange(Nz) * dz
+    zh = zi + 0.5 * dz
+    E = a0 * a_env(zi) * np.sin(-(zi - zc))
+    B = a0 * a_env(zh) * np.sin(-(zh - zc))
+    ones = np.ones((Nr + 1, 1))
+    o.set_field(oracle.ER, 1, ones * E)
+    o.set_field(oracle.EP, 1, 1j * ones * E)
+    o.set_field(oracle.BR, 1, -1j * ones * B)
+    o.set_field(oracle.BP, 1, ones * B)
+    o.start_fields()
+    o.set_particles([L / 2 / dz], [0.3], [0.1], [0.0], [0.0], [0.0], [0.0])
+    err = umax = 0.0
+    for _ in range(nsteps):
+        o.step(1)
+        P = o.particles()
+        u = np.array([P["ux"][0], P["uy"][0], P["uz"][0]])
+        err = max(err, abs(math.sqrt(1 + u @ u) - u[2] - 1.0))
+        umax = max(umax, abs(u[0]))
+    assert umax > 0.3  # the pulse went over the electron
+    return err, u
+
+
+@pytest.mark.slow
+def test_P4_grid_orbit_dual_beats_yee():
+    e_dual, u_dual = _grid_orbit(16)
+    e_yee, _ = _grid_orbit(1)
+    assert np.abs(u_dual).max() < 0.05  # the pulse has passed and left it nearly at rest
+    assert e_dual < 2e-3
+    assert e_yee > 3.0 * e_dual
+
+
+def test_laser_init_propagates_forward_at_c():
+    """The Eq. (18) pulse placed in m = 1 is a forward wave: its energy
+    centroid advances at the speed of light."""
+    Nz, Nr, M = 256, 32, 1
+    dz = LAMBDA0 / 16
+    dr = 4 * dz
+    dt, CE, CB, _ = setup_cached(16, M, dz, dr)
+    o = oracle.Oracle(Nz, Nr, M, dz, dr, dt, CE, CB)
+    o.add_laser(1.0, 4 * LAMBDA0, 2 * LAMBDA0, 5 * LAMBDA0, taper=LAMBDA0)
+    o.start_fields()
+
+    def centroid():
+        e = sum(np.abs(o.get_field(c, 1)) ** 2 for c in (oracle.ER, oracle.EP, oracle.EZ))
+        w = (e * (np.arange(Nr + 1) + 0.5)[:, None]).sum(axis=0)
+        return (w * np.arange(Nz) * dz).sum() / w.sum()
+
+    z0 = centroid()
+    n = 60
+    o.field_step(n)
+    assert abs((centroid() - z0) / (n * dt) - 1.0) < 0.02
