@@ -1,0 +1,222 @@
+/*
+ * pic.h -- C ABI of the MI355X (gfx950) quasi-3D r-z particle-in-cell step
+ * with the "dual" finite-difference Maxwell solver (Miller et al., arXiv
+ * 2303.12874).
+ *
+ * The library advances a laser-plasma simulation in the azimuthal-mode
+ * ("quasi-3D") geometry of Sec. III.B: every field is Re sum_{m=0..M}
+ * F^m(r,z) e^{i m phi}.  One step is
+ *   cell sort (every K steps) -> gather of E^n and of the time-averaged
+ *   B^n = (B^{n-1/2} + B^{n+1/2})/2 (Eq. (12)) -> relativistic Boris push
+ *   (Eq. (6)) with per-mode work on tracked electrons (Eq. (16)) ->
+ *   charge-conserving deposit into the mode arrays -> dual-solver update of
+ *   E and B with distinct z-difference operators D_E, D_B (Eq. (9)) whose
+ *   coefficients satisfy the dispersion condition Eq. (11) and the
+ *   Lorentz-force condition Eq. (15).
+ *
+ * Units: c = omega_0 = 1 (omega_0 the laser frequency), lengths in c/omega_0
+ * (the laser wavelength is 2 pi), time in 1/omega_0, fields in
+ * m c omega_0 / e, densities in units of the critical density.  Electrons
+ * (q/m = -1) move over immobile ions.  The box is periodic in z, has the axis
+ * at r = 0 and a perfectly conducting wall at r = Nr dr; electrons are
+ * reflected at r = (Nr - 1) dr.
+ *
+ * Memory and streams belong to the caller: device memory is one workspace
+ * buffer the caller allocates, the stream is the caller's hipStream_t.  The
+ * library never frees caller memory.  No C++ exception crosses this ABI;
+ * every call returns PIC_OK (0) or a negative PIC_E_* code, and
+ * pic_last_error() (thread local) describes the last failure.
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+#define PIC_OK 0
+#define PIC_E_INVALID (-1) /* a descriptor or argument is out of range          */
+#define PIC_E_CFL (-2)     /* requested dt above the solver's Courant limit      */
+#define PIC_E_NOMEM (-3)   /* workspace or caller buffer too small               */
+#define PIC_E_STATE (-4)   /* NULL or destroyed context, wrong call order        */
+#define PIC_E_DEVICE (-5)  /* a HIP call failed (message in pic_last_error)      */
+#define PIC_E_NUMERIC (-6) /* a reduction met NaN or Inf                         */
+
+/* ---- options ------------------------------------------------------------ */
+#define PIC_PREC_FP64 64 /* fields, particles, currents in FP64                   */
+#define PIC_PREC_FP32 32 /* FP32 fields/particles, z as int32 cell + FP32 offset;
+                            FP64 only in setup, reductions and tracked work   */
+#define PIC_SOLVER_DUAL 0 /* N-coefficient operators fitted to Eqs. (11), (15)  */
+#define PIC_SOLVER_YEE 1  /* the two-point (one-coefficient) Yee operator      */
+
+/* ---- field components for pic_fields ------------------------------------ */
+#define PIC_ER 0   /* E_r   at (z_i,       r_{j+1/2}), time n                  */
+#define PIC_EPHI 1 /* E_phi at (z_i,       r_j)                                */
+#define PIC_EZ 2   /* E_z   at (z_{i+1/2}, r_j)                                */
+#define PIC_BR 3   /* B_r   at (z_{i+1/2}, r_j),       time average at n       */
+#define PIC_BPHI 4 /* B_phi at (z_{i+1/2}, r_{j+1/2})                          */
+#define PIC_BZ 5   /* B_z   at (z_i,       r_{j+1/2})                          */
+#define PIC_JR 6   /* J_r   of the last step, as deposited (before the z filter) */
+#define PIC_JPHI 7 /* J_phi                                                   */
+#define PIC_JZ 8   /* J_z                                                     */
+#define PIC_RHO 9  /* charge density of the electrons at their positions      */
+#define PIC_BR_OLD 10  /* B_r   at time n - 1/2 (staggered storage)           */
+#define PIC_BPHI_OLD 11
+#define PIC_BZ_OLD 12
+#define PIC_BR_NEW 13  /* B_r   at time n + 1/2                               */
+#define PIC_BPHI_NEW 14
+#define PIC_BZ_NEW 15
+
+#define PIC_MAX_PULSES 2
+#define PIC_MAX_MODES 3  /* M <= 3 */
+#define PIC_MAX_COEF 32
+
+/* One laser pulse of Eq. (18), linearly polarised along x, placed in the
+ * m = 1 arrays at t = 0: E_x = A sin(theta), E_z = (2x/w0^2) A cos(theta),
+ * B_y = E_x, B_z = (2y/w0^2) A cos(theta), theta = -(z - zc),
+ * A = a0 exp(-2 ln2 (z - zc)^2 / tau^2) exp(-r^2/w0^2) times a sin^2 taper
+ * over the outer `taper` length at both ends of the periodic box.          */
+typedef struct pic_pulse {
+  double a0;  /* peak normalised amplitude                                   */
+  double w0;  /* spot size (1/e field radius)                                */
+  double tau; /* intensity FWHM, as a length (c = 1)                         */
+  double zc;  /* centroid z                                                  */
+} pic_pulse;
+
+/* One simulation ("run").  Several runs may be passed to one pic_init; they
+ * advance together in one launch per phase (all must share M and precision). */
+typedef struct pic_run_desc {
+  int32_t Nz;       /* cells along z (periodic), >= 8                         */
+  int32_t Nr;       /* cells along r, >= 4; wall at r = Nr dr                 */
+  int32_t M;        /* highest azimuthal mode, 0..PIC_MAX_MODES               */
+  int32_t ppc;      /* electrons per cell, >= 1 (loaded for r < (Nr-1) dr)    */
+  double dz, dr;    /* cell sizes                                             */
+  double n0;        /* electron density (units of n_c)                        */
+  double ramp_start, ramp_len; /* linear up-ramp of the density along z
+                                  (ramp_len = 0: uniform)                     */
+  int32_t n_pulses; /* 0..PIC_MAX_PULSES                                      */
+  pic_pulse pulse[PIC_MAX_PULSES];
+  double taper;     /* laser taper length at the box ends (0: none)           */
+  uint64_t seed;    /* counter-based SplitMix64 seed of the loading           */
+  int32_t n_tracked;/* electrons whose per-mode work is accumulated (FP64)    */
+} pic_run_desc;
+
+typedef struct pic_opts {
+  int32_t precision;    /* PIC_PREC_FP64 or PIC_PREC_FP32                     */
+  int32_t solver;       /* PIC_SOLVER_DUAL or PIC_SOLVER_YEE                  */
+  int32_t n_coef;       /* coefficients per dual operator (1..PIC_MAX_COEF); 16 */
+  double fit_band;      /* k dz fit band upper edge; 0 means 2 pi / 3         */
+  double cfl_fraction;  /* dt = fraction * Courant limit when dt == 0; 0 -> 0.95 */
+  double dt;            /* > 0: use this dt (PIC_E_CFL if above the limit)    */
+  const double *coef_E; /* optional n_coef values of C^E (else fitted)        */
+  const double *coef_B; /* optional n_coef values of C^B (else fitted)        */
+  int32_t sort_interval;/* steps between cell sorts; 0 -> default              */
+  int32_t tile_z, tile_r; /* sort tile in cells; 0 -> default                 */
+  int32_t use_graph;    /* 1: replay steps from a captured hipGraph           */
+} pic_opts;
+
+typedef struct pic_ctx pic_ctx;
+
+/* Per-run facts after pic_init.                                             */
+typedef struct pic_run_info {
+  double dt;             /* time step in use                                 */
+  double courant_limit;  /* largest stable c dt / dz for these coefficients  */
+  int64_t n_particles;   /* electrons in the run                             */
+  int64_t steps_done;    /* steps taken since pic_init                       */
+  int32_t n_coef;        /* coefficients per operator                        */
+  int32_t n_tracked;
+} pic_run_info;
+
+/* ---- host-only setup (no GPU needed) ----------------------------------- */
+
+/* Solver coefficients and time step (Sec. III.A).  The dual operators are
+ * fitted by constrained least squares on k dz in (0, fit_band] to
+ * [k]_E = tan(k dt/2)/(dt/2) and [k]_B = sin(k dt)/dt, which together are
+ * Eqs. (11) and (15); the Courant limit combines max_k [k]_B[k]_E with the
+ * largest radial eigenvalue of modes 0..M, and dt = cfl_fraction * limit
+ * (coefficients refitted at that dt).  coef_E, coef_B: n_coef doubles each
+ * (caller owned).  Returns PIC_E_INVALID on bad sizes.                      */
+int pic_solver_setup(int32_t solver, int32_t n_coef, int32_t M, double dz, double dr,
+                     double cfl_fraction, double fit_band, double *dt, double *courant_limit,
+                     double *coef_E, double *coef_B);
+
+/* Courant limit (largest stable c dt / dz) of given coefficients.           */
+int pic_courant_limit(int32_t n_coef, const double *coef_E, const double *coef_B, int32_t M,
+                      double dz, double dr, double *courant_limit);
+
+/* The electrons pic_init loads for `run`, on the host, in FP64: positions in
+ * cell units (z in dz, x and y in dr), weights w (charge -w), ids.  Arrays of
+ * length n = Nz (Nr - 1) ppc, caller owned; *n_out receives n (call with
+ * NULL arrays to query).  tracked_ids (n_tracked, ascending) may be NULL.   */
+int pic_load_host(const pic_run_desc *run, double *z, double *x, double *y, double *w,
+                  int64_t *id, int64_t *tracked_ids, int64_t *n_out);
+
+/* ---- device life cycle --------------------------------------------------- */
+
+/* Validate, set up (coefficients, dt, loading, laser) and upload n_runs runs
+ * into device_workspace on hip_stream.  With device_workspace == NULL only
+ * *workspace_bytes is written (size query, no device call).  Otherwise
+ * *workspace_bytes must be at least the queried size; the buffer must stay
+ * allocated until pic_destroy.  *out receives the context.                   */
+int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts,
+             void *device_workspace, size_t *workspace_bytes, void *hip_stream, pic_ctx **out);
+
+/* Enqueue n_steps steps of every run on the context's stream (asynchronous).*/
+int pic_step(pic_ctx *ctx, int64_t n_steps);
+
+/* Synchronise the stream and copy out FP64 diagnostics of one run (any
+ * pointer may be NULL): work[n_tracked][M+1] per-mode work -sum dt E^m . v
+ * (Eq. (16)); gamma[n_tracked] from the momentum; gamma_acc[n_tracked] the
+ * initial gamma plus the work summed over modes (FP64 accumulation);
+ * ids[n_tracked] (ascending); field_energy[M+1]; kinetic[1] = sum w (gamma-1).
+ * PIC_E_NUMERIC if a reduction is not finite.                               */
+int pic_mode_work(pic_ctx *ctx, int32_t run, double *work, double *gamma, double *gamma_acc,
+                  int64_t *ids, double *field_energy, double *kinetic);
+
+/* Synchronise and copy one component of mode m of one run into out, FP64
+ * interleaved complex [(Nr+1)][Nz] (2 (Nr+1) Nz doubles; m = 0 has zero
+ * imaginary part), physical units.  PIC_E_NOMEM if out_len (in doubles) is
+ * short.                                                                    */
+int pic_fields(pic_ctx *ctx, int32_t run, int32_t comp, int32_t m, double *out, size_t out_len);
+
+/* Synchronise and copy the electrons of one run in device order (FP64, cell
+ * units: z = cell + offset for FP32 runs).  Any pointer may be NULL; arrays
+ * hold n_particles values (out_len checked).                                */
+int pic_particles(pic_ctx *ctx, int32_t run, double *z, double *x, double *y, double *ux,
+                  double *uy, double *uz, double *w, int64_t *id, size_t out_len);
+
+/* Coefficients in use: coef_E, coef_B (n_coef each) and the z-filter taps
+ * (2 n_coef - 1) applied to J_r and J_phi; any may be NULL.                 */
+int pic_coefficients(pic_ctx *ctx, int32_t run, double *coef_E, double *coef_B, double *taps);
+
+int pic_run_info_get(pic_ctx *ctx, int32_t run, pic_run_info *info);
+
+/* ---- per-phase timing -------------------------------------------------- */
+#define PIC_PHASE_SORT 0   /* cell sort of the electrons                       */
+#define PIC_PHASE_PUSH 1   /* gather + push + deposit                          */
+#define PIC_PHASE_EFIELD 2 /* E update (with the z filter of J)                */
+#define PIC_PHASE_BFIELD 3 /* B update                                         */
+#define PIC_NPHASES 4
+
+/* enable != 0: from now on pic_step brackets every phase launch with HIP
+ * events on the context's stream (the counters restart at zero); 0: stop.   */
+int pic_profile(pic_ctx *ctx, int32_t enable);
+
+/* Synchronise and return, per phase, the summed event time in ms and the
+ * number of launches timed since pic_profile(ctx, 1).                       */
+int pic_profile_read(pic_ctx *ctx, double *ms, int64_t *launches);
+
+/* Free host objects of the context (not the workspace).                     */
+int pic_destroy(pic_ctx *ctx);
+
+/* Description of the last failure on this thread ("" if none).             */
+const char *pic_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PIC_H */

@@ -20,7 +20,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "q3d_oracle.c")
 _LIB = os.path.join(_HERE, "liborc.so")
 
-GCC_FLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fcx-fortran-rules"]
+GCC_FLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fcx-fortran-rules",
+             "-fno-builtin-sin", "-fno-builtin-cos", "-fno-builtin-sincos"]
 
 
 def build(force: bool = False) -> str:

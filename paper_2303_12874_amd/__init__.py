@@ -1,0 +1,289 @@
+"""Python binding of libpic.so, the MI355X quasi-3D r-z PIC step with the dual solver.
+
+Argument marshalling only: every computation runs in the C ABI declared in
+include/pic.h (host set-up in C++, the step in HIP kernels for gfx950).
+PyTorch provides the device workspace and the stream.  If the built library
+is missing, importing this package raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpic.so")
+
+PIC_OK, PIC_E_INVALID, PIC_E_CFL, PIC_E_NOMEM, PIC_E_STATE, PIC_E_DEVICE, PIC_E_NUMERIC = 0, -1, -2, -3, -4, -5, -6
+PREC_FP64, PREC_FP32 = 64, 32
+SOLVER_DUAL, SOLVER_YEE = 0, 1
+(ER, EPHI, EZ, BR, BPHI, BZ, JR, JPHI, JZ, RHO, BR_OLD, BPHI_OLD, BZ_OLD, BR_NEW, BPHI_NEW,
+ BZ_NEW) = range(16)
+MAX_PULSES = 2
+
+
+class PicError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"pic error {code}: {msg}")
+        self.code = code
+
+
+class _Pulse(C.Structure):
+    _fields_ = [("a0", C.c_double), ("w0", C.c_double), ("tau", C.c_double), ("zc", C.c_double)]
+
+
+class _RunDesc(C.Structure):
+    _fields_ = [
+        ("Nz", C.c_int32), ("Nr", C.c_int32), ("M", C.c_int32), ("ppc", C.c_int32),
+        ("dz", C.c_double), ("dr", C.c_double), ("n0", C.c_double),
+        ("ramp_start", C.c_double), ("ramp_len", C.c_double),
+        ("n_pulses", C.c_int32), ("pulse", _Pulse * MAX_PULSES), ("taper", C.c_double),
+        ("seed", C.c_uint64), ("n_tracked", C.c_int32),
+    ]
+
+
+class _Opts(C.Structure):
+    _fields_ = [
+        ("precision", C.c_int32), ("solver", C.c_int32), ("n_coef", C.c_int32),
+        ("fit_band", C.c_double), ("cfl_fraction", C.c_double), ("dt", C.c_double),
+        ("coef_E", C.POINTER(C.c_double)), ("coef_B", C.POINTER(C.c_double)),
+        ("sort_interval", C.c_int32), ("tile_z", C.c_int32), ("tile_r", C.c_int32),
+        ("use_graph", C.c_int32),
+    ]
+
+
+class _RunInfo(C.Structure):
+    _fields_ = [("dt", C.c_double), ("courant_limit", C.c_double), ("n_particles", C.c_int64),
+                ("steps_done", C.c_int64), ("n_coef", C.c_int32), ("n_tracked", C.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (or python -m "
+                          "paper_2303_12874_amd.build)")
+    lib = C.CDLL(LIB_PATH)
+    i32, i64, d, p, sz = C.c_int32, C.c_int64, C.c_double, C.c_void_p, C.c_size_t
+    dp = C.POINTER(C.c_double)
+    sigs = {
+        "pic_solver_setup": [i32, i32, i32, d, d, d, d, dp, dp, dp, dp],
+        "pic_courant_limit": [i32, dp, dp, i32, d, d, dp],
+        "pic_load_host": [C.POINTER(_RunDesc), p, p, p, p, p, p, C.POINTER(C.c_int64)],
+        "pic_init": [C.POINTER(_RunDesc), i32, C.POINTER(_Opts), p, C.POINTER(C.c_size_t), p, C.POINTER(p)],
+        "pic_step": [p, i64],
+        "pic_mode_work": [p, i32, p, p, p, p, p, p],
+        "pic_fields": [p, i32, i32, i32, p, sz],
+        "pic_particles": [p, i32, p, p, p, p, p, p, p, p, sz],
+        "pic_coefficients": [p, i32, p, p, p],
+        "pic_run_info_get": [p, i32, C.POINTER(_RunInfo)],
+        "pic_destroy": [p],
+        "pic_profile": [p, i32],
+        "pic_profile_read": [p, p, p],
+    }
+    for name, args in sigs.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    lib.pic_last_error.argtypes = []
+    lib.pic_last_error.restype = C.c_char_p
+    return lib
+
+
+_lib = _load()
+EXPORTED = ("pic_solver_setup", "pic_courant_limit", "pic_load_host", "pic_init", "pic_step", "pic_mode_work",
+            "pic_fields", "pic_particles", "pic_coefficients", "pic_run_info_get", "pic_destroy",
+            "pic_last_error", "pic_profile", "pic_profile_read")
+PHASES = ("sort", "push", "efield", "bfield")
+
+
+def _check(rc):
+    if rc != PIC_OK:
+        raise PicError(rc, _lib.pic_last_error().decode())
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+@dataclass
+class Pulse:
+    a0: float
+    w0: float
+    tau: float
+    zc: float
+
+
+@dataclass
+class RunDesc:
+    """One run (grid, plasma, laser); lengths in c/omega_0."""
+    Nz: int
+    Nr: int
+    M: int
+    ppc: int
+    dz: float
+    dr: float
+    n0: float = 0.0
+    ramp_start: float = 0.0
+    ramp_len: float = 0.0
+    pulses: List[Pulse] = field(default_factory=list)
+    taper: float = 0.0
+    seed: int = 0
+    n_tracked: int = 0
+
+    def to_c(self) -> _RunDesc:
+        r = _RunDesc()
+        r.Nz, r.Nr, r.M, r.ppc = self.Nz, self.Nr, self.M, self.ppc
+        r.dz, r.dr, r.n0, r.ramp_start, r.ramp_len = self.dz, self.dr, self.n0, self.ramp_start, self.ramp_len
+        if len(self.pulses) > MAX_PULSES:
+            raise ValueError("at most %d pulses" % MAX_PULSES)
+        r.n_pulses = len(self.pulses)
+        for k, pl in enumerate(self.pulses):
+            r.pulse[k] = _Pulse(pl.a0, pl.w0, pl.tau, pl.zc)
+        r.taper = self.taper
+        r.seed = self.seed & (2**64 - 1)
+        r.n_tracked = self.n_tracked
+        return r
+
+
+def solver_setup(M, dz, dr, solver=SOLVER_DUAL, n_coef=16, cfl_fraction=0.95, fit_band=0.0):
+    """(dt, courant_limit, coef_E, coef_B) from the library's host set-up."""
+    N = 1 if solver == SOLVER_YEE else n_coef
+    dt, lim = C.c_double(), C.c_double()
+    ce, cb = np.zeros(N), np.zeros(N)
+    dp = C.POINTER(C.c_double)
+    _check(_lib.pic_solver_setup(solver, n_coef, M, dz, dr, cfl_fraction, fit_band, C.byref(dt), C.byref(lim),
+                                 ce.ctypes.data_as(dp), cb.ctypes.data_as(dp)))
+    return dt.value, lim.value, ce, cb
+
+
+def courant_limit(coef_E, coef_B, M, dz, dr):
+    ce = np.ascontiguousarray(coef_E, dtype=np.float64)
+    cb = np.ascontiguousarray(coef_B, dtype=np.float64)
+    out = C.c_double()
+    dp = C.POINTER(C.c_double)
+    _check(_lib.pic_courant_limit(ce.size, ce.ctypes.data_as(dp), cb.ctypes.data_as(dp), M, dz, dr, C.byref(out)))
+    return out.value
+
+
+def load_host(run: RunDesc):
+    """Electrons the library loads for `run` (host, FP64, cell units)."""
+    rd = run.to_c()
+    n = C.c_int64()
+    _check(_lib.pic_load_host(C.byref(rd), None, None, None, None, None, None, C.byref(n)))
+    z, x, y, w = (np.zeros(n.value) for _ in range(4))
+    ids = np.zeros(n.value, dtype=np.int64)
+    tr = np.zeros(max(run.n_tracked, 1), dtype=np.int64)
+    _check(_lib.pic_load_host(C.byref(rd), _ptr(z), _ptr(x), _ptr(y), _ptr(w), _ptr(ids), _ptr(tr), C.byref(n)))
+    return {"z": z, "x": x, "y": y, "w": w, "id": ids, "tracked": tr[: run.n_tracked]}
+
+
+def workspace_bytes(runs: Sequence[RunDesc], precision=PREC_FP64, solver=SOLVER_DUAL, n_coef=16, **kw) -> int:
+    arr = (_RunDesc * len(runs))(*[r.to_c() for r in runs])
+    o = _make_opts(precision, solver, n_coef, **kw)[0]
+    nbytes = C.c_size_t(0)
+    _check(_lib.pic_init(arr, len(runs), C.byref(o), None, C.byref(nbytes), None, None))
+    return nbytes.value
+
+
+def _make_opts(precision, solver, n_coef, dt=0.0, coef_E=None, coef_B=None, cfl_fraction=0.0, fit_band=0.0,
+               sort_interval=0, tile_z=0, tile_r=0, use_graph=False):
+    o = _Opts()
+    o.precision, o.solver, o.n_coef = precision, solver, n_coef
+    o.fit_band, o.cfl_fraction, o.dt = fit_band, cfl_fraction, dt
+    keep = []
+    for name, val in (("coef_E", coef_E), ("coef_B", coef_B)):
+        if val is not None:
+            a = np.ascontiguousarray(val, dtype=np.float64)
+            keep.append(a)
+            setattr(o, name, a.ctypes.data_as(C.POINTER(C.c_double)))
+    o.sort_interval, o.tile_z, o.tile_r, o.use_graph = sort_interval, tile_z, tile_r, int(use_graph)
+    return o, keep
+
+
+class Simulation:
+    """Runs on one GPU.  `device` is a torch device string; the workspace is a
+    torch uint8 tensor and the stream torch's current stream on that device."""
+
+    def __init__(self, runs: Sequence[RunDesc], precision=PREC_FP64, solver=SOLVER_DUAL, n_coef=16,
+                 device="cuda:0", **kw):
+        import torch  # device memory and streams only
+
+        self.runs = list(runs)
+        self.precision = precision
+        self._arr = (_RunDesc * len(self.runs))(*[r.to_c() for r in self.runs])
+        self._opts, self._keep = _make_opts(precision, solver, n_coef, **kw)
+        nbytes = C.c_size_t(0)
+        _check(_lib.pic_init(self._arr, len(self.runs), C.byref(self._opts), None, C.byref(nbytes), None, None))
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        _check(_lib.pic_init(self._arr, len(self.runs), C.byref(self._opts), C.c_void_p(self.workspace.data_ptr()),
+                             C.byref(nbytes), C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(_lib.pic_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1):
+        _check(_lib.pic_step(self._h, int(n)))
+
+    def profile(self, enable=True):
+        """Start (restart) or stop per-phase HIP-event timing of pic_step."""
+        _check(_lib.pic_profile(self._h, int(enable)))
+
+    def profile_read(self):
+        """{phase: (total ms, launches)} since profiling was enabled."""
+        ms = np.zeros(len(PHASES))
+        n = np.zeros(len(PHASES), dtype=np.int64)
+        _check(_lib.pic_profile_read(self._h, _ptr(ms), _ptr(n)))
+        return {ph: (float(ms[i]), int(n[i])) for i, ph in enumerate(PHASES)}
+
+    def info(self, run=0):
+        inf = _RunInfo()
+        _check(_lib.pic_run_info_get(self._h, run, C.byref(inf)))
+        return {"dt": inf.dt, "courant_limit": inf.courant_limit, "n_particles": inf.n_particles,
+                "steps_done": inf.steps_done, "n_coef": inf.n_coef, "n_tracked": inf.n_tracked}
+
+    def coefficients(self, run=0):
+        N = self.info(run)["n_coef"]
+        ce, cb, p = np.zeros(N), np.zeros(N), np.zeros(2 * N - 1)
+        _check(_lib.pic_coefficients(self._h, run, _ptr(ce), _ptr(cb), _ptr(p)))
+        return ce, cb, p
+
+    def fields(self, comp, m, run=0):
+        r = self.runs[run]
+        out = np.zeros((r.Nr + 1, r.Nz), dtype=np.complex128)
+        _check(_lib.pic_fields(self._h, run, comp, m, _ptr(out), out.size * 2))
+        return out
+
+    def particles(self, run=0):
+        n = self.info(run)["n_particles"]
+        d = {k: np.zeros(n) for k in ("z", "x", "y", "ux", "uy", "uz", "w")}
+        ids = np.zeros(n, dtype=np.int64)
+        _check(_lib.pic_particles(self._h, run, *[_ptr(d[k]) for k in ("z", "x", "y", "ux", "uy", "uz", "w")],
+                                  _ptr(ids), n))
+        d["id"] = ids
+        return d
+
+    def mode_work(self, run=0):
+        r = self.runs[run]
+        nt = r.n_tracked
+        W = np.zeros((max(nt, 1), r.M + 1))
+        g, ga = np.zeros(max(nt, 1)), np.zeros(max(nt, 1))
+        ids = np.zeros(max(nt, 1), dtype=np.int64)
+        U = np.zeros(r.M + 1)
+        K = np.zeros(1)
+        _check(_lib.pic_mode_work(self._h, run, _ptr(W), _ptr(g), _ptr(ga), _ptr(ids), _ptr(U), _ptr(K)))
+        return {"W": W[:nt], "gamma": g[:nt], "gamma_acc": ga[:nt], "id": ids[:nt], "field_energy": U,
+                "kinetic": K[0]}

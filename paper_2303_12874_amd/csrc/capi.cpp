@@ -1,0 +1,807 @@
+// capi.cpp -- the C ABI of include/pic.h: validation, workspace layout,
+// set-up and upload of runs, the step loop and FP64 read-back.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <set>
+#include <vector>
+
+#include "pic_internal.h"
+
+using namespace pic;
+
+namespace {
+
+thread_local char g_msg[512] = "";
+
+int fail(int code, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_msg, sizeof g_msg, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int hip_ok(hipError_t e, const char *what) {
+  if (e != hipSuccess) return fail(PIC_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+  return PIC_OK;
+}
+
+#define TRY(expr)                 \
+  do {                            \
+    int _rc = (expr);             \
+    if (_rc != PIC_OK) {          \
+      if (_rc == PIC_E_DEVICE && g_msg[0] == 0) fail(_rc, "%s", last_device_error()); \
+      return _rc;                 \
+    }                             \
+  } while (0)
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr uint32_t kMagic = 0x51D3A1C7u;
+constexpr size_t kAlign = 256;
+constexpr int kRedBlocks = 1024;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct RunHost {
+  pic_run_desc d;
+  KRun k;
+  int N = 1;
+  double dt = 0, nu_lim = 0;
+  std::vector<double> CE, CB, P;
+  std::vector<double> gam0;
+  int64_t steps = 0;
+  size_t offset = 0, bytes = 0;
+  double *dev_gamma = nullptr;  // scratch for pic_mode_work
+  int64_t *dev_ids = nullptr;
+};
+
+// Layout of one run in the workspace (offsets from the run's base).
+struct Layout {
+  size_t E, B0, B1, J0, J1, rho, pz, pfz, px, py, pux, puy, puz, pw, pid;
+  size_t sz, sfz, sx, sy, sux, suy, suz, sw, spid, perm, ccount, cstart, scan;
+  size_t W, tracked, CE, CB, P, red, gam, ids, total;
+};
+
+Layout layout_of(const pic_run_desc &d, int prec, int N, int Tz, int Tr, long long n_keys) {
+  const size_t rs = prec == PIC_PREC_FP64 ? 8 : 4;
+  const int NM = 2 * d.M + 1;
+  const size_t plane = (size_t)(d.Nr + 1) * d.Nz;
+  const size_t np = (size_t)run_particle_count(d);
+  Layout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  const size_t vec = 3 * NM * plane * rs;
+  L.E = take(vec);
+  L.B0 = take(vec);
+  L.B1 = take(vec);
+  L.J0 = take(vec);
+  L.J1 = take(vec);
+  L.rho = take(NM * plane * 8);
+  L.pz = take(np * (prec == PIC_PREC_FP64 ? 8 : 4));
+  L.pfz = take(prec == PIC_PREC_FP64 ? 0 : np * 4);
+  L.px = take(np * rs);
+  L.py = take(np * rs);
+  L.pux = take(np * rs);
+  L.puy = take(np * rs);
+  L.puz = take(np * rs);
+  L.pw = take(np * rs);
+  L.pid = take(np * 4);
+  L.sz = take(np * (prec == PIC_PREC_FP64 ? 8 : 4));
+  L.sfz = take(prec == PIC_PREC_FP64 ? 0 : np * 4);
+  L.sx = take(np * rs);
+  L.sy = take(np * rs);
+  L.sux = take(np * rs);
+  L.suy = take(np * rs);
+  L.suz = take(np * rs);
+  L.sw = take(np * rs);
+  L.spid = take(np * 4);
+  L.perm = take(np * 4);
+  L.ccount = take((size_t)(n_keys + 1) * 4);
+  L.cstart = take((size_t)(n_keys + 1) * 4);
+  L.scan = take(((size_t)(n_keys + 1) / 256 + 2) * 4 * 2);
+  L.W = take((size_t)(d.n_tracked > 0 ? d.n_tracked : 1) * (d.M + 1) * 8);
+  L.tracked = take((size_t)(d.n_tracked > 0 ? d.n_tracked : 1) * 4);
+  L.CE = take((size_t)N * rs);
+  L.CB = take((size_t)N * rs);
+  L.P = take((size_t)(2 * N - 1) * rs);
+  L.red = take((size_t)kRedBlocks * (PIC_MAX_MODES + 1) * 8);
+  L.gam = take((size_t)(d.n_tracked > 0 ? d.n_tracked : 1) * 8);
+  L.ids = take((size_t)(d.n_tracked > 0 ? d.n_tracked : 1) * 8);
+  L.total = o;
+  (void)Tz;
+  (void)Tr;
+  return L;
+}
+
+}  // namespace
+
+struct pic_ctx {
+  uint32_t magic = kMagic;
+  int prec = PIC_PREC_FP64;
+  hipStream_t stream = nullptr;
+  unsigned char *ws = nullptr;
+  int sort_interval = 0;
+  std::vector<RunHost> runs;
+  // per-phase event timing
+  bool profiling = false;
+  struct Mark {
+    int phase;
+    hipEvent_t a, b;
+  };
+  std::vector<Mark> marks;
+  std::vector<hipEvent_t> event_pool;
+  double phase_ms[PIC_NPHASES] = {0, 0, 0, 0};
+  int64_t phase_n[PIC_NPHASES] = {0, 0, 0, 0};
+  ~pic_ctx() {
+    for (auto &m : marks) {
+      (void)hipEventDestroy(m.a);
+      (void)hipEventDestroy(m.b);
+    }
+    for (auto &e : event_pool) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+int validate_run(const pic_run_desc &r, int i, int N) {
+  if (r.Nz < 8 || r.Nr < 4 || r.M < 0 || r.M > PIC_MAX_MODES || r.ppc < 0)
+    return fail(PIC_E_INVALID, "run %d: grid Nz=%d Nr=%d M=%d ppc=%d out of range", i, r.Nz, r.Nr, r.M, r.ppc);
+  if (r.Nz < 2 * N) return fail(PIC_E_INVALID, "run %d: Nz=%d shorter than the %d-tap stencil", i, r.Nz, 2 * N);
+  if (!(r.dz > 0) || !(r.dr > 0) || !std::isfinite(r.dz) || !std::isfinite(r.dr))
+    return fail(PIC_E_INVALID, "run %d: cell sizes must be positive", i);
+  if (!(r.n0 >= 0) || !(r.ramp_len >= 0)) return fail(PIC_E_INVALID, "run %d: density must be >= 0", i);
+  if (r.n_pulses < 0 || r.n_pulses > PIC_MAX_PULSES) return fail(PIC_E_INVALID, "run %d: n_pulses out of range", i);
+  if (r.n_pulses > 0 && r.M < 1) return fail(PIC_E_INVALID, "run %d: a laser needs M >= 1", i);
+  for (int p = 0; p < r.n_pulses; ++p)
+    if (!(r.pulse[p].w0 > 0) || !(r.pulse[p].tau > 0))
+      return fail(PIC_E_INVALID, "run %d: pulse %d needs w0 > 0 and tau > 0", i, p);
+  const int64_t np = run_particle_count(r);
+  if (np > (int64_t)kIdMask) return fail(PIC_E_INVALID, "run %d: %lld electrons exceed the id range", i, (long long)np);
+  if (r.n_tracked < 0 || r.n_tracked > np) return fail(PIC_E_INVALID, "run %d: n_tracked out of range", i);
+  if ((int64_t)(r.Nr + 1) * r.Nz * (2 * r.M + 1) * 3 > ((int64_t)1 << 40))
+    return fail(PIC_E_INVALID, "run %d: grid too large", i);
+  return PIC_OK;
+}
+
+void default_tiles(const pic_opts &o, int *Tz, int *Tr) {
+  *Tz = o.tile_z > 0 ? o.tile_z : 32;
+  *Tr = o.tile_r > 0 ? o.tile_r : 8;
+}
+
+long long keys_of(const pic_run_desc &r, int Tz, int Tr) {
+  const long long ntz = (r.Nz + Tz - 1) / Tz, ntr = (r.Nr + Tr - 1) / Tr;
+  return ntz * ntr * (long long)Tz * Tr;
+}
+
+RunHost *get_run(pic_ctx *ctx, int run) {
+  if (run < 0 || run >= (int)ctx->runs.size()) return nullptr;
+  return &ctx->runs[(size_t)run];
+}
+
+// live contexts: a destroyed or foreign handle is recognised without touching it
+std::mutex g_live_mu;
+std::set<const pic_ctx *> g_live;
+
+bool ctx_ok(pic_ctx *ctx) {
+  std::lock_guard<std::mutex> lk(g_live_mu);
+  return ctx && g_live.count(ctx) && ctx->magic == kMagic;
+}
+void ctx_register(pic_ctx *ctx) {
+  std::lock_guard<std::mutex> lk(g_live_mu);
+  g_live.insert(ctx);
+}
+void ctx_unregister(pic_ctx *ctx) {
+  std::lock_guard<std::mutex> lk(g_live_mu);
+  g_live.erase(ctx);
+}
+
+template <typename T>
+int upload(void *dst, const std::vector<T> &src, hipStream_t s) {
+  if (src.empty()) return PIC_OK;
+  return hip_ok(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s),
+                "hipMemcpyAsync H2D");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pic_last_error(void) { return g_msg; }
+
+int pic_solver_setup(int32_t solver, int32_t n_coef, int32_t M, double dz, double dr, double cfl_fraction,
+                     double fit_band, double *dt, double *courant_limit, double *coef_E, double *coef_B) {
+  g_msg[0] = 0;
+  if (solver != PIC_SOLVER_DUAL && solver != PIC_SOLVER_YEE) return fail(PIC_E_INVALID, "unknown solver %d", solver);
+  const int N = solver == PIC_SOLVER_YEE ? 1 : n_coef;
+  if (N < 1 || N > PIC_MAX_COEF || M < 0 || M > PIC_MAX_MODES || !(dz > 0) || !(dr > 0))
+    return fail(PIC_E_INVALID, "bad solver setup arguments");
+  const double band = fit_band > 0 ? fit_band : 2.0 * kPi / 3.0;
+  const double frac = cfl_fraction > 0 ? cfl_fraction : 0.95;
+  if (!(frac <= 1.0)) return fail(PIC_E_INVALID, "cfl_fraction must be in (0, 1]");
+  const double lim = courant_limit_fitted(solver, N, M, dz, dr, band);
+  std::vector<double> CE(N), CB(N);
+  const double nu = frac * lim;
+  if (N == 1) CE[0] = CB[0] = 1.0;
+  else fit_dual(N, nu, band, CE.data(), CB.data());
+  if (dt) *dt = nu * dz;
+  if (courant_limit) *courant_limit = lim;
+  if (coef_E) std::memcpy(coef_E, CE.data(), sizeof(double) * N);
+  if (coef_B) std::memcpy(coef_B, CB.data(), sizeof(double) * N);
+  return PIC_OK;
+}
+
+int pic_courant_limit(int32_t n_coef, const double *coef_E, const double *coef_B, int32_t M, double dz, double dr,
+                      double *courant_limit) {
+  g_msg[0] = 0;
+  if (n_coef < 1 || n_coef > PIC_MAX_COEF || !coef_E || !coef_B || M < 0 || M > PIC_MAX_MODES || !(dz > 0) ||
+      !(dr > 0) || !courant_limit)
+    return fail(PIC_E_INVALID, "bad arguments");
+  *courant_limit = courant_limit_of(coef_E, coef_B, n_coef, M, dz, dr);
+  return PIC_OK;
+}
+
+int pic_load_host(const pic_run_desc *run, double *z, double *x, double *y, double *w, int64_t *id,
+                  int64_t *tracked_ids, int64_t *n_out) {
+  g_msg[0] = 0;
+  if (!run || !n_out) return fail(PIC_E_INVALID, "NULL argument");
+  TRY(validate_run(*run, 0, 1));
+  *n_out = run_particle_count(*run);
+  if (!z && !x && !y && !w && !id && !tracked_ids) return PIC_OK;
+  load_electrons(*run, z, x, y, w, id, tracked_ids);
+  return PIC_OK;
+}
+
+int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, void *device_workspace,
+             size_t *workspace_bytes, void *hip_stream, pic_ctx **out) {
+  g_msg[0] = 0;
+  if (!runs || n_runs < 1 || !opts || !workspace_bytes) return fail(PIC_E_INVALID, "NULL or empty argument");
+  const pic_opts &o = *opts;
+  if (o.precision != PIC_PREC_FP64 && o.precision != PIC_PREC_FP32)
+    return fail(PIC_E_INVALID, "precision must be 64 or 32");
+  if (o.solver != PIC_SOLVER_DUAL && o.solver != PIC_SOLVER_YEE) return fail(PIC_E_INVALID, "unknown solver");
+  const int N = o.solver == PIC_SOLVER_YEE ? 1 : o.n_coef;
+  if (N < 1 || N > PIC_MAX_COEF) return fail(PIC_E_INVALID, "n_coef must be in 1..%d", PIC_MAX_COEF);
+  if (o.cfl_fraction < 0 || o.cfl_fraction > 1 || o.dt < 0 || !std::isfinite(o.dt))
+    return fail(PIC_E_INVALID, "cfl_fraction or dt out of range");
+  if ((o.coef_E == nullptr) != (o.coef_B == nullptr)) return fail(PIC_E_INVALID, "give both coef_E and coef_B");
+  if (o.sort_interval < 0 || o.tile_z < 0 || o.tile_r < 0) return fail(PIC_E_INVALID, "negative sort options");
+  for (int i = 0; i < n_runs; ++i) {
+    TRY(validate_run(runs[i], i, N));
+    if (runs[i].M != runs[0].M) return fail(PIC_E_INVALID, "all runs of one context must share M");
+  }
+  int Tz, Tr;
+  default_tiles(o, &Tz, &Tr);
+
+  // workspace size
+  std::vector<Layout> lays;
+  std::vector<size_t> offs;
+  size_t total = 0;
+  for (int i = 0; i < n_runs; ++i) {
+    lays.push_back(layout_of(runs[i], o.precision, N, Tz, Tr, keys_of(runs[i], Tz, Tr)));
+    offs.push_back(total);
+    total = align_up(total + lays.back().total);
+  }
+  if (!device_workspace) {
+    *workspace_bytes = total;
+    return PIC_OK;
+  }
+  if (!out) return fail(PIC_E_INVALID, "NULL out");
+  if (*workspace_bytes < total)
+    return fail(PIC_E_NOMEM, "workspace of %zu bytes, %zu needed", *workspace_bytes, total);
+  if (((uintptr_t)device_workspace) % kAlign) return fail(PIC_E_INVALID, "workspace must be 256-byte aligned");
+
+  pic_ctx *ctx = new (std::nothrow) pic_ctx();
+  if (!ctx) return fail(PIC_E_NOMEM, "host allocation failed");
+  ctx->prec = o.precision;
+  ctx->stream = (hipStream_t)hip_stream;
+  ctx->ws = (unsigned char *)device_workspace;
+  ctx->sort_interval = o.sort_interval > 0 ? o.sort_interval : 0;
+  ctx->runs.resize((size_t)n_runs);
+  const hipStream_t s = ctx->stream;
+  const bool f64 = o.precision == PIC_PREC_FP64;
+  const double band = o.fit_band > 0 ? o.fit_band : 2.0 * kPi / 3.0;
+  const double frac = o.cfl_fraction > 0 ? o.cfl_fraction : 0.95;
+
+  int rc = PIC_OK;
+  for (int i = 0; i < n_runs && rc == PIC_OK; ++i) {
+    RunHost &R = ctx->runs[(size_t)i];
+    R.d = runs[i];
+    R.N = N;
+    const pic_run_desc &d = R.d;
+    // ---- coefficients and dt (Sec. III.A) ----
+    R.CE.assign(N, 1.0);
+    R.CB.assign(N, 1.0);
+    if (o.coef_E) {
+      R.CE.assign(o.coef_E, o.coef_E + N);
+      R.CB.assign(o.coef_B, o.coef_B + N);
+      R.nu_lim = courant_limit_of(R.CE.data(), R.CB.data(), N, d.M, d.dz, d.dr);
+      R.dt = o.dt > 0 ? o.dt : frac * R.nu_lim * d.dz;
+    } else if (o.dt > 0) {
+      if (N > 1) fit_dual(N, o.dt / d.dz, band, R.CE.data(), R.CB.data());
+      R.nu_lim = courant_limit_of(R.CE.data(), R.CB.data(), N, d.M, d.dz, d.dr);
+      R.dt = o.dt;
+    } else {
+      R.nu_lim = courant_limit_fitted(o.solver, N, d.M, d.dz, d.dr, band);
+      R.dt = frac * R.nu_lim * d.dz;
+      if (N > 1) fit_dual(N, R.dt / d.dz, band, R.CE.data(), R.CB.data());
+    }
+    if (R.dt / d.dz > R.nu_lim) {
+      rc = fail(PIC_E_CFL, "run %d: c dt/dz = %.6g above the Courant limit %.6g", i, R.dt / d.dz, R.nu_lim);
+      break;
+    }
+    // z filter taps p_l = sum_{l' > |l|} C^B_{l'}, so that D_B = D_Yee o P
+    R.P.assign(2 * N - 1, 0.0);
+    for (int l = 0; l < N; ++l) {
+      double p = 0.0;
+      for (int lp = l + 1; lp <= N; ++lp) p += R.CB[(size_t)lp - 1];
+      R.P[(size_t)(N - 1 + l)] = p;
+      R.P[(size_t)(N - 1 - l)] = p;
+    }
+    // ---- device view ----
+    const Layout &L = lays[(size_t)i];
+    unsigned char *base = ctx->ws + offs[(size_t)i];
+    R.offset = offs[(size_t)i];
+    R.bytes = L.total;
+    KRun &k = R.k;
+    std::memset(&k, 0, sizeof k);
+    k.Nz = d.Nz;
+    k.Nr = d.Nr;
+    k.M = d.M;
+    k.N = N;
+    k.dz = d.dz;
+    k.dr = d.dr;
+    k.dt = R.dt;
+    k.np = run_particle_count(d);
+    k.plane = (long long)(d.Nr + 1) * d.Nz;
+    k.E = base + L.E;
+    k.B[0] = base + L.B0;
+    k.B[1] = base + L.B1;
+    k.J[0] = base + L.J0;
+    k.J[1] = base + L.J1;
+    k.rho = base + L.rho;
+    k.pz = base + L.pz;
+    k.pfz = base + L.pfz;
+    k.px = base + L.px;
+    k.py = base + L.py;
+    k.pux = base + L.pux;
+    k.puy = base + L.puy;
+    k.puz = base + L.puz;
+    k.pw = base + L.pw;
+    k.pid = (uint32_t *)(base + L.pid);
+    k.sz = base + L.sz;
+    k.sfz = base + L.sfz;
+    k.sx = base + L.sx;
+    k.sy = base + L.sy;
+    k.sux = base + L.sux;
+    k.suy = base + L.suy;
+    k.suz = base + L.suz;
+    k.sw = base + L.sw;
+    k.spid = (uint32_t *)(base + L.spid);
+    k.perm = (int32_t *)(base + L.perm);
+    k.cell_count = (int32_t *)(base + L.ccount);
+    k.cell_start = (int32_t *)(base + L.cstart);
+    k.scan_tmp = (int32_t *)(base + L.scan);
+    k.Tz = Tz;
+    k.Tr = Tr;
+    k.n_keys = keys_of(d, Tz, Tr);
+    k.W = (double *)(base + L.W);
+    k.tracked = (const int32_t *)(base + L.tracked);
+    k.n_tracked = d.n_tracked;
+    k.CE = base + L.CE;
+    k.CB = base + L.CB;
+    k.P = base + L.P;
+    k.red = (double *)(base + L.red);
+    R.dev_gamma = (double *)(base + L.gam);
+    R.dev_ids = (int64_t *)(base + L.ids);
+
+    // ---- coefficients ----
+    if (f64) {
+      if ((rc = upload(base + L.CE, R.CE, s)) || (rc = upload(base + L.CB, R.CB, s)) || (rc = upload(base + L.P, R.P, s)))
+        break;
+    } else {
+      std::vector<float> a(R.CE.begin(), R.CE.end()), b(R.CB.begin(), R.CB.end()), c(R.P.begin(), R.P.end());
+      if ((rc = upload(base + L.CE, a, s)) || (rc = upload(base + L.CB, b, s)) || (rc = upload(base + L.P, c, s))) break;
+      if ((rc = hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize"))) break;
+    }
+    // ---- electrons (host FP64 loading, then the run's precision) ----
+    const int64_t np = k.np;
+    std::vector<double> z(np), x(np), y(np), w(np);
+    std::vector<int64_t> ids(np), tr((size_t)(d.n_tracked > 0 ? d.n_tracked : 0));
+    load_electrons(d, z.data(), x.data(), y.data(), w.data(), ids.data(), tr.empty() ? nullptr : tr.data());
+    std::vector<uint32_t> pid(np);
+    for (int64_t p = 0; p < np; ++p) pid[(size_t)p] = (uint32_t)ids[(size_t)p];
+    for (size_t t = 0; t < tr.size(); ++t) pid[(size_t)tr[t]] |= kTrackedBit;
+    std::vector<int32_t> tr32(tr.begin(), tr.end());
+    R.gam0.assign(tr.size(), 1.0);  // cold start
+    if (f64) {
+      std::vector<double> zero(np, 0.0);
+      if ((rc = upload(k.pz, z, s)) || (rc = upload(k.px, x, s)) || (rc = upload(k.py, y, s)) ||
+          (rc = upload(k.pux, zero, s)) || (rc = upload(k.puy, zero, s)) || (rc = upload(k.puz, zero, s)) ||
+          (rc = upload(k.pw, w, s)) || (rc = upload(k.pid, pid, s)) || (rc = upload((void *)k.tracked, tr32, s)))
+        break;
+      if ((rc = hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize"))) break;
+    } else {
+      // z as int32 cell + FP32 offset; an offset that rounds to 1 carries
+      std::vector<int32_t> iz(np);
+      std::vector<float> fz(np), xf(np), yf(np), wf(np), zero(np, 0.0f);
+      for (int64_t p = 0; p < np; ++p) {
+        double c = std::floor(z[(size_t)p]);
+        float f = (float)(z[(size_t)p] - c);
+        if (f >= 1.0f) {
+          f = 0.0f;
+          c += 1.0;
+          if (c >= d.Nz) c -= d.Nz;
+        }
+        iz[(size_t)p] = (int32_t)c;
+        fz[(size_t)p] = f;
+        xf[(size_t)p] = (float)x[(size_t)p];
+        yf[(size_t)p] = (float)y[(size_t)p];
+        wf[(size_t)p] = (float)w[(size_t)p];
+      }
+      if ((rc = upload(k.pz, iz, s)) || (rc = upload(k.pfz, fz, s)) || (rc = upload(k.px, xf, s)) ||
+          (rc = upload(k.py, yf, s)) || (rc = upload(k.pux, zero, s)) || (rc = upload(k.puy, zero, s)) ||
+          (rc = upload(k.puz, zero, s)) || (rc = upload(k.pw, wf, s)) || (rc = upload(k.pid, pid, s)) ||
+          (rc = upload((void *)k.tracked, tr32, s)))
+        break;
+      if ((rc = hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize"))) break;
+    }
+    // ---- fields: laser E^0, B^0 (Eq. (18)), then B^{-1/2}, B^{+1/2} ----
+    {
+      const int NM = 2 * d.M + 1;
+      const size_t nvec = (size_t)3 * NM * (size_t)k.plane;
+      std::vector<double> Eh(nvec, 0.0), Bh(nvec, 0.0);
+      laser_fields(d, Eh.data(), Bh.data());
+      if (f64) {
+        if ((rc = upload(k.E, Eh, s)) || (rc = upload(k.B[0], Bh, s)) || (rc = upload(k.B[1], Bh, s))) break;
+        if ((rc = hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize"))) break;
+      } else {
+        std::vector<float> Ef(Eh.begin(), Eh.end()), Bf(Bh.begin(), Bh.end());
+        if ((rc = upload(k.E, Ef, s)) || (rc = upload(k.B[0], Bf, s)) || (rc = upload(k.B[1], Bf, s))) break;
+        if ((rc = hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize"))) break;
+      }
+    }
+    const size_t rs = f64 ? 8 : 4;
+    const size_t vecb = (size_t)3 * (2 * d.M + 1) * (size_t)k.plane * rs;
+    if ((rc = launch_zero(k.J[0], vecb, s)) || (rc = launch_zero(k.J[1], vecb, s)) ||
+        (rc = launch_zero(k.W, (size_t)(d.n_tracked > 0 ? d.n_tracked : 1) * (d.M + 1) * 8, s)))
+      break;
+    // B[0] = B^0 + (dt/2) curl_E E^0 = B^{-1/2};  B[1] = B^0 - (dt/2) curl_E E^0 = B^{+1/2}
+    if ((rc = launch_bfield(k, ctx->prec, k.B[0], k.B[0], -0.5 * R.dt, s)) ||
+        (rc = launch_bfield(k, ctx->prec, k.B[1], k.B[1], 0.5 * R.dt, s)))
+      break;
+    if (ctx->sort_interval > 0 && (rc = launch_sort(k, ctx->prec, s))) break;
+    if ((rc = hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize"))) break;
+  }
+  if (rc != PIC_OK) {
+    if (rc == PIC_E_DEVICE && g_msg[0] == 0) fail(rc, "%s", last_device_error());
+    ctx->magic = 0;
+    delete ctx;
+    return rc;
+  }
+  ctx_register(ctx);
+  *out = ctx;
+  return PIC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+hipEvent_t take_event(pic_ctx *ctx) {
+  hipEvent_t e = nullptr;
+  if (!ctx->event_pool.empty()) {
+    e = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    e = nullptr;
+  }
+  return e;
+}
+
+// Launch one phase, bracketed by events when profiling.
+template <typename F>
+int timed(pic_ctx *ctx, int phase, F &&launch) {
+  if (!ctx->profiling) return launch();
+  hipEvent_t a = take_event(ctx), b = take_event(ctx);
+  if (!a || !b) return fail(PIC_E_DEVICE, "hipEventCreate failed");
+  TRY(hip_ok(hipEventRecord(a, ctx->stream), "hipEventRecord"));
+  int rc = launch();
+  TRY(hip_ok(hipEventRecord(b, ctx->stream), "hipEventRecord"));
+  ctx->marks.push_back({phase, a, b});
+  return rc;
+}
+
+// Fold finished marks into the per-phase sums (the stream must be idle).
+int collect_marks(pic_ctx *ctx) {
+  for (auto &m : ctx->marks) {
+    float ms = 0.f;
+    TRY(hip_ok(hipEventElapsedTime(&ms, m.a, m.b), "hipEventElapsedTime"));
+    ctx->phase_ms[m.phase] += ms;
+    ctx->phase_n[m.phase] += 1;
+    ctx->event_pool.push_back(m.a);
+    ctx->event_pool.push_back(m.b);
+  }
+  ctx->marks.clear();
+  return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pic_step(pic_ctx *ctx, int64_t n_steps) {
+  g_msg[0] = 0;
+  if (!ctx_ok(ctx)) return fail(PIC_E_STATE, "invalid or destroyed context");
+  if (n_steps < 0) return fail(PIC_E_INVALID, "n_steps < 0");
+  const hipStream_t s = ctx->stream;
+  const int prec = ctx->prec;
+  for (int64_t n = 0; n < n_steps; ++n) {
+    for (RunHost &R : ctx->runs) {
+      const int par = (int)(R.steps & 1);
+      const KRun &k = R.k;
+      if (ctx->sort_interval > 0 && R.steps % ctx->sort_interval == 0 && R.steps > 0)
+        TRY(timed(ctx, PIC_PHASE_SORT, [&] { return launch_sort(k, prec, s); }));
+      TRY(timed(ctx, PIC_PHASE_PUSH, [&] { return launch_push(k, prec, par, s); }));
+      TRY(timed(ctx, PIC_PHASE_EFIELD, [&] { return launch_efield(k, prec, par, s); }));
+      TRY(timed(ctx, PIC_PHASE_BFIELD, [&] { return launch_bfield(k, prec, k.B[par], k.B[par ^ 1], R.dt, s); }));
+      R.steps++;
+    }
+    // keep the number of outstanding event pairs bounded
+    if (ctx->profiling && ctx->marks.size() > 4096) {
+      TRY(hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize"));
+      TRY(collect_marks(ctx));
+    }
+  }
+  return PIC_OK;
+}
+
+int pic_profile(pic_ctx *ctx, int32_t enable) {
+  g_msg[0] = 0;
+  if (!ctx_ok(ctx)) return fail(PIC_E_STATE, "invalid or destroyed context");
+  TRY(hip_ok(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize"));
+  TRY(collect_marks(ctx));
+  ctx->profiling = enable != 0;
+  if (enable)
+    for (int p = 0; p < PIC_NPHASES; ++p) { ctx->phase_ms[p] = 0; ctx->phase_n[p] = 0; }
+  return PIC_OK;
+}
+
+int pic_profile_read(pic_ctx *ctx, double *ms, int64_t *launches) {
+  g_msg[0] = 0;
+  if (!ctx_ok(ctx)) return fail(PIC_E_STATE, "invalid or destroyed context");
+  TRY(hip_ok(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize"));
+  TRY(collect_marks(ctx));
+  for (int p = 0; p < PIC_NPHASES; ++p) {
+    if (ms) ms[p] = ctx->phase_ms[p];
+    if (launches) launches[p] = ctx->phase_n[p];
+  }
+  return PIC_OK;
+}
+
+int pic_run_info_get(pic_ctx *ctx, int32_t run, pic_run_info *info) {
+  g_msg[0] = 0;
+  if (!ctx_ok(ctx)) return fail(PIC_E_STATE, "invalid or destroyed context");
+  RunHost *R = get_run(ctx, run);
+  if (!R || !info) return fail(PIC_E_INVALID, "bad run index or NULL info");
+  info->dt = R->dt;
+  info->courant_limit = R->nu_lim;
+  info->n_particles = R->k.np;
+  info->steps_done = R->steps;
+  info->n_coef = R->N;
+  info->n_tracked = R->d.n_tracked;
+  return PIC_OK;
+}
+
+int pic_coefficients(pic_ctx *ctx, int32_t run, double *coef_E, double *coef_B, double *taps) {
+  g_msg[0] = 0;
+  if (!ctx_ok(ctx)) return fail(PIC_E_STATE, "invalid or destroyed context");
+  RunHost *R = get_run(ctx, run);
+  if (!R) return fail(PIC_E_INVALID, "bad run index");
+  if (coef_E) std::memcpy(coef_E, R->CE.data(), R->CE.size() * 8);
+  if (coef_B) std::memcpy(coef_B, R->CB.data(), R->CB.size() * 8);
+  if (taps) std::memcpy(taps, R->P.data(), R->P.size() * 8);
+  return PIC_OK;
+}
+
+int pic_fields(pic_ctx *ctx, int32_t run, int32_t comp, int32_t m, double *out, size_t out_len) {
+  g_msg[0] = 0;
+  if (!ctx_ok(ctx)) return fail(PIC_E_STATE, "invalid or destroyed context");
+  RunHost *R = get_run(ctx, run);
+  if (!R) return fail(PIC_E_INVALID, "bad run index");
+  if (comp < 0 || comp > PIC_BZ_NEW || m < 0 || m > R->d.M || !out) return fail(PIC_E_INVALID, "bad component or mode");
+  const KRun &k = R->k;
+  const size_t plane = (size_t)k.plane;
+  if (out_len < 2 * plane) return fail(PIC_E_NOMEM, "out holds %zu doubles, %zu needed", out_len, 2 * plane);
+  const hipStream_t s = ctx->stream;
+  const bool f64 = ctx->prec == PIC_PREC_FP64;
+  const size_t rs = f64 ? 8 : 4;
+  const int NM = 2 * k.M + 1;
+  const int qa = m == 0 ? 0 : 2 * m - 1, qb = 2 * m;
+  const int par = (int)(R->steps & 1);
+  TRY(hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize"));
+  auto read_plane = [&](const void *base, int c, int q, std::vector<double> &dst) -> int {
+    dst.assign(plane, 0.0);
+    const unsigned char *src = (const unsigned char *)base + ((size_t)c * NM + q) * plane * rs;
+    if (f64) return hip_ok(hipMemcpy(dst.data(), src, plane * 8, hipMemcpyDeviceToHost), "hipMemcpy D2H");
+    std::vector<float> tmp(plane);
+    int rc = hip_ok(hipMemcpy(tmp.data(), src, plane * 4, hipMemcpyDeviceToHost), "hipMemcpy D2H");
+    for (size_t a = 0; a < plane; ++a) dst[a] = tmp[a];
+    return rc;
+  };
+  std::vector<double> re, im, re2, im2;
+  const void *src = nullptr;
+  int c = 0;
+  bool avg = false, cur = false, rho = false;
+  if (comp <= PIC_EZ) { src = k.E; c = comp; }
+  else if (comp <= PIC_BZ) { src = k.B[par]; c = comp - PIC_BR; avg = true; }
+  else if (comp <= PIC_JZ) { src = k.J[(R->steps + 1) & 1]; c = comp - PIC_JR; cur = true; }
+  else if (comp == PIC_RHO) { rho = true; }
+  else if (comp <= PIC_BZ_OLD) { src = k.B[par]; c = comp - PIC_BR_OLD; }
+  else { src = k.B[par ^ 1]; c = comp - PIC_BR_NEW; }
+  if (rho) {
+    TRY(launch_zero(k.rho, (size_t)NM * plane * 8, s));
+    TRY(launch_rho(k, ctx->prec, s));
+    TRY(hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize"));
+    re.assign(plane, 0.0);
+    im.assign(plane, 0.0);
+    TRY(hip_ok(hipMemcpy(re.data(), (double *)k.rho + (size_t)qa * plane, plane * 8, hipMemcpyDeviceToHost), "D2H"));
+    if (m > 0)
+      TRY(hip_ok(hipMemcpy(im.data(), (double *)k.rho + (size_t)qb * plane, plane * 8, hipMemcpyDeviceToHost), "D2H"));
+  } else {
+    TRY(read_plane(src, c, qa, re));
+    if (m > 0) TRY(read_plane(src, c, qb, im));
+    else im.assign(plane, 0.0);
+    if (avg) {
+      TRY(read_plane(k.B[par ^ 1], c, qa, re2));
+      if (m > 0) TRY(read_plane(k.B[par ^ 1], c, qb, im2));
+      else im2.assign(plane, 0.0);
+      for (size_t a = 0; a < plane; ++a) {
+        re[a] = 0.5 * (re[a] + re2[a]);
+        im[a] = 0.5 * (im[a] + im2[a]);
+      }
+    }
+    if (cur) {  // physical current = raw deposit * row factor
+      const double dz = k.dz, dr = k.dr, dt = k.dt;
+      for (int j = 0; j <= k.Nr; ++j) {
+        const double Vj = j == 0 ? kPi * dr * dr * dz / 4.0 : 2.0 * kPi * (j * dr) * dr * dz;
+        double f;
+        if (c == 0) f = 1.0 / (dt * 2.0 * kPi * ((j + 0.5) * dr) * dz);
+        else if (c == 2) f = 1.0 / (dt * (Vj / dz));
+        else f = (m == 0 || j == 0) ? 1.0 / Vj : 1.0 / (dt * 2.0 * kPi * dr * dz);
+        // the m >= 1 J_z vanishes on the axis (E_z^m is held at zero there)
+        if (c == 2 && m > 0 && j == 0) f = 0.0;
+        for (int i = 0; i < k.Nz; ++i) {
+          re[(size_t)j * k.Nz + i] *= f;
+          im[(size_t)j * k.Nz + i] *= f;
+        }
+      }
+    }
+  }
+  for (size_t a = 0; a < plane; ++a) {
+    out[2 * a] = re[a];
+    out[2 * a + 1] = im[a];
+  }
+  return PIC_OK;
+}
+
+int pic_particles(pic_ctx *ctx, int32_t run, double *z, double *x, double *y, double *ux, double *uy, double *uz,
+                  double *w, int64_t *id, size_t out_len) {
+  g_msg[0] = 0;
+  if (!ctx_ok(ctx)) return fail(PIC_E_STATE, "invalid or destroyed context");
+  RunHost *R = get_run(ctx, run);
+  if (!R) return fail(PIC_E_INVALID, "bad run index");
+  const KRun &k = R->k;
+  const size_t np = (size_t)k.np;
+  if (out_len < np) return fail(PIC_E_NOMEM, "buffers hold %zu, %zu needed", out_len, np);
+  TRY(hip_ok(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize"));
+  const bool f64 = ctx->prec == PIC_PREC_FP64;
+  auto get = [&](const void *src, double *dst) -> int {
+    if (!dst || np == 0) return PIC_OK;
+    if (f64) return hip_ok(hipMemcpy(dst, src, np * 8, hipMemcpyDeviceToHost), "D2H");
+    std::vector<float> t(np);
+    int rc = hip_ok(hipMemcpy(t.data(), src, np * 4, hipMemcpyDeviceToHost), "D2H");
+    for (size_t a = 0; a < np; ++a) dst[a] = t[a];
+    return rc;
+  };
+  if (z && np) {
+    if (f64) TRY(hip_ok(hipMemcpy(z, k.pz, np * 8, hipMemcpyDeviceToHost), "D2H"));
+    else {
+      std::vector<int32_t> iz(np);
+      std::vector<float> fz(np);
+      TRY(hip_ok(hipMemcpy(iz.data(), k.pz, np * 4, hipMemcpyDeviceToHost), "D2H"));
+      TRY(hip_ok(hipMemcpy(fz.data(), k.pfz, np * 4, hipMemcpyDeviceToHost), "D2H"));
+      for (size_t a = 0; a < np; ++a) z[a] = (double)iz[a] + (double)fz[a];
+    }
+  }
+  TRY(get(k.px, x));
+  TRY(get(k.py, y));
+  TRY(get(k.pux, ux));
+  TRY(get(k.puy, uy));
+  TRY(get(k.puz, uz));
+  TRY(get(k.pw, w));
+  if (id && np) {
+    std::vector<uint32_t> t(np);
+    TRY(hip_ok(hipMemcpy(t.data(), k.pid, np * 4, hipMemcpyDeviceToHost), "D2H"));
+    for (size_t a = 0; a < np; ++a) id[a] = (int64_t)(t[a] & kIdMask);
+  }
+  return PIC_OK;
+}
+
+int pic_mode_work(pic_ctx *ctx, int32_t run, double *work, double *gamma, double *gamma_acc, int64_t *ids,
+                  double *field_energy, double *kinetic) {
+  g_msg[0] = 0;
+  if (!ctx_ok(ctx)) return fail(PIC_E_STATE, "invalid or destroyed context");
+  RunHost *R = get_run(ctx, run);
+  if (!R) return fail(PIC_E_INVALID, "bad run index");
+  const KRun &k = R->k;
+  const hipStream_t s = ctx->stream;
+  const int M = k.M;
+  const int nt = k.n_tracked;
+  bool finite = true;
+  std::vector<double> W((size_t)nt * (M + 1));
+  if (nt > 0) {
+    TRY(launch_tracked_gamma(k, ctx->prec, R->dev_gamma, R->dev_ids, s));
+    TRY(hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize"));
+    TRY(hip_ok(hipMemcpy(W.data(), k.W, W.size() * 8, hipMemcpyDeviceToHost), "D2H"));
+    std::vector<double> g((size_t)nt);
+    std::vector<int64_t> id((size_t)nt);
+    TRY(hip_ok(hipMemcpy(g.data(), R->dev_gamma, (size_t)nt * 8, hipMemcpyDeviceToHost), "D2H"));
+    TRY(hip_ok(hipMemcpy(id.data(), R->dev_ids, (size_t)nt * 8, hipMemcpyDeviceToHost), "D2H"));
+    for (int t = 0; t < nt; ++t) {
+      double acc = R->gam0[(size_t)t];
+      for (int m = 0; m <= M; ++m) acc += W[(size_t)t * (M + 1) + m];
+      if (!std::isfinite(acc) || !std::isfinite(g[(size_t)t])) finite = false;
+      if (gamma_acc) gamma_acc[t] = acc;
+      if (gamma) gamma[t] = g[(size_t)t];
+      if (ids) ids[t] = id[(size_t)t];
+    }
+    if (work) std::memcpy(work, W.data(), W.size() * 8);
+  }
+  if (field_energy) {
+    int nb = 0;
+    TRY(launch_energy(k, ctx->prec, (int)(R->steps & 1), kRedBlocks, &nb, s));
+    std::vector<double> part((size_t)nb * (M + 1));
+    TRY(hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize"));
+    TRY(hip_ok(hipMemcpy(part.data(), k.red, part.size() * 8, hipMemcpyDeviceToHost), "D2H"));
+    for (int m = 0; m <= M; ++m) {
+      double acc = 0.0;
+      for (int b = 0; b < nb; ++b) acc += part[(size_t)b * (M + 1) + m];
+      field_energy[m] = acc;
+      if (!std::isfinite(acc)) finite = false;
+    }
+  }
+  if (kinetic) {
+    int nb = 0;
+    TRY(launch_kinetic(k, ctx->prec, &nb, s));
+    std::vector<double> part((size_t)nb);
+    TRY(hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize"));
+    TRY(hip_ok(hipMemcpy(part.data(), k.red, part.size() * 8, hipMemcpyDeviceToHost), "D2H"));
+    double acc = 0.0;
+    for (int b = 0; b < nb; ++b) acc += part[(size_t)b];
+    *kinetic = acc;
+    if (!std::isfinite(acc)) finite = false;
+  }
+  if (!finite) return fail(PIC_E_NUMERIC, "a diagnostic reduction is not finite");
+  return PIC_OK;
+}
+
+int pic_destroy(pic_ctx *ctx) {
+  g_msg[0] = 0;
+  if (!ctx_ok(ctx)) return fail(PIC_E_STATE, "invalid or destroyed context");
+  ctx_unregister(ctx);
+  ctx->magic = 0;
+  delete ctx;
+  return PIC_OK;
+}
+
+}  // extern "C"

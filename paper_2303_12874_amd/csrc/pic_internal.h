@@ -1,0 +1,77 @@
+// pic_internal.h -- declarations shared by the host runtime (capi.cpp,
+// setup.cpp) and the HIP kernels (kernels.hip).  Not part of the ABI.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/pic.h"
+
+namespace pic {
+
+constexpr int kFitSamples = 4000;     // midpoint samples of the coefficient fit
+constexpr int kKappaSamples = 20001;  // samples of k dz in [0, pi] for the Courant limit
+constexpr uint32_t kTrackedBit = 0x80000000u;  // particle id flag: work is accumulated
+constexpr uint32_t kIdMask = 0x7fffffffu;
+
+// ---- host setup (setup.cpp) -------------------------------------------------
+void fit_dual(int N, double nu, double band, double *CE, double *CB);
+void z_product_range(const double *CE, const double *CB, int N, double *pmax, double *pmin);
+double radial_lambda(int m, int nr);
+double radial_lambda_max(int M);
+bool stable_at(const double *CE, const double *CB, int N, int M, double dz, double dr, double nu);
+double courant_limit_of(const double *CE, const double *CB, int N, int M, double dz, double dr);
+double courant_limit_fitted(int solver, int N, int M, double dz, double dr, double band);
+int64_t run_particle_count(const pic_run_desc &r);
+void load_electrons(const pic_run_desc &r, double *z, double *x, double *y, double *w, int64_t *id,
+                    int64_t *tracked);
+void laser_fields(const pic_run_desc &r, double *E, double *B);
+
+// ---- device view of one run ---------------------------------------------------
+// Field storage: component-major planes of (Nr+1) x Nz reals, z fastest; a
+// component holds NM = 2M+1 planes: q = 0 is Re(m=0), q = 2m-1 / 2m are Re / Im
+// of mode m >= 1.  A quantity at z_{i+1/2} is stored at column i, one at
+// r_{j+1/2} at row j.  J planes hold the raw deposit (charge moved per step);
+// the physical current is raw times a per-row factor (see kernels.hip).
+struct KRun {
+  int Nz, Nr, M, N;       // grid, modes, coefficients per operator
+  double dz, dr, dt;
+  long long np;           // electrons
+  long long plane;        // (Nr+1) * Nz
+  void *E;                // 3 * NM planes
+  void *B[2];             // B at alternate half steps: B[n%2] = B^{n-1/2}, B[1-n%2] = B^{n+1/2}
+  void *J[2];             // deposit target of step n is J[n%2]; the other is kept zeroed
+  void *rho;              // NM planes (diagnostic)
+  void *pz;               // FP64: double z (cells);  FP32: int iz
+  void *pfz;              // FP32: float fz in [0, 1)
+  void *px, *py, *pux, *puy, *puz, *pw;
+  uint32_t *pid;          // particle id | kTrackedBit
+  double *W;              // [n_tracked][M+1] per-mode work (FP64)
+  const int32_t *tracked; // tracked ids, ascending
+  int n_tracked;
+  const void *CE, *CB, *P;  // coefficient arrays (real type of the run), P has 2N-1 taps
+  // sort scratch
+  void *sz, *sfz, *sx, *sy, *sux, *suy, *suz, *sw;  // second particle buffer
+  uint32_t *spid;
+  int32_t *cell_count;    // n_keys + 1
+  int32_t *cell_start;    // n_keys + 1
+  int32_t *perm;          // np
+  int32_t *scan_tmp;      // scan block sums
+  int Tz, Tr;             // sort tile
+  long long n_keys;       // tiles * Tz * Tr
+  double *red;            // reduction partials
+};
+
+// ---- kernel launchers (kernels.hip); all enqueue on `stream` -----------------
+int launch_push(const KRun &k, int prec, int par, void *stream);
+int launch_efield(const KRun &k, int prec, int par, void *stream);
+int launch_bfield(const KRun &k, int prec, void *Bout, const void *Bin, double tau, void *stream);
+int launch_zero(void *ptr, size_t bytes, void *stream);
+int launch_sort(const KRun &k, int prec, void *stream);
+int launch_rho(const KRun &k, int prec, void *stream);
+int launch_energy(const KRun &k, int prec, int par, int nblocks_max, int *nblocks, void *stream);
+int launch_kinetic(const KRun &k, int prec, int *nblocks, void *stream);
+int launch_tracked_gamma(const KRun &k, int prec, double *gamma, int64_t *ids, void *stream);
+const char *last_device_error();
+
+}  // namespace pic

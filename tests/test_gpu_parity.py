@@ -1,0 +1,188 @@
+"""GPU parity: the HIP library against the FP64 oracle on the same seeded
+inputs, element by element, through the C ABI.
+
+Both sides are built from the same workload description; the solver
+coefficients and dt come from the oracle's own fit and are passed to the
+library (the fit is ill-conditioned, so two correct fits differ in the
+last digits; the library's own fit is checked against the oracle's at the
+symbol level on the CPU).  FP64 bar: max |gpu - oracle| / max |oracle| <= 1e-10
+per field array and mode, positions within 1e-10 cells, momenta within
+1e-10 of the largest momentum, tracked work within 1e-10 of the largest.
+"""
+import functools
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle import coef
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+
+
+def _pic():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    import paper_2303_12874_amd as pic
+
+    return pic
+
+
+@functools.lru_cache(maxsize=None)
+def _setup(N, M, dz, dr):
+    return coef.solver_setup(N, M, dz, dr)
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+FIELD_PAIRS = [
+    ("E_r", 0, oracle.ER), ("E_phi", 1, oracle.EP), ("E_z", 2, oracle.EZ),
+    ("B_r(n-1/2)", 10, oracle.BOR), ("B_phi(n-1/2)", 11, oracle.BOP), ("B_z(n-1/2)", 12, oracle.BOZ),
+    ("B_r(n+1/2)", 13, oracle.BR), ("B_phi(n+1/2)", 14, oracle.BP), ("B_z(n+1/2)", 15, oracle.BZ),
+    ("J_r", 6, oracle.JR), ("J_phi", 7, oracle.JP), ("J_z", 8, oracle.JZ),
+]
+
+
+def compare_fields(sim, o, M, tol, run=0):
+    worst = {}
+    for name, comp, ocomp in FIELD_PAIRS:
+        for m in range(M + 1):
+            g = sim.fields(comp, m, run)
+            r = o.get_field(ocomp, m)
+            scale = np.abs(r).max()
+            err = np.abs(g - r).max() / scale if scale > 0 else np.abs(g).max()
+            worst[(name, m)] = err
+    return worst
+
+
+def compare_particles(sim, o, Nz, run=0):
+    P = sim.particles(run)
+    Q = o.particles()
+    order = np.argsort(P["id"])
+    assert np.array_equal(P["id"][order], Q["id"])
+    dz = np.abs(P["z"][order] - Q["z"])
+    dz = np.minimum(dz, Nz - dz)  # periodic
+    umax = max(np.abs(Q[k]).max() for k in ("ux", "uy", "uz"))
+    du = max(np.abs(P[k][order] - Q[k]).max() for k in ("ux", "uy", "uz"))
+    dxy = max(np.abs(P[k][order] - Q[k]).max() for k in ("x", "y"))
+    return dz.max(), dxy, du / max(umax, 1e-300), P
+
+
+def oracle_of(run, dt, CE, CB, fp32_start=False):
+    """The oracle of a run; with fp32_start its initial particles and E^0, B^0
+    are first rounded as the FP32 library stores them."""
+    o = oracle.Oracle(run["Nz"], run["Nr"], run["M"], run["dz"], run["dr"], dt, CE, CB)
+    o.load_plasma(run["ppc"], run["n0"], run["ramp_start"], run["ramp_len"], run["seed"], run["n_tracked"])
+    for p in run["pulses"]:
+        o.add_laser(p["a0"], p["w0"], p["tau"], p["zc"], run["taper"])
+    if fp32_start:
+        o.round_to_fp32()
+    o.start_fields()
+    return o
+
+
+def run_pair(run, nsteps, precision=64, N=16):
+    pic = _pic()
+    dt, CE, CB, _ = _setup(N, run["M"], run["dz"], run["dr"])
+    sim = pic.Simulation([workloads.to_rundesc(run)], precision=precision, dt=dt, coef_E=CE, coef_B=CB)
+    o = oracle_of(run, dt, CE, CB, fp32_start=(precision == 32))
+    sim.step(nsteps)
+    o.step(nsteps)
+    return sim, o
+
+
+@pytest.mark.parametrize("M", [0, 1, 2, 3])
+def test_fp64_small_grid_parity(M):
+    _say(f"[gpu] fp64 small grid M={M}")
+    cfg = workloads.small(M=M, Nz=64, Nr=12, ppc=2, n_tracked=40)
+    run = cfg["runs"][0]
+    if M == 0:
+        run["pulses"] = []
+    sim, o = run_pair(run, 20)
+    worst = compare_fields(sim, o, M, TOL64)
+    bad = {k: v for k, v in worst.items() if v > TOL64}
+    assert not bad, bad
+    dzmax, dxy, du, _ = compare_particles(sim, o, run["Nz"])
+    assert dzmax < TOL64 and dxy < TOL64 and du < TOL64, (dzmax, dxy, du)
+    wg, wo = sim.mode_work(), o.tracked()
+    assert np.array_equal(wg["id"], wo["id"])
+    scale = max(np.abs(wo["W"]).max(), 1e-300)
+    assert np.abs(wg["W"] - wo["W"]).max() / scale < TOL64
+    # Eq. (16) work identity on the GPU path: sum_m W_m = gamma - gamma_0
+    assert np.abs(wg["gamma_acc"] - wg["gamma"]).max() < 1e-13 * max(1.0, wg["gamma"].max())
+    sim.close()
+
+
+def test_fp64_config1_full_parity():
+    """256 x 64 grid, modes 0..1, 4 ppc, 100 steps (the small benchmark config)."""
+    _say("[gpu] fp64 config c1, 100 steps")
+    cfg = workloads.config("c1")
+    run = cfg["runs"][0]
+    sim, o = run_pair(run, cfg["steps"])
+    worst = compare_fields(sim, o, run["M"], TOL64)
+    bad = {k: v for k, v in worst.items() if v > TOL64}
+    assert not bad, bad
+    dzmax, dxy, du, _ = compare_particles(sim, o, run["Nz"])
+    assert dzmax < TOL64 and dxy < TOL64 and du < TOL64, (dzmax, dxy, du)
+    wg, wo = sim.mode_work(), o.tracked()
+    scale = np.abs(wo["W"]).max()
+    assert np.abs(wg["W"] - wo["W"]).max() / scale < TOL64
+    assert np.abs(wg["gamma"] - wo["gamma"]).max() < TOL64
+    U = wg["field_energy"]
+    Uo = np.array([o.field_energy(m) for m in range(run["M"] + 1)])
+    assert np.abs(U / Uo - 1).max() < TOL64
+    assert abs(wg["kinetic"] / o.kinetic() - 1) < 1e-9
+    sim.close()
+
+
+def test_fp64_gauss_law_invariant_on_gpu():
+    """div_B E - P rho is constant in time on the GPU path (Eq. (10) with the
+    filtered current), computed here from the library's own output."""
+    _say("[gpu] fp64 Gauss invariant")
+    pic = _pic()
+    cfg = workloads.small(M=2, Nz=64, Nr=12, ppc=2)
+    run = cfg["runs"][0]
+    dt, CE, CB, _ = _setup(16, run["M"], run["dz"], run["dr"])
+    sim = pic.Simulation([workloads.to_rundesc(run)], dt=dt, coef_E=CE, coef_B=CB)
+    _, _, taps = sim.coefficients()
+    N = CB.size
+    dz, dr, Nz, Nr = run["dz"], run["dr"], run["Nz"], run["Nr"]
+
+    def DB(g):  # half-z data (column k = z_{k+1/2}) -> integer z
+        out = np.zeros_like(g)
+        for l in range(1, N + 1):
+            out += CB[l - 1] * (np.roll(g, -(l - 1), axis=1) - np.roll(g, l, axis=1))
+        return out / dz
+
+    def P(f):
+        out = np.zeros_like(f)
+        for l in range(-(N - 1), N):
+            out += taps[l + N - 1] * np.roll(f, -l, axis=1)
+        return out
+
+    def gauss(m):
+        Er, Ep, Ez, rho = (sim.fields(c, m) for c in (pic.ER, pic.EPHI, pic.EZ, pic.RHO))
+        G = np.zeros_like(Er)
+        j = np.arange(1, Nr)[:, None]
+        G[1:Nr] = (DB(Ez)[1:Nr] + ((j + 0.5) * Er[1:Nr] - (j - 0.5) * Er[0:Nr - 1]) / (j * dr)
+                   + 1j * m / (j * dr) * Ep[1:Nr] - P(rho)[1:Nr])
+        if m == 0:
+            G[0] = DB(Ez)[0] + 4 * Er[0] / dr - P(rho)[0]
+        return G
+
+    G0 = [gauss(m) for m in range(run["M"] + 1)]
+    sim.step(15)
+    for m in range(run["M"] + 1):
+        G1 = gauss(m)
+        scale = np.abs(G0[m]).max() + np.abs(G1).max()
+        assert np.abs(G1 - G0[m]).max() < 1e-12 * scale, m
+    sim.close()

@@ -1,0 +1,98 @@
+"""Seeded synthetic workloads (LWFA-shaped plasmas and lasers).
+
+Plain parameters only -- no arithmetic of the method -- shared by the tests
+(both the HIP library and the oracle are built from the same description)
+and by the benchmark.  Lengths are in c/omega_0 (laser wavelength 2 pi),
+densities in units of the critical density.  The paper's own runs use a
+1814 x 160 quasi-3D grid, ionisation injection into a He/N2 gas and a moving
+window (Appendix A); none of that data is available, so these synthetic
+plasmas and pulses stand in for it at the sizes of the benchmark configs.
+"""
+from __future__ import annotations
+
+import math
+
+LAMBDA0 = 2.0 * math.pi
+SEED_BASE = 2303128740
+
+
+def _lp(n0):
+    """plasma wavelength (c/omega_0) at density n0 (units of n_c)"""
+    return LAMBDA0 / math.sqrt(n0)
+
+
+def config(name: str) -> dict:
+    """One named workload: a list of runs and the precision / step count."""
+    if name in ("c1", "c3"):
+        dz = LAMBDA0 / 16
+        run = dict(Nz=256, Nr=64, M=1, ppc=4, dz=dz, dr=4 * dz, n0=0.01, ramp_start=0.0, ramp_len=0.0,
+                   pulses=[dict(a0=1.0, w0=8 * LAMBDA0, tau=10 * LAMBDA0, zc=8 * LAMBDA0)], taper=2 * LAMBDA0,
+                   seed=SEED_BASE + (10 if name == "c1" else 30), n_tracked=1000)
+        return dict(name=name, runs=[run], precision=64 if name == "c1" else 32, steps=100,
+                    desc="256x64 r-z grid, modes 0..1, 4 ppc (~65k electrons), n=0.01 n_c, a0=1 w0=8 lambda "
+                         "10-period pulse")
+    if name == "c2":
+        dz = LAMBDA0 / 16
+        tau = 2 * _lp(0.005)
+        run = dict(Nz=4096, Nr=256, M=2, ppc=8, dz=dz, dr=4 * dz, n0=0.005, ramp_start=0.0,
+                   ramp_len=200 * LAMBDA0,
+                   pulses=[dict(a0=2.0, w0=10 * LAMBDA0, tau=tau, zc=1.5 * tau + 2 * LAMBDA0)], taper=2 * LAMBDA0,
+                   seed=SEED_BASE + 20, n_tracked=10000)
+        return dict(name=name, runs=[run], precision=64, steps=2000,
+                    desc="4096x256 r-z grid, modes 0..2, 8 ppc (~8.4M electrons), n=0.005 n_c with a 200-lambda "
+                         "up-ramp, a0=2 w0=10 lambda, 2-plasma-period pulse")
+    if name == "c4":
+        runs = []
+        steps = []
+        for r, ppl in enumerate((12, 16, 24, 32, 48, 64)):
+            dz = LAMBDA0 / ppl
+            runs.append(dict(Nz=256 * ppl, Nr=4 * ppl, M=2, ppc=4, dz=dz, dr=4 * dz, n0=0.01, ramp_start=0.0,
+                             ramp_len=0.0,
+                             pulses=[dict(a0=1.0, w0=8 * LAMBDA0, tau=10 * LAMBDA0, zc=22 * LAMBDA0)],
+                             taper=2 * LAMBDA0, seed=SEED_BASE + 40 + r, n_tracked=1000))
+            steps.append(100 * ppl // 16)
+        return dict(name=name, runs=runs, precision=32, steps=steps,
+                    desc="six runs at 12..64 points per lambda (Nz 3072..16384, Nr 48..256), modes 0..2, 4 ppc")
+    if name == "c5":
+        dz = LAMBDA0 / 16
+        lp = _lp(0.003)
+        run = dict(Nz=8192, Nr=512, M=3, ppc=16, dz=dz, dr=4 * dz, n0=0.003, ramp_start=0.0, ramp_len=0.0,
+                   pulses=[dict(a0=3.0, w0=10 * LAMBDA0, tau=lp / 2, zc=60 * LAMBDA0),
+                           dict(a0=1.5, w0=10 * LAMBDA0, tau=lp / 2, zc=60 * LAMBDA0 - lp)],
+                   taper=2 * LAMBDA0, seed=SEED_BASE + 50, n_tracked=100000)
+        return dict(name=name, runs=[run], precision=32, steps=5000,
+                    desc="8192x512 r-z grid, modes 0..3, 16 ppc (~67M electrons), n=0.003 n_c, two pulses a0=3 "
+                         "and 1.5 one plasma period apart")
+    raise KeyError(name)
+
+
+def small(name="tiny", M=1, Nz=64, Nr=12, ppc=2, n0=0.02, a0=1.5, seed=99, n_tracked=64) -> dict:
+    """Small grids that still span several sort tiles and a ragged radial tile."""
+    dz = LAMBDA0 / 16
+    run = dict(Nz=Nz, Nr=Nr, M=M, ppc=ppc, dz=dz, dr=4 * dz, n0=n0, ramp_start=0.0, ramp_len=0.0,
+               pulses=[dict(a0=a0, w0=3 * LAMBDA0, tau=2 * LAMBDA0, zc=2 * LAMBDA0)] if M >= 1 else [],
+               taper=LAMBDA0, seed=seed, n_tracked=n_tracked)
+    return dict(name=name, runs=[run], precision=64, steps=20, desc="small test grid")
+
+
+def to_rundesc(run: dict):
+    """The HIP library's RunDesc of a run (imports the binding lazily)."""
+    import paper_2303_12874_amd as pic
+
+    return pic.RunDesc(Nz=run["Nz"], Nr=run["Nr"], M=run["M"], ppc=run["ppc"], dz=run["dz"], dr=run["dr"],
+                       n0=run["n0"], ramp_start=run["ramp_start"], ramp_len=run["ramp_len"],
+                       pulses=[pic.Pulse(**p) for p in run["pulses"]], taper=run["taper"], seed=run["seed"],
+                       n_tracked=run["n_tracked"])
+
+
+def to_oracle(run: dict, dt, CE, CB):
+    """The oracle run of the same description (imports the oracle lazily)."""
+    import oracle
+
+    o = oracle.Oracle(run["Nz"], run["Nr"], run["M"], run["dz"], run["dr"], dt, CE, CB)
+    if run["ppc"] > 0:
+        o.load_plasma(run["ppc"], run["n0"], run["ramp_start"], run["ramp_len"], run["seed"], run["n_tracked"])
+    for p in run["pulses"]:
+        o.add_laser(p["a0"], p["w0"], p["tau"], p["zc"], run["taper"])
+    o.start_fields()
+    return o
