@@ -1,0 +1,164 @@
+"""Benchmark: particle-steps/s of the quasi-3D r-z PIC step with the dual solver.
+
+One bench step = one time step of the whole hot path (cell sort when due,
+gather + push + deposit, E update with the filtered current, B update) on a
+synthetic LWFA-shaped plasma, with every input resident in HBM.  Prints one
+JSON line.  The default workload is the 4096 x 256, modes 0..2, 8 ppc FP64
+run; --workload c5 selects the 8192 x 512, modes 0..3, 16 ppc FP32 run.
+
+Per-kernel durations come from HIP events the library records around each
+launch on its own stream (pic_profile); the roofline object prices the
+dominant kernel's algorithmic bytes against the MI355X HBM peak.  The CPU
+baseline times the FP64 oracle (test infrastructure) on a bounded sample of
+the same workload on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import workloads  # noqa: E402
+
+METRIC = "particle-steps/s (gather+push+deposit+solve), FP32 vs FP64 GPU at stated error"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(run: dict, precision: int) -> dict:
+    """Bytes each kernel must move per launch: particle state
+    read and written once, field/current planes read or written once."""
+    w = 8 if precision == 64 else 4
+    NM = 2 * run["M"] + 1
+    np_ = run["Nz"] * (run["Nr"] - 1) * run["ppc"]
+    cells = (run["Nr"] + 1) * run["Nz"]
+    # particle: read z (+fz), x, y, ux, uy, uz, w, id; write z (+fz), x, y, ux, uy, uz
+    part_read = 7 * w + 4 + (4 if precision == 32 else 0)
+    part_write = 6 * w + (4 if precision == 32 else 0)
+    return {
+        "push": np_ * (part_read + part_write) + cells * 12 * NM * w,  # E, B(n-1/2), B(n+1/2) read; J written
+        "efield": cells * 15 * NM * w,  # B, J, E read; E, next J written
+        "bfield": cells * 9 * NM * w,  # E, B read; B written
+        "sort": np_ * 2 * (part_read + 4),  # read + permuted write of the particle state
+    }
+
+
+def cpu_baseline(run: dict, nsteps: int) -> dict:
+    """FP64 oracle (as it stands) on the host: nsteps full steps of the run."""
+    import oracle
+    from oracle import coef
+
+    dt, CE, CB, _ = coef.solver_setup(16, run["M"], run["dz"], run["dr"])
+    o = workloads.to_oracle(run, dt, CE, CB)
+    t0 = time.perf_counter()
+    o.step(nsteps)
+    el = time.perf_counter() - t0
+    np_ = o.np
+    return {"value": np_ * nsteps / el, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{nsteps} full step(s) of the same run ({np_} electrons), serial C oracle, "
+                      f"setup excluded, {el:.1f} s"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c5"])
+    ap.add_argument("--cpu-steps", type=int, default=1, help="oracle steps for the CPU baseline (0: skip)")
+    ap.add_argument("--sort-interval", type=int, default=0)
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}), flush=True)
+        return 2
+
+    import torch
+
+    import paper_2303_12874_amd as pic
+
+    cfg = workloads.config(args.workload)
+    run = cfg["runs"][0]
+    prec = cfg["precision"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t_init = time.perf_counter()
+    sim = pic.Simulation([workloads.to_rundesc(run)], precision=prec, sort_interval=args.sort_interval,
+                         device="cuda:0")
+    torch.cuda.synchronize()
+    t_init = time.perf_counter() - t_init
+    info = sim.info()
+    np_ = info["n_particles"]
+    print(f"# init {t_init:.1f} s, {np_} electrons, dt {info['dt']:.5f}, courant limit {info['courant_limit']:.4f}",
+          file=sys.stderr, flush=True)
+
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    print(f"# warmup {args.warmup} steps done", file=sys.stderr, flush=True)
+
+    sim.profile(True)
+    stream = torch.cuda.current_stream(dev)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    sim.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    elapsed_ms = ev0.elapsed_time(ev1)
+    phases = sim.profile_read()
+    sim.profile(False)
+    print(f"# timed {args.steps} steps: {elapsed_ms:.2f} ms", file=sys.stderr, flush=True)
+
+    # sanity of the state after the run (FP64 reductions)
+    mw = sim.mode_work()
+    finite = all(map(lambda v: v == v, list(mw["field_energy"]) + [mw["kinetic"]]))
+
+    ab = algorithmic_bytes(run, prec)
+    kernels = {}
+    for ph, (ms, n) in phases.items():
+        if n == 0:
+            continue
+        avg_s = ms / n * 1e-3
+        kernels[ph] = {"avg_ms": ms / n, "launches": n, "GBs": ab[ph] / avg_s / 1e9}
+    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
+    ach = kernels[dom]["GBs"]
+    value = np_ * args.steps / (elapsed_ms * 1e-3)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == 64 else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {cfg['desc']}", "grid": f"{run['Nz']}x{run['Nr']}",
+                   "modes": run["M"] + 1, "ppc": run["ppc"], "electrons": np_,
+                   "precision": f"fp{prec}", "solver": "dual, 16 coefficients per operator",
+                   "dt": info["dt"], "sort_interval": args.sort_interval},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": ab[dom], "avg_launch_ms": kernels[dom]["avg_ms"]},
+        "kernels": kernels,
+        "state_finite": finite,
+    }
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    if args.cpu_steps > 0:
+        print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(run, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
