@@ -45,6 +45,7 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr uint32_t kMagic = 0x51D3A1C7u;
 constexpr size_t kAlign = 256;
 constexpr int kRedBlocks = 1024;
+constexpr int kDefaultSortInterval = 4;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -63,7 +64,7 @@ struct RunHost {
 
 // Layout of one run in the workspace (offsets from the run's base).
 struct Layout {
-  size_t E, B0, B1, J0, J1, rho, pz, pfz, px, py, pux, puy, puz, pw, pid;
+  size_t E, B0, B1, Bbar, J0, J1, rho, pz, pfz, px, py, pux, puy, puz, pw, pid;
   size_t sz, sfz, sx, sy, sux, suy, suz, sw, spid, perm, ccount, cstart, scan;
   size_t W, tracked, CE, CB, P, red, gam, ids, total;
 };
@@ -84,6 +85,7 @@ Layout layout_of(const pic_run_desc &d, int prec, int N, int Tz, int Tr, long lo
   L.E = take(vec);
   L.B0 = take(vec);
   L.B1 = take(vec);
+  L.Bbar = take(vec);
   L.J0 = take(vec);
   L.J1 = take(vec);
   L.rho = take(NM * plane * 8);
@@ -173,9 +175,23 @@ int validate_run(const pic_run_desc &r, int i, int N) {
   return PIC_OK;
 }
 
-void default_tiles(const pic_opts &o, int *Tz, int *Tr) {
+constexpr size_t kMaxLds = 65536;  // LDS of one push workgroup (current window of a tile)
+
+size_t tile_lds(int M, int Tz, int Tr, int prec) {
+  return (size_t)3 * (2 * M + 1) * (Tz + 3) * (Tr + 3) * (prec == PIC_PREC_FP64 ? 8 : 4);
+}
+
+// Sort tile: 32 x 8 cells unless given; the radial extent shrinks until the
+// tile's current window fits the LDS budget.
+int choose_tiles(const pic_opts &o, int M, int *Tz, int *Tr) {
   *Tz = o.tile_z > 0 ? o.tile_z : 32;
   *Tr = o.tile_r > 0 ? o.tile_r : 8;
+  if (o.tile_r <= 0)
+    while (*Tr > 1 && tile_lds(M, *Tz, *Tr, o.precision) > kMaxLds) *Tr /= 2;
+  if (tile_lds(M, *Tz, *Tr, o.precision) > kMaxLds)
+    return fail(PIC_E_INVALID, "tile %dx%d needs %zu bytes of LDS (limit %zu)", *Tz, *Tr,
+                tile_lds(M, *Tz, *Tr, o.precision), kMaxLds);
+  return PIC_OK;
 }
 
 long long keys_of(const pic_run_desc &r, int Tz, int Tr) {
@@ -280,7 +296,7 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
     if (runs[i].M != runs[0].M) return fail(PIC_E_INVALID, "all runs of one context must share M");
   }
   int Tz, Tr;
-  default_tiles(o, &Tz, &Tr);
+  TRY(choose_tiles(o, runs[0].M, &Tz, &Tr));
 
   // workspace size
   std::vector<Layout> lays;
@@ -305,7 +321,7 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
   ctx->prec = o.precision;
   ctx->stream = (hipStream_t)hip_stream;
   ctx->ws = (unsigned char *)device_workspace;
-  ctx->sort_interval = o.sort_interval > 0 ? o.sort_interval : 0;
+  ctx->sort_interval = o.sort_interval > 0 ? o.sort_interval : kDefaultSortInterval;
   ctx->runs.resize((size_t)n_runs);
   const hipStream_t s = ctx->stream;
   const bool f64 = o.precision == PIC_PREC_FP64;
@@ -366,6 +382,7 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
     k.E = base + L.E;
     k.B[0] = base + L.B0;
     k.B[1] = base + L.B1;
+    k.Bbar = base + L.Bbar;
     k.J[0] = base + L.J0;
     k.J[1] = base + L.J1;
     k.rho = base + L.rho;
@@ -393,6 +410,8 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
     k.scan_tmp = (int32_t *)(base + L.scan);
     k.Tz = Tz;
     k.Tr = Tr;
+    k.ntz = (d.Nz + Tz - 1) / Tz;
+    k.ntr = (d.Nr + Tr - 1) / Tr;
     k.n_keys = keys_of(d, Tz, Tr);
     k.W = (double *)(base + L.W);
     k.tracked = (const int32_t *)(base + L.tracked);
@@ -462,11 +481,15 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
       std::vector<double> Eh(nvec, 0.0), Bh(nvec, 0.0);
       laser_fields(d, Eh.data(), Bh.data());
       if (f64) {
-        if ((rc = upload(k.E, Eh, s)) || (rc = upload(k.B[0], Bh, s)) || (rc = upload(k.B[1], Bh, s))) break;
+        if ((rc = upload(k.E, Eh, s)) || (rc = upload(k.B[0], Bh, s)) || (rc = upload(k.B[1], Bh, s)) ||
+            (rc = upload(k.Bbar, Bh, s)))
+          break;
         if ((rc = hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize"))) break;
       } else {
         std::vector<float> Ef(Eh.begin(), Eh.end()), Bf(Bh.begin(), Bh.end());
-        if ((rc = upload(k.E, Ef, s)) || (rc = upload(k.B[0], Bf, s)) || (rc = upload(k.B[1], Bf, s))) break;
+        if ((rc = upload(k.E, Ef, s)) || (rc = upload(k.B[0], Bf, s)) || (rc = upload(k.B[1], Bf, s)) ||
+            (rc = upload(k.Bbar, Bf, s)))
+          break;
         if ((rc = hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize"))) break;
       }
     }
@@ -476,10 +499,10 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
         (rc = launch_zero(k.W, (size_t)(d.n_tracked > 0 ? d.n_tracked : 1) * (d.M + 1) * 8, s)))
       break;
     // B[0] = B^0 + (dt/2) curl_E E^0 = B^{-1/2};  B[1] = B^0 - (dt/2) curl_E E^0 = B^{+1/2}
-    if ((rc = launch_bfield(k, ctx->prec, k.B[0], k.B[0], -0.5 * R.dt, s)) ||
-        (rc = launch_bfield(k, ctx->prec, k.B[1], k.B[1], 0.5 * R.dt, s)))
+    if ((rc = launch_bfield(k, ctx->prec, k.B[0], k.B[0], -0.5 * R.dt, nullptr, s)) ||
+        (rc = launch_bfield(k, ctx->prec, k.B[1], k.B[1], 0.5 * R.dt, nullptr, s)))
       break;
-    if (ctx->sort_interval > 0 && (rc = launch_sort(k, ctx->prec, s))) break;
+    if ((rc = launch_sort(k, ctx->prec, s))) break;  // the push kernel works tile by tile
     if ((rc = hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize"))) break;
   }
   if (rc != PIC_OK) {
@@ -548,12 +571,13 @@ int pic_step(pic_ctx *ctx, int64_t n_steps) {
   for (int64_t n = 0; n < n_steps; ++n) {
     for (RunHost &R : ctx->runs) {
       const int par = (int)(R.steps & 1);
-      const KRun &k = R.k;
-      if (ctx->sort_interval > 0 && R.steps % ctx->sort_interval == 0 && R.steps > 0)
+      KRun &k = R.k;
+      if (R.steps > 0 && R.steps % ctx->sort_interval == 0)
         TRY(timed(ctx, PIC_PHASE_SORT, [&] { return launch_sort(k, prec, s); }));
       TRY(timed(ctx, PIC_PHASE_PUSH, [&] { return launch_push(k, prec, par, s); }));
       TRY(timed(ctx, PIC_PHASE_EFIELD, [&] { return launch_efield(k, prec, par, s); }));
-      TRY(timed(ctx, PIC_PHASE_BFIELD, [&] { return launch_bfield(k, prec, k.B[par], k.B[par ^ 1], R.dt, s); }));
+      TRY(timed(ctx, PIC_PHASE_BFIELD,
+                [&] { return launch_bfield(k, prec, k.B[par], k.B[par ^ 1], R.dt, k.Bbar, s); }));
       R.steps++;
     }
     // keep the number of outstanding event pairs bounded
@@ -643,7 +667,7 @@ int pic_fields(pic_ctx *ctx, int32_t run, int32_t comp, int32_t m, double *out, 
   int c = 0;
   bool avg = false, cur = false, rho = false;
   if (comp <= PIC_EZ) { src = k.E; c = comp; }
-  else if (comp <= PIC_BZ) { src = k.B[par]; c = comp - PIC_BR; avg = true; }
+  else if (comp <= PIC_BZ) { src = k.Bbar; c = comp - PIC_BR; }
   else if (comp <= PIC_JZ) { src = k.J[(R->steps + 1) & 1]; c = comp - PIC_JR; cur = true; }
   else if (comp == PIC_RHO) { rho = true; }
   else if (comp <= PIC_BZ_OLD) { src = k.B[par]; c = comp - PIC_BR_OLD; }

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
+#include <utility>
 
 #include "pic_internal.h"
 
@@ -81,332 +82,380 @@ __device__ __forceinline__ void interp(const R *__restrict__ F, long long plane,
   }
 }
 
+// One workgroup per sort tile of Tz x Tr cells.  The tile's electrons (the
+// range the last cell sort assigned to it) are processed in contiguous
+// per-thread chunks, so that at any instant the 64 lanes of a wavefront sit
+// in different cells: their field reads fall on neighbouring nodes and their
+// LDS atomics rarely collide.  The current of the whole tile is accumulated
+// in LDS over the node window [z0-1, z0+Tz+2) x [r0-1, r0+Tr+2) (every move
+// of less than one cell from a cell of the tile stays inside it) and added to
+// the global arrays once; an electron that drifted out of the window since
+// the last sort deposits straight to global memory.
 template <typename R, int M>
 __global__ __launch_bounds__(256) void push_kernel(KRun k, int par) {
   constexpr int NM = 2 * M + 1;
   constexpr bool F64 = std::is_same<R, double>::value;
-  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= k.np) return;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  R *lds = (R *)lds_raw;
+  const int tile = blockIdx.x;
+  const int TZ = k.Tz, TR = k.Tr;
+  const int WZ = TZ + 3, WR = TR + 3;
+  const int tz = tile % k.ntz, tr = tile / k.ntz;
+  const int zlo = tz * TZ - 1, rlo = tr * TR - 1;
+  const long long TT = (long long)TZ * TR;
+  const int beg = k.cell_start[tile * TT], end = k.cell_start[(tile + 1) * TT];
+  if (beg >= end) return;
+  const int nlds = 3 * NM * WZ * WR;
+  for (int e = threadIdx.x; e < nlds; e += blockDim.x) lds[e] = R(0);
+  __syncthreads();
+
   const int Nz = k.Nz, Nr = k.Nr;
   const long long plane = k.plane;
   const R dt = (R)k.dt, dz = (R)k.dz, dr = (R)k.dr;
   const R *E = (const R *)k.E;
-  const R *Bo = (const R *)k.B[par];
-  const R *Bn = (const R *)k.B[par ^ 1];
+  const R *Bb = (const R *)k.Bbar;
   R *J = (R *)k.J[par];
   R *X = (R *)k.px, *Y = (R *)k.py, *UX = (R *)k.pux, *UY = (R *)k.puy, *UZ = (R *)k.puz;
-  const R q = -((const R *)k.pw)[p];
-  const uint32_t pidw = k.pid[p];
 
-  // ---- old position ----
-  int i0;
-  R f0, z0 = 0;
-  if constexpr (F64) {
-    z0 = ((const double *)k.pz)[p];
-    const R fl = floor(z0);
-    i0 = (int)fl;
-    f0 = z0 - fl;
-  } else {
-    i0 = ((const int *)k.pz)[p];
-    f0 = ((const float *)k.pfz)[p];
-  }
-  i0 = wrap_any(i0, Nz);
-  const R x0 = X[p], y0 = Y[p];
-  const R r20 = fma(x0, x0, y0 * y0), r0 = sqrt(r20);
-  const int j0 = clampi(radial_index(r20, r0), 0, Nr - 2);
-  R c0 = 1, s0 = 0;
-  if (r0 > R(0)) {
-    c0 = x0 / r0;
-    s0 = y0 / r0;
-  }
+  // add v to component c (0 r, 1 phi, 2 z), plane q, node (row, unwrapped column)
+  auto dep = [&](int c, int q, int row, int colu, R v) {
+    const int lc = colu - zlo, lr = row - rlo;
+    if ((unsigned)lc < (unsigned)WZ && (unsigned)lr < (unsigned)WR)
+      atomic_add(&lds[((c * NM + q) * WR + lr) * WZ + lc], v);
+    else
+      atomic_add(J + (long long)(c * NM + q) * plane + (long long)row * Nz + wrap_once(colu, Nz), v);
+  };
 
-  // ---- gather (Eq. (12) average for B) ----
-  int ih;
-  R fh;
-  if constexpr (F64) {
-    const R zz = z0 - R(0.5);
-    const R fl = floor(zz);
-    ih = (int)fl;
-    fh = zz - fl;
-  } else {
-    if (f0 >= R(0.5)) { ih = i0; fh = f0 - R(0.5); }
-    else { ih = i0 - 1; fh = f0 + R(0.5); }
-  }
-  const int ci0 = i0, ci1 = wrap_once(i0 + 1, Nz);
-  const int ch0 = wrap_any(ih, Nz), ch1 = wrap_once(ch0 + 1, Nz);
-  const R fr = r0 - (R)j0;
-  const R rr = r0 - R(0.5);
-  const R flr = floor(rr);
-  int jh = (int)flr;
-  const R frh = rr - flr;
-  jh = clampi(jh, -1, Nr - 2);
-  const bool mir = jh < 0;
+  const int n = end - beg;
+  const int chunk = (n + (int)blockDim.x - 1) / (int)blockDim.x;
+  const int my0 = beg + (int)threadIdx.x * chunk;
+  const int my1 = min(my0 + chunk, end);
+  for (int p = my0; p < my1; ++p) {
+    const R q = -((const R *)k.pw)[p];
+    const uint32_t pidw = k.pid[p];
 
-  R er[NM], ep[NM], ez[NM], br[NM], bp[NM], bz[NM], t[NM];
-  interp<R, NM, true, false>(E + 0 * NM * plane, plane, Nz, ci0, ci1, jh, mir, f0, frh, er);
-  interp<R, NM, false, false>(E + 1 * NM * plane, plane, Nz, ci0, ci1, j0, false, f0, fr, ep);
-  interp<R, NM, false, true>(E + 2 * NM * plane, plane, Nz, ch0, ch1, j0, false, fh, fr, ez);
-  interp<R, NM, false, false>(Bo + 0 * NM * plane, plane, Nz, ch0, ch1, j0, false, fh, fr, br);
-  interp<R, NM, false, false>(Bn + 0 * NM * plane, plane, Nz, ch0, ch1, j0, false, fh, fr, t);
-#pragma unroll
-  for (int qq = 0; qq < NM; ++qq) br[qq] = R(0.5) * (br[qq] + t[qq]);
-  interp<R, NM, true, false>(Bo + 1 * NM * plane, plane, Nz, ch0, ch1, jh, mir, fh, frh, bp);
-  interp<R, NM, true, false>(Bn + 1 * NM * plane, plane, Nz, ch0, ch1, jh, mir, fh, frh, t);
-#pragma unroll
-  for (int qq = 0; qq < NM; ++qq) bp[qq] = R(0.5) * (bp[qq] + t[qq]);
-  interp<R, NM, true, true>(Bo + 2 * NM * plane, plane, Nz, ci0, ci1, jh, mir, f0, frh, bz);
-  interp<R, NM, true, true>(Bn + 2 * NM * plane, plane, Nz, ci0, ci1, jh, mir, f0, frh, t);
-#pragma unroll
-  for (int qq = 0; qq < NM; ++qq) bz[qq] = R(0.5) * (bz[qq] + t[qq]);
-
-  // ---- reconstruct Re sum_m F^m e^{i m phi}, rotate to Cartesian ----
-  R Em[M + 1][3];
-  R Ec[3], Bc[3];
-  {
-    // m = 0
-    Em[0][0] = er[0] * c0 - ep[0] * s0;
-    Em[0][1] = er[0] * s0 + ep[0] * c0;
-    Em[0][2] = ez[0];
-    Bc[0] = br[0] * c0 - bp[0] * s0;
-    Bc[1] = br[0] * s0 + bp[0] * c0;
-    Bc[2] = bz[0];
-    R ere = 1, eim = 0;
-#pragma unroll
-    for (int m = 1; m <= M; ++m) {
-      const R nre = ere * c0 - eim * s0;
-      const R nim = ere * s0 + eim * c0;
-      ere = nre;
-      eim = nim;
-      const int a = 2 * m - 1, b = 2 * m;
-      const R Fr = er[a] * ere - er[b] * eim, Fp = ep[a] * ere - ep[b] * eim;
-      Em[m][0] = Fr * c0 - Fp * s0;
-      Em[m][1] = Fr * s0 + Fp * c0;
-      Em[m][2] = ez[a] * ere - ez[b] * eim;
-      const R Gr = br[a] * ere - br[b] * eim, Gp = bp[a] * ere - bp[b] * eim;
-      Bc[0] += Gr * c0 - Gp * s0;
-      Bc[1] += Gr * s0 + Gp * c0;
-      Bc[2] += bz[a] * ere - bz[b] * eim;
+    // ---- old position ----
+    int i0;
+    R f0, z0 = 0;
+    if constexpr (F64) {
+      z0 = ((const double *)k.pz)[p];
+      const R fl = floor(z0);
+      i0 = (int)fl;
+      f0 = z0 - fl;
+    } else {
+      i0 = ((const int *)k.pz)[p];
+      f0 = ((const float *)k.pfz)[p];
     }
-    Ec[0] = Em[0][0];
-    Ec[1] = Em[0][1];
-    Ec[2] = Em[0][2];
-#pragma unroll
-    for (int m = 1; m <= M; ++m) {
-      Ec[0] += Em[m][0];
-      Ec[1] += Em[m][1];
-      Ec[2] += Em[m][2];
+    i0 = wrap_any(i0, Nz);
+    const R x0 = X[p], y0 = Y[p];
+    const R r20 = fma(x0, x0, y0 * y0), r0 = sqrt(r20);
+    const int j0 = clampi(radial_index(r20, r0), 0, Nr - 2);
+    R c0 = 1, s0 = 0;
+    if (r0 > R(0)) {
+      c0 = x0 / r0;
+      s0 = y0 / r0;
     }
-  }
 
-  // ---- Boris, q/m = -1 ----
-  const R u[3] = {UX[p], UY[p], UZ[p]};
-  R um[3], up[3], un[3], tt[3], ss[3], u1[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) um[a] = u[a] - R(0.5) * dt * Ec[a];
-  const R gm = sqrt(R(1) + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
-#pragma unroll
-  for (int a = 0; a < 3; ++a) tt[a] = -R(0.5) * dt * Bc[a] / gm;
-  const R t2 = tt[0] * tt[0] + tt[1] * tt[1] + tt[2] * tt[2];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) ss[a] = R(2) * tt[a] / (R(1) + t2);
-  u1[0] = um[0] + (um[1] * tt[2] - um[2] * tt[1]);
-  u1[1] = um[1] + (um[2] * tt[0] - um[0] * tt[2]);
-  u1[2] = um[2] + (um[0] * tt[1] - um[1] * tt[0]);
-  up[0] = um[0] + (u1[1] * ss[2] - u1[2] * ss[1]);
-  up[1] = um[1] + (u1[2] * ss[0] - u1[0] * ss[2]);
-  up[2] = um[2] + (u1[0] * ss[1] - u1[1] * ss[0]);
-#pragma unroll
-  for (int a = 0; a < 3; ++a) un[a] = up[a] - R(0.5) * dt * Ec[a];
-  const R g_new = sqrt(R(1) + un[0] * un[0] + un[1] * un[1] + un[2] * un[2]);
+    // ---- gather E^n and Bbar^n = (B^{n-1/2} + B^{n+1/2})/2 (Eq. (12)) ----
+    int ih;
+    R fh;
+    if constexpr (F64) {
+      const R zz = z0 - R(0.5);
+      const R fl = floor(zz);
+      ih = (int)fl;
+      fh = zz - fl;
+    } else {
+      if (f0 >= R(0.5)) {
+        ih = i0;
+        fh = f0 - R(0.5);
+      } else {
+        ih = i0 - 1;
+        fh = f0 + R(0.5);
+      }
+    }
+    const int ci0 = i0, ci1 = wrap_once(i0 + 1, Nz);
+    const int ch0 = wrap_any(ih, Nz), ch1 = wrap_once(ch0 + 1, Nz);
+    const R fr = r0 - (R)j0;
+    const R rr = r0 - R(0.5);
+    const R flr = floor(rr);
+    int jh = (int)flr;
+    const R frh = rr - flr;
+    jh = clampi(jh, -1, Nr - 2);
+    const bool mir = jh < 0;
 
-  // ---- per-mode work of tracked electrons (FP64), Eq. (16) ----
-  if (pidw & kTrackedBit) {
-    const int32_t idv = (int32_t)(pidw & kIdMask);
-    int lo = 0, hi = k.n_tracked;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (k.tracked[mid] < idv) lo = mid + 1;
-      else hi = mid;
-    }
-    if (lo < k.n_tracked && k.tracked[lo] == idv) {
-      const double g_old = sqrt(1.0 + (double)u[0] * u[0] + (double)u[1] * u[1] + (double)u[2] * u[2]);
-      const double inv = 1.0 / (g_old + (double)g_new);
-      const double v0 = ((double)um[0] + (double)up[0]) * inv;
-      const double v1 = ((double)um[1] + (double)up[1]) * inv;
-      const double v2 = ((double)um[2] + (double)up[2]) * inv;
-      double *W = k.W + (long long)lo * (M + 1);
-#pragma unroll
-      for (int m = 0; m <= M; ++m)
-        W[m] += -k.dt * ((double)Em[m][0] * v0 + (double)Em[m][1] * v1 + (double)Em[m][2] * v2);
-    }
-  }
+    R er[NM], ep[NM], ez[NM], br[NM], bp[NM], bz[NM];
+    interp<R, NM, true, false>(E + 0 * NM * plane, plane, Nz, ci0, ci1, jh, mir, f0, frh, er);
+    interp<R, NM, false, false>(E + 1 * NM * plane, plane, Nz, ci0, ci1, j0, false, f0, fr, ep);
+    interp<R, NM, false, true>(E + 2 * NM * plane, plane, Nz, ch0, ch1, j0, false, fh, fr, ez);
+    interp<R, NM, false, false>(Bb + 0 * NM * plane, plane, Nz, ch0, ch1, j0, false, fh, fr, br);
+    interp<R, NM, true, false>(Bb + 1 * NM * plane, plane, Nz, ch0, ch1, jh, mir, fh, frh, bp);
+    interp<R, NM, true, true>(Bb + 2 * NM * plane, plane, Nz, ci0, ci1, jh, mir, f0, frh, bz);
 
-  // ---- move ----
-  int i1;
-  R f1;
-  R z1 = 0;
-  if constexpr (F64) {
-    z1 = z0 + dt * un[2] / g_new / dz;
-    const R fl = floor(z1);
-    i1 = (int)fl;
-    f1 = z1 - fl;
-  } else {
-    f1 = f0 + dt * un[2] / g_new / dz;
-    i1 = i0;
-    if (f1 >= R(1)) { f1 -= R(1); i1 += 1; }
-    else if (f1 < R(0)) {
-      f1 += R(1);
-      i1 -= 1;
-      if (f1 == R(1)) { f1 = R(0); i1 += 1; }
+    // ---- reconstruct Re sum_m F^m e^{i m phi}, rotate to Cartesian ----
+    R Em[M + 1][3];
+    R Ec[3], Bc[3];
+    {
+      Em[0][0] = er[0] * c0 - ep[0] * s0;
+      Em[0][1] = er[0] * s0 + ep[0] * c0;
+      Em[0][2] = ez[0];
+      Bc[0] = br[0] * c0 - bp[0] * s0;
+      Bc[1] = br[0] * s0 + bp[0] * c0;
+      Bc[2] = bz[0];
+      R ere = 1, eim = 0;
+#pragma unroll
+      for (int m = 1; m <= M; ++m) {
+        const R nre = ere * c0 - eim * s0;
+        const R nim = ere * s0 + eim * c0;
+        ere = nre;
+        eim = nim;
+        const int a = 2 * m - 1, b = 2 * m;
+        const R Fr = er[a] * ere - er[b] * eim, Fp = ep[a] * ere - ep[b] * eim;
+        Em[m][0] = Fr * c0 - Fp * s0;
+        Em[m][1] = Fr * s0 + Fp * c0;
+        Em[m][2] = ez[a] * ere - ez[b] * eim;
+        const R Gr = br[a] * ere - br[b] * eim, Gp = bp[a] * ere - bp[b] * eim;
+        Bc[0] += Gr * c0 - Gp * s0;
+        Bc[1] += Gr * s0 + Gp * c0;
+        Bc[2] += bz[a] * ere - bz[b] * eim;
+      }
+      Ec[0] = Em[0][0];
+      Ec[1] = Em[0][1];
+      Ec[2] = Em[0][2];
+#pragma unroll
+      for (int m = 1; m <= M; ++m) {
+        Ec[0] += Em[m][0];
+        Ec[1] += Em[m][1];
+        Ec[2] += Em[m][2];
+      }
     }
-  }
-  R x1 = x0 + dt * un[0] / g_new / dr;
-  R y1 = y0 + dt * un[1] / g_new / dr;
-  const R Rw = (R)(Nr - 1);
-  R r21 = fma(x1, x1, y1 * y1), r1 = sqrt(r21);
-  if (r1 >= Rw) {  // specular reflection at r = (Nr - 1) dr
-    const R nx = x1 / r1, ny = y1 / r1;
-    const R sc = (R(2) * Rw - r1) / r1;
-    x1 *= sc;
-    y1 *= sc;
-    const R ur = un[0] * nx + un[1] * ny;
-    un[0] -= R(2) * ur * nx;
-    un[1] -= R(2) * ur * ny;
-    r21 = fma(x1, x1, y1 * y1);
-    r1 = sqrt(r21);
-    if (r1 >= Rw) {  // rounding left it on the wall: pull it just inside
-      const R sc2 = (Rw * (R(1) - R(F64 ? 1e-12 : 1e-6))) / r1;
-      x1 *= sc2;
-      y1 *= sc2;
+
+    // ---- Boris, q/m = -1 (Eq. (6)) ----
+    const R u[3] = {UX[p], UY[p], UZ[p]};
+    R um[3], up[3], un[3], tt[3], ss[3], u1[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) um[a] = u[a] - R(0.5) * dt * Ec[a];
+    const R gm = sqrt(R(1) + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) tt[a] = -R(0.5) * dt * Bc[a] / gm;
+    const R t2 = tt[0] * tt[0] + tt[1] * tt[1] + tt[2] * tt[2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ss[a] = R(2) * tt[a] / (R(1) + t2);
+    u1[0] = um[0] + (um[1] * tt[2] - um[2] * tt[1]);
+    u1[1] = um[1] + (um[2] * tt[0] - um[0] * tt[2]);
+    u1[2] = um[2] + (um[0] * tt[1] - um[1] * tt[0]);
+    up[0] = um[0] + (u1[1] * ss[2] - u1[2] * ss[1]);
+    up[1] = um[1] + (u1[2] * ss[0] - u1[0] * ss[2]);
+    up[2] = um[2] + (u1[0] * ss[1] - u1[1] * ss[0]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) un[a] = up[a] - R(0.5) * dt * Ec[a];
+    const R g_new = sqrt(R(1) + un[0] * un[0] + un[1] * un[1] + un[2] * un[2]);
+
+    // ---- per-mode work of tracked electrons (FP64), Eq. (16) ----
+    if (pidw & kTrackedBit) {
+      const int32_t idv = (int32_t)(pidw & kIdMask);
+      int lo = 0, hi = k.n_tracked;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (k.tracked[mid] < idv) lo = mid + 1;
+        else hi = mid;
+      }
+      if (lo < k.n_tracked && k.tracked[lo] == idv) {
+        const double g_old = sqrt(1.0 + (double)u[0] * u[0] + (double)u[1] * u[1] + (double)u[2] * u[2]);
+        const double inv = 1.0 / (g_old + (double)g_new);
+        const double v0 = ((double)um[0] + (double)up[0]) * inv;
+        const double v1 = ((double)um[1] + (double)up[1]) * inv;
+        const double v2 = ((double)um[2] + (double)up[2]) * inv;
+        double *W = k.W + (long long)lo * (M + 1);
+#pragma unroll
+        for (int m = 0; m <= M; ++m)
+          W[m] += -k.dt * ((double)Em[m][0] * v0 + (double)Em[m][1] * v1 + (double)Em[m][2] * v2);
+      }
+    }
+
+    // ---- move ----
+    int i1;
+    R f1;
+    R z1 = 0;
+    if constexpr (F64) {
+      z1 = z0 + dt * un[2] / g_new / dz;
+      const R fl = floor(z1);
+      i1 = (int)fl;
+      f1 = z1 - fl;
+    } else {
+      f1 = f0 + dt * un[2] / g_new / dz;
+      i1 = i0;
+      if (f1 >= R(1)) {
+        f1 -= R(1);
+        i1 += 1;
+      } else if (f1 < R(0)) {
+        f1 += R(1);
+        i1 -= 1;
+        if (f1 == R(1)) {
+          f1 = R(0);
+          i1 += 1;
+        }
+      }
+    }
+    R x1 = x0 + dt * un[0] / g_new / dr;
+    R y1 = y0 + dt * un[1] / g_new / dr;
+    const R Rw = (R)(Nr - 1);
+    R r21 = fma(x1, x1, y1 * y1), r1 = sqrt(r21);
+    if (r1 >= Rw) {  // specular reflection at r = (Nr - 1) dr
+      const R nx = x1 / r1, ny = y1 / r1;
+      const R sc = (R(2) * Rw - r1) / r1;
+      x1 *= sc;
+      y1 *= sc;
+      const R ur = un[0] * nx + un[1] * ny;
+      un[0] -= R(2) * ur * nx;
+      un[1] -= R(2) * ur * ny;
       r21 = fma(x1, x1, y1 * y1);
       r1 = sqrt(r21);
+      if (r1 >= Rw) {  // rounding left it on the wall: pull it just inside
+        const R sc2 = (Rw * (R(1) - R(F64 ? 1e-12 : 1e-6))) / r1;
+        x1 *= sc2;
+        y1 *= sc2;
+        r21 = fma(x1, x1, y1 * y1);
+        r1 = sqrt(r21);
+      }
     }
-  }
-  int j1 = clampi(radial_index(r21, r1), j0 - 1, j0 + 1);
-  j1 = clampi(j1, 0, Nr - 2);
-  R c1 = 1, s1 = 0;
-  if (r1 > R(0)) {
-    c1 = x1 / r1;
-    s1 = y1 / r1;
-  }
-  const R g1 = r1 - (R)j1;
+    int j1 = clampi(radial_index(r21, r1), j0 - 1, j0 + 1);
+    j1 = clampi(j1, 0, Nr - 2);
+    R c1 = 1, s1 = 0;
+    if (r1 > R(0)) {
+      c1 = x1 / r1;
+      s1 = y1 / r1;
+    }
+    const R g1 = r1 - (R)j1;
 
-  // ---- charge-conserving deposit of J^{n+1/2} ----
-  {
-    const R xm = R(0.5) * (x0 + x1), ym = R(0.5) * (y0 + y1);
-    const R rm = sqrt(xm * xm + ym * ym);
-    R cmid = 1, smid = 0, vphi = 0;
-    if (rm > R(0)) {
-      cmid = xm / rm;
-      smid = ym / rm;
-      vphi = (cmid * un[1] - smid * un[0]) / g_new;
-    }
-    const int di = clampi(i1 - i0, -1, 1);
-    const int oz0 = di < 0 ? 1 : 0, oz1 = oz0 + di;  // offsets of the two cells in the window
-    const int ib = i0 - oz0;
-    const int dj = j1 - j0;
-    const int or0 = dj < 0 ? 1 : 0, or1 = or0 + dj;
-    const int jb = j0 - or0;
-    R Sz0[3], Sz1[3], Sr0[3], Sr1[3];
-    const R g0 = fr;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      Sz0[a] = (a == oz0) ? R(1) - f0 : ((a == oz0 + 1) ? f0 : R(0));
-      Sz1[a] = (a == oz1) ? R(1) - f1 : ((a == oz1 + 1) ? f1 : R(0));
-      Sr0[a] = (a == or0) ? R(1) - g0 : ((a == or0 + 1) ? g0 : R(0));
-      Sr1[a] = (a == or1) ? R(1) - g1 : ((a == or1 + 1) ? g1 : R(0));
-    }
-    int col[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) col[a] = wrap_any(ib + a, Nz);
-    R Wz[3][3], Wr[3][3], Ss[3][3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        Wz[a][b] = (Sz1[a] - Sz0[a]) * (Sr0[b] + Sr1[b]) * R(0.5);
-        Wr[a][b] = (Sr1[b] - Sr0[b]) * (Sz0[a] + Sz1[a]) * R(0.5);
-        Ss[a][b] = Sz0[a] * Sr0[b] + Sz1[a] * Sr1[b];
+    // ---- charge-conserving deposit of J^{n+1/2} ----
+    {
+      const R xm = R(0.5) * (x0 + x1), ym = R(0.5) * (y0 + y1);
+      const R rm = sqrt(xm * xm + ym * ym);
+      R cmid = 1, smid = 0, vphi = 0;
+      if (rm > R(0)) {
+        cmid = xm / rm;
+        smid = ym / rm;
+        vphi = (cmid * un[1] - smid * un[0]) / g_new;
       }
-    R *Jr = J, *Jp = J + NM * plane, *Jz = J + 2 * NM * plane;
-    // e^{-i m phi} at old, new and mid positions, by recurrence
-    R e0r = 1, e0i = 0, e1r = 1, e1i = 0, emr = 1, emi = 0;
-#pragma unroll
-    for (int m = 0; m <= M; ++m) {
-      if (m > 0) {
-        R tr = e0r * c0 + e0i * s0, ti = e0i * c0 - e0r * s0;
-        e0r = tr; e0i = ti;
-        tr = e1r * c1 + e1i * s1; ti = e1i * c1 - e1r * s1;
-        e1r = tr; e1i = ti;
-        tr = emr * cmid + emi * smid; ti = emi * cmid - emr * smid;
-        emr = tr; emi = ti;
-      }
-      const R cq = (m == 0 ? R(1) : R(2)) * q;
-      const R xr = R(0.5) * (e0r + e1r), xi = R(0.5) * (e0i + e1i);
-      const int qa = m == 0 ? 0 : 2 * m - 1, qb = 2 * m;
-      // J_z at (ib+a+1/2, jb+b)
-#pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        R run = 0;
-        const long long rowo = (long long)(jb + b) * Nz;
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          run += Wz[a][b];
-          const R v = -cq * run;
-          atomic_add(Jz + qa * plane + rowo + col[a], v * xr);
-          if (m > 0) atomic_add(Jz + qb * plane + rowo + col[a], v * xi);
-        }
-      }
-      // J_r at (ib+a, jb+b+1/2)
+      const int di = clampi(i1 - i0, -1, 1);
+      const int oz0 = di < 0 ? 1 : 0, oz1 = oz0 + di;  // cells of the two positions in the 3-node window
+      const int ib = i0 - oz0;
+      const int dj = j1 - j0;
+      const int or0 = dj < 0 ? 1 : 0, or1 = or0 + dj;
+      const int jb = j0 - or0;
+      R Sz0[3], Sz1[3], Sr0[3], Sr1[3];
+      const R g0 = fr;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        R run = 0;
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          run += Wr[a][b];
-          const R v = -cq * run;
-          const long long o = (long long)(jb + b) * Nz + col[a];
-          atomic_add(Jr + qa * plane + o, v * xr);
-          if (m > 0) atomic_add(Jr + qb * plane + o, v * xi);
-        }
+        Sz0[a] = (a == oz0) ? R(1) - f0 : ((a == oz0 + 1) ? f0 : R(0));
+        Sz1[a] = (a == oz1) ? R(1) - f1 : ((a == oz1 + 1) ? f1 : R(0));
+        Sr0[a] = (a == or0) ? R(1) - g0 : ((a == or0 + 1) ? g0 : R(0));
+        Sr1[a] = (a == or1) ? R(1) - g1 : ((a == or1 + 1) ? g1 : R(0));
       }
-      // J_phi at (ib+a, jb+b)
-      const R dre = e1r - e0r, dim_ = e1i - e0i;
+      R Wz[3][3], Wr[3][3], Ss[3][3];
 #pragma unroll
       for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
-          const int j = jb + b;
-          const long long o = (long long)j * Nz + col[a];
-          const R h = R(0.5) * cq * Ss[a][b];
-          if (m == 0) {
-            atomic_add(Jp + o, h * vphi);
-          } else if (m == 1 && j == 0) {
-            atomic_add(Jp + qa * plane + o, h * vphi * emr);
-            atomic_add(Jp + qb * plane + o, h * vphi * emi);
-          } else if (j > 0) {  // the closure carries r_j: nothing on the axis
-            // (i/m)(e1 - e0) = (-(e1-e0).im, (e1-e0).re) / m
-            atomic_add(Jp + qa * plane + o, -h * dim_ / (R)m);
-            atomic_add(Jp + qb * plane + o, h * dre / (R)m);
+          Wz[a][b] = (Sz1[a] - Sz0[a]) * (Sr0[b] + Sr1[b]) * R(0.5);
+          Wr[a][b] = (Sr1[b] - Sr0[b]) * (Sz0[a] + Sz1[a]) * R(0.5);
+          Ss[a][b] = Sz0[a] * Sr0[b] + Sz1[a] * Sr1[b];
+        }
+      // e^{-i m phi} at the old, new and mid positions, by recurrence
+      R e0r = 1, e0i = 0, e1r = 1, e1i = 0, emr = 1, emi = 0;
+#pragma unroll
+      for (int m = 0; m <= M; ++m) {
+        if (m > 0) {
+          R tr_ = e0r * c0 + e0i * s0, ti = e0i * c0 - e0r * s0;
+          e0r = tr_;
+          e0i = ti;
+          tr_ = e1r * c1 + e1i * s1;
+          ti = e1i * c1 - e1r * s1;
+          e1r = tr_;
+          e1i = ti;
+          tr_ = emr * cmid + emi * smid;
+          ti = emi * cmid - emr * smid;
+          emr = tr_;
+          emi = ti;
+        }
+        const R cq = (m == 0 ? R(1) : R(2)) * q;
+        const R xr = R(0.5) * (e0r + e1r), xi = R(0.5) * (e0i + e1i);
+        const int qa = m == 0 ? 0 : 2 * m - 1, qb = 2 * m;
+        // J_z at (ib+a+1/2, jb+b): minus the running sum of Wz behind the face
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          R run = 0;
+#pragma unroll
+          for (int a = 0; a < 2; ++a) {
+            run += Wz[a][b];
+            const R v = -cq * run;
+            dep(2, qa, jb + b, ib + a, v * xr);
+            if (m > 0) dep(2, qb, jb + b, ib + a, v * xi);
           }
         }
+        // J_r at (ib+a, jb+b+1/2)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          R run = 0;
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            run += Wr[a][b];
+            const R v = -cq * run;
+            dep(0, qa, jb + b, ib + a, v * xr);
+            if (m > 0) dep(0, qb, jb + b, ib + a, v * xi);
+          }
+        }
+        // J_phi at (ib+a, jb+b)
+        const R dre = e1r - e0r, dim_ = e1i - e0i;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = 0; b < 3; ++b) {
+            const int j = jb + b;
+            const R h = R(0.5) * cq * Ss[a][b];
+            if (m == 0) {
+              dep(1, 0, j, ib + a, h * vphi);
+            } else if (m == 1 && j == 0) {
+              dep(1, qa, j, ib + a, h * vphi * emr);
+              dep(1, qb, j, ib + a, h * vphi * emi);
+            } else if (j > 0) {  // the closure carries r_j: nothing on the axis
+              // (i/m)(e1 - e0) = (-(e1-e0).im, (e1-e0).re) / m
+              dep(1, qa, j, ib + a, -h * dim_ / (R)m);
+              dep(1, qb, j, ib + a, h * dre / (R)m);
+            }
+          }
+      }
     }
+
+    // ---- store (periodic in z) ----
+    if constexpr (F64) {
+      if (z1 < R(0)) z1 += (R)Nz;
+      if (z1 >= (R)Nz) z1 -= (R)Nz;
+      ((double *)k.pz)[p] = z1;
+    } else {
+      ((int *)k.pz)[p] = wrap_any(i1, Nz);
+      ((float *)k.pfz)[p] = f1;
+    }
+    X[p] = x1;
+    Y[p] = y1;
+    UX[p] = un[0];
+    UY[p] = un[1];
+    UZ[p] = un[2];
   }
 
-  // ---- store (periodic in z) ----
-  if constexpr (F64) {
-    if (z1 < R(0)) z1 += (R)Nz;
-    if (z1 >= (R)Nz) z1 -= (R)Nz;
-    ((double *)k.pz)[p] = z1;
-  } else {
-    ((int *)k.pz)[p] = wrap_any(i1, Nz);
-    ((float *)k.pfz)[p] = f1;
+  // ---- flush the tile's current ----
+  __syncthreads();
+  for (int e = threadIdx.x; e < nlds; e += blockDim.x) {
+    const R v = lds[e];
+    if (v == R(0)) continue;
+    const int lc = e % WZ;
+    const int rest = e / WZ;
+    const int lr = rest % WR;
+    const int cq = rest / WR;  // c * NM + q
+    const int row = rlo + lr;
+    if (row < 0 || row > Nr) continue;
+    atomic_add(J + (long long)cq * plane + (long long)row * Nz + wrap_once(zlo + lc, Nz), v);
   }
-  X[p] = x1;
-  Y[p] = y1;
-  UX[p] = un[0];
-  UY[p] = un[1];
-  UZ[p] = un[2];
 }
 
 // ---------------------------------------------------------------------------
@@ -529,8 +578,10 @@ __global__ __launch_bounds__(256) void efield_kernel(KRun k, int par) {
   for (int c = 0; c < 3 * NM; ++c) Jn[c * plane + row + i] = R(0);
 }
 
+// Bout = Bin - tau curl_E E; with avg != nullptr also avg = (Bin + Bout)/2,
+// the time-centred B that the next gather uses (Eq. (12)).
 template <typename R, int M>
-__global__ __launch_bounds__(256) void bfield_kernel(KRun k, R *Bout, const R *Bin, R tau) {
+__global__ __launch_bounds__(256) void bfield_kernel(KRun k, R *Bout, const R *Bin, R tau, R *avg) {
   constexpr int NM = 2 * M + 1;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
@@ -598,9 +649,16 @@ __global__ __launch_bounds__(256) void bfield_kernel(KRun k, R *Bout, const R *B
     for (int h = 0; h < 2; ++h) {
       if (h >= nq) break;
       const int qq = h == 0 ? qa : qb;
-      Bout[(0 * NM + qq) * plane + row + i] = nbr[h];
-      Bout[(1 * NM + qq) * plane + row + i] = nbp[h];
-      Bout[(2 * NM + qq) * plane + row + i] = nbz[h];
+      const long long o0 = (0 * NM + qq) * plane + row + i, o1 = (1 * NM + qq) * plane + row + i,
+                      o2 = (2 * NM + qq) * plane + row + i;
+      if (avg) {
+        avg[o0] = R(0.5) * (Bin[o0] + nbr[h]);
+        avg[o1] = R(0.5) * (Bin[o1] + nbp[h]);
+        avg[o2] = R(0.5) * (Bin[o2] + nbz[h]);
+      }
+      Bout[o0] = nbr[h];
+      Bout[o1] = nbp[h];
+      Bout[o2] = nbz[h];
     }
   }
 }
@@ -741,10 +799,133 @@ __global__ __launch_bounds__(256) void tracked_gamma_kernel(KRun k, double *gamm
   ids[lo] = idv;
 }
 
+
+// ---------------------------------------------------------------------------
+// cell sort: electrons ordered by (tile, cell in tile, id); tiles of Tz x Tr
+// cells numbered z-fastest, cells inside a tile z-fastest.  Counting sort on
+// the cell order, then the ids of each cell in ascending order, so that the
+// permutation is unique whatever order the atomics ran in.
+
+template <typename R>
+__device__ __forceinline__ int cell_order(const KRun &k, long long p) {
+  int iz;
+  if constexpr (std::is_same<R, double>::value) {
+    iz = (int)floor(((const double *)k.pz)[p]);
+  } else {
+    iz = ((const int *)k.pz)[p];
+  }
+  iz = wrap_any(iz, k.Nz);
+  const R x = ((const R *)k.px)[p], y = ((const R *)k.py)[p];
+  const R r2 = fma(x, x, y * y);
+  const int ir = clampi(radial_index(r2, sqrt(r2)), 0, k.Nr - 1);
+  const int tile = (ir / k.Tr) * k.ntz + iz / k.Tz;
+  const int local = (ir % k.Tr) * k.Tz + iz % k.Tz;
+  return tile * (k.Tz * k.Tr) + local;
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void sort_key_kernel(KRun k, int32_t *keys) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= k.np) return;
+  const int key = cell_order<R>(k, p);
+  keys[p] = key;
+  atomicAdd(&k.cell_count[key], 1);
+}
+
+// exclusive scan of 1024-element blocks; block totals to bsum
+__global__ __launch_bounds__(256) void scan_block_kernel(const int32_t *in, int32_t *out, int32_t *bsum,
+                                                          long long n) {
+  __shared__ int32_t sh[256];
+  const long long base = (long long)blockIdx.x * 1024 + threadIdx.x * 4;
+  int32_t v[4];
+  int32_t tot = 0;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    v[a] = (base + a < n) ? in[base + a] : 0;
+    tot += v[a];
+  }
+  sh[threadIdx.x] = tot;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {  // inclusive Hillis-Steele scan of the thread totals
+    const int32_t t = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += t;
+    __syncthreads();
+  }
+  int32_t run = sh[threadIdx.x] - tot;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    if (base + a < n) out[base + a] = run;
+    run += v[a];
+  }
+  if (threadIdx.x == 255 && bsum) bsum[blockIdx.x] = sh[255];
+}
+
+__global__ __launch_bounds__(256) void scan_add_kernel(int32_t *out, const int32_t *boff, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] += boff[i / 1024];
+}
+
+__global__ __launch_bounds__(256) void copy_i32_kernel(int32_t *dst, const int32_t *src, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(256) void sort_scatter_kernel(KRun k, const int32_t *keys, int32_t *cursor) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= k.np) return;
+  const int key = keys[p];
+  const int pos = atomicAdd(&cursor[key], 1);
+  k.perm[pos] = (int32_t)p;
+}
+
+// within each cell, order the electrons by id (insertion sort; cells are short)
+__global__ __launch_bounds__(256) void sort_cells_kernel(KRun k) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= k.n_keys) return;
+  const int b = k.cell_start[c], e = k.cell_start[c + 1];
+  for (int a = b + 1; a < e; ++a) {
+    const int32_t v = k.perm[a];
+    const uint32_t key = k.pid[v] & kIdMask;
+    int t = a - 1;
+    while (t >= b && (k.pid[k.perm[t]] & kIdMask) > key) {
+      k.perm[t + 1] = k.perm[t];
+      --t;
+    }
+    k.perm[t + 1] = v;
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void sort_permute_kernel(KRun k) {
+  const long long d = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= k.np) return;
+  const int s = k.perm[d];
+  if constexpr (std::is_same<R, double>::value) {
+    ((double *)k.sz)[d] = ((const double *)k.pz)[s];
+  } else {
+    ((int *)k.sz)[d] = ((const int *)k.pz)[s];
+    ((float *)k.sfz)[d] = ((const float *)k.pfz)[s];
+  }
+  ((R *)k.sx)[d] = ((const R *)k.px)[s];
+  ((R *)k.sy)[d] = ((const R *)k.py)[s];
+  ((R *)k.sux)[d] = ((const R *)k.pux)[s];
+  ((R *)k.suy)[d] = ((const R *)k.puy)[s];
+  ((R *)k.suz)[d] = ((const R *)k.puz)[s];
+  ((R *)k.sw)[d] = ((const R *)k.pw)[s];
+  k.spid[d] = k.pid[s];
+}
+
 // ---------------------------------------------------------------------------
 // launch helpers
 
 thread_local char g_err[256] = "";
+
+size_t push_lds_bytes(const KRun &k, size_t word) {
+  return (size_t)3 * (2 * k.M + 1) * (k.Tz + 3) * (k.Tr + 3) * word;
+}
+
+
 
 int check(hipError_t e, const char *what) {
   if (e != hipSuccess) {
@@ -752,6 +933,18 @@ int check(hipError_t e, const char *what) {
     return PIC_E_DEVICE;
   }
   return PIC_OK;
+}
+
+int scan_exclusive(int32_t *data_in, int32_t *out, long long n, int32_t *tmp, hipStream_t s) {
+  const long long nb = (n + 1023) / 1024;
+  int32_t *bsum = nb > 1 ? tmp : nullptr;
+  scan_block_kernel<<<(unsigned)nb, 256, 0, s>>>(data_in, out, bsum, n);
+  int rc = check(hipGetLastError(), "scan_block_kernel");
+  if (rc || nb <= 1) return rc;
+  rc = scan_exclusive(bsum, bsum, nb, tmp + nb, s);
+  if (rc) return rc;
+  scan_add_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(out, bsum, n);
+  return check(hipGetLastError(), "scan_add_kernel");
 }
 
 template <template <typename, int> class F, typename... A>
@@ -778,8 +971,9 @@ template <typename R, int M>
 struct PushL {
   static int run(const KRun &k, int par, hipStream_t s) {
     if (k.np == 0) return PIC_OK;
-    const unsigned blocks = (unsigned)((k.np + 255) / 256);
-    push_kernel<R, M><<<blocks, 256, 0, s>>>(k, par);
+    const unsigned blocks = (unsigned)((long long)k.ntz * k.ntr);
+    const size_t lds = push_lds_bytes(k, sizeof(R));
+    push_kernel<R, M><<<blocks, 256, lds, s>>>(k, par);
     return check(hipGetLastError(), "push_kernel");
   }
 };
@@ -793,9 +987,9 @@ struct EL {
 };
 template <typename R, int M>
 struct BL {
-  static int run(const KRun &k, void *out, const void *in, double tau, hipStream_t s) {
+  static int run(const KRun &k, void *out, const void *in, double tau, void *avg, hipStream_t s) {
     dim3 g((k.Nz + 255) / 256, k.Nr + 1);
-    bfield_kernel<R, M><<<g, 256, 0, s>>>(k, (R *)out, (const R *)in, (R)tau);
+    bfield_kernel<R, M><<<g, 256, 0, s>>>(k, (R *)out, (const R *)in, (R)tau, (R *)avg);
     return check(hipGetLastError(), "bfield_kernel");
   }
 };
@@ -825,8 +1019,8 @@ int launch_push(const KRun &k, int prec, int par, void *stream) {
 int launch_efield(const KRun &k, int prec, int par, void *stream) {
   return dispatch_M<EL>(prec, k.M, k, par, (hipStream_t)stream);
 }
-int launch_bfield(const KRun &k, int prec, void *Bout, const void *Bin, double tau, void *stream) {
-  return dispatch_M<BL>(prec, k.M, k, Bout, Bin, tau, (hipStream_t)stream);
+int launch_bfield(const KRun &k, int prec, void *Bout, const void *Bin, double tau, void *avg, void *stream) {
+  return dispatch_M<BL>(prec, k.M, k, Bout, Bin, tau, avg, (hipStream_t)stream);
 }
 int launch_rho(const KRun &k, int prec, void *stream) {
   return dispatch_M<RhoL>(prec, k.M, k, (hipStream_t)stream);
@@ -863,6 +1057,42 @@ int launch_tracked_gamma(const KRun &k, int prec, double *gamma, int64_t *ids, v
   else tracked_gamma_kernel<float><<<blocks, 256, 0, (hipStream_t)stream>>>(k, gamma, ids);
   return check(hipGetLastError(), "tracked_gamma_kernel");
 }
-int launch_sort(const KRun &, int, void *) { return PIC_OK; }
+size_t lds_bytes_of(const KRun &k, int prec) { return push_lds_bytes(k, prec == PIC_PREC_FP64 ? 8 : 4); }
+
+int launch_sort(KRun &k, int prec, void *stream) {
+  const hipStream_t s = (hipStream_t)stream;
+  const long long nk = k.n_keys + 1;
+  int rc = launch_zero(k.cell_count, (size_t)nk * 4, stream);
+  if (rc) return rc;
+  if (k.np > 0) {
+    const unsigned pb = (unsigned)((k.np + 255) / 256);
+    int32_t *keys = (int32_t *)k.spid;  // free until the permutation writes it
+    if (prec == PIC_PREC_FP64) sort_key_kernel<double><<<pb, 256, 0, s>>>(k, keys);
+    else sort_key_kernel<float><<<pb, 256, 0, s>>>(k, keys);
+    if ((rc = check(hipGetLastError(), "sort_key_kernel"))) return rc;
+    if ((rc = scan_exclusive(k.cell_count, k.cell_start, nk, k.scan_tmp, s))) return rc;
+    copy_i32_kernel<<<(unsigned)((nk + 255) / 256), 256, 0, s>>>(k.cell_count, k.cell_start, nk);
+    if ((rc = check(hipGetLastError(), "copy_i32_kernel"))) return rc;
+    sort_scatter_kernel<<<pb, 256, 0, s>>>(k, keys, k.cell_count);
+    if ((rc = check(hipGetLastError(), "sort_scatter_kernel"))) return rc;
+    sort_cells_kernel<<<(unsigned)((k.n_keys + 255) / 256), 256, 0, s>>>(k);
+    if ((rc = check(hipGetLastError(), "sort_cells_kernel"))) return rc;
+    if (prec == PIC_PREC_FP64) sort_permute_kernel<double><<<pb, 256, 0, s>>>(k);
+    else sort_permute_kernel<float><<<pb, 256, 0, s>>>(k);
+    if ((rc = check(hipGetLastError(), "sort_permute_kernel"))) return rc;
+    std::swap(k.pz, k.sz);
+    std::swap(k.pfz, k.sfz);
+    std::swap(k.px, k.sx);
+    std::swap(k.py, k.sy);
+    std::swap(k.pux, k.sux);
+    std::swap(k.puy, k.suy);
+    std::swap(k.puz, k.suz);
+    std::swap(k.pw, k.sw);
+    std::swap(k.pid, k.spid);
+  } else {
+    if ((rc = scan_exclusive(k.cell_count, k.cell_start, nk, k.scan_tmp, s))) return rc;
+  }
+  return PIC_OK;
+}
 
 }  // namespace pic

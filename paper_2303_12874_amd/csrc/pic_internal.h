@@ -40,6 +40,7 @@ struct KRun {
   long long plane;        // (Nr+1) * Nz
   void *E;                // 3 * NM planes
   void *B[2];             // B at alternate half steps: B[n%2] = B^{n-1/2}, B[1-n%2] = B^{n+1/2}
+  void *Bbar;             // (B^{n-1/2} + B^{n+1/2})/2, written by the B update
   void *J[2];             // deposit target of step n is J[n%2]; the other is kept zeroed
   void *rho;              // NM planes (diagnostic)
   void *pz;               // FP64: double z (cells);  FP32: int iz
@@ -57,7 +58,8 @@ struct KRun {
   int32_t *cell_start;    // n_keys + 1
   int32_t *perm;          // np
   int32_t *scan_tmp;      // scan block sums
-  int Tz, Tr;             // sort tile
+  int Tz, Tr;             // sort tile (cells)
+  int ntz, ntr;           // tiles along z and r
   long long n_keys;       // tiles * Tz * Tr
   double *red;            // reduction partials
 };
@@ -65,9 +67,10 @@ struct KRun {
 // ---- kernel launchers (kernels.hip); all enqueue on `stream` -----------------
 int launch_push(const KRun &k, int prec, int par, void *stream);
 int launch_efield(const KRun &k, int prec, int par, void *stream);
-int launch_bfield(const KRun &k, int prec, void *Bout, const void *Bin, double tau, void *stream);
+int launch_bfield(const KRun &k, int prec, void *Bout, const void *Bin, double tau, void *avg, void *stream);
 int launch_zero(void *ptr, size_t bytes, void *stream);
-int launch_sort(const KRun &k, int prec, void *stream);
+int launch_sort(KRun &k, int prec, void *stream);  // swaps k's particle buffers
+size_t lds_bytes_of(const KRun &k, int prec);
 int launch_rho(const KRun &k, int prec, void *stream);
 int launch_energy(const KRun &k, int prec, int par, int nblocks_max, int *nblocks, void *stream);
 int launch_kinetic(const KRun &k, int prec, int *nblocks, void *stream);

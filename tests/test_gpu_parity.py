@@ -186,3 +186,41 @@ def test_fp64_gauss_law_invariant_on_gpu():
         scale = np.abs(G0[m]).max() + np.abs(G1).max()
         assert np.abs(G1 - G0[m]).max() < 1e-12 * scale, m
     sim.close()
+
+
+def _oracle_order(o, Tz, Tr):
+    """ids in (tile, cell, id) order, from the oracle's own positions"""
+    P = o.particles()
+    ords = o.cell_order(Tz, Tr)
+    return P["id"][np.lexsort((P["id"], ords))]
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_initial_cell_sort_bit_exact(precision):
+    """The cell sort after loading orders electrons exactly as the oracle's
+    (tile, cell, id) key on the identical loaded state."""
+    _say(f"[gpu] initial sort fp{precision}")
+    pic = _pic()
+    run = workloads.config("c1")["runs"][0]
+    dt, CE, CB, _ = _setup(16, run["M"], run["dz"], run["dr"])
+    sim = pic.Simulation([workloads.to_rundesc(run)], precision=precision, dt=dt, coef_E=CE, coef_B=CB,
+                         tile_z=32, tile_r=8)
+    o = oracle_of(run, dt, CE, CB, fp32_start=(precision == 32))
+    assert np.array_equal(sim.particles()["id"], _oracle_order(o, 32, 8))
+    sim.close()
+
+
+def test_cell_sort_after_steps_bit_exact():
+    """FP64 run with a sort every 4 steps: after 9 steps the order is the one
+    the oracle's key gives for its state after 8 steps."""
+    _say("[gpu] sort after 8 steps")
+    pic = _pic()
+    run = workloads.small(M=2, Nz=96, Nr=20, ppc=3, n_tracked=10)["runs"][0]
+    dt, CE, CB, _ = _setup(16, run["M"], run["dz"], run["dr"])
+    sim = pic.Simulation([workloads.to_rundesc(run)], dt=dt, coef_E=CE, coef_B=CB, sort_interval=4,
+                         tile_z=16, tile_r=4)
+    o = oracle_of(run, dt, CE, CB)
+    sim.step(9)
+    o.step(8)
+    assert np.array_equal(sim.particles()["id"], _oracle_order(o, 16, 4))
+    sim.close()
