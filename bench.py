@@ -72,6 +72,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c5"])
     ap.add_argument("--cpu-steps", type=int, default=1, help="oracle steps for the CPU baseline (0: skip)")
     ap.add_argument("--sort-interval", type=int, default=0)
+    ap.add_argument("--precision", type=int, default=0, choices=[0, 32, 64],
+                    help="override the workload's precision (0: as defined)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}), flush=True)
@@ -83,7 +85,7 @@ def main(argv=None):
 
     cfg = workloads.config(args.workload)
     run = cfg["runs"][0]
-    prec = cfg["precision"]
+    prec = args.precision or cfg["precision"]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t_init = time.perf_counter()

@@ -71,7 +71,7 @@ struct Layout {
 
 Layout layout_of(const pic_run_desc &d, int prec, int N, int Tz, int Tr, long long n_keys) {
   const size_t rs = prec == PIC_PREC_FP64 ? 8 : 4;
-  const int NM = 2 * d.M + 1;
+  const int NM = 2 * d.M + 1;  // mode planes per component
   const size_t plane = (size_t)(d.Nr + 1) * d.Nz;
   const size_t np = (size_t)run_particle_count(d);
   Layout L{};
@@ -175,10 +175,12 @@ int validate_run(const pic_run_desc &r, int i, int N) {
   return PIC_OK;
 }
 
-constexpr size_t kMaxLds = 65536;  // LDS of one push workgroup (current window of a tile)
+// LDS of one push workgroup (the current window of its tile); 48 KB keeps three
+// workgroups per CU, which the latency-bound gather needs
+constexpr size_t kMaxLds = 49152;
 
-size_t tile_lds(int M, int Tz, int Tr, int prec) {
-  return (size_t)3 * (2 * M + 1) * (Tz + 3) * (Tr + 3) * (prec == PIC_PREC_FP64 ? 8 : 4);
+size_t tile_lds(int M, int Tz, int Tr, int) {  // FP64 accumulators for both precisions
+  return (size_t)3 * (2 * M + 1) * (Tz + 3) * (Tr + 3) * 8;
 }
 
 // Sort tile: 32 x 8 cells unless given; the radial extent shrinks until the
@@ -476,8 +478,7 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
     }
     // ---- fields: laser E^0, B^0 (Eq. (18)), then B^{-1/2}, B^{+1/2} ----
     {
-      const int NM = 2 * d.M + 1;
-      const size_t nvec = (size_t)3 * NM * (size_t)k.plane;
+      const size_t nvec = (size_t)3 * (2 * d.M + 1) * (size_t)k.plane;
       std::vector<double> Eh(nvec, 0.0), Bh(nvec, 0.0);
       laser_fields(d, Eh.data(), Bh.data());
       if (f64) {
@@ -648,24 +649,31 @@ int pic_fields(pic_ctx *ctx, int32_t run, int32_t comp, int32_t m, double *out, 
   if (out_len < 2 * plane) return fail(PIC_E_NOMEM, "out holds %zu doubles, %zu needed", out_len, 2 * plane);
   const hipStream_t s = ctx->stream;
   const bool f64 = ctx->prec == PIC_PREC_FP64;
-  const size_t rs = f64 ? 8 : 4;
   const int NM = 2 * k.M + 1;
   const int qa = m == 0 ? 0 : 2 * m - 1, qb = 2 * m;
   const int par = (int)(R->steps & 1);
   TRY(hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize"));
-  auto read_plane = [&](const void *base, int c, int q, std::vector<double> &dst) -> int {
-    dst.assign(plane, 0.0);
-    const unsigned char *src = (const unsigned char *)base + ((size_t)c * NM + q) * plane * rs;
-    if (f64) return hip_ok(hipMemcpy(dst.data(), src, plane * 8, hipMemcpyDeviceToHost), "hipMemcpy D2H");
-    std::vector<float> tmp(plane);
-    int rc = hip_ok(hipMemcpy(tmp.data(), src, plane * 4, hipMemcpyDeviceToHost), "hipMemcpy D2H");
-    for (size_t a = 0; a < plane; ++a) dst[a] = tmp[a];
+  // copy the (Re, Im) planes of mode m of one component
+  std::vector<double> re(plane, 0.0), im(plane, 0.0);
+  auto read_plane = [&](const void *base, int c, int q, bool is_f64, std::vector<double> &dst) -> int {
+    if (is_f64) {
+      const double *src = (const double *)base + ((size_t)c * NM + q) * plane;
+      return hip_ok(hipMemcpy(dst.data(), src, plane * 8, hipMemcpyDeviceToHost), "hipMemcpy D2H");
+    }
+    std::vector<float> t(plane);
+    const float *src = (const float *)base + ((size_t)c * NM + q) * plane;
+    int rc = hip_ok(hipMemcpy(t.data(), src, plane * 4, hipMemcpyDeviceToHost), "hipMemcpy D2H");
+    for (size_t a = 0; a < plane; ++a) dst[a] = t[a];
     return rc;
   };
-  std::vector<double> re, im, re2, im2;
+  auto read_comp = [&](const void *base, int c, bool is_f64) -> int {
+    int rc = read_plane(base, c, qa, is_f64, re);
+    if (rc == PIC_OK && m > 0) rc = read_plane(base, c, qb, is_f64, im);
+    return rc;
+  };
   const void *src = nullptr;
   int c = 0;
-  bool avg = false, cur = false, rho = false;
+  bool cur = false, rho = false;
   if (comp <= PIC_EZ) { src = k.E; c = comp; }
   else if (comp <= PIC_BZ) { src = k.Bbar; c = comp - PIC_BR; }
   else if (comp <= PIC_JZ) { src = k.J[(R->steps + 1) & 1]; c = comp - PIC_JR; cur = true; }
@@ -676,24 +684,9 @@ int pic_fields(pic_ctx *ctx, int32_t run, int32_t comp, int32_t m, double *out, 
     TRY(launch_zero(k.rho, (size_t)NM * plane * 8, s));
     TRY(launch_rho(k, ctx->prec, s));
     TRY(hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize"));
-    re.assign(plane, 0.0);
-    im.assign(plane, 0.0);
-    TRY(hip_ok(hipMemcpy(re.data(), (double *)k.rho + (size_t)qa * plane, plane * 8, hipMemcpyDeviceToHost), "D2H"));
-    if (m > 0)
-      TRY(hip_ok(hipMemcpy(im.data(), (double *)k.rho + (size_t)qb * plane, plane * 8, hipMemcpyDeviceToHost), "D2H"));
+    TRY(read_comp(k.rho, 0, true));
   } else {
-    TRY(read_plane(src, c, qa, re));
-    if (m > 0) TRY(read_plane(src, c, qb, im));
-    else im.assign(plane, 0.0);
-    if (avg) {
-      TRY(read_plane(k.B[par ^ 1], c, qa, re2));
-      if (m > 0) TRY(read_plane(k.B[par ^ 1], c, qb, im2));
-      else im2.assign(plane, 0.0);
-      for (size_t a = 0; a < plane; ++a) {
-        re[a] = 0.5 * (re[a] + re2[a]);
-        im[a] = 0.5 * (im[a] + im2[a]);
-      }
-    }
+    TRY(read_comp(src, c, f64));
     if (cur) {  // physical current = raw deposit * row factor
       const double dz = k.dz, dr = k.dr, dt = k.dt;
       for (int j = 0; j <= k.Nr; ++j) {

@@ -1,15 +1,24 @@
 // kernels.hip -- gfx950 kernels of the quasi-3D r-z PIC step with the dual
 // Maxwell solver (arXiv 2303.12874, Sec. III).  One step of a run is
-//   push:   gather E^n and (B^{n-1/2} + B^{n+1/2})/2 (Eq. (12)) at each
-//           electron, Boris push (Eq. (6)), per-mode work of tracked
-//           electrons (Eq. (16)), move, charge-conserving deposit of the
-//           current J^{n+1/2} into the mode arrays (global atomics);
+//   push:   per sort tile, gather E^n and Bbar^n = (B^{n-1/2} + B^{n+1/2})/2
+//           (Eq. (12)) at each electron, Boris push (Eq. (6)), per-mode work
+//           of tracked electrons (Eq. (16)), move, charge-conserving deposit
+//           of J^{n+1/2} into an LDS window, flushed once per tile;
 //   efield: E^{n+1} = E^n + dt (curl_B B^{n+1/2} - J'), J' = (P J_r, P J_phi, J_z)
 //           with the z filter P that makes the two-point continuity of the
 //           deposit hold for D_B (Gauss's law with [k]_B, Eq. (10));
 //           also clears the other current buffer;
 //   bfield: B^{n+3/2} = B^{n+1/2} - dt curl_E E^{n+1}, into the buffer that
-//           held B^{n-1/2}.
+//           held B^{n-1/2}, and Bbar^{n+1} for the next gather.
+//
+// Field layout: for component c, mode plane q holds (Nr+1) x Nz reals, z
+// fastest, at (c * NM + q) * (Nr+1) * Nz; NM = 2M+1 planes: q = 0 is Re of
+// m = 0, q = 2m-1 and 2m are Re and Im of mode m >= 1.  Threads of a
+// wavefront sit in consecutive cells (columns), so every plane read is one
+// coalesced row segment.  Inside the kernels a node is handled as a record
+// of NMP = 2(M+1) reals, (Re, Im) of every mode with Im of m = 0 zero.
+// A quantity at z_{i+1/2} is stored at column i, one at r_{j+1/2} at row j.
+//
 // Every global index is clamped or wrapped into its array, whatever the
 // particle data hold, so corrupted particles give NaN fields, not faults.
 #include <hip/hip_runtime.h>
@@ -23,11 +32,7 @@ namespace pic {
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
-
-template <typename R>
-struct C2 {
-  R re, im;
-};
+constexpr int kFieldTile = 128;  // z-columns per field-update workgroup
 
 __device__ __forceinline__ int wrap_once(int c, int n) {
   c += (c < 0) ? n : 0;
@@ -40,6 +45,16 @@ __device__ __forceinline__ int wrap_any(int c, int n) {
 }
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// Electrons of a tile are stored transposed: with n electrons in (cell, id)
+// order L[0..n) and chunk = ceil(n / 256), thread t of the tile's workgroup
+// handles L[t chunk + it] for it = 0, 1, ..., and round `it` of the 256
+// threads reads consecutive slots.  round_count = threads active in round it.
+__device__ __forceinline__ int round_count(int n, int chunk, int it) {
+  if (it >= n) return 0;
+  const int c = (n - 1 - it) / chunk + 1;
+  return c < 256 ? c : 256;
+}
+
 // largest integer j with j^2 <= r2 (r = sqrt(r2) rounded)
 template <typename R>
 __device__ __forceinline__ int radial_index(R r2, R r) {
@@ -49,36 +64,104 @@ __device__ __forceinline__ int radial_index(R r2, R r) {
   return j;
 }
 
+// Relaxed hardware float atomics (no denormal-mode emulation).  The LDS and
+// the global forms use different scopes so that the compiler never merges a
+// workgroup-local and a device-memory update into one flat-address atomic.
 template <typename R>
-__device__ __forceinline__ void atomic_add(R *a, R v) {
-  unsafeAtomicAdd(a, v);
+__device__ __forceinline__ void atomic_add(R *a, R v) {  // device memory
+  [[clang::atomic(no_remote_memory, no_fine_grained_memory, ignore_denormal_mode)]] {
+    __hip_atomic_fetch_add(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+template <typename R>
+__device__ __forceinline__ void lds_add(R *a, R v) {  // LDS
+  [[clang::atomic(ignore_denormal_mode)]] {
+    __hip_atomic_fetch_add(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
 }
 
-// mirror sign of plane q at r_{-1/2}: (-1)^{m+1} for r/phi components,
-// (-1)^m for z components, m = (q+1)/2.
-__host__ __device__ constexpr int mode_of(int q) { return (q + 1) / 2; }
-__host__ __device__ constexpr int mirror_sign(int q, bool zcomp) {
-  return ((mode_of(q) % 2 == 0) == zcomp) ? 1 : -1;
+// ---- node records -----------------------------------------------------------
+// A record of NMP reals starts at a multiple of its own size from a 256-byte
+// aligned base, so it is 16-byte aligned when its size is a multiple of 16
+// (always for FP64; FP32 with M odd) and 8-byte aligned otherwise.
+template <typename R, int NMP>
+struct RecVec {
+  static constexpr int bytes = NMP * (int)sizeof(R);
+  static constexpr int vbytes = (bytes % 16 == 0) ? 16 : 8;
+  static constexpr int per = vbytes / (int)sizeof(R);  // reals per vector
+  static constexpr int nv = NMP / per;
+  using V = typename std::conditional<sizeof(R) == 8, double2,
+                                      typename std::conditional<vbytes == 16, float4, float2>::type>::type;
+};
+
+template <typename R, int NMP>
+__device__ __forceinline__ void load_rec(const R *__restrict__ p, R out[NMP]) {
+  using T = RecVec<R, NMP>;
+  const typename T::V *q = reinterpret_cast<const typename T::V *>(p);
+#pragma unroll
+  for (int a = 0; a < T::nv; ++a) {
+    const typename T::V x = q[a];
+    const R *xs = reinterpret_cast<const R *>(&x);
+#pragma unroll
+    for (int b = 0; b < T::per; ++b) out[a * T::per + b] = xs[b];
+  }
+}
+template <typename R, int NMP>
+__device__ __forceinline__ void store_rec(R *__restrict__ p, const R in[NMP]) {
+  using T = RecVec<R, NMP>;
+  typename T::V *q = reinterpret_cast<typename T::V *>(p);
+#pragma unroll
+  for (int a = 0; a < T::nv; ++a) {
+    typename T::V x;
+    R *xs = reinterpret_cast<R *>(&x);
+#pragma unroll
+    for (int b = 0; b < T::per; ++b) xs[b] = in[a * T::per + b];
+    q[a] = x;
+  }
 }
 
-// Bilinear interpolation of the NM planes of one component.
-template <typename R, int NM, bool HALF_R, bool ZCOMP>
-__device__ __forceinline__ void interp(const R *__restrict__ F, long long plane, int Nz, int ca, int cb,
-                                       int row0, bool mirror, R fz, R fr, R out[NM]) {
+// A node of one component from the mode planes (stride `plane`): record slot
+// s = 2m (Re), 2m+1 (Im); slot 1 (Im of m = 0) is not stored.
+template <typename R, int NMP>
+__device__ __forceinline__ void load_node(const R *__restrict__ F, long long plane, long long node, R out[NMP]) {
+  out[0] = F[node];
+  out[1] = R(0);
+#pragma unroll
+  for (int s = 2; s < NMP; ++s) out[s] = F[(s - 1) * plane + node];
+}
+template <typename R, int NMP>
+__device__ __forceinline__ void store_node(R *__restrict__ F, long long plane, long long node, const R in[NMP]) {
+  F[node] = in[0];
+#pragma unroll
+  for (int s = 2; s < NMP; ++s) F[(s - 1) * plane + node] = in[s];
+}
+
+// mirror sign of mode m at r_{-1/2}: (-1)^{m+1} for r and phi components,
+// (-1)^m for z components (the point (-r, phi) is (r, phi + pi)).
+__host__ __device__ constexpr int mirror_sign_m(int m, bool zcomp) { return ((m % 2 == 0) == zcomp) ? 1 : -1; }
+
+// Bilinear interpolation of one component's records (all modes).
+template <typename R, int NMP, bool HALF_R, bool ZCOMP>
+__device__ __forceinline__ void interp(const R *__restrict__ F, long long plane, int Nz, int ca, int cb, int row0,
+                                       bool mirror, R fz, R fr, R out[NMP]) {
   const R w00 = (R(1) - fz) * (R(1) - fr), w10 = fz * (R(1) - fr);
   const R w01 = (R(1) - fz) * fr, w11 = fz * fr;
   const long long o0 = (long long)(mirror ? 0 : row0) * Nz;
   const long long o1 = (long long)(row0 + 1) * Nz;
+  R a[NMP], b[NMP], c[NMP], d[NMP];
+  load_node<R, NMP>(F, plane, o0 + ca, a);
+  load_node<R, NMP>(F, plane, o0 + cb, b);
+  load_node<R, NMP>(F, plane, o1 + ca, c);
+  load_node<R, NMP>(F, plane, o1 + cb, d);
 #pragma unroll
-  for (int q = 0; q < NM; ++q) {
-    const R *P = F + q * plane;
-    R v00 = P[o0 + ca], v10 = P[o0 + cb];
+  for (int s = 0; s < NMP; ++s) {
+    R va = a[s], vb = b[s];
     if (HALF_R && mirror) {
-      const R s = (R)mirror_sign(q, ZCOMP);
-      v00 *= s;
-      v10 *= s;
+      const R sg = (R)mirror_sign_m(s / 2, ZCOMP);
+      va *= sg;
+      vb *= sg;
     }
-    out[q] = w00 * v00 + w10 * v10 + w01 * P[o1 + ca] + w11 * P[o1 + cb];
+    out[s] = w00 * va + w10 * vb + w01 * c[s] + w11 * d[s];
   }
 }
 
@@ -93,10 +176,14 @@ __device__ __forceinline__ void interp(const R *__restrict__ F, long long plane,
 // the last sort deposits straight to global memory.
 template <typename R, int M>
 __global__ __launch_bounds__(256) void push_kernel(KRun k, int par) {
-  constexpr int NM = 2 * M + 1;
+  constexpr int NM = 2 * M + 1;       // current planes in the LDS window
+  constexpr int NMP = 2 * (M + 1);    // reals per field record
   constexpr bool F64 = std::is_same<R, double>::value;
+  // the tile current is accumulated in FP64 for both precisions: the LDS
+  // double-precision atomic add is the fast one on gfx950, and the sum of
+  // thousands of FP32 contributions keeps its low bits until the flush
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  R *lds = (R *)lds_raw;
+  double *lds = (double *)lds_raw;
   const int tile = blockIdx.x;
   const int TZ = k.Tz, TR = k.Tr;
   const int WZ = TZ + 3, WR = TR + 3;
@@ -106,31 +193,29 @@ __global__ __launch_bounds__(256) void push_kernel(KRun k, int par) {
   const int beg = k.cell_start[tile * TT], end = k.cell_start[(tile + 1) * TT];
   if (beg >= end) return;
   const int nlds = 3 * NM * WZ * WR;
-  for (int e = threadIdx.x; e < nlds; e += blockDim.x) lds[e] = R(0);
+  for (int e = threadIdx.x; e < nlds; e += blockDim.x) lds[e] = 0.0;
   __syncthreads();
 
   const int Nz = k.Nz, Nr = k.Nr;
   const long long plane = k.plane;
-  const R dt = (R)k.dt, dz = (R)k.dz, dr = (R)k.dr;
+  const long long cstride = plane * NM;  // reals per component
+  const R dt = (R)k.dt;
   const R *E = (const R *)k.E;
   const R *Bb = (const R *)k.Bbar;
   R *J = (R *)k.J[par];
   R *X = (R *)k.px, *Y = (R *)k.py, *UX = (R *)k.pux, *UY = (R *)k.puy, *UZ = (R *)k.puz;
 
-  // add v to component c (0 r, 1 phi, 2 z), plane q, node (row, unwrapped column)
-  auto dep = [&](int c, int q, int row, int colu, R v) {
-    const int lc = colu - zlo, lr = row - rlo;
-    if ((unsigned)lc < (unsigned)WZ && (unsigned)lr < (unsigned)WR)
-      atomic_add(&lds[((c * NM + q) * WR + lr) * WZ + lc], v);
-    else
-      atomic_add(J + (long long)(c * NM + q) * plane + (long long)row * Nz + wrap_once(colu, Nz), v);
-  };
+  const int WRWZ = WR * WZ;
 
   const int n = end - beg;
-  const int chunk = (n + (int)blockDim.x - 1) / (int)blockDim.x;
-  const int my0 = beg + (int)threadIdx.x * chunk;
-  const int my1 = min(my0 + chunk, end);
-  for (int p = my0; p < my1; ++p) {
+  const int chunk = (n + 255) / 256;
+  const R dt_dz = (R)(k.dt / k.dz), dt_dr = (R)(k.dt / k.dr);
+  int base = 0;
+  for (int it = 0; it < chunk; ++it) {
+    const int cnt = round_count(n, chunk, it);
+    const int p = beg + base + (int)threadIdx.x;
+    base += cnt;
+    if ((int)threadIdx.x >= cnt) continue;
     const R q = -((const R *)k.pw)[p];
     const uint32_t pidw = k.pid[p];
 
@@ -152,8 +237,9 @@ __global__ __launch_bounds__(256) void push_kernel(KRun k, int par) {
     const int j0 = clampi(radial_index(r20, r0), 0, Nr - 2);
     R c0 = 1, s0 = 0;
     if (r0 > R(0)) {
-      c0 = x0 / r0;
-      s0 = y0 / r0;
+      const R ir = R(1) / r0;
+      c0 = x0 * ir;
+      s0 = y0 * ir;
     }
 
     // ---- gather E^n and Bbar^n = (B^{n-1/2} + B^{n+1/2})/2 (Eq. (12)) ----
@@ -183,13 +269,13 @@ __global__ __launch_bounds__(256) void push_kernel(KRun k, int par) {
     jh = clampi(jh, -1, Nr - 2);
     const bool mir = jh < 0;
 
-    R er[NM], ep[NM], ez[NM], br[NM], bp[NM], bz[NM];
-    interp<R, NM, true, false>(E + 0 * NM * plane, plane, Nz, ci0, ci1, jh, mir, f0, frh, er);
-    interp<R, NM, false, false>(E + 1 * NM * plane, plane, Nz, ci0, ci1, j0, false, f0, fr, ep);
-    interp<R, NM, false, true>(E + 2 * NM * plane, plane, Nz, ch0, ch1, j0, false, fh, fr, ez);
-    interp<R, NM, false, false>(Bb + 0 * NM * plane, plane, Nz, ch0, ch1, j0, false, fh, fr, br);
-    interp<R, NM, true, false>(Bb + 1 * NM * plane, plane, Nz, ch0, ch1, jh, mir, fh, frh, bp);
-    interp<R, NM, true, true>(Bb + 2 * NM * plane, plane, Nz, ci0, ci1, jh, mir, f0, frh, bz);
+    R er[NMP], ep[NMP], ez[NMP], br[NMP], bp[NMP], bz[NMP];
+    interp<R, NMP, true, false>(E + 0 * cstride, plane, Nz, ci0, ci1, jh, mir, f0, frh, er);
+    interp<R, NMP, false, false>(E + 1 * cstride, plane, Nz, ci0, ci1, j0, false, f0, fr, ep);
+    interp<R, NMP, false, true>(E + 2 * cstride, plane, Nz, ch0, ch1, j0, false, fh, fr, ez);
+    interp<R, NMP, false, false>(Bb + 0 * cstride, plane, Nz, ch0, ch1, j0, false, fh, fr, br);
+    interp<R, NMP, true, false>(Bb + 1 * cstride, plane, Nz, ch0, ch1, jh, mir, fh, frh, bp);
+    interp<R, NMP, true, true>(Bb + 2 * cstride, plane, Nz, ci0, ci1, jh, mir, f0, frh, bz);
 
     // ---- reconstruct Re sum_m F^m e^{i m phi}, rotate to Cartesian ----
     R Em[M + 1][3];
@@ -208,7 +294,7 @@ __global__ __launch_bounds__(256) void push_kernel(KRun k, int par) {
         const R nim = ere * s0 + eim * c0;
         ere = nre;
         eim = nim;
-        const int a = 2 * m - 1, b = 2 * m;
+        const int a = 2 * m, b = 2 * m + 1;
         const R Fr = er[a] * ere - er[b] * eim, Fp = ep[a] * ere - ep[b] * eim;
         Em[m][0] = Fr * c0 - Fp * s0;
         Em[m][1] = Fr * s0 + Fp * c0;
@@ -235,11 +321,13 @@ __global__ __launch_bounds__(256) void push_kernel(KRun k, int par) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) um[a] = u[a] - R(0.5) * dt * Ec[a];
     const R gm = sqrt(R(1) + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
+    const R hb = -R(0.5) * dt / gm;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) tt[a] = -R(0.5) * dt * Bc[a] / gm;
+    for (int a = 0; a < 3; ++a) tt[a] = hb * Bc[a];
     const R t2 = tt[0] * tt[0] + tt[1] * tt[1] + tt[2] * tt[2];
+    const R sf = R(2) / (R(1) + t2);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) ss[a] = R(2) * tt[a] / (R(1) + t2);
+    for (int a = 0; a < 3; ++a) ss[a] = sf * tt[a];
     u1[0] = um[0] + (um[1] * tt[2] - um[2] * tt[1]);
     u1[1] = um[1] + (um[2] * tt[0] - um[0] * tt[2]);
     u1[2] = um[2] + (um[0] * tt[1] - um[1] * tt[0]);
@@ -249,6 +337,7 @@ __global__ __launch_bounds__(256) void push_kernel(KRun k, int par) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) un[a] = up[a] - R(0.5) * dt * Ec[a];
     const R g_new = sqrt(R(1) + un[0] * un[0] + un[1] * un[1] + un[2] * un[2]);
+    const R inv_g = R(1) / g_new;
 
     // ---- per-mode work of tracked electrons (FP64), Eq. (16) ----
     if (pidw & kTrackedBit) {
@@ -277,12 +366,12 @@ __global__ __launch_bounds__(256) void push_kernel(KRun k, int par) {
     R f1;
     R z1 = 0;
     if constexpr (F64) {
-      z1 = z0 + dt * un[2] / g_new / dz;
+      z1 = z0 + un[2] * inv_g * dt_dz;
       const R fl = floor(z1);
       i1 = (int)fl;
       f1 = z1 - fl;
     } else {
-      f1 = f0 + dt * un[2] / g_new / dz;
+      f1 = f0 + un[2] * inv_g * dt_dz;
       i1 = i0;
       if (f1 >= R(1)) {
         f1 -= R(1);
@@ -296,8 +385,8 @@ __global__ __launch_bounds__(256) void push_kernel(KRun k, int par) {
         }
       }
     }
-    R x1 = x0 + dt * un[0] / g_new / dr;
-    R y1 = y0 + dt * un[1] / g_new / dr;
+    R x1 = x0 + un[0] * inv_g * dt_dr;
+    R y1 = y0 + un[1] * inv_g * dt_dr;
     const R Rw = (R)(Nr - 1);
     R r21 = fma(x1, x1, y1 * y1), r1 = sqrt(r21);
     if (r1 >= Rw) {  // specular reflection at r = (Nr - 1) dr
@@ -322,8 +411,9 @@ __global__ __launch_bounds__(256) void push_kernel(KRun k, int par) {
     j1 = clampi(j1, 0, Nr - 2);
     R c1 = 1, s1 = 0;
     if (r1 > R(0)) {
-      c1 = x1 / r1;
-      s1 = y1 / r1;
+      const R ir = R(1) / r1;
+      c1 = x1 * ir;
+      s1 = y1 * ir;
     }
     const R g1 = r1 - (R)j1;
 
@@ -333,9 +423,10 @@ __global__ __launch_bounds__(256) void push_kernel(KRun k, int par) {
       const R rm = sqrt(xm * xm + ym * ym);
       R cmid = 1, smid = 0, vphi = 0;
       if (rm > R(0)) {
-        cmid = xm / rm;
-        smid = ym / rm;
-        vphi = (cmid * un[1] - smid * un[0]) / g_new;
+        const R ir = R(1) / rm;
+        cmid = xm * ir;
+        smid = ym * ir;
+        vphi = (cmid * un[1] - smid * un[0]) * inv_g;
       }
       const int di = clampi(i1 - i0, -1, 1);
       const int oz0 = di < 0 ? 1 : 0, oz1 = oz0 + di;  // cells of the two positions in the 3-node window
@@ -343,6 +434,19 @@ __global__ __launch_bounds__(256) void push_kernel(KRun k, int par) {
       const int dj = j1 - j0;
       const int or0 = dj < 0 ? 1 : 0, or1 = or0 + dj;
       const int jb = j0 - or0;
+      // the 3 x 3 node window [ib, ib+2] x [jb, jb+2] inside the tile's LDS window?
+      const bool inwin = (ib - zlo >= 0) && (ib + 2 - zlo < WZ) && (jb - rlo >= 0) && (jb + 2 - rlo < WR);
+      double *lwin = lds + (jb - rlo) * WZ + (ib - zlo);
+      int col[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) col[a] = wrap_once(ib + a, Nz);
+      // add v to component c (0 r, 1 phi, 2 z), plane qq, window node (a, b)
+      auto dep = [&](int c, int qq, int b, int a, R v) {
+        if (inwin)
+          lds_add(lwin + (c * NM + qq) * WRWZ + b * WZ + a, (double)v);
+        else
+          atomic_add(J + (c * NM + qq) * plane + (long long)(jb + b) * Nz + col[a], v);
+      };
       R Sz0[3], Sz1[3], Sr0[3], Sr1[3];
       const R g0 = fr;
 #pragma unroll
@@ -389,8 +493,8 @@ __global__ __launch_bounds__(256) void push_kernel(KRun k, int par) {
           for (int a = 0; a < 2; ++a) {
             run += Wz[a][b];
             const R v = -cq * run;
-            dep(2, qa, jb + b, ib + a, v * xr);
-            if (m > 0) dep(2, qb, jb + b, ib + a, v * xi);
+            dep(2, qa, b, a, v * xr);
+            if (m > 0) dep(2, qb, b, a, v * xi);
           }
         }
         // J_r at (ib+a, jb+b+1/2)
@@ -401,8 +505,8 @@ __global__ __launch_bounds__(256) void push_kernel(KRun k, int par) {
           for (int b = 0; b < 2; ++b) {
             run += Wr[a][b];
             const R v = -cq * run;
-            dep(0, qa, jb + b, ib + a, v * xr);
-            if (m > 0) dep(0, qb, jb + b, ib + a, v * xi);
+            dep(0, qa, b, a, v * xr);
+            if (m > 0) dep(0, qb, b, a, v * xi);
           }
         }
         // J_phi at (ib+a, jb+b)
@@ -414,14 +518,14 @@ __global__ __launch_bounds__(256) void push_kernel(KRun k, int par) {
             const int j = jb + b;
             const R h = R(0.5) * cq * Ss[a][b];
             if (m == 0) {
-              dep(1, 0, j, ib + a, h * vphi);
+              dep(1, 0, b, a, h * vphi);
             } else if (m == 1 && j == 0) {
-              dep(1, qa, j, ib + a, h * vphi * emr);
-              dep(1, qb, j, ib + a, h * vphi * emi);
+              dep(1, qa, b, a, h * vphi * emr);
+              dep(1, qb, b, a, h * vphi * emi);
             } else if (j > 0) {  // the closure carries r_j: nothing on the axis
               // (i/m)(e1 - e0) = (-(e1-e0).im, (e1-e0).re) / m
-              dep(1, qa, j, ib + a, -h * dim_ / (R)m);
-              dep(1, qb, j, ib + a, h * dre / (R)m);
+              dep(1, qa, b, a, -h * dim_ * (R(1) / (R)m));
+              dep(1, qb, b, a, h * dre * (R(1) / (R)m));
             }
           }
       }
@@ -446,57 +550,65 @@ __global__ __launch_bounds__(256) void push_kernel(KRun k, int par) {
   // ---- flush the tile's current ----
   __syncthreads();
   for (int e = threadIdx.x; e < nlds; e += blockDim.x) {
-    const R v = lds[e];
+    const R v = (R)lds[e];
     if (v == R(0)) continue;
     const int lc = e % WZ;
     const int rest = e / WZ;
     const int lr = rest % WR;
     const int cq = rest / WR;  // c * NM + q
+    const int c = cq / NM, q = cq % NM;
     const int row = rlo + lr;
     if (row < 0 || row > Nr) continue;
-    atomic_add(J + (long long)cq * plane + (long long)row * Nz + wrap_once(zlo + lc, Nz), v);
+    atomic_add(J + (c * NM + q) * plane + (long long)row * Nz + wrap_once(zlo + lc, Nz), v);
   }
 }
 
 // ---------------------------------------------------------------------------
-// field update
+// field update.  One workgroup = kFieldTile consecutive columns of one row j;
+// the rows whose z differences or z filter need neighbours (+-N columns) are
+// first staged in LDS with coalesced record loads, every other operand is a
+// record of the thread's own column.
 
+// complex (re, im) helpers on records
 template <typename R>
-__device__ __forceinline__ R DB(const R *__restrict__ g, const R *__restrict__ CB, int N, int Nz, int i) {
-  // sum_l C^B_l (g_{i+l-1/2} - g_{i-l+1/2}), g_{k+1/2} stored at column k
-  R s = 0;
-  for (int l = 1; l <= N; ++l) s += CB[l - 1] * (g[wrap_once(i + l - 1, Nz)] - g[wrap_once(i - l, Nz)]);
-  return s;
-}
-template <typename R>
-__device__ __forceinline__ R DE(const R *__restrict__ f, const R *__restrict__ CE, int N, int Nz, int i) {
-  // sum_l C^E_l (f_{i+l} - f_{i-l+1}), evaluated at z_{i+1/2}
-  R s = 0;
-  for (int l = 1; l <= N; ++l) s += CE[l - 1] * (f[wrap_once(i + l, Nz)] - f[wrap_once(i - l + 1, Nz)]);
-  return s;
-}
-template <typename R>
-__device__ __forceinline__ R Pf(const R *__restrict__ f, const R *__restrict__ P, int N, int Nz, int i) {
-  R s = 0;
-  for (int l = -(N - 1); l <= N - 1; ++l) s += P[l + N - 1] * f[wrap_once(i + l, Nz)];
-  return s;
-}
+struct Cx {
+  R re, im;
+};
 
 template <typename R, int M>
-__global__ __launch_bounds__(256) void efield_kernel(KRun k, int par) {
-  constexpr int NM = 2 * M + 1;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y;
-  if (i >= k.Nz) return;
+__global__ __launch_bounds__(kFieldTile) void efield_kernel(KRun k, int par) {
+  constexpr int NMP = 2 * (M + 1);
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  R *lds = (R *)lds_raw;
   const int Nz = k.Nz, Nr = k.Nr, N = k.N;
-  const long long plane = k.plane;
-  const R dt = (R)k.dt, dr = (R)k.dr;
-  const R *CB = (const R *)k.CB, *P = (const R *)k.P;
-  R *E = (R *)k.E;
-  const R *B = (const R *)k.B[par ^ 1];
+  const int j = blockIdx.y;
+  const int i0 = blockIdx.x * kFieldTile;
+  const int t = threadIdx.x;
+  const int W = kFieldTile + 2 * N;  // staged columns i0-N .. i0+kFieldTile+N-1
+  const long long plane = k.plane, cstride = plane * (NMP - 1);  // NM planes per component
+  const long long row = (long long)j * Nz;
+  const R *B = (const R *)k.B[par ^ 1];  // B^{n+1/2}
   const R *Jc = (const R *)k.J[par];
   R *Jn = (R *)k.J[par ^ 1];
-  const long long row = (long long)j * Nz, rowm = (long long)(j - 1) * Nz;
+  R *E = (R *)k.E;
+  R *sBp = lds, *sBr = lds + W * NMP, *sJr = lds + 2 * W * NMP, *sJp = lds + 3 * W * NMP;
+  for (int r = t; r < W; r += kFieldTile) {
+    const int col = wrap_any(i0 - N + r, Nz);
+    R v[NMP];
+    load_node<R, NMP>(B + 1 * cstride, plane, row + col, v);  // B_phi (half row j)
+    store_rec<R, NMP>(sBp + r * NMP, v);
+    load_node<R, NMP>(B + 0 * cstride, plane, row + col, v);  // B_r
+    store_rec<R, NMP>(sBr + r * NMP, v);
+    load_node<R, NMP>(Jc + 0 * cstride, plane, row + col, v);  // J_r
+    store_rec<R, NMP>(sJr + r * NMP, v);
+    load_node<R, NMP>(Jc + 1 * cstride, plane, row + col, v);  // J_phi
+    store_rec<R, NMP>(sJp + r * NMP, v);
+  }
+  __syncthreads();
+  const int i = i0 + t;
+  if (i >= Nz) return;
+  const R dt = (R)k.dt, dr = (R)k.dr, idz = (R)(1.0 / k.dz);
+  const R *CB = (const R *)k.CB, *P = (const R *)k.P;
   // physical current = raw deposit * factor of the row
   const double dzd = k.dz, drd = k.dr, dtd = k.dt;
   const double Vj = j == 0 ? kPi * drd * drd * dzd / 4.0 : 2.0 * kPi * (j * drd) * drd * dzd;
@@ -505,162 +617,217 @@ __global__ __launch_bounds__(256) void efield_kernel(KRun k, int par) {
   const R fp_direct = (R)(1.0 / Vj);
   const R fp_closure = (R)(1.0 / (dtd * 2.0 * kPi * drd * dzd));
   const R rh = ((R)j + R(0.5)) * dr;
+  const int c0 = t + N;  // LDS index of column i
 
+  // z operators on the staged rows, all modes at once
+  R dbp[NMP], dbr[NMP], pjr[NMP], pjp[NMP];
 #pragma unroll
-  for (int m = 0; m <= M; ++m) {
-    const int qa = m == 0 ? 0 : 2 * m - 1, qb = 2 * m;
-    const int nq = m == 0 ? 1 : 2;
-    const R mm = (R)m;
-    // (re, im) of the quantities needed, for both planes of the mode
-    R Er_new[2], Ep_new[2], Ez_new[2];
+  for (int s = 0; s < NMP; ++s) dbp[s] = dbr[s] = pjr[s] = pjp[s] = R(0);
+  for (int l = 1; l <= N; ++l) {  // D_B: sum_l C^B_l (g_{i+l-1/2} - g_{i-l+1/2})
+    const R cb = CB[l - 1];
+    const R *ap = sBp + (c0 + l - 1) * NMP, *am = sBp + (c0 - l) * NMP;
+    const R *bp_ = sBr + (c0 + l - 1) * NMP, *bm = sBr + (c0 - l) * NMP;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) { Er_new[h] = 0; Ep_new[h] = 0; Ez_new[h] = 0; }
-    // E_r at (i, j+1/2)
-    if (j < Nr) {
-      R bzr = B[(2 * NM + qa) * plane + row + i], bzi = (m > 0) ? B[(2 * NM + qb) * plane + row + i] : R(0);
-      // (i m / r) B_z = (-m Bz_im, m Bz_re) / r
-      R cr[2] = {-mm * bzi / rh, mm * bzr / rh};
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        if (h >= nq) break;
-        const int qq = h == 0 ? qa : qb;
-        cr[h] -= DB(B + (1 * NM + qq) * plane + row, CB, N, Nz, i) / (R)k.dz;
-        const R jr = Pf(Jc + (0 * NM + qq) * plane + row, P, N, Nz, i) * frr;
-        Er_new[h] = E[(0 * NM + qq) * plane + row + i] + dt * (cr[h] - jr);
-      }
-    }
-    // E_phi at (i, j)
-    const bool phi_zero = (j == Nr) || (j == 0 && m != 1);
-    if (!phi_zero) {
-      const R fpf = (m == 0 || j == 0) ? fp_direct : fp_closure;
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        if (h >= nq) break;
-        const int qq = h == 0 ? qa : qb;
-        R cp = DB(B + (0 * NM + qq) * plane + row, CB, N, Nz, i) / (R)k.dz;
-        if (j == 0) cp -= R(2) * B[(2 * NM + qq) * plane + row + i] / dr;
-        else cp -= (B[(2 * NM + qq) * plane + row + i] - B[(2 * NM + qq) * plane + rowm + i]) / dr;
-        const R jp = Pf(Jc + (1 * NM + qq) * plane + row, P, N, Nz, i) * fpf;
-        Ep_new[h] = E[(1 * NM + qq) * plane + row + i] + dt * (cp - jp);
-      }
-    }
-    // E_z at (i+1/2, j)
-    const bool z_zero = (j == Nr) || (j == 0 && m != 0);
-    if (!z_zero) {
-      if (j == 0) {
-        const R cz = R(4) * B[(1 * NM + qa) * plane + row + i] / dr;
-        Ez_new[0] = E[(2 * NM + qa) * plane + row + i] + dt * (cz - Jc[(2 * NM + qa) * plane + row + i] * fz);
-      } else {
-        const R rj = (R)j * dr;
-        R brr = B[(0 * NM + qa) * plane + row + i], bri = (m > 0) ? B[(0 * NM + qb) * plane + row + i] : R(0);
-        R imb[2] = {-mm * bri / rj, mm * brr / rj};  // (i m / r) B_r
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          if (h >= nq) break;
-          const int qq = h == 0 ? qa : qb;
-          const R cz = (((R)j + R(0.5)) * B[(1 * NM + qq) * plane + row + i] -
-                        ((R)j - R(0.5)) * B[(1 * NM + qq) * plane + rowm + i]) / rj - imb[h];
-          Ez_new[h] = E[(2 * NM + qq) * plane + row + i] + dt * (cz - Jc[(2 * NM + qq) * plane + row + i] * fz);
-        }
-      }
-    }
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      if (h >= nq) break;
-      const int qq = h == 0 ? qa : qb;
-      E[(0 * NM + qq) * plane + row + i] = Er_new[h];
-      E[(1 * NM + qq) * plane + row + i] = Ep_new[h];
-      E[(2 * NM + qq) * plane + row + i] = Ez_new[h];
+    for (int s = 0; s < NMP; ++s) {
+      dbp[s] += cb * (ap[s] - am[s]);
+      dbr[s] += cb * (bp_[s] - bm[s]);
     }
   }
-  // clear the other current buffer for the next deposit
+  {
+    const R p0 = P[N - 1];
 #pragma unroll
-  for (int c = 0; c < 3 * NM; ++c) Jn[c * plane + row + i] = R(0);
+    for (int s = 0; s < NMP; ++s) {
+      pjr[s] = p0 * sJr[c0 * NMP + s];
+      pjp[s] = p0 * sJp[c0 * NMP + s];
+    }
+  }
+  for (int l = 1; l < N; ++l) {  // symmetric filter P
+    const R pl = P[N - 1 + l];
+    const R *a1 = sJr + (c0 + l) * NMP, *a2 = sJr + (c0 - l) * NMP;
+    const R *b1 = sJp + (c0 + l) * NMP, *b2 = sJp + (c0 - l) * NMP;
+#pragma unroll
+    for (int s = 0; s < NMP; ++s) {
+      pjr[s] += pl * (a1[s] + a2[s]);
+      pjp[s] += pl * (b1[s] + b2[s]);
+    }
+  }
+
+  R er[NMP], ep[NMP], ez[NMP], bz[NMP], bzm[NMP], bpm[NMP], jz[NMP];
+  load_node<R, NMP>(E + 0 * cstride, plane, row + i, er);
+  load_node<R, NMP>(E + 1 * cstride, plane, row + i, ep);
+  load_node<R, NMP>(E + 2 * cstride, plane, row + i, ez);
+  load_node<R, NMP>(B + 2 * cstride, plane, row + i, bz);
+  load_node<R, NMP>(Jc + 2 * cstride, plane, row + i, jz);
+  if (j > 0) {
+    load_node<R, NMP>(B + 2 * cstride, plane, row - Nz + i, bzm);
+    load_node<R, NMP>(B + 1 * cstride, plane, row - Nz + i, bpm);
+  } else {
+#pragma unroll
+    for (int s = 0; s < NMP; ++s) bzm[s] = bpm[s] = R(0);
+  }
+  const R *bpc = sBp + c0 * NMP, *brc = sBr + c0 * NMP;
+#pragma unroll
+  for (int m = 0; m <= M; ++m) {
+    const int a = 2 * m, b = 2 * m + 1;
+    const R mm = (R)m;
+    // E_r at (i, j+1/2): (i m / r) B_z - D_B B_phi - P J_r
+    if (j < Nr) {
+      const R cre = -mm * bz[b] / rh - dbp[a] * idz, cim = mm * bz[a] / rh - dbp[b] * idz;
+      er[a] += dt * (cre - pjr[a] * frr);
+      er[b] += dt * (cim - pjr[b] * frr);
+    } else {
+      er[a] = er[b] = R(0);
+    }
+    // E_phi at (i, j): D_B B_r - dB_z/dr - P J_phi
+    if (j == Nr || (j == 0 && m != 1)) {
+      ep[a] = ep[b] = R(0);
+    } else {
+      const R fpf = (m == 0 || j == 0) ? fp_direct : fp_closure;
+      R dre, dim_;
+      if (j == 0) {
+        dre = R(2) * bz[a] / dr;
+        dim_ = R(2) * bz[b] / dr;
+      } else {
+        dre = (bz[a] - bzm[a]) / dr;
+        dim_ = (bz[b] - bzm[b]) / dr;
+      }
+      ep[a] += dt * (dbr[a] * idz - dre - pjp[a] * fpf);
+      ep[b] += dt * (dbr[b] * idz - dim_ - pjp[b] * fpf);
+    }
+    // E_z at (i+1/2, j): (1/r) d(r B_phi)/dr - (i m / r) B_r - J_z
+    if (j == Nr || (j == 0 && m != 0)) {
+      ez[a] = ez[b] = R(0);
+    } else if (j == 0) {
+      ez[a] += dt * (R(4) * bpc[a] / dr - jz[a] * fz);
+      ez[b] += dt * (R(4) * bpc[b] / dr - jz[b] * fz);
+    } else {
+      const R rj = (R)j * dr;
+      const R jp5 = (R)j + R(0.5), jm5 = (R)j - R(0.5);
+      const R cre = (jp5 * bpc[a] - jm5 * bpm[a]) / rj + mm * brc[b] / rj;
+      const R cim = (jp5 * bpc[b] - jm5 * bpm[b]) / rj - mm * brc[a] / rj;
+      ez[a] += dt * (cre - jz[a] * fz);
+      ez[b] += dt * (cim - jz[b] * fz);
+    }
+  }
+  store_node<R, NMP>(E + 0 * cstride, plane, row + i, er);
+  store_node<R, NMP>(E + 1 * cstride, plane, row + i, ep);
+  store_node<R, NMP>(E + 2 * cstride, plane, row + i, ez);
+  // clear the other current buffer for the next deposit
+  R zero[NMP];
+#pragma unroll
+  for (int s = 0; s < NMP; ++s) zero[s] = R(0);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) store_node<R, NMP>(Jn + c * cstride, plane, row + i, zero);
 }
 
 // Bout = Bin - tau curl_E E; with avg != nullptr also avg = (Bin + Bout)/2,
-// the time-centred B that the next gather uses (Eq. (12)).
+// the time-centred B that the next gather uses (Eq. (12)).  Bout may be Bin.
 template <typename R, int M>
-__global__ __launch_bounds__(256) void bfield_kernel(KRun k, R *Bout, const R *Bin, R tau, R *avg) {
-  constexpr int NM = 2 * M + 1;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y;
-  if (i >= k.Nz) return;
+__global__ __launch_bounds__(kFieldTile) void bfield_kernel(KRun k, R *Bout, const R *Bin, R tau, R *avg) {
+  constexpr int NMP = 2 * (M + 1);
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  R *lds = (R *)lds_raw;
   const int Nz = k.Nz, Nr = k.Nr, N = k.N;
-  const long long plane = k.plane;
-  const R dr = (R)k.dr, dz = (R)k.dz;
-  const R *CE = (const R *)k.CE;
+  const int j = blockIdx.y;
+  const int i0 = blockIdx.x * kFieldTile;
+  const int t = threadIdx.x;
+  const int W = kFieldTile + 2 * N;  // staged columns i0-N+1 .. i0+kFieldTile+N
+  const long long plane = k.plane, cstride = plane * (NMP - 1);  // NM planes per component
+  const long long row = (long long)j * Nz;
   const R *E = (const R *)k.E;
-  const long long row = (long long)j * Nz, rowp = (long long)(j + 1) * Nz;
-  const int ip = wrap_once(i + 1, Nz);
-  (void)ip;
+  R *sEp = lds, *sEr = lds + W * NMP;
+  for (int r = t; r < W; r += kFieldTile) {
+    const int col = wrap_any(i0 - N + 1 + r, Nz);
+    R v[NMP];
+    load_node<R, NMP>(E + 1 * cstride, plane, row + col, v);  // E_phi row j
+    store_rec<R, NMP>(sEp + r * NMP, v);
+    load_node<R, NMP>(E + 0 * cstride, plane, row + col, v);  // E_r (half row j; zero on row Nr)
+    store_rec<R, NMP>(sEr + r * NMP, v);
+  }
+  __syncthreads();
+  const int i = i0 + t;
+  if (i >= Nz) return;
+  const R dr = (R)k.dr, idz = (R)(1.0 / k.dz);
+  const R *CE = (const R *)k.CE;
+  const int c0 = t + N - 1;  // LDS index of column i
+  R dep_[NMP], der[NMP];
 #pragma unroll
-  for (int m = 0; m <= M; ++m) {
-    const int qa = m == 0 ? 0 : 2 * m - 1, qb = 2 * m;
-    const int nq = m == 0 ? 1 : 2;
-    const R mm = (R)m;
-    R nbr[2] = {0, 0}, nbp[2] = {0, 0}, nbz[2] = {0, 0};
-    // B_r at (i+1/2, j)
-    const bool br_zero = (j == 0 && m != 1);
-    if (!br_zero) {
-      R curl[2];
-      if (j == 0) {  // m = 1: (i m/r) E_z -> i E_z(r_1)/dr
-        const R ezr = E[(2 * NM + qa) * plane + rowp + i], ezi = E[(2 * NM + qb) * plane + rowp + i];
-        curl[0] = -ezi / dr;
-        curl[1] = ezr / dr;
-      } else {
-        const R rj = (R)j * dr;
-        const R ezr = E[(2 * NM + qa) * plane + row + i], ezi = (m > 0) ? E[(2 * NM + qb) * plane + row + i] : R(0);
-        curl[0] = -mm * ezi / rj;
-        curl[1] = mm * ezr / rj;
-      }
+  for (int s = 0; s < NMP; ++s) dep_[s] = der[s] = R(0);
+  for (int l = 1; l <= N; ++l) {  // D_E: sum_l C^E_l (f_{i+l} - f_{i-l+1}), at z_{i+1/2}
+    const R ce = CE[l - 1];
+    const R *a1 = sEp + (c0 + l) * NMP, *a2 = sEp + (c0 - l + 1) * NMP;
+    const R *b1 = sEr + (c0 + l) * NMP, *b2 = sEr + (c0 - l + 1) * NMP;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        if (h >= nq) break;
-        const int qq = h == 0 ? qa : qb;
-        const R c = curl[h] - DE(E + (1 * NM + qq) * plane + row, CE, N, Nz, i) / dz;
-        nbr[h] = Bin[(0 * NM + qq) * plane + row + i] - tau * c;
-      }
-    }
-    if (j < Nr) {
-      const R rh = ((R)j + R(0.5)) * dr;
-      // B_phi at (i+1/2, j+1/2)
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        if (h >= nq) break;
-        const int qq = h == 0 ? qa : qb;
-        const R c = DE(E + (0 * NM + qq) * plane + row, CE, N, Nz, i) / dz -
-                    (E[(2 * NM + qq) * plane + rowp + i] - E[(2 * NM + qq) * plane + row + i]) / dr;
-        nbp[h] = Bin[(1 * NM + qq) * plane + row + i] - tau * c;
-      }
-      // B_z at (i, j+1/2)
-      const R err = E[(0 * NM + qa) * plane + row + i], eri = (m > 0) ? E[(0 * NM + qb) * plane + row + i] : R(0);
-      const R ime[2] = {-mm * eri / rh, mm * err / rh};  // (i m / r) E_r
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        if (h >= nq) break;
-        const int qq = h == 0 ? qa : qb;
-        const R c = (((R)(j + 1) * dr) * E[(1 * NM + qq) * plane + rowp + i] -
-                     ((R)j * dr) * E[(1 * NM + qq) * plane + row + i]) / (rh * dr) - ime[h];
-        nbz[h] = Bin[(2 * NM + qq) * plane + row + i] - tau * c;
-      }
-    }
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      if (h >= nq) break;
-      const int qq = h == 0 ? qa : qb;
-      const long long o0 = (0 * NM + qq) * plane + row + i, o1 = (1 * NM + qq) * plane + row + i,
-                      o2 = (2 * NM + qq) * plane + row + i;
-      if (avg) {
-        avg[o0] = R(0.5) * (Bin[o0] + nbr[h]);
-        avg[o1] = R(0.5) * (Bin[o1] + nbp[h]);
-        avg[o2] = R(0.5) * (Bin[o2] + nbz[h]);
-      }
-      Bout[o0] = nbr[h];
-      Bout[o1] = nbp[h];
-      Bout[o2] = nbz[h];
+    for (int s = 0; s < NMP; ++s) {
+      dep_[s] += ce * (a1[s] - a2[s]);
+      der[s] += ce * (b1[s] - b2[s]);
     }
   }
+  R bin_r[NMP], bin_p[NMP], bin_z[NMP], ez[NMP], ezp[NMP], epp[NMP];
+  load_node<R, NMP>(Bin + 0 * cstride, plane, row + i, bin_r);
+  load_node<R, NMP>(Bin + 1 * cstride, plane, row + i, bin_p);
+  load_node<R, NMP>(Bin + 2 * cstride, plane, row + i, bin_z);
+  load_node<R, NMP>(E + 2 * cstride, plane, row + i, ez);
+  const bool up = j < Nr;
+  if (up) {
+    load_node<R, NMP>(E + 2 * cstride, plane, row + Nz + i, ezp);
+    load_node<R, NMP>(E + 1 * cstride, plane, row + Nz + i, epp);
+  } else {
+#pragma unroll
+    for (int s = 0; s < NMP; ++s) ezp[s] = epp[s] = R(0);
+  }
+  const R *epc = sEp + c0 * NMP, *erc = sEr + c0 * NMP;
+  R nbr[NMP], nbp[NMP], nbz[NMP];
+#pragma unroll
+  for (int m = 0; m <= M; ++m) {
+    const int a = 2 * m, b = 2 * m + 1;
+    const R mm = (R)m;
+    // B_r at (i+1/2, j): (i m / r) E_z - D_E E_phi; on the axis only m = 1 (E_z^1 ~ r)
+    if (j == 0 && m != 1) {
+      nbr[a] = nbr[b] = R(0);
+    } else {
+      R cre, cim;
+      if (j == 0) {  // i E_z(r_1) / dr
+        cre = -ezp[b] / dr;
+        cim = ezp[a] / dr;
+      } else {
+        const R rj = (R)j * dr;
+        cre = -mm * ez[b] / rj;
+        cim = mm * ez[a] / rj;
+      }
+      nbr[a] = bin_r[a] - tau * (cre - dep_[a] * idz);
+      nbr[b] = bin_r[b] - tau * (cim - dep_[b] * idz);
+    }
+    if (up) {
+      const R rh = ((R)j + R(0.5)) * dr;
+      // B_phi at (i+1/2, j+1/2): D_E E_r - dE_z/dr
+      nbp[a] = bin_p[a] - tau * (der[a] * idz - (ezp[a] - ez[a]) / dr);
+      nbp[b] = bin_p[b] - tau * (der[b] * idz - (ezp[b] - ez[b]) / dr);
+      // B_z at (i, j+1/2): (1/r) d(r E_phi)/dr - (i m / r) E_r
+      const R rj1 = (R)(j + 1) * dr, rj = (R)j * dr;
+      const R cre = (rj1 * epp[a] - rj * epc[a]) / (rh * dr) + mm * erc[b] / rh;
+      const R cim = (rj1 * epp[b] - rj * epc[b]) / (rh * dr) - mm * erc[a] / rh;
+      nbz[a] = bin_z[a] - tau * cre;
+      nbz[b] = bin_z[b] - tau * cim;
+    } else {
+      nbp[a] = nbp[b] = nbz[a] = nbz[b] = R(0);
+    }
+  }
+  if (avg) {
+    R v[NMP];
+#pragma unroll
+    for (int s = 0; s < NMP; ++s) v[s] = R(0.5) * (bin_r[s] + nbr[s]);
+    store_node<R, NMP>(avg + 0 * cstride, plane, row + i, v);
+#pragma unroll
+    for (int s = 0; s < NMP; ++s) v[s] = R(0.5) * (bin_p[s] + nbp[s]);
+    store_node<R, NMP>(avg + 1 * cstride, plane, row + i, v);
+#pragma unroll
+    for (int s = 0; s < NMP; ++s) v[s] = R(0.5) * (bin_z[s] + nbz[s]);
+    store_node<R, NMP>(avg + 2 * cstride, plane, row + i, v);
+  }
+  store_node<R, NMP>(Bout + 0 * cstride, plane, row + i, nbr);
+  store_node<R, NMP>(Bout + 1 * cstride, plane, row + i, nbp);
+  store_node<R, NMP>(Bout + 2 * cstride, plane, row + i, nbz);
 }
 
 // ---------------------------------------------------------------------------
@@ -673,10 +840,9 @@ __global__ void zero_kernel(uint4 *p, size_t n16, unsigned char *tail, size_t nt
   if (t < ntail) tail[t] = 0;
 }
 
-// charge density of the electrons (diagnostic), physical units
+// charge density of the electrons (diagnostic), FP64 records, physical units
 template <typename R, int M>
 __global__ __launch_bounds__(256) void rho_kernel(KRun k) {
-  constexpr int NM = 2 * M + 1;
   constexpr bool F64 = std::is_same<R, double>::value;
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= k.np) return;
@@ -698,7 +864,10 @@ __global__ __launch_bounds__(256) void rho_kernel(KRun k) {
   const int j0 = clampi(radial_index(r2, r), 0, Nr - 1);
   const R fr = r - (R)j0;
   R c = 1, s = 0;
-  if (r > R(0)) { c = x / r; s = y / r; }
+  if (r > R(0)) {
+    c = x / r;
+    s = y / r;
+  }
   const double q = -(double)((const R *)k.pw)[p];
   double *rho = (double *)k.rho;
   const double dzd = k.dz, drd = k.dr;
@@ -716,13 +885,12 @@ __global__ __launch_bounds__(256) void rho_kernel(KRun k) {
         if (m > 0 && j == 0) continue;  // the m >= 1 density vanishes on the axis
         const double V = j == 0 ? kPi * drd * drd * dzd / 4.0 : 2.0 * kPi * (j * drd) * drd * dzd;
         const double S = (a ? (double)f0 : 1.0 - (double)f0) * (b ? (double)fr : 1.0 - (double)fr);
-        const long long o = (long long)j * Nz + wrap_once(i0 + a, Nz);
+        const long long node = (long long)j * Nz + wrap_once(i0 + a, Nz);
         const int qa = m == 0 ? 0 : 2 * m - 1;
-        atomic_add(rho + qa * k.plane + o, cm * q * er * S / V);
-        if (m > 0) atomic_add(rho + (2 * m) * k.plane + o, cm * q * ei * S / V);
+        atomic_add(rho + qa * k.plane + node, cm * q * er * S / V);
+        if (m > 0) atomic_add(rho + (qa + 1) * k.plane + node, cm * q * ei * S / V);
       }
   }
-  (void)NM;
 }
 
 // field energy per mode: per-block partial sums red[block * (M+1) + m]
@@ -730,11 +898,11 @@ template <typename R, int M>
 __global__ __launch_bounds__(256) void energy_kernel(KRun k, int par) {
   constexpr int NM = 2 * M + 1;
   __shared__ double sh[256 * (M + 1)];
-  const long long n = k.plane;
+  const long long n = k.plane, cs = n * NM;
   const int tid = threadIdx.x;
   double acc[M + 1];
   for (int m = 0; m <= M; ++m) acc[m] = 0.0;
-  const R *E = (const R *)k.E, *B0 = (const R *)k.B[par], *B1 = (const R *)k.B[par ^ 1];
+  const R *E = (const R *)k.E, *Bb = (const R *)k.Bbar;
   const double dzd = k.dz, drd = k.dr;
   for (long long idx = (long long)blockIdx.x * blockDim.x + tid; idx < n; idx += (long long)gridDim.x * blockDim.x) {
     const int j = (int)(idx / k.Nz);
@@ -742,14 +910,14 @@ __global__ __launch_bounds__(256) void energy_kernel(KRun k, int par) {
     const double vh = j < k.Nr ? 2.0 * kPi * ((j + 0.5) * drd) * drd * dzd : 0.0;
     for (int q = 0; q < NM; ++q) {
       const int m = (q + 1) / 2;
-      auto bb = [&](int c) {
-        const double v = 0.5 * ((double)B0[(c * NM + q) * n + idx] + (double)B1[(c * NM + q) * n + idx]);
+      auto sq = [&](const R *F, int c) {
+        const double v = F[c * cs + q * n + idx];
         return v * v;
       };
-      const double er = E[(0 * NM + q) * n + idx], ep = E[(1 * NM + q) * n + idx], ez = E[(2 * NM + q) * n + idx];
-      acc[m] += vh * (er * er + bb(1) + bb(2)) + vn * (ep * ep + ez * ez + bb(0));
+      acc[m] += vh * (sq(E, 0) + sq(Bb, 1) + sq(Bb, 2)) + vn * (sq(E, 1) + sq(E, 2) + sq(Bb, 0));
     }
   }
+  (void)par;
   for (int m = 0; m <= M; ++m) sh[m * 256 + tid] = acc[m];
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
@@ -799,8 +967,6 @@ __global__ __launch_bounds__(256) void tracked_gamma_kernel(KRun k, double *gamm
   ids[lo] = idv;
 }
 
-
-// ---------------------------------------------------------------------------
 // cell sort: electrons ordered by (tile, cell in tile, id); tiles of Tz x Tr
 // cells numbered z-fastest, cells inside a tile z-fastest.  Counting sort on
 // the cell order, then the ids of each cell in ascending order, so that the
@@ -898,22 +1064,35 @@ __global__ __launch_bounds__(256) void sort_cells_kernel(KRun k) {
 
 template <typename R>
 __global__ __launch_bounds__(256) void sort_permute_kernel(KRun k) {
-  const long long d = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (d >= k.np) return;
-  const int s = k.perm[d];
-  if constexpr (std::is_same<R, double>::value) {
-    ((double *)k.sz)[d] = ((const double *)k.pz)[s];
-  } else {
-    ((int *)k.sz)[d] = ((const int *)k.pz)[s];
-    ((float *)k.sfz)[d] = ((const float *)k.pfz)[s];
+  // one workgroup per tile: write the tile's electrons in the transposed
+  // order the push kernel reads (see round_count)
+  const long long TT = (long long)k.Tz * k.Tr;
+  const int beg = k.cell_start[blockIdx.x * TT], end = k.cell_start[(blockIdx.x + 1) * TT];
+  const int n = end - beg;
+  if (n <= 0) return;
+  const int chunk = (n + 255) / 256;
+  const int t = threadIdx.x;
+  int base = 0;
+  for (int it = 0; it < chunk; ++it) {
+    const int cnt = round_count(n, chunk, it);
+    const int d = beg + base + t;
+    base += cnt;
+    if (t >= cnt) continue;
+    const int s = k.perm[beg + t * chunk + it];
+    if constexpr (std::is_same<R, double>::value) {
+      ((double *)k.sz)[d] = ((const double *)k.pz)[s];
+    } else {
+      ((int *)k.sz)[d] = ((const int *)k.pz)[s];
+      ((float *)k.sfz)[d] = ((const float *)k.pfz)[s];
+    }
+    ((R *)k.sx)[d] = ((const R *)k.px)[s];
+    ((R *)k.sy)[d] = ((const R *)k.py)[s];
+    ((R *)k.sux)[d] = ((const R *)k.pux)[s];
+    ((R *)k.suy)[d] = ((const R *)k.puy)[s];
+    ((R *)k.suz)[d] = ((const R *)k.puz)[s];
+    ((R *)k.sw)[d] = ((const R *)k.pw)[s];
+    k.spid[d] = k.pid[s];
   }
-  ((R *)k.sx)[d] = ((const R *)k.px)[s];
-  ((R *)k.sy)[d] = ((const R *)k.py)[s];
-  ((R *)k.sux)[d] = ((const R *)k.pux)[s];
-  ((R *)k.suy)[d] = ((const R *)k.puy)[s];
-  ((R *)k.suz)[d] = ((const R *)k.puz)[s];
-  ((R *)k.sw)[d] = ((const R *)k.pw)[s];
-  k.spid[d] = k.pid[s];
 }
 
 // ---------------------------------------------------------------------------
@@ -972,7 +1151,7 @@ struct PushL {
   static int run(const KRun &k, int par, hipStream_t s) {
     if (k.np == 0) return PIC_OK;
     const unsigned blocks = (unsigned)((long long)k.ntz * k.ntr);
-    const size_t lds = push_lds_bytes(k, sizeof(R));
+    const size_t lds = push_lds_bytes(k, sizeof(double));
     push_kernel<R, M><<<blocks, 256, lds, s>>>(k, par);
     return check(hipGetLastError(), "push_kernel");
   }
@@ -980,16 +1159,18 @@ struct PushL {
 template <typename R, int M>
 struct EL {
   static int run(const KRun &k, int par, hipStream_t s) {
-    dim3 g((k.Nz + 255) / 256, k.Nr + 1);
-    efield_kernel<R, M><<<g, 256, 0, s>>>(k, par);
+    dim3 g((k.Nz + kFieldTile - 1) / kFieldTile, k.Nr + 1);
+    const size_t lds = (size_t)4 * (kFieldTile + 2 * k.N) * 2 * (M + 1) * sizeof(R);
+    efield_kernel<R, M><<<g, kFieldTile, lds, s>>>(k, par);
     return check(hipGetLastError(), "efield_kernel");
   }
 };
 template <typename R, int M>
 struct BL {
   static int run(const KRun &k, void *out, const void *in, double tau, void *avg, hipStream_t s) {
-    dim3 g((k.Nz + 255) / 256, k.Nr + 1);
-    bfield_kernel<R, M><<<g, 256, 0, s>>>(k, (R *)out, (const R *)in, (R)tau, (R *)avg);
+    dim3 g((k.Nz + kFieldTile - 1) / kFieldTile, k.Nr + 1);
+    const size_t lds = (size_t)2 * (kFieldTile + 2 * k.N) * 2 * (M + 1) * sizeof(R);
+    bfield_kernel<R, M><<<g, kFieldTile, lds, s>>>(k, (R *)out, (const R *)in, (R)tau, (R *)avg);
     return check(hipGetLastError(), "bfield_kernel");
   }
 };
@@ -1057,7 +1238,7 @@ int launch_tracked_gamma(const KRun &k, int prec, double *gamma, int64_t *ids, v
   else tracked_gamma_kernel<float><<<blocks, 256, 0, (hipStream_t)stream>>>(k, gamma, ids);
   return check(hipGetLastError(), "tracked_gamma_kernel");
 }
-size_t lds_bytes_of(const KRun &k, int prec) { return push_lds_bytes(k, prec == PIC_PREC_FP64 ? 8 : 4); }
+size_t lds_bytes_of(const KRun &k, int) { return push_lds_bytes(k, sizeof(double)); }
 
 int launch_sort(KRun &k, int prec, void *stream) {
   const hipStream_t s = (hipStream_t)stream;
@@ -1077,8 +1258,9 @@ int launch_sort(KRun &k, int prec, void *stream) {
     if ((rc = check(hipGetLastError(), "sort_scatter_kernel"))) return rc;
     sort_cells_kernel<<<(unsigned)((k.n_keys + 255) / 256), 256, 0, s>>>(k);
     if ((rc = check(hipGetLastError(), "sort_cells_kernel"))) return rc;
-    if (prec == PIC_PREC_FP64) sort_permute_kernel<double><<<pb, 256, 0, s>>>(k);
-    else sort_permute_kernel<float><<<pb, 256, 0, s>>>(k);
+    const unsigned tb = (unsigned)((long long)k.ntz * k.ntr);
+    if (prec == PIC_PREC_FP64) sort_permute_kernel<double><<<tb, 256, 0, s>>>(k);
+    else sort_permute_kernel<float><<<tb, 256, 0, s>>>(k);
     if ((rc = check(hipGetLastError(), "sort_permute_kernel"))) return rc;
     std::swap(k.pz, k.sz);
     std::swap(k.pfz, k.sfz);

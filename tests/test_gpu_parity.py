@@ -188,11 +188,25 @@ def test_fp64_gauss_law_invariant_on_gpu():
     sim.close()
 
 
-def _oracle_order(o, Tz, Tr):
-    """ids in (tile, cell, id) order, from the oracle's own positions"""
+def _oracle_order(o, Tz, Tr, threads=256):
+    """ids in (tile, cell, id) order from the oracle's own positions, each
+    tile's list then stored transposed as the library's workgroup reads it:
+    with n electrons and chunk = ceil(n / threads), round `it` holds
+    L[t chunk + it] for t = 0, 1, ... while t chunk + it < n."""
     P = o.particles()
     ords = o.cell_order(Tz, Tr)
-    return P["id"][np.lexsort((P["id"], ords))]
+    order = np.lexsort((P["id"], ords))
+    ids, tiles = P["id"][order], ords[order] // (Tz * Tr)
+    out = []
+    for tile in np.unique(tiles):
+        L = ids[tiles == tile]
+        n = L.size
+        chunk = -(-n // threads)
+        for it in range(chunk):
+            t = np.arange(threads)
+            t = t[t * chunk + it < n]
+            out.append(L[t * chunk + it])
+    return np.concatenate(out)
 
 
 @pytest.mark.parametrize("precision", [64, 32])
