@@ -31,7 +31,7 @@ HBM_PEAK_GBS = 8000.0
 
 
 def algorithmic_bytes(run: dict, precision: int) -> dict:
-    """Bytes each kernel must move per launch (see DESIGN.md): particle state
+    """Bytes each kernel must move per launch: particle state
     read and written once, field/current planes read or written once."""
     w = 8 if precision == 64 else 4
     NM = 2 * run["M"] + 1
@@ -41,9 +41,9 @@ def algorithmic_bytes(run: dict, precision: int) -> dict:
     part_read = 7 * w + 4 + (4 if precision == 32 else 0)
     part_write = 6 * w + (4 if precision == 32 else 0)
     return {
-        "push": np_ * (part_read + part_write) + cells * 12 * NM * w,  # E, B(n-1/2), B(n+1/2) read; J written
-        "efield": cells * 15 * NM * w,  # B, J, E read; E, next J written
-        "bfield": cells * 9 * NM * w,  # E, B read; B written
+        "push": np_ * (part_read + part_write) + cells * 9 * NM * w,  # E, Bbar read; J written
+        "efield": cells * 15 * NM * w,  # B, J, E read; E and the next J written
+        "bfield": cells * 12 * NM * w,  # E, B read; B and Bbar written
         "sort": np_ * 2 * (part_read + 4),  # read + permuted write of the particle state
     }
 
@@ -145,7 +145,7 @@ def main(argv=None):
         "config": {"workload": f"{args.workload}: {cfg['desc']}", "grid": f"{run['Nz']}x{run['Nr']}",
                    "modes": run["M"] + 1, "ppc": run["ppc"], "electrons": np_,
                    "precision": f"fp{prec}", "solver": "dual, 16 coefficients per operator",
-                   "dt": info["dt"], "sort_interval": args.sort_interval},
+                   "dt": info["dt"], "sort_interval": args.sort_interval or 4},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_launch": ab[dom], "avg_launch_ms": kernels[dom]["avg_ms"]},
