@@ -15,6 +15,7 @@ the same workload on the host.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -46,6 +47,22 @@ def algorithmic_bytes(run: dict, precision: int) -> dict:
         "bfield": cells * 12 * NM * w,  # E, B read; B and Bbar written
         "sort": np_ * 2 * (part_read + 4),  # read + permuted write of the particle state
     }
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE
+    counter passes (copy-calibrated), or None when the kernels changed since."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "hbm_traffic.json")) as f:
+            t = json.load(f)
+        with open(os.path.join(ROOT, "paper_2303_12874_amd", "csrc", "kernels.hip"), "rb") as f:
+            h = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if t.get("kernels_sha256") != h:
+        return None
+    e = t.get("workloads", {}).get(workload, {}).get(kernel)
+    return None if e is None else e["read_bytes"] + e["write_bytes"]
 
 
 def cpu_baseline(run: dict, nsteps: int) -> dict:
@@ -128,6 +145,8 @@ def main(argv=None):
         kernels[ph] = {"avg_ms": ms / n, "launches": n, "GBs": ab[ph] / avg_s / 1e9}
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
     ach = kernels[dom]["GBs"]
+    default_opts = args.sort_interval in (0, 4) and args.precision in (0, cfg["precision"])
+    traffic = measured_traffic(args.workload, dom) if default_opts else None
     value = np_ * args.steps / (elapsed_ms * 1e-3)
     out = {
         "metric": METRIC,
@@ -147,7 +166,7 @@ def main(argv=None):
                    "precision": f"fp{prec}", "solver": "dual, 16 coefficients per operator",
                    "dt": info["dt"], "sort_interval": args.sort_interval or 4},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                     "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": ab[dom], "avg_launch_ms": kernels[dom]["avg_ms"]},
         "kernels": kernels,
         "state_finite": finite,
