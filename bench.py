@@ -89,6 +89,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c5"])
     ap.add_argument("--cpu-steps", type=int, default=1, help="oracle steps for the CPU baseline (0: skip)")
     ap.add_argument("--sort-interval", type=int, default=0)
+    ap.add_argument("--tile-z", type=int, default=0, help="sort tile extent in z (0: library default)")
+    ap.add_argument("--tile-r", type=int, default=0, help="sort tile extent in r (0: library default)")
     ap.add_argument("--precision", type=int, default=0, choices=[0, 32, 64],
                     help="override the workload's precision (0: as defined)")
     args = ap.parse_args(argv)
@@ -107,7 +109,7 @@ def main(argv=None):
     torch.cuda.set_device(dev)
     t_init = time.perf_counter()
     sim = pic.Simulation([workloads.to_rundesc(run)], precision=prec, sort_interval=args.sort_interval,
-                         device="cuda:0")
+                         tile_z=args.tile_z, tile_r=args.tile_r, device="cuda:0")
     torch.cuda.synchronize()
     t_init = time.perf_counter() - t_init
     info = sim.info()
@@ -145,7 +147,8 @@ def main(argv=None):
         kernels[ph] = {"avg_ms": ms / n, "launches": n, "GBs": ab[ph] / avg_s / 1e9}
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
     ach = kernels[dom]["GBs"]
-    default_opts = args.sort_interval in (0, 4) and args.precision in (0, cfg["precision"])
+    default_opts = (args.sort_interval in (0, 4) and args.precision in (0, cfg["precision"])
+                    and args.tile_z == 0 and args.tile_r == 0)
     traffic = measured_traffic(args.workload, dom) if default_opts else None
     value = np_ * args.steps / (elapsed_ms * 1e-3)
     out = {
@@ -164,7 +167,8 @@ def main(argv=None):
         "config": {"workload": f"{args.workload}: {cfg['desc']}", "grid": f"{run['Nz']}x{run['Nr']}",
                    "modes": run["M"] + 1, "ppc": run["ppc"], "electrons": np_,
                    "precision": f"fp{prec}", "solver": "dual, 16 coefficients per operator",
-                   "dt": info["dt"], "sort_interval": args.sort_interval or 4},
+                   "dt": info["dt"], "sort_interval": args.sort_interval or 4,
+                   "tile": "%dx%d" % info["tile"]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": ab[dom], "avg_launch_ms": kernels[dom]["avg_ms"]},

@@ -129,6 +129,8 @@ typedef struct pic_run_info {
   int64_t steps_done;    /* steps taken since pic_init                       */
   int32_t n_coef;        /* coefficients per operator                        */
   int32_t n_tracked;
+  int32_t tile_z;        /* sort tile in use (cells along z and r)           */
+  int32_t tile_r;
 } pic_run_info;
 
 /* ---- host-only setup (no GPU needed) ----------------------------------- */

@@ -57,7 +57,8 @@ class _Opts(C.Structure):
 
 class _RunInfo(C.Structure):
     _fields_ = [("dt", C.c_double), ("courant_limit", C.c_double), ("n_particles", C.c_int64),
-                ("steps_done", C.c_int64), ("n_coef", C.c_int32), ("n_tracked", C.c_int32)]
+                ("steps_done", C.c_int64), ("n_coef", C.c_int32), ("n_tracked", C.c_int32),
+                ("tile_z", C.c_int32), ("tile_r", C.c_int32)]
 
 
 def _load():
@@ -253,7 +254,8 @@ class Simulation:
         inf = _RunInfo()
         _check(_lib.pic_run_info_get(self._h, run, C.byref(inf)))
         return {"dt": inf.dt, "courant_limit": inf.courant_limit, "n_particles": inf.n_particles,
-                "steps_done": inf.steps_done, "n_coef": inf.n_coef, "n_tracked": inf.n_tracked}
+                "steps_done": inf.steps_done, "n_coef": inf.n_coef, "n_tracked": inf.n_tracked,
+                "tile": (inf.tile_z, inf.tile_r)}
 
     def coefficients(self, run=0):
         N = self.info(run)["n_coef"]

@@ -175,24 +175,23 @@ int validate_run(const pic_run_desc &r, int i, int N) {
   return PIC_OK;
 }
 
-// LDS of one push workgroup (the current window of its tile); 48 KB keeps three
-// workgroups per CU, which the latency-bound gather needs
-constexpr size_t kMaxLds = 49152;
-
-size_t tile_lds(int M, int Tz, int Tr, int) {  // FP64 accumulators for both precisions
-  return (size_t)3 * (2 * M + 1) * (Tz + 3) * (Tr + 3) * 8;
-}
-
-// Sort tile: 32 x 8 cells unless given; the radial extent shrinks until the
-// tile's current window fits the LDS budget.
+// Sort tile: 32 x 8 cells unless given.  A default extent shrinks until the
+// push workgroup's LDS (current and field windows) fits the budget of two
+// workgroups per CU: the radial extent halves down to 4, then the axial one
+// steps down by 2 to 16, then the radial one halves again.
 int choose_tiles(const pic_opts &o, int M, int *Tz, int *Tr) {
   *Tz = o.tile_z > 0 ? o.tile_z : 32;
   *Tr = o.tile_r > 0 ? o.tile_r : 8;
-  if (o.tile_r <= 0)
-    while (*Tr > 1 && tile_lds(M, *Tz, *Tr, o.precision) > kMaxLds) *Tr /= 2;
-  if (tile_lds(M, *Tz, *Tr, o.precision) > kMaxLds)
+  auto over = [&] { return push_lds_bytes(M, *Tz, *Tr, o.precision) > kPushLdsDefault; };
+  while (over()) {
+    if (o.tile_r <= 0 && *Tr > 4) *Tr /= 2;
+    else if (o.tile_z <= 0 && *Tz > 16) *Tz -= 2;
+    else if (o.tile_r <= 0 && *Tr > 1) *Tr /= 2;
+    else break;
+  }
+  if (push_lds_bytes(M, *Tz, *Tr, o.precision) > kPushLdsMax)
     return fail(PIC_E_INVALID, "tile %dx%d needs %zu bytes of LDS (limit %zu)", *Tz, *Tr,
-                tile_lds(M, *Tz, *Tr, o.precision), kMaxLds);
+                push_lds_bytes(M, *Tz, *Tr, o.precision), kPushLdsMax);
   return PIC_OK;
 }
 
@@ -624,6 +623,8 @@ int pic_run_info_get(pic_ctx *ctx, int32_t run, pic_run_info *info) {
   info->steps_done = R->steps;
   info->n_coef = R->N;
   info->n_tracked = R->d.n_tracked;
+  info->tile_z = R->k.Tz;
+  info->tile_r = R->k.Tr;
   return PIC_OK;
 }
 

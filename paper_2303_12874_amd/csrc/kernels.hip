@@ -121,9 +121,10 @@ __device__ __forceinline__ void store_rec(R *__restrict__ p, const R in[NMP]) {
 }
 
 // A node of one component from the mode planes (stride `plane`): record slot
-// s = 2m (Re), 2m+1 (Im); slot 1 (Im of m = 0) is not stored.
-template <typename R, int NMP>
-__device__ __forceinline__ void load_node(const R *__restrict__ F, long long plane, long long node, R out[NMP]) {
+// s = 2m (Re), 2m+1 (Im); slot 1 (Im of m = 0) is not stored.  I is the index
+// type: 64-bit for device memory, 32-bit for LDS.
+template <typename R, int NMP, typename I = long long>
+__device__ __forceinline__ void load_node(const R *__restrict__ F, I plane, I node, R out[NMP]) {
   out[0] = F[node];
   out[1] = R(0);
 #pragma unroll
@@ -140,19 +141,22 @@ __device__ __forceinline__ void store_node(R *__restrict__ F, long long plane, l
 // (-1)^m for z components (the point (-r, phi) is (r, phi + pi)).
 __host__ __device__ constexpr int mirror_sign_m(int m, bool zcomp) { return ((m % 2 == 0) == zcomp) ? 1 : -1; }
 
-// Bilinear interpolation of one component's records (all modes).
-template <typename R, int NMP, bool HALF_R, bool ZCOMP>
-__device__ __forceinline__ void interp(const R *__restrict__ F, long long plane, int Nz, int ca, int cb, int row0,
-                                       bool mirror, R fz, R fr, R out[NMP]) {
+// Bilinear interpolation of one component (all modes) from the records of
+// four nodes: pa, pb on the lower row (columns ca, cb), pc, pd on the upper
+// row; plane q of a record sits at offset q * pstride (the plane stride in
+// device memory, 1 inside an LDS node record).  With `mirror` the lower row
+// is the image of r_{-1/2} (pa, pb point at row r_{1/2}) and each mode takes
+// its mirror sign.
+template <typename R, int NMP, bool HALF_R, bool ZCOMP, typename I>
+__device__ __forceinline__ void interp4(const R *pa, const R *pb, const R *pc, const R *pd, I pstride,
+                                        bool mirror, R fz, R fr, R out[NMP]) {
   const R w00 = (R(1) - fz) * (R(1) - fr), w10 = fz * (R(1) - fr);
   const R w01 = (R(1) - fz) * fr, w11 = fz * fr;
-  const long long o0 = (long long)(mirror ? 0 : row0) * Nz;
-  const long long o1 = (long long)(row0 + 1) * Nz;
   R a[NMP], b[NMP], c[NMP], d[NMP];
-  load_node<R, NMP>(F, plane, o0 + ca, a);
-  load_node<R, NMP>(F, plane, o0 + cb, b);
-  load_node<R, NMP>(F, plane, o1 + ca, c);
-  load_node<R, NMP>(F, plane, o1 + cb, d);
+  load_node<R, NMP, I>(pa, pstride, 0, a);
+  load_node<R, NMP, I>(pb, pstride, 0, b);
+  load_node<R, NMP, I>(pc, pstride, 0, c);
+  load_node<R, NMP, I>(pd, pstride, 0, d);
 #pragma unroll
   for (int s = 0; s < NMP; ++s) {
     R va = a[s], vb = b[s];
@@ -165,26 +169,43 @@ __device__ __forceinline__ void interp(const R *__restrict__ F, long long plane,
   }
 }
 
+// Tiles are numbered z-fastest; workgroups go to the 8 XCDs round-robin.
+// Give each XCD a contiguous run of tiles so that neighbours, whose field and
+// current windows overlap, share one L2.
+__device__ __forceinline__ int xcd_tile(int b, int ntiles) {
+  const int n8 = ntiles & ~7;
+  return b < n8 ? (b & 7) * (n8 >> 3) + (b >> 3) : b;
+}
+
 // One workgroup per sort tile of Tz x Tr cells.  The tile's electrons (the
 // range the last cell sort assigned to it) are processed in contiguous
-// per-thread chunks, so that at any instant the 64 lanes of a wavefront sit
-// in different cells: their field reads fall on neighbouring nodes and their
-// LDS atomics rarely collide.  The current of the whole tile is accumulated
-// in LDS over the node window [z0-1, z0+Tz+2) x [r0-1, r0+Tr+2) (every move
-// of less than one cell from a cell of the tile stays inside it) and added to
-// the global arrays once; an electron that drifted out of the window since
-// the last sort deposits straight to global memory.
+// per-thread chunks, spread so that the 64 lanes of a wavefront sit in
+// distinct cells and their LDS atomics do not collide.  Two LDS windows, both
+// node-major (all planes of a node contiguous, so that every component and
+// mode offset is an immediate):
+//  * E and Bbar over the tile's field window, staged once, which the gather
+//    reads: records of 6 NM reals (E_r, E_phi, E_z, Bbar_r, Bbar_phi,
+//    Bbar_z, each NM planes) and one pad;
+//  * the current of the whole tile over the node window [z0-1, z0+Tz+2) x
+//    [r0-1, r0+Tr+2) (every move of less than one cell from a cell of the
+//    tile stays inside it), records of 3 NM FP64 sums, added to the global
+//    arrays once.
+// An electron that drifted out of either window since the last sort gathers
+// from, or deposits to, global memory directly.
 template <typename R, int M>
 __global__ __launch_bounds__(256) void push_kernel(KRun k, int par) {
-  constexpr int NM = 2 * M + 1;       // current planes in the LDS window
-  constexpr int NMP = 2 * (M + 1);    // reals per field record
+  constexpr int NM = 2 * M + 1;       // planes per component
+  constexpr int NMP = 2 * (M + 1);    // reals per field record in registers
+  constexpr int FS = 6 * NM + 1;      // reals per field-window node, odd: lanes in
+                                      // consecutive nodes hit distinct LDS banks
+  constexpr int JS = 3 * NM;          // FP64 sums per current-window node
   constexpr bool F64 = std::is_same<R, double>::value;
   // the tile current is accumulated in FP64 for both precisions: the LDS
   // double-precision atomic add is the fast one on gfx950, and the sum of
   // thousands of FP32 contributions keeps its low bits until the flush
   extern __shared__ __align__(16) unsigned char lds_raw[];
   double *lds = (double *)lds_raw;
-  const int tile = blockIdx.x;
+  const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
   const int TZ = k.Tz, TR = k.Tr;
   const int WZ = TZ + 3, WR = TR + 3;
   const int tz = tile % k.ntz, tr = tile / k.ntz;
@@ -192,9 +213,8 @@ __global__ __launch_bounds__(256) void push_kernel(KRun k, int par) {
   const long long TT = (long long)TZ * TR;
   const int beg = k.cell_start[tile * TT], end = k.cell_start[(tile + 1) * TT];
   if (beg >= end) return;
-  const int nlds = 3 * NM * WZ * WR;
+  const int nlds = JS * WZ * WR;
   for (int e = threadIdx.x; e < nlds; e += blockDim.x) lds[e] = 0.0;
-  __syncthreads();
 
   const int Nz = k.Nz, Nr = k.Nr;
   const long long plane = k.plane;
@@ -202,20 +222,48 @@ __global__ __launch_bounds__(256) void push_kernel(KRun k, int par) {
   const R dt = (R)k.dt;
   const R *E = (const R *)k.E;
   const R *Bb = (const R *)k.Bbar;
+  const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6, nwave = (int)blockDim.x >> 6;
+
+  // ---- stage the field window ----
+  const int FZ = TZ + 2 + 2 * kFieldMarginZ, FR = TR + 2 + 2 * kFieldMarginR;
+  const int fz0 = tz * TZ - 1 - kFieldMarginZ, fr0 = tr * TR - 1 - kFieldMarginR;
+  R *fw = (R *)(lds + nlds);
+  // each thread takes one node and loads it from all 6 NM planes at once,
+  // so that the loads are in flight together
+  for (int e = threadIdx.x; e < FZ * FR; e += blockDim.x) {
+    const int row = e / FZ, col = e - row * FZ;
+    const int grow = fr0 + row;
+    const bool ok = grow >= 0 && grow <= Nr;
+    const long long g = (long long)(ok ? grow : 0) * Nz + wrap_any(fz0 + col, Nz);
+    R v[FS];
+#pragma unroll
+    for (int cq = 0; cq < FS; ++cq) {
+      const int c = cq / NM, q = cq % NM;
+      v[cq] = ok ? (c < 3 ? E : Bb)[(c % 3) * cstride + q * plane + g] : R(0);
+    }
+#pragma unroll
+    for (int cq = 0; cq < FS; ++cq) fw[e * FS + cq] = v[cq];
+  }
+  __syncthreads();
   R *J = (R *)k.J[par];
   R *X = (R *)k.px, *Y = (R *)k.py, *UX = (R *)k.pux, *UY = (R *)k.puy, *UZ = (R *)k.puz;
 
-  const int WRWZ = WR * WZ;
-
   const int n = end - beg;
   const int chunk = (n + 255) / 256;
+  // Thread t takes list column S (t mod 256/S) + t / (256/S): with S at least
+  // the number of columns per cell, the 64 lanes of a wavefront work in
+  // distinct cells and their LDS atomics do not collide on one address.
+  int S = 1;
+  while (S < 4 && (long long)S * chunk * TT < n) S *= 2;
+  const int per = 256 / S;
+  const int colm = S * ((int)threadIdx.x % per) + (int)threadIdx.x / per;
   const R dt_dz = (R)(k.dt / k.dz), dt_dr = (R)(k.dt / k.dr);
   int base = 0;
   for (int it = 0; it < chunk; ++it) {
     const int cnt = round_count(n, chunk, it);
-    const int p = beg + base + (int)threadIdx.x;
+    const int p = beg + base + colm;
     base += cnt;
-    if ((int)threadIdx.x >= cnt) continue;
+    if (colm >= cnt) continue;
     const R q = -((const R *)k.pw)[p];
     const uint32_t pidw = k.pid[p];
 
@@ -270,12 +318,46 @@ __global__ __launch_bounds__(256) void push_kernel(KRun k, int par) {
     const bool mir = jh < 0;
 
     R er[NMP], ep[NMP], ez[NMP], br[NMP], bp[NMP], bz[NMP];
-    interp<R, NMP, true, false>(E + 0 * cstride, plane, Nz, ci0, ci1, jh, mir, f0, frh, er);
-    interp<R, NMP, false, false>(E + 1 * cstride, plane, Nz, ci0, ci1, j0, false, f0, fr, ep);
-    interp<R, NMP, false, true>(E + 2 * cstride, plane, Nz, ch0, ch1, j0, false, fh, fr, ez);
-    interp<R, NMP, false, false>(Bb + 0 * cstride, plane, Nz, ch0, ch1, j0, false, fh, fr, br);
-    interp<R, NMP, true, false>(Bb + 1 * cstride, plane, Nz, ch0, ch1, jh, mir, fh, frh, bp);
-    interp<R, NMP, true, true>(Bb + 2 * cstride, plane, Nz, ci0, ci1, jh, mir, f0, frh, bz);
+    // stencil in the field window: columns of i0 (periodic) and of the half-z
+    // stencil (i0 - 1 or i0), rows of j0 and of the half-r stencil
+    int fc = i0 - fz0;
+    fc += (fc < 0) ? Nz : 0;
+    fc -= (fc >= Nz) ? Nz : 0;
+    const int a0 = fc, h0 = fc - (ch0 == ci0 ? 0 : 1);
+    const int ri0 = j0 - fr0, rh0 = (mir ? 0 : jh) - fr0, rh1 = jh + 1 - fr0;
+    if (h0 >= 0 && a0 + 1 <= FZ - 1 && ri0 >= 0 && rh0 >= 0 && ri0 + 1 <= FR - 1 && rh1 <= FR - 1) {
+      const R *li0 = fw + ri0 * FZ * FS, *li1 = li0 + FZ * FS;  // rows of j0, j0 + 1
+      const R *lh0 = fw + rh0 * FZ * FS, *lh1 = fw + rh1 * FZ * FS;  // half-r rows
+      const int A0 = a0 * FS, A1 = A0 + FS, H0 = h0 * FS, H1 = H0 + FS;
+      interp4<R, NMP, true, false, int>(lh0 + A0, lh0 + A1, lh1 + A0, lh1 + A1, 1, mir, f0, frh, er);
+      interp4<R, NMP, false, false, int>(li0 + A0 + NM, li0 + A1 + NM, li1 + A0 + NM, li1 + A1 + NM, 1, false, f0,
+                                         fr, ep);
+      interp4<R, NMP, false, true, int>(li0 + H0 + 2 * NM, li0 + H1 + 2 * NM, li1 + H0 + 2 * NM, li1 + H1 + 2 * NM,
+                                        1, false, fh, fr, ez);
+      interp4<R, NMP, false, false, int>(li0 + H0 + 3 * NM, li0 + H1 + 3 * NM, li1 + H0 + 3 * NM,
+                                         li1 + H1 + 3 * NM, 1, false, fh, fr, br);
+      interp4<R, NMP, true, false, int>(lh0 + H0 + 4 * NM, lh0 + H1 + 4 * NM, lh1 + H0 + 4 * NM, lh1 + H1 + 4 * NM,
+                                        1, mir, fh, frh, bp);
+      interp4<R, NMP, true, true, int>(lh0 + A0 + 5 * NM, lh0 + A1 + 5 * NM, lh1 + A0 + 5 * NM, lh1 + A1 + 5 * NM,
+                                       1, mir, f0, frh, bz);
+    } else {
+      const long long gi0 = (long long)j0 * Nz, gi1 = gi0 + Nz;
+      const long long gh0 = (long long)(mir ? 0 : jh) * Nz, gh1 = (long long)(jh + 1) * Nz;
+      const R *er_ = E, *ep_ = E + cstride, *ez_ = E + 2 * cstride;
+      const R *br_ = Bb, *bp_ = Bb + cstride, *bz_ = Bb + 2 * cstride;
+      interp4<R, NMP, true, false, long long>(er_ + gh0 + ci0, er_ + gh0 + ci1, er_ + gh1 + ci0, er_ + gh1 + ci1,
+                                              plane, mir, f0, frh, er);
+      interp4<R, NMP, false, false, long long>(ep_ + gi0 + ci0, ep_ + gi0 + ci1, ep_ + gi1 + ci0, ep_ + gi1 + ci1,
+                                               plane, false, f0, fr, ep);
+      interp4<R, NMP, false, true, long long>(ez_ + gi0 + ch0, ez_ + gi0 + ch1, ez_ + gi1 + ch0, ez_ + gi1 + ch1,
+                                              plane, false, fh, fr, ez);
+      interp4<R, NMP, false, false, long long>(br_ + gi0 + ch0, br_ + gi0 + ch1, br_ + gi1 + ch0, br_ + gi1 + ch1,
+                                               plane, false, fh, fr, br);
+      interp4<R, NMP, true, false, long long>(bp_ + gh0 + ch0, bp_ + gh0 + ch1, bp_ + gh1 + ch0, bp_ + gh1 + ch1,
+                                              plane, mir, fh, frh, bp);
+      interp4<R, NMP, true, true, long long>(bz_ + gh0 + ci0, bz_ + gh0 + ci1, bz_ + gh1 + ci0, bz_ + gh1 + ci1,
+                                             plane, mir, f0, frh, bz);
+    }
 
     // ---- reconstruct Re sum_m F^m e^{i m phi}, rotate to Cartesian ----
     R Em[M + 1][3];
@@ -434,19 +516,9 @@ __global__ __launch_bounds__(256) void push_kernel(KRun k, int par) {
       const int dj = j1 - j0;
       const int or0 = dj < 0 ? 1 : 0, or1 = or0 + dj;
       const int jb = j0 - or0;
-      // the 3 x 3 node window [ib, ib+2] x [jb, jb+2] inside the tile's LDS window?
-      const bool inwin = (ib - zlo >= 0) && (ib + 2 - zlo < WZ) && (jb - rlo >= 0) && (jb + 2 - rlo < WR);
-      double *lwin = lds + (jb - rlo) * WZ + (ib - zlo);
-      int col[3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) col[a] = wrap_once(ib + a, Nz);
-      // add v to component c (0 r, 1 phi, 2 z), plane qq, window node (a, b)
-      auto dep = [&](int c, int qq, int b, int a, R v) {
-        if (inwin)
-          lds_add(lwin + (c * NM + qq) * WRWZ + b * WZ + a, (double)v);
-        else
-          atomic_add(J + (c * NM + qq) * plane + (long long)(jb + b) * Nz + col[a], v);
-      };
+      // the third node column (row) of the window carries current only for an
+      // electron that crossed a z (r) cell face; skip it when no lane did
+      const bool zx = __any(di != 0), rx = __any(dj != 0);
       R Sz0[3], Sz1[3], Sr0[3], Sr1[3];
       const R g0 = fr;
 #pragma unroll
@@ -465,69 +537,99 @@ __global__ __launch_bounds__(256) void push_kernel(KRun k, int par) {
           Wr[a][b] = (Sr1[b] - Sr0[b]) * (Sz0[a] + Sz1[a]) * R(0.5);
           Ss[a][b] = Sz0[a] * Sr0[b] + Sz1[a] * Sr1[b];
         }
-      // e^{-i m phi} at the old, new and mid positions, by recurrence
-      R e0r = 1, e0i = 0, e1r = 1, e1i = 0, emr = 1, emi = 0;
+      // the whole deposit, into `dep(c, plane, b, a, v)`: component c (0 r,
+      // 1 phi, 2 z), window node (ib + a, jb + b)
+      auto deposit = [&](auto &&dep) {
+        // e^{-i m phi} at the old, new and mid positions, by recurrence
+        R e0r = 1, e0i = 0, e1r = 1, e1i = 0, emr = 1, emi = 0;
 #pragma unroll
-      for (int m = 0; m <= M; ++m) {
-        if (m > 0) {
-          R tr_ = e0r * c0 + e0i * s0, ti = e0i * c0 - e0r * s0;
-          e0r = tr_;
-          e0i = ti;
-          tr_ = e1r * c1 + e1i * s1;
-          ti = e1i * c1 - e1r * s1;
-          e1r = tr_;
-          e1i = ti;
-          tr_ = emr * cmid + emi * smid;
-          ti = emi * cmid - emr * smid;
-          emr = tr_;
-          emi = ti;
-        }
-        const R cq = (m == 0 ? R(1) : R(2)) * q;
-        const R xr = R(0.5) * (e0r + e1r), xi = R(0.5) * (e0i + e1i);
-        const int qa = m == 0 ? 0 : 2 * m - 1, qb = 2 * m;
-        // J_z at (ib+a+1/2, jb+b): minus the running sum of Wz behind the face
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-          R run = 0;
-#pragma unroll
-          for (int a = 0; a < 2; ++a) {
-            run += Wz[a][b];
-            const R v = -cq * run;
-            dep(2, qa, b, a, v * xr);
-            if (m > 0) dep(2, qb, b, a, v * xi);
+        for (int m = 0; m <= M; ++m) {
+          if (m > 0) {
+            R tr_ = e0r * c0 + e0i * s0, ti = e0i * c0 - e0r * s0;
+            e0r = tr_;
+            e0i = ti;
+            tr_ = e1r * c1 + e1i * s1;
+            ti = e1i * c1 - e1r * s1;
+            e1r = tr_;
+            e1i = ti;
+            tr_ = emr * cmid + emi * smid;
+            ti = emi * cmid - emr * smid;
+            emr = tr_;
+            emi = ti;
           }
-        }
-        // J_r at (ib+a, jb+b+1/2)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          R run = 0;
-#pragma unroll
-          for (int b = 0; b < 2; ++b) {
-            run += Wr[a][b];
-            const R v = -cq * run;
-            dep(0, qa, b, a, v * xr);
-            if (m > 0) dep(0, qb, b, a, v * xi);
-          }
-        }
-        // J_phi at (ib+a, jb+b)
-        const R dre = e1r - e0r, dim_ = e1i - e0i;
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
+          const R cq = (m == 0 ? R(1) : R(2)) * q;
+          const R xr = R(0.5) * (e0r + e1r), xi = R(0.5) * (e0i + e1i);
+          const int qa = m == 0 ? 0 : 2 * m - 1, qb = 2 * m;
+          // J_z at (ib+a+1/2, jb+b): minus the running sum of Wz behind the face
 #pragma unroll
           for (int b = 0; b < 3; ++b) {
-            const int j = jb + b;
-            const R h = R(0.5) * cq * Ss[a][b];
-            if (m == 0) {
-              dep(1, 0, b, a, h * vphi);
-            } else if (m == 1 && j == 0) {
-              dep(1, qa, b, a, h * vphi * emr);
-              dep(1, qb, b, a, h * vphi * emi);
-            } else if (j > 0) {  // the closure carries r_j: nothing on the axis
-              // (i/m)(e1 - e0) = (-(e1-e0).im, (e1-e0).re) / m
-              dep(1, qa, b, a, -h * dim_ * (R(1) / (R)m));
-              dep(1, qb, b, a, h * dre * (R(1) / (R)m));
+            if (b == 2 && !rx) continue;
+            R run = 0;
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+              if (a == 1 && !zx) continue;
+              run += Wz[a][b];
+              const R v = -cq * run;
+              dep(2, qa, b, a, v * xr);
+              if (m > 0) dep(2, qb, b, a, v * xi);
             }
           }
+          // J_r at (ib+a, jb+b+1/2)
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            if (a == 2 && !zx) continue;
+            R run = 0;
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+              if (b == 1 && !rx) continue;
+              run += Wr[a][b];
+              const R v = -cq * run;
+              dep(0, qa, b, a, v * xr);
+              if (m > 0) dep(0, qb, b, a, v * xi);
+            }
+          }
+          // J_phi at (ib+a, jb+b): m = 0 from v_phi; m >= 1 from the closure
+          // (i/m)(e1 - e0) times r_j, which vanishes on the axis, where m = 1
+          // takes v_phi instead
+          const R dre = e1r - e0r, dim_ = e1i - e0i;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            if (a == 2 && !zx) continue;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+              if (b == 2 && !rx) continue;
+              const R h = R(0.5) * cq * Ss[a][b];
+              if (m == 0) {
+                dep(1, 0, b, a, h * vphi);
+              } else {
+                const bool axis = jb + b == 0;
+                R va = -h * dim_ * (R(1) / (R)m), vb = h * dre * (R(1) / (R)m);
+                if (m == 1) {
+                  va = axis ? h * vphi * emr : va;
+                  vb = axis ? h * vphi * emi : vb;
+                } else {
+                  va = axis ? R(0) : va;
+                  vb = axis ? R(0) : vb;
+                }
+                dep(1, qa, b, a, va);
+                dep(1, qb, b, a, vb);
+              }
+            }
+          }
+        }
+      };
+      // the 3 x 3 node window [ib, ib+2] x [jb, jb+2] inside the tile's LDS window?
+      if ((ib - zlo >= 0) && (ib + 2 - zlo < WZ) && (jb - rlo >= 0) && (jb + 2 - rlo < WR)) {
+        double *jw = lds + ((jb - rlo) * WZ + (ib - zlo)) * JS;
+        const int rowJ = WZ * JS;
+        deposit([&](int c, int qq, int b, int a, R v) { lds_add(jw + b * rowJ + a * JS + c * NM + qq, (double)v); });
+      } else {
+        int col[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) col[a] = wrap_once(ib + a, Nz);
+        deposit([&](int c, int qq, int b, int a, R v) {
+          atomic_add(J + (c * NM + qq) * plane + (long long)(jb + b) * Nz + col[a], v);
+        });
       }
     }
 
@@ -547,19 +649,18 @@ __global__ __launch_bounds__(256) void push_kernel(KRun k, int par) {
     UZ[p] = un[2];
   }
 
-  // ---- flush the tile's current ----
+  // ---- flush the tile's current: one wavefront per (component, plane, row) ----
   __syncthreads();
-  for (int e = threadIdx.x; e < nlds; e += blockDim.x) {
-    const R v = (R)lds[e];
-    if (v == R(0)) continue;
-    const int lc = e % WZ;
-    const int rest = e / WZ;
-    const int lr = rest % WR;
-    const int cq = rest / WR;  // c * NM + q
-    const int c = cq / NM, q = cq % NM;
+  for (int line = wave; line < JS * WR; line += nwave) {  // line = (c NM + q) WR + lr
+    const int cq = line / WR, lr = line - cq * WR;
     const int row = rlo + lr;
     if (row < 0 || row > Nr) continue;
-    atomic_add(J + (c * NM + q) * plane + (long long)row * Nz + wrap_once(zlo + lc, Nz), v);
+    R *dst = J + cq * plane + (long long)row * Nz;
+    const double *src = lds + lr * WZ * JS + cq;
+    for (int lc = lane; lc < WZ; lc += 64) {
+      const R v = (R)src[lc * JS];
+      if (v != R(0)) atomic_add(dst + wrap_any(zlo + lc, Nz), v);
+    }
   }
 }
 
@@ -1100,9 +1201,6 @@ __global__ __launch_bounds__(256) void sort_permute_kernel(KRun k) {
 
 thread_local char g_err[256] = "";
 
-size_t push_lds_bytes(const KRun &k, size_t word) {
-  return (size_t)3 * (2 * k.M + 1) * (k.Tz + 3) * (k.Tr + 3) * word;
-}
 
 
 
@@ -1151,7 +1249,14 @@ struct PushL {
   static int run(const KRun &k, int par, hipStream_t s) {
     if (k.np == 0) return PIC_OK;
     const unsigned blocks = (unsigned)((long long)k.ntz * k.ntr);
-    const size_t lds = push_lds_bytes(k, sizeof(double));
+    const size_t lds = push_lds_bytes(M, k.Tz, k.Tr, std::is_same<R, double>::value ? PIC_PREC_FP64 : PIC_PREC_FP32);
+    static size_t lds_set = 0;  // dynamic LDS above 64 KB must be allowed per kernel
+    if (lds > 65536 && lds > lds_set) {
+      const hipError_t e =
+          hipFuncSetAttribute((const void *)push_kernel<R, M>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return check(e, "hipFuncSetAttribute(push_kernel)");
+      lds_set = lds;
+    }
     push_kernel<R, M><<<blocks, 256, lds, s>>>(k, par);
     return check(hipGetLastError(), "push_kernel");
   }
@@ -1238,7 +1343,6 @@ int launch_tracked_gamma(const KRun &k, int prec, double *gamma, int64_t *ids, v
   else tracked_gamma_kernel<float><<<blocks, 256, 0, (hipStream_t)stream>>>(k, gamma, ids);
   return check(hipGetLastError(), "tracked_gamma_kernel");
 }
-size_t lds_bytes_of(const KRun &k, int) { return push_lds_bytes(k, sizeof(double)); }
 
 int launch_sort(KRun &k, int prec, void *stream) {
   const hipStream_t s = (hipStream_t)stream;

@@ -64,13 +64,37 @@ struct KRun {
   double *red;            // reduction partials
 };
 
+// ---- push workgroup LDS ---------------------------------------------------------
+// One push workgroup per sort tile of Tz x Tr cells.  Its LDS holds
+//  * the tile's current window, FP64 for both precisions, 3 components x NM
+//    planes x (Tz+3) x (Tr+3) nodes from cell (z0-1, r0-1): every move of
+//    less than a cell from a cell of the tile deposits inside it;
+//  * the field window of E and Bbar, records of 6 components x NM planes
+//    (+1 pad) for (Tz+2+2 kFieldMarginZ) x (Tr+2+2 kFieldMarginR) nodes from
+//    column z0-1-kFieldMarginZ and row r0-1-kFieldMarginR: the gather stencil
+//    of every electron within the margins of the tile.
+constexpr int kFieldMarginZ = 1;  // columns for electrons that drifted since the sort
+constexpr int kFieldMarginR = 0;
+constexpr size_t kPushLdsDefault = 81920;  // default tile choice: two workgroups per CU
+constexpr size_t kPushLdsMax = 163840;     // gfx950 LDS per workgroup
+
+inline int field_window_z(int Tz) { return Tz + 2 + 2 * kFieldMarginZ; }
+inline int field_window_r(int Tr) { return Tr + 2 + 2 * kFieldMarginR; }
+inline size_t current_window_words(int M, int Tz, int Tr) {
+  return (size_t)3 * (2 * M + 1) * (Tz + 3) * (Tr + 3);
+}
+inline size_t push_lds_bytes(int M, int Tz, int Tr, int precision) {
+  const size_t w = precision == PIC_PREC_FP64 ? 8 : 4;
+  return current_window_words(M, Tz, Tr) * 8 +
+         (size_t)(6 * (2 * M + 1) + 1) * field_window_z(Tz) * field_window_r(Tr) * w;
+}
+
 // ---- kernel launchers (kernels.hip); all enqueue on `stream` -----------------
 int launch_push(const KRun &k, int prec, int par, void *stream);
 int launch_efield(const KRun &k, int prec, int par, void *stream);
 int launch_bfield(const KRun &k, int prec, void *Bout, const void *Bin, double tau, void *avg, void *stream);
 int launch_zero(void *ptr, size_t bytes, void *stream);
 int launch_sort(KRun &k, int prec, void *stream);  // swaps k's particle buffers
-size_t lds_bytes_of(const KRun &k, int prec);
 int launch_rho(const KRun &k, int prec, void *stream);
 int launch_energy(const KRun &k, int prec, int par, int nblocks_max, int *nblocks, void *stream);
 int launch_kinetic(const KRun &k, int prec, int *nblocks, void *stream);
