@@ -107,7 +107,7 @@ Layout layout_of(const pic_run_desc &d, int prec, int N, int Tz, int Tr, long lo
   L.suz = take(np * rs);
   L.sw = take(np * rs);
   L.spid = take(np * 4);
-  L.perm = take(np * 4);
+  L.perm = take(np * 8);
   L.ccount = take((size_t)(n_keys + 1) * 4);
   L.cstart = take((size_t)(n_keys + 1) * 4);
   L.scan = take(((size_t)(n_keys + 1) / 256 + 2) * 4 * 2);
@@ -405,7 +405,7 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
     k.suz = base + L.suz;
     k.sw = base + L.sw;
     k.spid = (uint32_t *)(base + L.spid);
-    k.perm = (int32_t *)(base + L.perm);
+    k.perm = (uint64_t *)(base + L.perm);
     k.cell_count = (int32_t *)(base + L.ccount);
     k.cell_start = (int32_t *)(base + L.cstart);
     k.scan_tmp = (int32_t *)(base + L.scan);

@@ -33,6 +33,7 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kFieldTile = 128;  // z-columns per field-update workgroup
+constexpr int kSortLdsEntries = 6144;  // sort entries of a tile held in LDS (48 KB)
 
 __device__ __forceinline__ int wrap_once(int c, int n) {
   c += (c < 0) ? n : 0;
@@ -1138,39 +1139,41 @@ __global__ __launch_bounds__(256) void copy_i32_kernel(int32_t *dst, const int32
   if (i < n) dst[i] = src[i];
 }
 
+// each electron's entry (id, source index) into its cell's range, in
+// whatever order the atomics run
 __global__ __launch_bounds__(256) void sort_scatter_kernel(KRun k, const int32_t *keys, int32_t *cursor) {
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= k.np) return;
-  const int key = keys[p];
-  const int pos = atomicAdd(&cursor[key], 1);
-  k.perm[pos] = (int32_t)p;
+  const int pos = atomicAdd(&cursor[keys[p]], 1);
+  k.perm[pos] = ((uint64_t)(k.pid[p] & kIdMask) << 32) | (uint64_t)p;
 }
 
-// within each cell, order the electrons by id (insertion sort; cells are short)
-__global__ __launch_bounds__(256) void sort_cells_kernel(KRun k) {
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= k.n_keys) return;
-  const int b = k.cell_start[c], e = k.cell_start[c + 1];
+// entries of one cell [b, e) in ascending id (insertion sort; cells are short)
+__device__ __forceinline__ void sort_cell(uint64_t *ent, int b, int e) {
   for (int a = b + 1; a < e; ++a) {
-    const int32_t v = k.perm[a];
-    const uint32_t key = k.pid[v] & kIdMask;
+    const uint64_t v = ent[a];
     int t = a - 1;
-    while (t >= b && (k.pid[k.perm[t]] & kIdMask) > key) {
-      k.perm[t + 1] = k.perm[t];
+    while (t >= b && ent[t] > v) {  // ids are unique, so the entry order is the id order
+      ent[t + 1] = ent[t];
       --t;
     }
-    k.perm[t + 1] = v;
+    ent[t + 1] = v;
   }
 }
 
+// Order a tile's n entries `ent` by (cell, id), then gather its electrons into
+// the transposed order the push kernel reads (see round_count).  Inlined with
+// `ent` either in LDS or in device memory, so that every access has a known
+// address space.  Cell bounds are clamped to the tile and a source index out
+// of range is skipped, so that no data can drive an access out of bounds.
 template <typename R>
-__global__ __launch_bounds__(256) void sort_permute_kernel(KRun k) {
-  // one workgroup per tile: write the tile's electrons in the transposed
-  // order the push kernel reads (see round_count)
+__device__ __forceinline__ void sort_tile(const KRun &k, uint64_t *ent, long long c0, int beg, int n) {
   const long long TT = (long long)k.Tz * k.Tr;
-  const int beg = k.cell_start[blockIdx.x * TT], end = k.cell_start[(blockIdx.x + 1) * TT];
-  const int n = end - beg;
-  if (n <= 0) return;
+  for (long long c = threadIdx.x; c < TT; c += blockDim.x) {
+    const int b = clampi(k.cell_start[c0 + c] - beg, 0, n), e = clampi(k.cell_start[c0 + c + 1] - beg, 0, n);
+    sort_cell(ent, b, e);
+  }
+  __syncthreads();
   const int chunk = (n + 255) / 256;
   const int t = threadIdx.x;
   int base = 0;
@@ -1179,7 +1182,8 @@ __global__ __launch_bounds__(256) void sort_permute_kernel(KRun k) {
     const int d = beg + base + t;
     base += cnt;
     if (t >= cnt) continue;
-    const int s = k.perm[beg + t * chunk + it];
+    const long long s = (long long)(ent[t * chunk + it] & 0xffffffffu);
+    if (s >= k.np) continue;
     if constexpr (std::is_same<R, double>::value) {
       ((double *)k.sz)[d] = ((const double *)k.pz)[s];
     } else {
@@ -1193,6 +1197,26 @@ __global__ __launch_bounds__(256) void sort_permute_kernel(KRun k) {
     ((R *)k.suz)[d] = ((const R *)k.puz)[s];
     ((R *)k.sw)[d] = ((const R *)k.pw)[s];
     k.spid[d] = k.pid[s];
+  }
+}
+
+// One workgroup per tile: its entries, ordered in LDS, or in place in device
+// memory for a tile too dense for the LDS budget.
+template <typename R>
+__global__ __launch_bounds__(256) void sort_tile_kernel(KRun k) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const long long TT = (long long)k.Tz * k.Tr;
+  const long long c0 = (long long)blockIdx.x * TT;
+  const int beg = k.cell_start[c0], end = k.cell_start[c0 + TT];
+  const int n = end - beg;
+  if (n <= 0 || beg < 0 || end > k.np) return;
+  if (n <= kSortLdsEntries) {
+    uint64_t *ent = (uint64_t *)lds_raw;
+    for (int a = threadIdx.x; a < n; a += blockDim.x) ent[a] = k.perm[beg + a];
+    __syncthreads();
+    sort_tile<R>(k, ent, c0, beg, n);
+  } else {
+    sort_tile<R>(k, k.perm + beg, c0, beg, n);
   }
 }
 
@@ -1360,12 +1384,11 @@ int launch_sort(KRun &k, int prec, void *stream) {
     if ((rc = check(hipGetLastError(), "copy_i32_kernel"))) return rc;
     sort_scatter_kernel<<<pb, 256, 0, s>>>(k, keys, k.cell_count);
     if ((rc = check(hipGetLastError(), "sort_scatter_kernel"))) return rc;
-    sort_cells_kernel<<<(unsigned)((k.n_keys + 255) / 256), 256, 0, s>>>(k);
-    if ((rc = check(hipGetLastError(), "sort_cells_kernel"))) return rc;
     const unsigned tb = (unsigned)((long long)k.ntz * k.ntr);
-    if (prec == PIC_PREC_FP64) sort_permute_kernel<double><<<tb, 256, 0, s>>>(k);
-    else sort_permute_kernel<float><<<tb, 256, 0, s>>>(k);
-    if ((rc = check(hipGetLastError(), "sort_permute_kernel"))) return rc;
+    const size_t lds = (size_t)kSortLdsEntries * sizeof(uint64_t);
+    if (prec == PIC_PREC_FP64) sort_tile_kernel<double><<<tb, 256, lds, s>>>(k);
+    else sort_tile_kernel<float><<<tb, 256, lds, s>>>(k);
+    if ((rc = check(hipGetLastError(), "sort_tile_kernel"))) return rc;
     std::swap(k.pz, k.sz);
     std::swap(k.pfz, k.sfz);
     std::swap(k.px, k.sx);

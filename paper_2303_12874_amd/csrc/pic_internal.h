@@ -56,7 +56,7 @@ struct KRun {
   uint32_t *spid;
   int32_t *cell_count;    // n_keys + 1
   int32_t *cell_start;    // n_keys + 1
-  int32_t *perm;          // np
+  uint64_t *perm;         // np sort entries: id << 32 | source index
   int32_t *scan_tmp;      // scan block sums
   int Tz, Tr;             // sort tile (cells)
   int ntz, ntr;           // tiles along z and r
