@@ -259,29 +259,55 @@ __global__ __launch_bounds__(256) void push_kernel(KRun k, int par) {
   const int per = 256 / S;
   const int colm = S * ((int)threadIdx.x % per) + (int)threadIdx.x / per;
   const R dt_dz = (R)(k.dt / k.dz), dt_dr = (R)(k.dt / k.dr);
+  // the electron of the next round is loaded while this round's is pushed
+  R nw = 0, nz = 0, nfz = 0, nx = 0, ny = 0, nux = 0, nuy = 0, nuz = 0;
+  int niz = 0;
+  uint32_t nid = 0;
+  auto fetch = [&](int pp) {
+    nw = ((const R *)k.pw)[pp];
+    nid = k.pid[pp];
+    if constexpr (F64) {
+      nz = ((const double *)k.pz)[pp];
+    } else {
+      niz = ((const int *)k.pz)[pp];
+      nfz = ((const float *)k.pfz)[pp];
+    }
+    nx = X[pp];
+    ny = Y[pp];
+    nux = UX[pp];
+    nuy = UY[pp];
+    nuz = UZ[pp];
+  };
   int base = 0;
+  int cnt = round_count(n, chunk, 0);
+  if (colm < cnt) fetch(beg + colm);
   for (int it = 0; it < chunk; ++it) {
-    const int cnt = round_count(n, chunk, it);
     const int p = beg + base + colm;
+    const bool act = colm < cnt;
+    const R cw = nw, cz = nz, cfz = nfz, cx = nx, cy = ny, cux = nux, cuy = nuy, cuz = nuz;
+    const int ciz = niz;
+    const uint32_t cid = nid;
     base += cnt;
-    if (colm >= cnt) continue;
-    const R q = -((const R *)k.pw)[p];
-    const uint32_t pidw = k.pid[p];
+    cnt = (it + 1 < chunk) ? round_count(n, chunk, it + 1) : 0;
+    if (colm < cnt) fetch(beg + base + colm);
+    if (!act) continue;
+    const R q = -cw;
+    const uint32_t pidw = cid;
 
     // ---- old position ----
-    int i0;
+    int i0, dh;  // cell of z, and -1 or 0: the half-z stencil starts at i0 + dh
     R f0, z0 = 0;
     if constexpr (F64) {
-      z0 = ((const double *)k.pz)[p];
+      z0 = cz;
       const R fl = floor(z0);
       i0 = (int)fl;
       f0 = z0 - fl;
     } else {
-      i0 = ((const int *)k.pz)[p];
-      f0 = ((const float *)k.pfz)[p];
+      i0 = ciz;
+      f0 = cfz;
     }
-    i0 = wrap_any(i0, Nz);
-    const R x0 = X[p], y0 = Y[p];
+    if ((unsigned)i0 >= (unsigned)Nz) i0 = wrap_any(i0, Nz);
+    const R x0 = cx, y0 = cy;
     const R r20 = fma(x0, x0, y0 * y0), r0 = sqrt(r20);
     const int j0 = clampi(radial_index(r20, r0), 0, Nr - 2);
     R c0 = 1, s0 = 0;
@@ -292,24 +318,23 @@ __global__ __launch_bounds__(256) void push_kernel(KRun k, int par) {
     }
 
     // ---- gather E^n and Bbar^n = (B^{n-1/2} + B^{n+1/2})/2 (Eq. (12)) ----
-    int ih;
     R fh;
     if constexpr (F64) {
       const R zz = z0 - R(0.5);
       const R fl = floor(zz);
-      ih = (int)fl;
       fh = zz - fl;
+      dh = fl < floor(z0) ? -1 : 0;
     } else {
       if (f0 >= R(0.5)) {
-        ih = i0;
+        dh = 0;
         fh = f0 - R(0.5);
       } else {
-        ih = i0 - 1;
+        dh = -1;
         fh = f0 + R(0.5);
       }
     }
     const int ci0 = i0, ci1 = wrap_once(i0 + 1, Nz);
-    const int ch0 = wrap_any(ih, Nz), ch1 = wrap_once(ch0 + 1, Nz);
+    const int ch0 = wrap_once(i0 + dh, Nz), ch1 = wrap_once(ch0 + 1, Nz);
     const R fr = r0 - (R)j0;
     const R rr = r0 - R(0.5);
     const R flr = floor(rr);
@@ -324,7 +349,7 @@ __global__ __launch_bounds__(256) void push_kernel(KRun k, int par) {
     int fc = i0 - fz0;
     fc += (fc < 0) ? Nz : 0;
     fc -= (fc >= Nz) ? Nz : 0;
-    const int a0 = fc, h0 = fc - (ch0 == ci0 ? 0 : 1);
+    const int a0 = fc, h0 = fc + dh;
     const int ri0 = j0 - fr0, rh0 = (mir ? 0 : jh) - fr0, rh1 = jh + 1 - fr0;
     if (h0 >= 0 && a0 + 1 <= FZ - 1 && ri0 >= 0 && rh0 >= 0 && ri0 + 1 <= FR - 1 && rh1 <= FR - 1) {
       const R *li0 = fw + ri0 * FZ * FS, *li1 = li0 + FZ * FS;  // rows of j0, j0 + 1
@@ -399,7 +424,7 @@ __global__ __launch_bounds__(256) void push_kernel(KRun k, int par) {
     }
 
     // ---- Boris, q/m = -1 (Eq. (6)) ----
-    const R u[3] = {UX[p], UY[p], UZ[p]};
+    const R u[3] = {cux, cuy, cuz};
     R um[3], up[3], un[3], tt[3], ss[3], u1[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) um[a] = u[a] - R(0.5) * dt * Ec[a];
@@ -640,7 +665,7 @@ __global__ __launch_bounds__(256) void push_kernel(KRun k, int par) {
       if (z1 >= (R)Nz) z1 -= (R)Nz;
       ((double *)k.pz)[p] = z1;
     } else {
-      ((int *)k.pz)[p] = wrap_any(i1, Nz);
+      ((int *)k.pz)[p] = wrap_once(i1, Nz);
       ((float *)k.pfz)[p] = f1;
     }
     X[p] = x1;
