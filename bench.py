@@ -147,7 +147,7 @@ def main(argv=None):
         kernels[ph] = {"avg_ms": ms / n, "launches": n, "GBs": ab[ph] / avg_s / 1e9}
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
     ach = kernels[dom]["GBs"]
-    default_opts = (args.sort_interval in (0, 4) and args.precision in (0, cfg["precision"])
+    default_opts = (args.sort_interval in (0, 8) and args.precision in (0, cfg["precision"])
                     and args.tile_z == 0 and args.tile_r == 0)
     traffic = measured_traffic(args.workload, dom) if default_opts else None
     value = np_ * args.steps / (elapsed_ms * 1e-3)
@@ -167,7 +167,7 @@ def main(argv=None):
         "config": {"workload": f"{args.workload}: {cfg['desc']}", "grid": f"{run['Nz']}x{run['Nr']}",
                    "modes": run["M"] + 1, "ppc": run["ppc"], "electrons": np_,
                    "precision": f"fp{prec}", "solver": "dual, 16 coefficients per operator",
-                   "dt": info["dt"], "sort_interval": args.sort_interval or 4,
+                   "dt": info["dt"], "sort_interval": args.sort_interval or 8,
                    "tile": "%dx%d" % info["tile"]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS, "traffic": traffic,

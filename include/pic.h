@@ -103,6 +103,9 @@ typedef struct pic_run_desc {
   double taper;     /* laser taper length at the box ends (0: none)           */
   uint64_t seed;    /* counter-based SplitMix64 seed of the loading           */
   int32_t n_tracked;/* electrons whose per-mode work is accumulated (FP64)    */
+  int64_t n_steps;  /* steps this run takes in total (0: no limit); pic_step
+                       leaves a run alone once it has taken them, so runs of
+                       one context can end at different times                 */
 } pic_run_desc;
 
 typedef struct pic_opts {
@@ -116,7 +119,8 @@ typedef struct pic_opts {
   const double *coef_B; /* optional n_coef values of C^B (else fitted)        */
   int32_t sort_interval;/* steps between cell sorts; 0 -> default              */
   int32_t tile_z, tile_r; /* sort tile in cells; 0 -> default                 */
-  int32_t use_graph;    /* 1: replay steps from a captured hipGraph           */
+  int32_t use_graph;    /* 1: capture each distinct step (the launches of all
+                           runs) once as a hipGraph and replay it             */
 } pic_opts;
 
 typedef struct pic_ctx pic_ctx;
@@ -202,7 +206,8 @@ int pic_run_info_get(pic_ctx *ctx, int32_t run, pic_run_info *info);
 #define PIC_PHASE_PUSH 1   /* gather + push + deposit                          */
 #define PIC_PHASE_EFIELD 2 /* E update (with the z filter of J)                */
 #define PIC_PHASE_BFIELD 3 /* B update                                         */
-#define PIC_NPHASES 4
+#define PIC_PHASE_STEP 4   /* a whole step replayed from a captured graph      */
+#define PIC_NPHASES 5
 
 /* enable != 0: from now on pic_step brackets every phase launch with HIP
  * events on the context's stream (the counters restart at zero); 0: stop.   */

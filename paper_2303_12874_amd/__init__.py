@@ -41,7 +41,7 @@ class _RunDesc(C.Structure):
         ("dz", C.c_double), ("dr", C.c_double), ("n0", C.c_double),
         ("ramp_start", C.c_double), ("ramp_len", C.c_double),
         ("n_pulses", C.c_int32), ("pulse", _Pulse * MAX_PULSES), ("taper", C.c_double),
-        ("seed", C.c_uint64), ("n_tracked", C.c_int32),
+        ("seed", C.c_uint64), ("n_tracked", C.c_int32), ("n_steps", C.c_int64),
     ]
 
 
@@ -96,7 +96,7 @@ _lib = _load()
 EXPORTED = ("pic_solver_setup", "pic_courant_limit", "pic_load_host", "pic_init", "pic_step", "pic_mode_work",
             "pic_fields", "pic_particles", "pic_coefficients", "pic_run_info_get", "pic_destroy",
             "pic_last_error", "pic_profile", "pic_profile_read")
-PHASES = ("sort", "push", "efield", "bfield")
+PHASES = ("sort", "push", "efield", "bfield", "step")  # "step": a whole step replayed from a graph
 
 
 def _check(rc):
@@ -132,6 +132,7 @@ class RunDesc:
     taper: float = 0.0
     seed: int = 0
     n_tracked: int = 0
+    n_steps: int = 0  # steps the run takes in total (0: no limit)
 
     def to_c(self) -> _RunDesc:
         r = _RunDesc()
@@ -145,6 +146,7 @@ class RunDesc:
         r.taper = self.taper
         r.seed = self.seed & (2**64 - 1)
         r.n_tracked = self.n_tracked
+        r.n_steps = self.n_steps
         return r
 
 

@@ -6,9 +6,11 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <set>
+#include <string>
 #include <vector>
 
 #include "pic_internal.h"
@@ -45,7 +47,7 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr uint32_t kMagic = 0x51D3A1C7u;
 constexpr size_t kAlign = 256;
 constexpr int kRedBlocks = 1024;
-constexpr int kDefaultSortInterval = 4;
+constexpr int kDefaultSortInterval = 8;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -142,14 +144,26 @@ struct pic_ctx {
   };
   std::vector<Mark> marks;
   std::vector<hipEvent_t> event_pool;
-  double phase_ms[PIC_NPHASES] = {0, 0, 0, 0};
-  int64_t phase_n[PIC_NPHASES] = {0, 0, 0, 0};
+  double phase_ms[PIC_NPHASES] = {0, 0, 0, 0, 0};
+  int64_t phase_n[PIC_NPHASES] = {0, 0, 0, 0, 0};
+  // captured steps: keyed by the launch arguments of the step, each holds the
+  // graph and the run views (particle buffers swapped by a sort) after it
+  bool use_graph = false;
+  struct Captured {
+    hipGraphExec_t exec;
+    Batch after;
+  };
+  std::map<std::string, Captured> graphs;
+  hipStream_t capture_stream = nullptr;  // the caller's stream may be the legacy default stream,
+                                         // which cannot be captured: steps are captured here
   ~pic_ctx() {
     for (auto &m : marks) {
       (void)hipEventDestroy(m.a);
       (void)hipEventDestroy(m.b);
     }
     for (auto &e : event_pool) (void)hipEventDestroy(e);
+    for (auto &g : graphs) (void)hipGraphExecDestroy(g.second.exec);
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
   }
 };
 
@@ -170,6 +184,7 @@ int validate_run(const pic_run_desc &r, int i, int N) {
   const int64_t np = run_particle_count(r);
   if (np > (int64_t)kIdMask) return fail(PIC_E_INVALID, "run %d: %lld electrons exceed the id range", i, (long long)np);
   if (r.n_tracked < 0 || r.n_tracked > np) return fail(PIC_E_INVALID, "run %d: n_tracked out of range", i);
+  if (r.n_steps < 0) return fail(PIC_E_INVALID, "run %d: n_steps < 0", i);
   if ((int64_t)(r.Nr + 1) * r.Nz * (2 * r.M + 1) * 3 > ((int64_t)1 << 40))
     return fail(PIC_E_INVALID, "run %d: grid too large", i);
   return PIC_OK;
@@ -198,6 +213,14 @@ int choose_tiles(const pic_opts &o, int M, int *Tz, int *Tr) {
 long long keys_of(const pic_run_desc &r, int Tz, int Tr) {
   const long long ntz = (r.Nz + Tz - 1) / Tz, ntr = (r.Nr + Tr - 1) / Tr;
   return ntz * ntr * (long long)Tz * Tr;
+}
+
+Batch batch_of_one(const KRun &k) {
+  Batch b;
+  std::memset(&b, 0, sizeof b);
+  b.n = 1;
+  b.run[0] = k;
+  return b;
 }
 
 RunHost *get_run(pic_ctx *ctx, int run) {
@@ -323,13 +346,14 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
   ctx->stream = (hipStream_t)hip_stream;
   ctx->ws = (unsigned char *)device_workspace;
   ctx->sort_interval = o.sort_interval > 0 ? o.sort_interval : kDefaultSortInterval;
+  ctx->use_graph = o.use_graph != 0;
   ctx->runs.resize((size_t)n_runs);
   const hipStream_t s = ctx->stream;
   const bool f64 = o.precision == PIC_PREC_FP64;
   const double band = o.fit_band > 0 ? o.fit_band : 2.0 * kPi / 3.0;
   const double frac = o.cfl_fraction > 0 ? o.cfl_fraction : 0.95;
 
-  int rc = PIC_OK;
+  int rc = prepare_kernels(o.precision, runs[0].M, Tz, Tr);
   for (int i = 0; i < n_runs && rc == PIC_OK; ++i) {
     RunHost &R = ctx->runs[(size_t)i];
     R.d = runs[i];
@@ -499,10 +523,17 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
         (rc = launch_zero(k.W, (size_t)(d.n_tracked > 0 ? d.n_tracked : 1) * (d.M + 1) * 8, s)))
       break;
     // B[0] = B^0 + (dt/2) curl_E E^0 = B^{-1/2};  B[1] = B^0 - (dt/2) curl_E E^0 = B^{+1/2}
-    if ((rc = launch_bfield(k, ctx->prec, k.B[0], k.B[0], -0.5 * R.dt, nullptr, s)) ||
-        (rc = launch_bfield(k, ctx->prec, k.B[1], k.B[1], 0.5 * R.dt, nullptr, s)))
-      break;
-    if ((rc = launch_sort(k, ctx->prec, s))) break;  // the push kernel works tile by tile
+    Batch b = batch_of_one(k);
+    for (int h = 0; h < 2 && rc == PIC_OK; ++h) {
+      b.bout[0] = k.B[h];
+      b.bin[0] = k.B[h];
+      b.avg[0] = nullptr;
+      b.tau[0] = (h == 0 ? -0.5 : 0.5) * R.dt;
+      rc = launch_bfield(b, ctx->prec, s);
+    }
+    if (rc) break;
+    if ((rc = launch_sort(b, ctx->prec, s))) break;  // the push kernel works tile by tile
+    k = b.run[0];
     if ((rc = hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize"))) break;
   }
   if (rc != PIC_OK) {
@@ -544,6 +575,73 @@ int timed(pic_ctx *ctx, int phase, F &&launch) {
   return rc;
 }
 
+// Enqueue one step of the runs `ids` (at most kMaxBatch, all at the same step
+// count): sort when due, then push, E update and B update, one launch per
+// phase for all of them -- or the replay of that step's captured graph.
+int step_batch(pic_ctx *ctx, const std::vector<int> &ids) {
+  hipStream_t s = ctx->stream;  // where the launches go: the caller's stream, or the capture stream
+  const int prec = ctx->prec;
+  const int64_t step = ctx->runs[(size_t)ids[0]].steps;
+  const int par = (int)(step & 1);
+  const bool sort = step > 0 && step % ctx->sort_interval == 0;
+  Batch b;
+  std::memset(&b, 0, sizeof b);  // every byte defined: the batch is a capture key
+  b.n = (int)ids.size();
+  b.par = par;
+  for (int i = 0; i < b.n; ++i) {
+    const RunHost &R = ctx->runs[(size_t)ids[(size_t)i]];
+    b.run[i] = R.k;
+    b.bout[i] = R.k.B[par];
+    b.bin[i] = R.k.B[par ^ 1];
+    b.avg[i] = R.k.Bbar;
+    b.tau[i] = R.dt;
+  }
+  auto launches = [&](bool events) {
+    auto ph = [&](int phase, auto &&f) { return events ? timed(ctx, phase, f) : f(); };
+    if (sort) TRY(ph(PIC_PHASE_SORT, [&] { return launch_sort(b, prec, s); }));
+    TRY(ph(PIC_PHASE_PUSH, [&] { return launch_push(b, prec, s); }));
+    TRY(ph(PIC_PHASE_EFIELD, [&] { return launch_efield(b, prec, s); }));
+    TRY(ph(PIC_PHASE_BFIELD, [&] { return launch_bfield(b, prec, s); }));
+    return PIC_OK;
+  };
+  if (!ctx->use_graph) {
+    TRY(launches(true));
+  } else {
+    std::string key((const char *)&b, sizeof b);
+    key.push_back(sort ? 1 : 0);
+    auto it = ctx->graphs.find(key);
+    if (it == ctx->graphs.end()) {
+      if (!ctx->capture_stream)
+        TRY(hip_ok(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking), "hipStreamCreateWithFlags"));
+      s = ctx->capture_stream;
+      TRY(hip_ok(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture"));
+      const int rc = launches(false);
+      hipGraph_t g = nullptr;
+      const hipError_t e = hipStreamEndCapture(s, &g);
+      s = ctx->stream;
+      if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      TRY(hip_ok(e, "hipStreamEndCapture"));
+      pic_ctx::Captured c;
+      const hipError_t ei = hipGraphInstantiate(&c.exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      TRY(hip_ok(ei, "hipGraphInstantiate"));
+      c.after = b;  // run views after the step (a sort swaps particle buffers)
+      it = ctx->graphs.emplace(std::move(key), c).first;
+    }
+    TRY(timed(ctx, PIC_PHASE_STEP, [&] { return hip_ok(hipGraphLaunch(it->second.exec, s), "hipGraphLaunch"); }));
+    b = it->second.after;
+  }
+  for (int i = 0; i < b.n; ++i) {
+    RunHost &R = ctx->runs[(size_t)ids[(size_t)i]];
+    R.k = b.run[i];
+    R.steps++;
+  }
+  return PIC_OK;
+}
+
 // Fold finished marks into the per-phase sums (the stream must be idle).
 int collect_marks(pic_ctx *ctx) {
   for (auto &m : ctx->marks) {
@@ -567,18 +665,18 @@ int pic_step(pic_ctx *ctx, int64_t n_steps) {
   if (!ctx_ok(ctx)) return fail(PIC_E_STATE, "invalid or destroyed context");
   if (n_steps < 0) return fail(PIC_E_INVALID, "n_steps < 0");
   const hipStream_t s = ctx->stream;
-  const int prec = ctx->prec;
+  std::vector<int> ids;
   for (int64_t n = 0; n < n_steps; ++n) {
-    for (RunHost &R : ctx->runs) {
-      const int par = (int)(R.steps & 1);
-      KRun &k = R.k;
-      if (R.steps > 0 && R.steps % ctx->sort_interval == 0)
-        TRY(timed(ctx, PIC_PHASE_SORT, [&] { return launch_sort(k, prec, s); }));
-      TRY(timed(ctx, PIC_PHASE_PUSH, [&] { return launch_push(k, prec, par, s); }));
-      TRY(timed(ctx, PIC_PHASE_EFIELD, [&] { return launch_efield(k, prec, par, s); }));
-      TRY(timed(ctx, PIC_PHASE_BFIELD,
-                [&] { return launch_bfield(k, prec, k.B[par], k.B[par ^ 1], R.dt, k.Bbar, s); }));
-      R.steps++;
+    // the runs that still have steps to take, all at the same step count
+    ids.clear();
+    for (size_t r = 0; r < ctx->runs.size(); ++r) {
+      const RunHost &R = ctx->runs[r];
+      if (R.d.n_steps == 0 || R.steps < R.d.n_steps) ids.push_back((int)r);
+    }
+    if (ids.empty()) break;
+    for (size_t g = 0; g < ids.size(); g += kMaxBatch) {
+      const std::vector<int> grp(ids.begin() + (long)g, ids.begin() + (long)std::min(ids.size(), g + kMaxBatch));
+      TRY(step_batch(ctx, grp));
     }
     // keep the number of outstanding event pairs bounded
     if (ctx->profiling && ctx->marks.size() > 4096) {

@@ -178,6 +178,14 @@ __device__ __forceinline__ int xcd_tile(int b, int ntiles) {
   return b < n8 ? (b & 7) * (n8 >> 3) + (b >> 3) : b;
 }
 
+// run of a batch that owns block g of the launch
+__device__ __forceinline__ int batch_run(const Batch &b, long long g) {
+  int r = 0;
+#pragma unroll
+  for (int i = 1; i < kMaxBatch; ++i) r += (i < b.n && g >= b.off[i]) ? 1 : 0;
+  return r;
+}
+
 // One workgroup per sort tile of Tz x Tr cells.  The tile's electrons (the
 // range the last cell sort assigned to it) are processed in contiguous
 // per-thread chunks, spread so that the 64 lanes of a wavefront sit in
@@ -194,7 +202,7 @@ __device__ __forceinline__ int xcd_tile(int b, int ntiles) {
 // An electron that drifted out of either window since the last sort gathers
 // from, or deposits to, global memory directly.
 template <typename R, int M>
-__global__ __launch_bounds__(256) void push_kernel(KRun k, int par) {
+__global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
   constexpr int NM = 2 * M + 1;       // planes per component
   constexpr int NMP = 2 * (M + 1);    // reals per field record in registers
   constexpr int FS = 6 * NM + 1;      // reals per field-window node, odd: lanes in
@@ -206,7 +214,11 @@ __global__ __launch_bounds__(256) void push_kernel(KRun k, int par) {
   // thousands of FP32 contributions keeps its low bits until the flush
   extern __shared__ __align__(16) unsigned char lds_raw[];
   double *lds = (double *)lds_raw;
-  const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+  const int gt = xcd_tile((int)blockIdx.x, (int)gridDim.x);  // tile over all runs of the batch
+  const int rn = batch_run(bt, gt);
+  const KRun &k = bt.run[rn];
+  const int par = bt.par;
+  const int tile = gt - (int)bt.off[rn];
   const int TZ = k.Tz, TR = k.Tr;
   const int WZ = TZ + 3, WR = TR + 3;
   const int tz = tile % k.ntz, tr = tile / k.ntz;
@@ -703,13 +715,18 @@ struct Cx {
 };
 
 template <typename R, int M>
-__global__ __launch_bounds__(kFieldTile) void efield_kernel(KRun k, int par) {
+__global__ __launch_bounds__(kFieldTile) void efield_kernel(const Batch bt) {
   constexpr int NMP = 2 * (M + 1);
   extern __shared__ __align__(16) unsigned char lds_raw[];
   R *lds = (R *)lds_raw;
+  const int rn = batch_run(bt, blockIdx.x);
+  const KRun &k = bt.run[rn];
+  const int par = bt.par;
   const int Nz = k.Nz, Nr = k.Nr, N = k.N;
-  const int j = blockIdx.y;
-  const int i0 = blockIdx.x * kFieldTile;
+  const int ncol = (Nz + kFieldTile - 1) / kFieldTile;
+  const int blk = (int)(blockIdx.x - bt.off[rn]);  // (row j, column block) of this run
+  const int j = blk / ncol;
+  const int i0 = (blk - j * ncol) * kFieldTile;
   const int t = threadIdx.x;
   const int W = kFieldTile + 2 * N;  // staged columns i0-N .. i0+kFieldTile+N-1
   const long long plane = k.plane, cstride = plane * (NMP - 1);  // NM planes per component
@@ -850,13 +867,21 @@ __global__ __launch_bounds__(kFieldTile) void efield_kernel(KRun k, int par) {
 // Bout = Bin - tau curl_E E; with avg != nullptr also avg = (Bin + Bout)/2,
 // the time-centred B that the next gather uses (Eq. (12)).  Bout may be Bin.
 template <typename R, int M>
-__global__ __launch_bounds__(kFieldTile) void bfield_kernel(KRun k, R *Bout, const R *Bin, R tau, R *avg) {
+__global__ __launch_bounds__(kFieldTile) void bfield_kernel(const Batch bt) {
   constexpr int NMP = 2 * (M + 1);
   extern __shared__ __align__(16) unsigned char lds_raw[];
   R *lds = (R *)lds_raw;
+  const int rn = batch_run(bt, blockIdx.x);
+  const KRun &k = bt.run[rn];
+  R *Bout = (R *)bt.bout[rn];
+  const R *Bin = (const R *)bt.bin[rn];
+  R *avg = (R *)bt.avg[rn];
+  const R tau = (R)bt.tau[rn];
   const int Nz = k.Nz, Nr = k.Nr, N = k.N;
-  const int j = blockIdx.y;
-  const int i0 = blockIdx.x * kFieldTile;
+  const int ncol = (Nz + kFieldTile - 1) / kFieldTile;
+  const int blk = (int)(blockIdx.x - bt.off[rn]);  // (row j, column block) of this run
+  const int j = blk / ncol;
+  const int i0 = (blk - j * ncol) * kFieldTile;
   const int t = threadIdx.x;
   const int W = kFieldTile + 2 * N;  // staged columns i0-N+1 .. i0+kFieldTile+N
   const long long plane = k.plane, cstride = plane * (NMP - 1);  // NM planes per component
@@ -1116,12 +1141,15 @@ __device__ __forceinline__ int cell_order(const KRun &k, long long p) {
   return tile * (k.Tz * k.Tr) + local;
 }
 
+// the keys go to the run's spid buffer, free until the gather writes it
 template <typename R>
-__global__ __launch_bounds__(256) void sort_key_kernel(KRun k, int32_t *keys) {
-  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void sort_key_kernel(const Batch bt) {
+  const int rn = batch_run(bt, blockIdx.x);
+  const KRun &k = bt.run[rn];
+  const long long p = (long long)(blockIdx.x - bt.off[rn]) * blockDim.x + threadIdx.x;
   if (p >= k.np) return;
   const int key = cell_order<R>(k, p);
-  keys[p] = key;
+  ((int32_t *)k.spid)[p] = key;
   atomicAdd(&k.cell_count[key], 1);
 }
 
@@ -1166,10 +1194,13 @@ __global__ __launch_bounds__(256) void copy_i32_kernel(int32_t *dst, const int32
 
 // each electron's entry (id, source index) into its cell's range, in
 // whatever order the atomics run
-__global__ __launch_bounds__(256) void sort_scatter_kernel(KRun k, const int32_t *keys, int32_t *cursor) {
-  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void sort_scatter_kernel(const Batch bt) {
+  const int rn = batch_run(bt, blockIdx.x);
+  const KRun &k = bt.run[rn];
+  const long long p = (long long)(blockIdx.x - bt.off[rn]) * blockDim.x + threadIdx.x;
   if (p >= k.np) return;
-  const int pos = atomicAdd(&cursor[keys[p]], 1);
+  // cell_count holds a copy of cell_start, used as the fill cursor
+  const int pos = atomicAdd(&k.cell_count[((const int32_t *)k.spid)[p]], 1);
   k.perm[pos] = ((uint64_t)(k.pid[p] & kIdMask) << 32) | (uint64_t)p;
 }
 
@@ -1228,10 +1259,12 @@ __device__ __forceinline__ void sort_tile(const KRun &k, uint64_t *ent, long lon
 // One workgroup per tile: its entries, ordered in LDS, or in place in device
 // memory for a tile too dense for the LDS budget.
 template <typename R>
-__global__ __launch_bounds__(256) void sort_tile_kernel(KRun k) {
+__global__ __launch_bounds__(256) void sort_tile_kernel(const Batch bt) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int rn = batch_run(bt, blockIdx.x);
+  const KRun &k = bt.run[rn];
   const long long TT = (long long)k.Tz * k.Tr;
-  const long long c0 = (long long)blockIdx.x * TT;
+  const long long c0 = (long long)(blockIdx.x - bt.off[rn]) * TT;
   const int beg = k.cell_start[c0], end = k.cell_start[c0 + TT];
   const int n = end - beg;
   if (n <= 0 || beg < 0 || end > k.np) return;
@@ -1293,38 +1326,57 @@ int dispatch_M(int prec, int M, A &&...a) {
   return PIC_E_INVALID;
 }
 
+// block offsets of the runs of a batch, `per(k)` blocks each; false if the
+// launch would be empty
+template <typename F>
+bool set_offsets(Batch &b, F per) {
+  b.off[0] = 0;
+  for (int i = 0; i < b.n; ++i) b.off[i + 1] = b.off[i] + per(b.run[i]);
+  for (int i = b.n; i < kMaxBatch; ++i) b.off[i + 1] = b.off[b.n];
+  return b.off[b.n] > 0;
+}
+
+template <typename R>
+constexpr int prec_of() {
+  return std::is_same<R, double>::value ? PIC_PREC_FP64 : PIC_PREC_FP32;
+}
+
+template <typename R, int M>
+struct PrepL {
+  static int run(int Tz, int Tr) {
+    // dynamic LDS above 64 KB must be allowed per kernel, once, outside any capture
+    const size_t lds = push_lds_bytes(M, Tz, Tr, prec_of<R>());
+    if (lds <= 65536) return PIC_OK;
+    return check(hipFuncSetAttribute((const void *)push_kernel<R, M>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds),
+                 "hipFuncSetAttribute(push_kernel)");
+  }
+};
 template <typename R, int M>
 struct PushL {
-  static int run(const KRun &k, int par, hipStream_t s) {
-    if (k.np == 0) return PIC_OK;
-    const unsigned blocks = (unsigned)((long long)k.ntz * k.ntr);
-    const size_t lds = push_lds_bytes(M, k.Tz, k.Tr, std::is_same<R, double>::value ? PIC_PREC_FP64 : PIC_PREC_FP32);
-    static size_t lds_set = 0;  // dynamic LDS above 64 KB must be allowed per kernel
-    if (lds > 65536 && lds > lds_set) {
-      const hipError_t e =
-          hipFuncSetAttribute((const void *)push_kernel<R, M>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      if (e != hipSuccess) return check(e, "hipFuncSetAttribute(push_kernel)");
-      lds_set = lds;
-    }
-    push_kernel<R, M><<<blocks, 256, lds, s>>>(k, par);
+  static int run(Batch &b, hipStream_t s) {
+    if (!set_offsets(b, [](const KRun &k) { return k.np > 0 ? (long long)k.ntz * k.ntr : 0LL; })) return PIC_OK;
+    const KRun &k0 = b.run[0];
+    const size_t lds = push_lds_bytes(M, k0.Tz, k0.Tr, prec_of<R>());
+    push_kernel<R, M><<<(unsigned)b.off[b.n], 256, lds, s>>>(b);
     return check(hipGetLastError(), "push_kernel");
   }
 };
 template <typename R, int M>
 struct EL {
-  static int run(const KRun &k, int par, hipStream_t s) {
-    dim3 g((k.Nz + kFieldTile - 1) / kFieldTile, k.Nr + 1);
-    const size_t lds = (size_t)4 * (kFieldTile + 2 * k.N) * 2 * (M + 1) * sizeof(R);
-    efield_kernel<R, M><<<g, kFieldTile, lds, s>>>(k, par);
+  static int run(Batch &b, hipStream_t s) {
+    set_offsets(b, [](const KRun &k) { return (long long)((k.Nz + kFieldTile - 1) / kFieldTile) * (k.Nr + 1); });
+    const size_t lds = (size_t)4 * (kFieldTile + 2 * b.run[0].N) * 2 * (M + 1) * sizeof(R);
+    efield_kernel<R, M><<<(unsigned)b.off[b.n], kFieldTile, lds, s>>>(b);
     return check(hipGetLastError(), "efield_kernel");
   }
 };
 template <typename R, int M>
 struct BL {
-  static int run(const KRun &k, void *out, const void *in, double tau, void *avg, hipStream_t s) {
-    dim3 g((k.Nz + kFieldTile - 1) / kFieldTile, k.Nr + 1);
-    const size_t lds = (size_t)2 * (kFieldTile + 2 * k.N) * 2 * (M + 1) * sizeof(R);
-    bfield_kernel<R, M><<<g, kFieldTile, lds, s>>>(k, (R *)out, (const R *)in, (R)tau, (R *)avg);
+  static int run(Batch &b, hipStream_t s) {
+    set_offsets(b, [](const KRun &k) { return (long long)((k.Nz + kFieldTile - 1) / kFieldTile) * (k.Nr + 1); });
+    const size_t lds = (size_t)2 * (kFieldTile + 2 * b.run[0].N) * 2 * (M + 1) * sizeof(R);
+    bfield_kernel<R, M><<<(unsigned)b.off[b.n], kFieldTile, lds, s>>>(b);
     return check(hipGetLastError(), "bfield_kernel");
   }
 };
@@ -1348,15 +1400,16 @@ struct EnL {
 
 const char *last_device_error() { return g_err; }
 
-int launch_push(const KRun &k, int prec, int par, void *stream) {
-  return dispatch_M<PushL>(prec, k.M, k, par, (hipStream_t)stream);
+int launch_push(Batch &b, int prec, void *stream) {
+  return dispatch_M<PushL>(prec, b.run[0].M, b, (hipStream_t)stream);
 }
-int launch_efield(const KRun &k, int prec, int par, void *stream) {
-  return dispatch_M<EL>(prec, k.M, k, par, (hipStream_t)stream);
+int launch_efield(Batch &b, int prec, void *stream) {
+  return dispatch_M<EL>(prec, b.run[0].M, b, (hipStream_t)stream);
 }
-int launch_bfield(const KRun &k, int prec, void *Bout, const void *Bin, double tau, void *avg, void *stream) {
-  return dispatch_M<BL>(prec, k.M, k, Bout, Bin, tau, avg, (hipStream_t)stream);
+int launch_bfield(Batch &b, int prec, void *stream) {
+  return dispatch_M<BL>(prec, b.run[0].M, b, (hipStream_t)stream);
 }
+int prepare_kernels(int prec, int M, int Tz, int Tr) { return dispatch_M<PrepL>(prec, M, Tz, Tr); }
 int launch_rho(const KRun &k, int prec, void *stream) {
   return dispatch_M<RhoL>(prec, k.M, k, (hipStream_t)stream);
 }
@@ -1393,27 +1446,36 @@ int launch_tracked_gamma(const KRun &k, int prec, double *gamma, int64_t *ids, v
   return check(hipGetLastError(), "tracked_gamma_kernel");
 }
 
-int launch_sort(KRun &k, int prec, void *stream) {
+int launch_sort(Batch &b, int prec, void *stream) {
   const hipStream_t s = (hipStream_t)stream;
-  const long long nk = k.n_keys + 1;
-  int rc = launch_zero(k.cell_count, (size_t)nk * 4, stream);
-  if (rc) return rc;
-  if (k.np > 0) {
-    const unsigned pb = (unsigned)((k.np + 255) / 256);
-    int32_t *keys = (int32_t *)k.spid;  // free until the permutation writes it
-    if (prec == PIC_PREC_FP64) sort_key_kernel<double><<<pb, 256, 0, s>>>(k, keys);
-    else sort_key_kernel<float><<<pb, 256, 0, s>>>(k, keys);
+  int rc;
+  for (int i = 0; i < b.n; ++i)
+    if ((rc = launch_zero(b.run[i].cell_count, (size_t)(b.run[i].n_keys + 1) * 4, stream))) return rc;
+  const auto pblocks = [](const KRun &k) { return (k.np + 255) / 256; };
+  if (set_offsets(b, pblocks)) {
+    if (prec == PIC_PREC_FP64) sort_key_kernel<double><<<(unsigned)b.off[b.n], 256, 0, s>>>(b);
+    else sort_key_kernel<float><<<(unsigned)b.off[b.n], 256, 0, s>>>(b);
     if ((rc = check(hipGetLastError(), "sort_key_kernel"))) return rc;
+  }
+  for (int i = 0; i < b.n; ++i) {
+    const KRun &k = b.run[i];
+    const long long nk = k.n_keys + 1;
     if ((rc = scan_exclusive(k.cell_count, k.cell_start, nk, k.scan_tmp, s))) return rc;
+    if (k.np == 0) continue;
     copy_i32_kernel<<<(unsigned)((nk + 255) / 256), 256, 0, s>>>(k.cell_count, k.cell_start, nk);
     if ((rc = check(hipGetLastError(), "copy_i32_kernel"))) return rc;
-    sort_scatter_kernel<<<pb, 256, 0, s>>>(k, keys, k.cell_count);
-    if ((rc = check(hipGetLastError(), "sort_scatter_kernel"))) return rc;
-    const unsigned tb = (unsigned)((long long)k.ntz * k.ntr);
-    const size_t lds = (size_t)kSortLdsEntries * sizeof(uint64_t);
-    if (prec == PIC_PREC_FP64) sort_tile_kernel<double><<<tb, 256, lds, s>>>(k);
-    else sort_tile_kernel<float><<<tb, 256, lds, s>>>(k);
-    if ((rc = check(hipGetLastError(), "sort_tile_kernel"))) return rc;
+  }
+  if (!set_offsets(b, pblocks)) return PIC_OK;
+  sort_scatter_kernel<<<(unsigned)b.off[b.n], 256, 0, s>>>(b);
+  if ((rc = check(hipGetLastError(), "sort_scatter_kernel"))) return rc;
+  set_offsets(b, [](const KRun &k) { return k.np > 0 ? (long long)k.ntz * k.ntr : 0LL; });
+  const size_t lds = (size_t)kSortLdsEntries * sizeof(uint64_t);
+  if (prec == PIC_PREC_FP64) sort_tile_kernel<double><<<(unsigned)b.off[b.n], 256, lds, s>>>(b);
+  else sort_tile_kernel<float><<<(unsigned)b.off[b.n], 256, lds, s>>>(b);
+  if ((rc = check(hipGetLastError(), "sort_tile_kernel"))) return rc;
+  for (int i = 0; i < b.n; ++i) {
+    KRun &k = b.run[i];
+    if (k.np == 0) continue;
     std::swap(k.pz, k.sz);
     std::swap(k.pfz, k.sfz);
     std::swap(k.px, k.sx);
@@ -1423,8 +1485,6 @@ int launch_sort(KRun &k, int prec, void *stream) {
     std::swap(k.puz, k.suz);
     std::swap(k.pw, k.sw);
     std::swap(k.pid, k.spid);
-  } else {
-    if ((rc = scan_exclusive(k.cell_count, k.cell_start, nk, k.scan_tmp, s))) return rc;
   }
   return PIC_OK;
 }

@@ -89,12 +89,31 @@ inline size_t push_lds_bytes(int M, int Tz, int Tr, int precision) {
          (size_t)(6 * (2 * M + 1) + 1) * field_window_z(Tz) * field_window_r(Tr) * w;
 }
 
+// ---- batched launches ---------------------------------------------------------
+// The hot kernels take up to kMaxBatch runs at once (one launch per phase for
+// all of them): a workgroup finds its run from its block index and the
+// per-run first blocks in `off`, which the launcher fills.  Runs of one batch
+// share precision, M, N and the sort tile, and step together (same parity).
+constexpr int kMaxBatch = 8;
+struct Batch {
+  int n;                            // runs in the batch
+  int par;                          // step parity: deposit into J[par], B^{n+1/2} in B[par ^ 1]
+  long long off[kMaxBatch + 1];     // first block of each run in the launch (set by the launcher)
+  KRun run[kMaxBatch];
+  // B update operands per run: Bout = Bin - tau curl_E E, and avg = (Bin + Bout)/2 when not NULL
+  void *bout[kMaxBatch];
+  const void *bin[kMaxBatch];
+  void *avg[kMaxBatch];
+  double tau[kMaxBatch];
+};
+
 // ---- kernel launchers (kernels.hip); all enqueue on `stream` -----------------
-int launch_push(const KRun &k, int prec, int par, void *stream);
-int launch_efield(const KRun &k, int prec, int par, void *stream);
-int launch_bfield(const KRun &k, int prec, void *Bout, const void *Bin, double tau, void *avg, void *stream);
+int launch_push(Batch &b, int prec, void *stream);
+int launch_efield(Batch &b, int prec, void *stream);
+int launch_bfield(Batch &b, int prec, void *stream);
+int launch_sort(Batch &b, int prec, void *stream);  // swaps the runs' particle buffers in b
+int prepare_kernels(int prec, int M, int Tz, int Tr);  // per-kernel attributes, before any capture
 int launch_zero(void *ptr, size_t bytes, void *stream);
-int launch_sort(KRun &k, int prec, void *stream);  // swaps k's particle buffers
 int launch_rho(const KRun &k, int prec, void *stream);
 int launch_energy(const KRun &k, int prec, int par, int nblocks_max, int *nblocks, void *stream);
 int launch_kinetic(const KRun &k, int prec, int *nblocks, void *stream);

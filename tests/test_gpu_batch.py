@@ -1,0 +1,94 @@
+"""GPU parity of the batched form: several runs of different grids, cell
+sizes and step limits in one context (one launch per phase for all of them),
+each against its own FP64 oracle, and captured-graph replay against eager
+stepping.
+
+Every run of a context shares the solver options, so the runs here share the
+oracle's coefficients and dt fitted for the finest cell (the coarser runs are
+then further below their Courant limit); each oracle gets the identical
+inputs.  Bar as in the single-run FP64 parity tests: 1e-10 per field array
+and mode, positions and momenta.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from test_gpu_parity import TOL64, _pic, _say, _setup, compare_fields, compare_particles, oracle_of
+
+pytestmark = pytest.mark.gpu
+
+
+def _runs():
+    """Three small runs: different dz (so different c dt/dz), grids, seeds."""
+    out = []
+    for r, (ppl, Nz, Nr, ppc) in enumerate(((16, 64, 12, 2), (20, 80, 14, 3), (24, 96, 16, 2))):
+        run = workloads.small(M=2, Nz=Nz, Nr=Nr, ppc=ppc, seed=700 + r, n_tracked=30)["runs"][0]
+        run["dz"] = workloads.LAMBDA0 / ppl
+        run["dr"] = 4 * run["dz"]
+        out.append(run)
+    return out
+
+
+def test_batched_runs_with_step_limits_match_oracles():
+    """Runs stepped together stop at their own limits and each matches its
+    oracle stepped the same number of times."""
+    _say("[gpu] batched runs with step limits")
+    pic = _pic()
+    runs = _runs()
+    dt, CE, CB, _ = _setup(16, 2, runs[-1]["dz"], runs[-1]["dr"])  # finest cell sets dt
+    limits = [12, 20, 0]
+    sim = pic.Simulation([workloads.to_rundesc(r, n_steps=n) for r, n in zip(runs, limits)], dt=dt, coef_E=CE,
+                         coef_B=CB)
+    sim.step(20)
+    for i, (run, lim) in enumerate(zip(runs, limits)):
+        steps = lim or 20
+        assert sim.info(i)["steps_done"] == steps
+        o = oracle_of(run, dt, CE, CB)
+        o.step(steps)
+        worst = compare_fields(sim, o, run["M"], TOL64, run=i)
+        bad = {k: v for k, v in worst.items() if v > TOL64}
+        assert not bad, (i, bad)
+        dzmax, dxy, du, _ = compare_particles(sim, o, run["Nz"], run=i)
+        assert dzmax < TOL64 and dxy < TOL64 and du < TOL64, (i, dzmax, dxy, du)
+        wg, wo = sim.mode_work(i), o.tracked()
+        assert np.array_equal(wg["id"], wo["id"])
+        scale = max(np.abs(wo["W"]).max(), 1e-300)
+        assert np.abs(wg["W"] - wo["W"]).max() / scale < TOL64, i
+    sim.close()
+
+
+def test_graph_replay_matches_eager_and_oracle():
+    """Two identical batched contexts, one stepping eagerly and one replaying
+    captured graphs, advanced in chunks with reads and syncs in between (sorts
+    every 4 steps, so the replays cross sorted and unsorted steps of both
+    parities); every chunk agrees to 1e-12, and the end state matches the
+    oracles to 1e-10."""
+    _say("[gpu] graph replay vs eager")
+    pic = _pic()
+    runs = _runs()[:2]
+    dt, CE, CB, _ = _setup(16, 2, runs[-1]["dz"], runs[-1]["dr"])
+    descs = [workloads.to_rundesc(r) for r in runs]
+    eager = pic.Simulation(descs, dt=dt, coef_E=CE, coef_B=CB, sort_interval=4)
+    graph = pic.Simulation(descs, dt=dt, coef_E=CE, coef_B=CB, sort_interval=4, use_graph=True)
+    done = 0
+    for chunk in (3, 5, 6, 4):
+        eager.step(chunk)
+        graph.step(chunk)
+        done += chunk
+        for i, run in enumerate(runs):
+            for comp in (0, 1, 2, 6, 7, 8, 13, 14, 15):
+                for m in range(run["M"] + 1):
+                    a, b = eager.fields(comp, m, i), graph.fields(comp, m, i)
+                    scale = max(np.abs(a).max(), 1e-300)
+                    assert np.abs(a - b).max() / scale < 1e-12, (done, i, comp, m)
+        _say(f"  chunk to step {done} agrees")
+    for i, run in enumerate(runs):
+        o = oracle_of(run, dt, CE, CB)
+        o.step(done)
+        worst = compare_fields(graph, o, run["M"], TOL64, run=i)
+        bad = {k: v for k, v in worst.items() if v > TOL64}
+        assert not bad, (i, bad)
+    eager.close()
+    graph.close()

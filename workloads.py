@@ -75,14 +75,14 @@ def small(name="tiny", M=1, Nz=64, Nr=12, ppc=2, n0=0.02, a0=1.5, seed=99, n_tra
     return dict(name=name, runs=[run], precision=64, steps=20, desc="small test grid")
 
 
-def to_rundesc(run: dict):
+def to_rundesc(run: dict, n_steps: int = 0):
     """The HIP library's RunDesc of a run (imports the binding lazily)."""
     import paper_2303_12874_amd as pic
 
     return pic.RunDesc(Nz=run["Nz"], Nr=run["Nr"], M=run["M"], ppc=run["ppc"], dz=run["dz"], dr=run["dr"],
                        n0=run["n0"], ramp_start=run["ramp_start"], ramp_len=run["ramp_len"],
                        pulses=[pic.Pulse(**p) for p in run["pulses"]], taper=run["taper"], seed=run["seed"],
-                       n_tracked=run["n_tracked"])
+                       n_tracked=run["n_tracked"], n_steps=n_steps)
 
 
 def to_oracle(run: dict, dt, CE, CB):
