@@ -4,7 +4,9 @@ One bench step = one time step of the whole hot path (cell sort when due,
 gather + push + deposit, E update with the filtered current, B update) on a
 synthetic LWFA-shaped plasma, with every input resident in HBM.  Prints one
 JSON line.  The default workload is the 4096 x 256, modes 0..2, 8 ppc FP64
-run; --workload c5 selects the 8192 x 512, modes 0..3, 16 ppc FP32 run.
+run; --workload c5 selects the 8192 x 512, modes 0..3, 16 ppc FP32 run, and
+--workload c4 the six-run FP32 convergence scan (12..64 points per
+wavelength) stepped as one batch, each run for its own number of steps.
 
 Per-kernel durations come from HIP events the library records around each
 launch on its own stream (pic_profile); the roofline object prices the
@@ -65,32 +67,38 @@ def measured_traffic(workload: str, kernel: str):
     return None if e is None else e["read_bytes"] + e["write_bytes"]
 
 
-def cpu_baseline(run: dict, nsteps: int) -> dict:
-    """FP64 oracle (as it stands) on the host: nsteps full steps of the run."""
+def cpu_baseline(runs: list, nsteps: int) -> dict:
+    """FP64 oracle (as it stands) on the host: nsteps full steps of every run."""
     import oracle
     from oracle import coef
 
-    dt, CE, CB, _ = coef.solver_setup(16, run["M"], run["dz"], run["dr"])
-    o = workloads.to_oracle(run, dt, CE, CB)
-    t0 = time.perf_counter()
-    o.step(nsteps)
-    el = time.perf_counter() - t0
-    np_ = o.np
-    return {"value": np_ * nsteps / el, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nsteps} full step(s) of the same run ({np_} electrons), serial C oracle, "
+    tot, el = 0, 0.0
+    for run in runs:
+        dt, CE, CB, _ = coef.solver_setup(16, run["M"], run["dz"], run["dr"])
+        o = workloads.to_oracle(run, dt, CE, CB)
+        t0 = time.perf_counter()
+        o.step(nsteps)
+        el += time.perf_counter() - t0
+        tot += o.np * nsteps
+        del o
+    what = "the same run" if len(runs) == 1 else f"each of the {len(runs)} runs"
+    return {"value": tot / el, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{nsteps} full step(s) of {what} ({tot // nsteps} electrons), serial C oracle, "
                       f"setup excluded, {el:.1f} s"}
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c5"])
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 200; c4: each run its own count, at most --steps)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps first (default 20; c4: 8)")
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--cpu-steps", type=int, default=1, help="oracle steps for the CPU baseline (0: skip)")
     ap.add_argument("--sort-interval", type=int, default=0)
     ap.add_argument("--tile-z", type=int, default=0, help="sort tile extent in z (0: library default)")
     ap.add_argument("--tile-r", type=int, default=0, help="sort tile extent in r (0: library default)")
+    ap.add_argument("--graph", action="store_true", help="replay captured steps (per-phase timing then unavailable)")
     ap.add_argument("--precision", type=int, default=0, choices=[0, 32, 64],
                     help="override the workload's precision (0: as defined)")
     args = ap.parse_args(argv)
@@ -103,75 +111,114 @@ def main(argv=None):
     import paper_2303_12874_amd as pic
 
     cfg = workloads.config(args.workload)
-    run = cfg["runs"][0]
+    runs = cfg["runs"]
+    multi = len(runs) > 1
+    K = args.steps if args.steps is not None else (max(cfg["steps"]) if multi else 200)
+    W = args.warmup if args.warmup is not None else (8 if multi else 20)
+    per_run = [min(n, K) for n in cfg["steps"]] if multi else [K]
     prec = args.precision or cfg["precision"]
+    sort_k = args.sort_interval or 8
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+
+    def make(limits):
+        return pic.Simulation([workloads.to_rundesc(r, n_steps=n) for r, n in zip(runs, limits)], precision=prec,
+                              sort_interval=args.sort_interval, tile_z=args.tile_z, tile_r=args.tile_r,
+                              use_graph=args.graph, device="cuda:0")
+
+    if multi:  # warm up on a context of its own, so that the timed job starts at step 0
+        warm = make([0] * len(runs))
+        warm.step(W)
+        torch.cuda.synchronize()
+        warm.close()
+        del warm
+        torch.cuda.empty_cache()
     t_init = time.perf_counter()
-    sim = pic.Simulation([workloads.to_rundesc(run)], precision=prec, sort_interval=args.sort_interval,
-                         tile_z=args.tile_z, tile_r=args.tile_r, device="cuda:0")
+    sim = make(per_run if multi else [0])
     torch.cuda.synchronize()
     t_init = time.perf_counter() - t_init
-    info = sim.info()
-    np_ = info["n_particles"]
-    print(f"# init {t_init:.1f} s, {np_} electrons, dt {info['dt']:.5f}, courant limit {info['courant_limit']:.4f}",
+    infos = [sim.info(i) for i in range(len(runs))]
+    nps = [inf["n_particles"] for inf in infos]
+    print(f"# init {t_init:.1f} s, {sum(nps)} electrons in {len(runs)} run(s), dt {[round(i['dt'], 5) for i in infos]}",
           file=sys.stderr, flush=True)
-
-    sim.step(args.warmup)
-    torch.cuda.synchronize()
-    print(f"# warmup {args.warmup} steps done", file=sys.stderr, flush=True)
+    if not multi:
+        sim.step(W)
+        torch.cuda.synchronize()
+    print(f"# warmup {W} steps done", file=sys.stderr, flush=True)
 
     sim.profile(True)
     stream = torch.cuda.current_stream(dev)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     ev0.record(stream)
-    sim.step(args.steps)
+    sim.step(K)
     ev1.record(stream)
     torch.cuda.synchronize()
     elapsed_ms = ev0.elapsed_time(ev1)
     phases = sim.profile_read()
     sim.profile(False)
-    print(f"# timed {args.steps} steps: {elapsed_ms:.2f} ms", file=sys.stderr, flush=True)
+    print(f"# timed {K} steps: {elapsed_ms:.2f} ms", file=sys.stderr, flush=True)
 
     # sanity of the state after the run (FP64 reductions)
-    mw = sim.mode_work()
-    finite = all(map(lambda v: v == v, list(mw["field_energy"]) + [mw["kinetic"]]))
+    finite = True
+    for i in range(len(runs)):
+        mw = sim.mode_work(i)
+        finite = finite and all(map(lambda v: v == v, list(mw["field_energy"]) + [mw["kinetic"]]))
 
-    ab = algorithmic_bytes(run, prec)
+    # algorithmic bytes of each phase over the timed region, summed over the runs
+    first = 0 if multi else W
+
+    def phase_bytes(ph):
+        tot = 0
+        for run, n in zip(runs, per_run):
+            ab = algorithmic_bytes(run, prec)
+            sorts = sum(1 for st in range(first, first + n) if st > 0 and st % sort_k == 0)
+            if ph == "sort":
+                tot += sorts * ab["sort"]
+            elif ph == "step":
+                tot += sorts * ab["sort"] + n * (ab["push"] + ab["efield"] + ab["bfield"])
+            else:
+                tot += n * ab[ph]
+        return tot
+
     kernels = {}
     for ph, (ms, n) in phases.items():
         if n == 0:
             continue
-        avg_s = ms / n * 1e-3
-        kernels[ph] = {"avg_ms": ms / n, "launches": n, "GBs": ab[ph] / avg_s / 1e9}
+        kernels[ph] = {"avg_ms": ms / n, "launches": n, "GBs": phase_bytes(ph) / (ms * 1e-3) / 1e9}
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
     ach = kernels[dom]["GBs"]
     default_opts = (args.sort_interval in (0, 8) and args.precision in (0, cfg["precision"])
-                    and args.tile_z == 0 and args.tile_r == 0)
+                    and args.tile_z == 0 and args.tile_r == 0 and not args.graph)
     traffic = measured_traffic(args.workload, dom) if default_opts else None
-    value = np_ * args.steps / (elapsed_ms * 1e-3)
+    particle_steps = sum(n * s for n, s in zip(nps, per_run))
+    value = particle_steps / (elapsed_ms * 1e-3)
+    run = runs[0]
+    config = {"workload": f"{args.workload}: {cfg['desc']}",
+              "grid": ", ".join(f"{r['Nz']}x{r['Nr']}" for r in runs), "modes": run["M"] + 1,
+              "ppc": run["ppc"], "electrons": sum(nps), "precision": f"fp{prec}",
+              "solver": "dual, 16 coefficients per operator", "dt": [i["dt"] for i in infos] if multi else infos[0]["dt"],
+              "sort_interval": sort_k, "tile": "%dx%d" % infos[0]["tile"], "graph": bool(args.graph)}
+    if multi:
+        config["steps_per_run"] = per_run
     out = {
         "metric": METRIC,
         "value": value,
         "unit": "particle-steps/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": elapsed_ms / args.steps,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": elapsed_ms / K,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if prec == 64 else "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {cfg['desc']}", "grid": f"{run['Nz']}x{run['Nr']}",
-                   "modes": run["M"] + 1, "ppc": run["ppc"], "electrons": np_,
-                   "precision": f"fp{prec}", "solver": "dual, 16 coefficients per operator",
-                   "dt": info["dt"], "sort_interval": args.sort_interval or 8,
-                   "tile": "%dx%d" % info["tile"]},
+        "config": config,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
-                     "bytes_per_launch": ab[dom], "avg_launch_ms": kernels[dom]["avg_ms"]},
+                     "bytes_per_launch": phase_bytes(dom) / kernels[dom]["launches"],
+                     "avg_launch_ms": kernels[dom]["avg_ms"]},
         "kernels": kernels,
         "state_finite": finite,
     }
@@ -180,7 +227,7 @@ def main(argv=None):
     torch.cuda.empty_cache()
     if args.cpu_steps > 0:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(run, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(runs, args.cpu_steps)
     print(json.dumps(out), flush=True)
     return 0
 
