@@ -7,6 +7,8 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <thread>
+#include <utility>
 #include <vector>
 
 namespace pic {
@@ -258,36 +260,59 @@ void load_electrons(const pic_run_desc &r, double *z, double *x, double *y, doub
                     int64_t *tracked) {
   const int nrc = r.Nr - 1;
   const int64_t np = run_particle_count(r);
-#pragma omp parallel for schedule(static)
-  for (int iz = 0; iz < r.Nz; ++iz)
-    for (int ir = 0; ir < nrc; ++ir)
-      for (int s = 0; s < r.ppc; ++s) {
-        int64_t pid = ((int64_t)iz * nrc + ir) * r.ppc + s;
-        double zc = iz + draw(r.seed, pid, 0);
-        double rc = ir + draw(r.seed, pid, 1);
-        double phi = 2.0 * kPi * draw(r.seed, pid, 2);
-        double n = r.n0;
-        if (r.ramp_len > 0.0) {
-          double f = (zc * r.dz - r.ramp_start) / r.ramp_len;
-          f = f < 0.0 ? 0.0 : (f > 1.0 ? 1.0 : f);
-          n = r.n0 * f;
+  const int nt_want = r.n_tracked > 0 && tracked ? r.n_tracked : 0;
+  // Every draw is a pure function of (seed, pid, d), so z-columns load in
+  // parallel with bit-identical results.  Each thread also keeps the
+  // n_tracked smallest (U3, pid) of its columns; the union holds the global
+  // n_tracked smallest.
+  using Key = std::pair<double, int64_t>;
+  unsigned nth = std::thread::hardware_concurrency();
+  nth = nth < 1 ? 1 : (nth > 16 ? 16 : nth);
+  if ((int64_t)nth > r.Nz) nth = (unsigned)r.Nz;
+  std::vector<std::vector<Key>> best(nth);
+  auto work = [&](unsigned t) {
+    const int z0 = (int)((int64_t)r.Nz * t / nth), z1 = (int)((int64_t)r.Nz * (t + 1) / nth);
+    std::vector<Key> &cand = best[t];
+    for (int iz = z0; iz < z1; ++iz)
+      for (int ir = 0; ir < nrc; ++ir)
+        for (int s = 0; s < r.ppc; ++s) {
+          int64_t pid = ((int64_t)iz * nrc + ir) * r.ppc + s;
+          double zc = iz + draw(r.seed, pid, 0);
+          double rc = ir + draw(r.seed, pid, 1);
+          double phi = 2.0 * kPi * draw(r.seed, pid, 2);
+          double n = r.n0;
+          if (r.ramp_len > 0.0) {
+            double f = (zc * r.dz - r.ramp_start) / r.ramp_len;
+            f = f < 0.0 ? 0.0 : (f > 1.0 ? 1.0 : f);
+            n = r.n0 * f;
+          }
+          if (z) z[pid] = zc;
+          if (x) x[pid] = rc * std::cos(phi);
+          if (y) y[pid] = rc * std::sin(phi);
+          if (w) w[pid] = n * (2.0 * kPi) * (rc * r.dr) * r.dr * r.dz / r.ppc;
+          if (id) id[pid] = pid;
+          if (nt_want) {
+            cand.push_back({draw(r.seed, pid, 3), pid});
+            if (cand.size() >= 2 * (size_t)nt_want + 1024) {  // keep the n_tracked smallest
+              std::nth_element(cand.begin(), cand.begin() + (nt_want - 1), cand.end());
+              cand.resize((size_t)nt_want);
+            }
+          }
         }
-        if (z) z[pid] = zc;
-        if (x) x[pid] = rc * std::cos(phi);
-        if (y) y[pid] = rc * std::sin(phi);
-        if (w) w[pid] = n * (2.0 * kPi) * (rc * r.dr) * r.dr * r.dz / r.ppc;
-        if (id) id[pid] = pid;
-      }
-  if (tracked && r.n_tracked > 0) {
-    std::vector<std::pair<double, int64_t>> keys((size_t)np);
-    for (int64_t p = 0; p < np; ++p) keys[(size_t)p] = {draw(r.seed, p, 3), p};
-    std::nth_element(keys.begin(), keys.begin() + (r.n_tracked - 1), keys.end());
-    std::vector<int64_t> sel((size_t)r.n_tracked);
-    // the n_tracked smallest keys are in [0, n_tracked) after nth_element
-    std::sort(keys.begin(), keys.begin() + r.n_tracked);
-    for (int k = 0; k < r.n_tracked; ++k) sel[(size_t)k] = keys[(size_t)k].second;
+  };
+  std::vector<std::thread> pool;
+  for (unsigned t = 1; t < nth; ++t) pool.emplace_back(work, t);
+  work(0);
+  for (auto &th : pool) th.join();
+  if (nt_want && np > 0) {
+    std::vector<Key> keys;
+    for (auto &c : best) keys.insert(keys.end(), c.begin(), c.end());
+    std::nth_element(keys.begin(), keys.begin() + (nt_want - 1), keys.end());
+    std::sort(keys.begin(), keys.begin() + nt_want);
+    std::vector<int64_t> sel((size_t)nt_want);
+    for (int k = 0; k < nt_want; ++k) sel[(size_t)k] = keys[(size_t)k].second;
     std::sort(sel.begin(), sel.end());
-    for (int k = 0; k < r.n_tracked; ++k) tracked[k] = sel[(size_t)k];
+    for (int k = 0; k < nt_want; ++k) tracked[k] = sel[(size_t)k];
   }
 }
 
