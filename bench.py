@@ -99,6 +99,8 @@ def main(argv=None):
     ap.add_argument("--tile-z", type=int, default=0, help="sort tile extent in z (0: library default)")
     ap.add_argument("--tile-r", type=int, default=0, help="sort tile extent in r (0: library default)")
     ap.add_argument("--graph", action="store_true", help="replay captured steps (per-phase timing then unavailable)")
+    ap.add_argument("--autotune", type=int, default=None,
+                    help="1: tile and sort interval from the library's autotuner (default: on for c4 only)")
     ap.add_argument("--precision", type=int, default=0, choices=[0, 32, 64],
                     help="override the workload's precision (0: as defined)")
     args = ap.parse_args(argv)
@@ -117,9 +119,20 @@ def main(argv=None):
     W = args.warmup if args.warmup is not None else (8 if multi else 20)
     per_run = [min(n, K) for n in cfg["steps"]] if multi else [K]
     prec = args.precision or cfg["precision"]
-    sort_k = args.sort_interval or 8
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    tune = None
+    if args.autotune if args.autotune is not None else multi:
+        t0 = time.perf_counter()
+        tune = pic.autotune([workloads.to_rundesc(r) for r in runs], precision=prec, tile_z=args.tile_z,
+                            tile_r=args.tile_r, device="cuda:0")
+        torch.cuda.empty_cache()
+        args.tile_z, args.tile_r = tune["tile_z"], tune["tile_r"]
+        args.sort_interval = args.sort_interval or tune["sort_interval"]
+        tune["seconds"] = time.perf_counter() - t0
+        print(f"# autotune {tune['seconds']:.1f} s: tile {args.tile_z}x{args.tile_r}, sort every "
+              f"{args.sort_interval}; {tune['candidates']}", file=sys.stderr, flush=True)
+    sort_k = args.sort_interval or 8
 
     def make(limits):
         return pic.Simulation([workloads.to_rundesc(r, n_steps=n) for r, n in zip(runs, limits)], precision=prec,
@@ -189,7 +202,7 @@ def main(argv=None):
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
     ach = kernels[dom]["GBs"]
     default_opts = (args.sort_interval in (0, 8) and args.precision in (0, cfg["precision"])
-                    and args.tile_z == 0 and args.tile_r == 0 and not args.graph)
+                    and args.tile_z == 0 and args.tile_r == 0 and not args.graph and tune is None)
     traffic = measured_traffic(args.workload, dom) if default_opts else None
     particle_steps = sum(n * s for n, s in zip(nps, per_run))
     value = particle_steps / (elapsed_ms * 1e-3)
@@ -201,6 +214,9 @@ def main(argv=None):
               "sort_interval": sort_k, "tile": "%dx%d" % infos[0]["tile"], "graph": bool(args.graph)}
     if multi:
         config["steps_per_run"] = per_run
+    if tune is not None:
+        config["autotune"] = {"seconds": round(tune["seconds"], 1),
+                              "candidates": [list(c[:3]) + [round(c[3], 4)] for c in tune["candidates"]]}
     out = {
         "metric": METRIC,
         "value": value,

@@ -217,6 +217,32 @@ int pic_profile(pic_ctx *ctx, int32_t enable);
  * number of launches timed since pic_profile(ctx, 1).                       */
 int pic_profile_read(pic_ctx *ctx, double *ms, int64_t *launches);
 
+/* ---- autotuner ---------------------------------------------------------- */
+#define PIC_MAX_TUNE 16
+
+typedef struct pic_tune_report {
+  int32_t n;                          /* tiles tried                          */
+  int32_t tile_z[PIC_MAX_TUNE], tile_r[PIC_MAX_TUNE];
+  int32_t interval[PIC_MAX_TUNE];     /* best sort interval for that tile     */
+  double ms_per_step[PIC_MAX_TUNE];   /* measured cost per step at it         */
+  int32_t best;                       /* index of the choice written to opts  */
+} pic_tune_report;
+
+/* Pick the sort tile and the sort interval K for these runs and options by
+ * measurement (neither changes the physics, only the summation order of the
+ * deposit).  For every candidate tile whose push workgroup fits the LDS
+ * (the tile in opts, if set, is the only candidate) a trial context is built
+ * in device_workspace on hip_stream; after one untimed step and a timed sort,
+ * trial_steps steps (4..64) are timed one by one with HIP events, t_k at k
+ * steps after the sort, and K = argmin (t_sort + sum_{k<K} t_k) / K.  The
+ * fastest (tile, K) is written to opts->tile_z, tile_r, sort_interval; the
+ * trial contexts are destroyed.  With device_workspace NULL only the bytes
+ * needed (the largest trial context) are written to *workspace_bytes.
+ * report may be NULL.  Times are those of the early, still cold plasma of
+ * the trial, which the caller should keep in mind for long runs.            */
+int pic_autotune(const pic_run_desc *runs, int32_t n_runs, pic_opts *opts, void *device_workspace,
+                 size_t *workspace_bytes, void *hip_stream, int32_t trial_steps, pic_tune_report *report);
+
 /* Free host objects of the context (not the workspace).                     */
 int pic_destroy(pic_ctx *ctx);
 

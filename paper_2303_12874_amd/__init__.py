@@ -61,6 +61,14 @@ class _RunInfo(C.Structure):
                 ("tile_z", C.c_int32), ("tile_r", C.c_int32)]
 
 
+MAX_TUNE = 16
+
+
+class _TuneReport(C.Structure):
+    _fields_ = [("n", C.c_int32), ("tile_z", C.c_int32 * MAX_TUNE), ("tile_r", C.c_int32 * MAX_TUNE),
+                ("interval", C.c_int32 * MAX_TUNE), ("ms_per_step", C.c_double * MAX_TUNE), ("best", C.c_int32)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (or python -m "
@@ -82,6 +90,8 @@ def _load():
         "pic_destroy": [p],
         "pic_profile": [p, i32],
         "pic_profile_read": [p, p, p],
+        "pic_autotune": [C.POINTER(_RunDesc), i32, C.POINTER(_Opts), p, C.POINTER(C.c_size_t), p, i32,
+                         C.POINTER(_TuneReport)],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)
@@ -95,7 +105,7 @@ def _load():
 _lib = _load()
 EXPORTED = ("pic_solver_setup", "pic_courant_limit", "pic_load_host", "pic_init", "pic_step", "pic_mode_work",
             "pic_fields", "pic_particles", "pic_coefficients", "pic_run_info_get", "pic_destroy",
-            "pic_last_error", "pic_profile", "pic_profile_read")
+            "pic_last_error", "pic_profile", "pic_profile_read", "pic_autotune")
 PHASES = ("sort", "push", "efield", "bfield", "step")  # "step": a whole step replayed from a graph
 
 
@@ -203,6 +213,28 @@ def _make_opts(precision, solver, n_coef, dt=0.0, coef_E=None, coef_B=None, cfl_
             setattr(o, name, a.ctypes.data_as(C.POINTER(C.c_double)))
     o.sort_interval, o.tile_z, o.tile_r, o.use_graph = sort_interval, tile_z, tile_r, int(use_graph)
     return o, keep
+
+
+def autotune(runs: Sequence[RunDesc], precision=PREC_FP64, solver=SOLVER_DUAL, n_coef=16, device="cuda:0",
+             trial_steps=16, **kw) -> dict:
+    """Sort tile and sort interval picked by pic_autotune for these runs and
+    options: {"tile_z", "tile_r", "sort_interval", "candidates": [(tile_z,
+    tile_r, interval, ms_per_step), ...]}.  Pass the first three to
+    Simulation.  Trial contexts live in a temporary torch workspace."""
+    import torch  # device memory and streams only
+
+    arr = (_RunDesc * len(runs))(*[r.to_c() for r in runs])
+    opts, keep = _make_opts(precision, solver, n_coef, **kw)
+    nbytes = C.c_size_t(0)
+    _check(_lib.pic_autotune(arr, len(runs), C.byref(opts), None, C.byref(nbytes), None, int(trial_steps), None))
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=torch.device(device))
+    stream = torch.cuda.current_stream(torch.device(device))
+    rep = _TuneReport()
+    _check(_lib.pic_autotune(arr, len(runs), C.byref(opts), C.c_void_p(ws.data_ptr()), C.byref(nbytes),
+                             C.c_void_p(stream.cuda_stream), int(trial_steps), C.byref(rep)))
+    del ws, keep
+    cands = [(rep.tile_z[i], rep.tile_r[i], rep.interval[i], rep.ms_per_step[i]) for i in range(rep.n)]
+    return {"tile_z": opts.tile_z, "tile_r": opts.tile_r, "sort_interval": opts.sort_interval, "candidates": cands}
 
 
 class Simulation:

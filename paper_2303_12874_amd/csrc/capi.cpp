@@ -642,6 +642,23 @@ int step_batch(pic_ctx *ctx, const std::vector<int> &ids) {
   return PIC_OK;
 }
 
+// Sort every run of the context now (outside the step cadence).
+int sort_runs_now(pic_ctx *ctx) {
+  for (size_t g = 0; g < ctx->runs.size(); g += kMaxBatch) {
+    Batch b;
+    std::memset(&b, 0, sizeof b);
+    b.n = (int)std::min(ctx->runs.size() - g, (size_t)kMaxBatch);
+    for (int i = 0; i < b.n; ++i) b.run[i] = ctx->runs[g + (size_t)i].k;
+    TRY(launch_sort(b, ctx->prec, ctx->stream));
+    for (int i = 0; i < b.n; ++i) ctx->runs[g + (size_t)i].k = b.run[i];
+  }
+  return PIC_OK;
+}
+
+// Candidate sort tiles of the autotuner (those whose push workgroup fits the LDS).
+constexpr int kTuneTiles[][2] = {{32, 8}, {32, 6}, {32, 4}, {30, 4}, {24, 8}, {24, 4}, {16, 8},
+                                 {16, 4}, {64, 4}, {64, 2}, {48, 4}, {32, 2}};
+
 // Fold finished marks into the per-phase sums (the stream must be idle).
 int collect_marks(pic_ctx *ctx) {
   for (auto &m : ctx->marks) {
@@ -684,6 +701,113 @@ int pic_step(pic_ctx *ctx, int64_t n_steps) {
       TRY(collect_marks(ctx));
     }
   }
+  return PIC_OK;
+}
+
+int pic_autotune(const pic_run_desc *runs, int32_t n_runs, pic_opts *opts, void *device_workspace,
+                 size_t *workspace_bytes, void *hip_stream, int32_t trial_steps, pic_tune_report *report) {
+  g_msg[0] = 0;
+  if (!runs || n_runs < 1 || !opts || !workspace_bytes) return fail(PIC_E_INVALID, "NULL or empty argument");
+  if (trial_steps < 4 || trial_steps > 64) return fail(PIC_E_INVALID, "trial_steps must be in 4..64");
+  if (opts->precision != PIC_PREC_FP64 && opts->precision != PIC_PREC_FP32)
+    return fail(PIC_E_INVALID, "precision must be 64 or 32");
+  std::vector<pic_run_desc> rd(runs, runs + n_runs);
+  for (auto &r : rd) r.n_steps = 0;  // trials take as many steps as they need
+  std::vector<std::pair<int, int>> cand;
+  if (opts->tile_z > 0 || opts->tile_r > 0) {
+    int Tz, Tr;
+    TRY(choose_tiles(*opts, rd[0].M, &Tz, &Tr));
+    cand.push_back({Tz, Tr});
+  } else {
+    for (const auto &t : kTuneTiles)
+      if (push_lds_bytes(rd[0].M, t[0], t[1], opts->precision) <= kPushLdsMax && cand.size() < PIC_MAX_TUNE)
+        cand.push_back({t[0], t[1]});
+  }
+  pic_opts o = *opts;
+  o.use_graph = 0;
+  o.sort_interval = 1 << 30;  // no sort inside the timed steps
+  size_t need = 0;
+  for (const auto &c : cand) {
+    o.tile_z = c.first;
+    o.tile_r = c.second;
+    size_t b = 0;
+    TRY(pic_init(rd.data(), n_runs, &o, nullptr, &b, nullptr, nullptr));
+    need = std::max(need, b);
+  }
+  if (!device_workspace) {
+    *workspace_bytes = need;
+    return PIC_OK;
+  }
+  if (*workspace_bytes < need) return fail(PIC_E_NOMEM, "workspace of %zu bytes, %zu needed", *workspace_bytes, need);
+  const hipStream_t s = (hipStream_t)hip_stream;
+  const int T = trial_steps;
+  std::vector<hipEvent_t> ev((size_t)T + 2, nullptr);
+  for (auto &e : ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      for (auto &x : ev)
+        if (x) (void)hipEventDestroy(x);
+      return fail(PIC_E_DEVICE, "hipEventCreate failed");
+    }
+  pic_tune_report rep;
+  std::memset(&rep, 0, sizeof rep);
+  rep.best = -1;
+  double best = 0.0;
+  int rc = PIC_OK;
+  for (size_t i = 0; i < cand.size() && rc == PIC_OK; ++i) {
+    o.tile_z = cand[i].first;
+    o.tile_r = cand[i].second;
+    pic_ctx *ctx = nullptr;
+    size_t b = *workspace_bytes;
+    if ((rc = pic_init(rd.data(), n_runs, &o, device_workspace, &b, hip_stream, &ctx))) break;
+    // one untimed step (kernels loaded, caches warm), then a timed sort: the
+    // timed steps start from a freshly sorted state
+    rc = pic_step(ctx, 1);
+    if (!rc) rc = hip_ok(hipEventRecord(ev[0], s), "hipEventRecord");
+    if (!rc) rc = sort_runs_now(ctx);
+    if (!rc) rc = hip_ok(hipEventRecord(ev[1], s), "hipEventRecord");
+    for (int k = 0; k < T && !rc; ++k) {
+      rc = pic_step(ctx, 1);
+      if (!rc) rc = hip_ok(hipEventRecord(ev[(size_t)k + 2], s), "hipEventRecord");
+    }
+    if (!rc) rc = hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize");
+    double t_sort = 0.0, sum = 0.0, cost = 0.0;
+    int bestK = 1;
+    for (int k = 0; k <= T && !rc; ++k) {
+      float ms = 0.f;
+      rc = hip_ok(hipEventElapsedTime(&ms, ev[(size_t)k], ev[(size_t)k + 1]), "hipEventElapsedTime");
+      if (k == 0) {
+        t_sort = ms;
+        continue;
+      }
+      sum += ms;
+      const double c = (t_sort + sum) / k;  // mean step cost when sorting every k steps
+      if (k == 1 || c < cost) {
+        cost = c;
+        bestK = k;
+      }
+    }
+    const int rd_rc = pic_destroy(ctx);
+    if (rc) break;
+    if (rd_rc) {
+      rc = rd_rc;
+      break;
+    }
+    rep.tile_z[rep.n] = cand[i].first;
+    rep.tile_r[rep.n] = cand[i].second;
+    rep.interval[rep.n] = bestK;
+    rep.ms_per_step[rep.n] = cost;
+    if (rep.best < 0 || cost < best) {
+      best = cost;
+      rep.best = rep.n;
+    }
+    rep.n++;
+  }
+  for (auto &e : ev) (void)hipEventDestroy(e);
+  if (rc) return rc;
+  opts->tile_z = rep.tile_z[rep.best];
+  opts->tile_r = rep.tile_r[rep.best];
+  opts->sort_interval = rep.interval[rep.best];
+  if (report) *report = rep;
   return PIC_OK;
 }
 

@@ -7,7 +7,10 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <thread>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -221,7 +224,26 @@ double courant_limit_of(const double *CE, const double *CB, int N, int M, double
 }
 
 // Bisection on c dt/dz with a refit at every trial (the targets depend on dt).
+// The fitted limit depends on dz and dr only through dz/dr; runs that share
+// (solver, N, M, dz/dr, band) -- the cells of a resolution scan -- share it.
+static double courant_limit_search(int solver, int N, int M, double dz, double dr, double band);
+
 double courant_limit_fitted(int solver, int N, int M, double dz, double dr, double band) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, int, double, double>, double> memo;
+  const auto key = std::make_tuple(solver, N, M, dz / dr, band);
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = memo.find(key);
+    if (it != memo.end()) return it->second;
+  }
+  const double lim = courant_limit_search(solver, N, M, dz, dr, band);
+  std::lock_guard<std::mutex> lk(mu);
+  memo[key] = lim;
+  return lim;
+}
+
+static double courant_limit_search(int solver, int N, int M, double dz, double dr, double band) {
   std::vector<double> CE(N), CB(N);
   double lo = 0.0, hi = 1.0;
   for (int it = 0; it < 60; ++it) {

@@ -124,3 +124,33 @@ def test_loader_ramp_bit_exact():
     o.load_plasma(run["ppc"], run["n0"], run["ramp_start"], run["ramp_len"], run["seed"], run["n_tracked"])
     assert np.array_equal(L["w"], o.particles()["w"])
     assert (L["w"] == 0).any() and (L["w"] > 0).any()
+
+
+def _tune_query(runs, trial_steps=16, **kw):
+    arr = (pic._RunDesc * len(runs))(*[r.to_c() for r in runs])
+    opts, keep = pic._make_opts(kw.pop("precision", pic.PREC_FP64), pic.SOLVER_DUAL, 16, **kw)
+    nbytes = ctypes.c_size_t(0)
+    rc = pic._lib.pic_autotune(arr, len(runs), ctypes.byref(opts), None, ctypes.byref(nbytes), None, trial_steps,
+                               None)
+    return rc, nbytes.value, opts
+
+
+def test_autotune_workspace_query_covers_every_candidate():
+    """The autotuner's size query needs no device and covers its largest
+    trial context: at least the context of any fitting candidate tile."""
+    runs = [_desc(M=2, Nz=96, Nr=20), _desc(M=2, Nz=64, Nr=12)]
+    rc, need, opts = _tune_query(runs)
+    assert rc == pic.PIC_OK and need > 0
+    for tz, tr in ((32, 8), (16, 4), (64, 2)):
+        assert need >= pic.workspace_bytes(runs, tile_z=tz, tile_r=tr)
+    # a fixed tile is the only candidate
+    rc, need1, _ = _tune_query(runs, tile_z=16, tile_r=4)
+    assert rc == pic.PIC_OK and need1 == pic.workspace_bytes(runs, tile_z=16, tile_r=4)
+
+
+def test_autotune_rejects_bad_arguments():
+    runs = [_desc(M=1)]
+    assert _tune_query(runs, trial_steps=2)[0] == pic.PIC_E_INVALID
+    assert _tune_query(runs, trial_steps=65)[0] == pic.PIC_E_INVALID
+    assert _tune_query(runs, precision=16)[0] == pic.PIC_E_INVALID
+    assert _tune_query([_desc(M=1), _desc(M=2)])[0] == pic.PIC_E_INVALID

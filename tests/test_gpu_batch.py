@@ -92,3 +92,31 @@ def test_graph_replay_matches_eager_and_oracle():
         assert not bad, (i, bad)
     eager.close()
     graph.close()
+
+
+def test_autotune_reports_candidates_and_choice_keeps_parity():
+    """The autotuner times every fitting candidate tile on the GPU, returns
+    the cheapest (tile, interval), and a run with that choice still matches
+    the oracle (the choice changes no physics)."""
+    _say("[gpu] autotune")
+    pic = _pic()
+    runs = _runs()[:2]
+    dt, CE, CB, _ = _setup(16, 2, runs[-1]["dz"], runs[-1]["dr"])
+    descs = [workloads.to_rundesc(r) for r in runs]
+    t = pic.autotune(descs, dt=dt, coef_E=CE, coef_B=CB, trial_steps=8)
+    cands = t["candidates"]
+    assert len(cands) >= 4
+    assert all(ms > 0 and 1 <= k <= 8 for _, _, k, ms in cands)
+    best = min(cands, key=lambda c: c[3])
+    assert (t["tile_z"], t["tile_r"], t["sort_interval"]) == best[:3]
+    _say(f"  chose {best}")
+    sim = pic.Simulation(descs, dt=dt, coef_E=CE, coef_B=CB, tile_z=t["tile_z"], tile_r=t["tile_r"],
+                         sort_interval=t["sort_interval"])
+    sim.step(12)
+    for i, run in enumerate(runs):
+        o = oracle_of(run, dt, CE, CB)
+        o.step(12)
+        worst = compare_fields(sim, o, run["M"], TOL64, run=i)
+        bad = {k: v for k, v in worst.items() if v > TOL64}
+        assert not bad, (i, bad)
+    sim.close()
