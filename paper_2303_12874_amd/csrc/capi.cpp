@@ -68,7 +68,7 @@ struct RunHost {
 struct Layout {
   size_t E, B0, B1, Bbar, J0, J1, rho, pz, pfz, px, py, pux, puy, puz, pw, pid;
   size_t sz, sfz, sx, sy, sux, suy, suz, sw, spid, perm, ccount, cstart, scan;
-  size_t W, tracked, CE, CB, P, red, gam, ids, total;
+  size_t W, tracked, CE, CB, P, red, gam, ids, work, total;
 };
 
 Layout layout_of(const pic_run_desc &d, int prec, int N, int Tz, int Tr, long long n_keys) {
@@ -119,6 +119,7 @@ Layout layout_of(const pic_run_desc &d, int prec, int N, int Tz, int Tr, long lo
   L.CB = take((size_t)N * rs);
   L.P = take((size_t)(2 * N - 1) * rs);
   L.red = take((size_t)kRedBlocks * (PIC_MAX_MODES + 1) * 8);
+  L.work = take(16);
   L.gam = take((size_t)(d.n_tracked > 0 ? d.n_tracked : 1) * 8);
   L.ids = take((size_t)(d.n_tracked > 0 ? d.n_tracked : 1) * 8);
   L.total = o;
@@ -445,6 +446,7 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
     k.CB = base + L.CB;
     k.P = base + L.P;
     k.red = (double *)(base + L.red);
+    k.work = (int32_t *)(base + L.work);
     R.dev_gamma = (double *)(base + L.gam);
     R.dev_ids = (int64_t *)(base + L.ids);
 

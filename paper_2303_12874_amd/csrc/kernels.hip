@@ -153,29 +153,20 @@ __device__ __forceinline__ void interp4(const R *pa, const R *pb, const R *pc, c
                                         bool mirror, R fz, R fr, R out[NMP]) {
   const R w00 = (R(1) - fz) * (R(1) - fr), w10 = fz * (R(1) - fr);
   const R w01 = (R(1) - fz) * fr, w11 = fz * fr;
+  // lower-row weights of the modes whose mirror sign is -1
+  const R n00 = (HALF_R && mirror) ? -w00 : w00, n10 = (HALF_R && mirror) ? -w10 : w10;
   R a[NMP], b[NMP], c[NMP], d[NMP];
   load_node<R, NMP, I>(pa, pstride, 0, a);
   load_node<R, NMP, I>(pb, pstride, 0, b);
   load_node<R, NMP, I>(pc, pstride, 0, c);
   load_node<R, NMP, I>(pd, pstride, 0, d);
+  out[1] = R(0);  // Im of m = 0
 #pragma unroll
   for (int s = 0; s < NMP; ++s) {
-    R va = a[s], vb = b[s];
-    if (HALF_R && mirror) {
-      const R sg = (R)mirror_sign_m(s / 2, ZCOMP);
-      va *= sg;
-      vb *= sg;
-    }
-    out[s] = w00 * va + w10 * vb + w01 * c[s] + w11 * d[s];
+    if (s == 1) continue;
+    const bool neg = HALF_R && mirror_sign_m(s / 2, ZCOMP) < 0;
+    out[s] = (neg ? n00 : w00) * a[s] + (neg ? n10 : w10) * b[s] + w01 * c[s] + w11 * d[s];
   }
-}
-
-// Tiles are numbered z-fastest; workgroups go to the 8 XCDs round-robin.
-// Give each XCD a contiguous run of tiles so that neighbours, whose field and
-// current windows overlap, share one L2.
-__device__ __forceinline__ int xcd_tile(int b, int ntiles) {
-  const int n8 = ntiles & ~7;
-  return b < n8 ? (b & 7) * (n8 >> 3) + (b >> 3) : b;
 }
 
 // run of a batch that owns block g of the launch
@@ -214,50 +205,72 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
   // thousands of FP32 contributions keeps its low bits until the flush
   extern __shared__ __align__(16) unsigned char lds_raw[];
   double *lds = (double *)lds_raw;
-  const int gt = xcd_tile((int)blockIdx.x, (int)gridDim.x);  // tile over all runs of the batch
+  const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6, nwave = (int)blockDim.x >> 6;
+  const int par = bt.par;
+  const int TZ = bt.run[0].Tz, TR = bt.run[0].Tr;  // one sort tile for every run of a batch
+  const int WZ = TZ + 3, WR = TR + 3;
+  const long long TT = (long long)TZ * TR;
+  const int nlds = JS * WZ * WR;
+  const int FZ = TZ + 2 + 2 * kFieldMarginZ, FR = TR + 2 + 2 * kFieldMarginR;
+  R *fw = (R *)(lds + nlds);
+
+  // Persistent: each workgroup takes tiles (of all runs of the batch) from a
+  // ticket counter, zero before the launch, until none are left; the dealing
+  // is dynamic, so tiles of uneven cost (the laser region) spread evenly.
+  const int ntiles = (int)bt.off[bt.n];
+  __shared__ int ticket;
+  if (threadIdx.x == 0) ticket = atomicAdd(bt.run[0].work, 1);
+  __syncthreads();
+  int gt = ticket;
+  const int t_hi = ntiles;
+  // node e of the field window of tile g (run, then tile of the run): all
+  // 6 NM planes, loaded together so that they are in flight at once
+  auto stage_load = [&](int g, int e, R v[FS]) {
+    const int rg = batch_run(bt, g);
+    const KRun &kg = bt.run[rg];
+    const int tl = g - (int)bt.off[rg];
+    const int fz0g = (tl % kg.ntz) * TZ - 1 - kFieldMarginZ, fr0g = (tl / kg.ntz) * TR - 1 - kFieldMarginR;
+    const int row = e / FZ, col = e - row * FZ;
+    const int grow = fr0g + row;
+    const bool ok = grow >= 0 && grow <= kg.Nr;
+    const long long pl = kg.plane;
+    const long long gg = (long long)(ok ? grow : 0) * kg.Nz + wrap_any(fz0g + col, kg.Nz);
+    const R *Eg = (const R *)kg.E, *Bg = (const R *)kg.Bbar;
+#pragma unroll
+    for (int cq = 0; cq < FS; ++cq) {
+      const int c = cq / NM, q = cq % NM;
+      v[cq] = (ok && cq < 6 * NM) ? (c < 3 ? Eg : Bg)[(c % 3) * pl * NM + q * pl + gg] : R(0);
+    }
+  };
+  auto stage_store = [&](int e, const R v[FS]) {
+#pragma unroll
+    for (int cq = 0; cq < FS; ++cq) fw[e * FS + cq] = v[cq];
+  };
+
+  // the current window starts at zero; each flush clears what it adds
+  for (int e = threadIdx.x; e < nlds; e += blockDim.x) lds[e] = 0.0;
+  if (gt < t_hi)
+    for (int e = threadIdx.x; e < FZ * FR; e += blockDim.x) {
+      R v[FS];
+      stage_load(gt, e, v);
+      stage_store(e, v);
+    }
+  __syncthreads();
+
+  while (gt < t_hi) {
   const int rn = batch_run(bt, gt);
   const KRun &k = bt.run[rn];
-  const int par = bt.par;
   const int tile = gt - (int)bt.off[rn];
-  const int TZ = k.Tz, TR = k.Tr;
-  const int WZ = TZ + 3, WR = TR + 3;
   const int tz = tile % k.ntz, tr = tile / k.ntz;
   const int zlo = tz * TZ - 1, rlo = tr * TR - 1;
-  const long long TT = (long long)TZ * TR;
   const int beg = k.cell_start[tile * TT], end = k.cell_start[(tile + 1) * TT];
-  if (beg >= end) return;
-  const int nlds = JS * WZ * WR;
-  for (int e = threadIdx.x; e < nlds; e += blockDim.x) lds[e] = 0.0;
-
   const int Nz = k.Nz, Nr = k.Nr;
   const long long plane = k.plane;
   const long long cstride = plane * NM;  // reals per component
   const R dt = (R)k.dt;
   const R *E = (const R *)k.E;
   const R *Bb = (const R *)k.Bbar;
-  const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6, nwave = (int)blockDim.x >> 6;
-
-  // ---- stage the field window ----
-  const int FZ = TZ + 2 + 2 * kFieldMarginZ, FR = TR + 2 + 2 * kFieldMarginR;
   const int fz0 = tz * TZ - 1 - kFieldMarginZ, fr0 = tr * TR - 1 - kFieldMarginR;
-  R *fw = (R *)(lds + nlds);
-  // each thread takes one node and loads it from all 6 NM planes at once,
-  // so that the loads are in flight together
-  for (int e = threadIdx.x; e < FZ * FR; e += blockDim.x) {
-    const int row = e / FZ, col = e - row * FZ;
-    const int grow = fr0 + row;
-    const bool ok = grow >= 0 && grow <= Nr;
-    const long long g = (long long)(ok ? grow : 0) * Nz + wrap_any(fz0 + col, Nz);
-    R v[FS];
-#pragma unroll
-    for (int cq = 0; cq < FS; ++cq) {
-      const int c = cq / NM, q = cq % NM;
-      v[cq] = ok ? (c < 3 ? E : Bb)[(c % 3) * cstride + q * plane + g] : R(0);
-    }
-#pragma unroll
-    for (int cq = 0; cq < FS; ++cq) fw[e * FS + cq] = v[cq];
-  }
-  __syncthreads();
   R *J = (R *)k.J[par];
   R *X = (R *)k.px, *Y = (R *)k.py, *UX = (R *)k.pux, *UY = (R *)k.puy, *UZ = (R *)k.puz;
 
@@ -577,6 +590,35 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
         }
       // the whole deposit, into `dep(c, plane, b, a, v)`: component c (0 r,
       // 1 phi, 2 z), window node (ib + a, jb + b)
+      // Node weights, shared by every mode (in FP64 for both precisions: each
+      // contribution is then one FP64 product of a node weight and a mode
+      // coefficient): J_z at face (ib+a+1/2, jb+b) carries minus the running
+      // sum of Wz behind it, J_r at (ib+a, jb+b+1/2) minus the running sum of
+      // Wr below it, J_phi at node (ib+a, jb+b) half the summed shape.
+      double wz[3][2], wr[3][2], ws[3][3];
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        R run = 0;
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          run += Wz[a][b];
+          wz[b][a] = -(double)run;
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        R run = 0;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          run += Wr[a][b];
+          wr[a][b] = -(double)run;
+        }
+#pragma unroll
+        for (int b = 0; b < 3; ++b) ws[a][b] = (double)(R(0.5) * Ss[a][b]);
+      }
+      const bool axis_row = jb == 0;  // row b = 0 of the window is the axis
+      // the whole deposit, into `dep(c, plane, b, a, v)`: component c (0 r,
+      // 1 phi, 2 z), window node (ib + a, jb + b)
       auto deposit = [&](auto &&dep) {
         // e^{-i m phi} at the old, new and mid positions, by recurrence
         R e0r = 1, e0i = 0, e1r = 1, e1i = 0, emr = 1, emi = 0;
@@ -596,62 +638,51 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
             emi = ti;
           }
           const R cq = (m == 0 ? R(1) : R(2)) * q;
-          const R xr = R(0.5) * (e0r + e1r), xi = R(0.5) * (e0i + e1i);
           const int qa = m == 0 ? 0 : 2 * m - 1, qb = 2 * m;
-          // J_z at (ib+a+1/2, jb+b): minus the running sum of Wz behind the face
+          // mode coefficients: the flux phase cq xi for J_z and J_r; for
+          // J_phi, m = 0 takes cq v_phi, m >= 1 the closure cq (i/m)(e1 - e0)
+          // times r_j (zero on the axis row, where m = 1 takes cq v_phi e_mid)
+          const double fa = (double)(cq * (R(0.5) * (e0r + e1r))), fb = (double)(cq * (R(0.5) * (e0i + e1i)));
+          double pa, pb, pa0, pb0;
+          if (m == 0) {
+            pa = pa0 = (double)(cq * vphi);
+            pb = pb0 = 0.0;
+          } else {
+            pa = (double)(-cq * (e1i - e0i) * (R(1) / (R)m));
+            pb = (double)(cq * (e1r - e0r) * (R(1) / (R)m));
+            const double ax_a = m == 1 ? (double)(cq * vphi * emr) : 0.0;
+            const double ax_b = m == 1 ? (double)(cq * vphi * emi) : 0.0;
+            pa0 = axis_row ? ax_a : pa;
+            pb0 = axis_row ? ax_b : pb;
+          }
 #pragma unroll
           for (int b = 0; b < 3; ++b) {
             if (b == 2 && !rx) continue;
-            R run = 0;
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
               if (a == 1 && !zx) continue;
-              run += Wz[a][b];
-              const R v = -cq * run;
-              dep(2, qa, b, a, v * xr);
-              if (m > 0) dep(2, qb, b, a, v * xi);
+              dep(2, qa, b, a, wz[b][a] * fa);
+              if (m > 0) dep(2, qb, b, a, wz[b][a] * fb);
             }
           }
-          // J_r at (ib+a, jb+b+1/2)
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
             if (a == 2 && !zx) continue;
-            R run = 0;
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
               if (b == 1 && !rx) continue;
-              run += Wr[a][b];
-              const R v = -cq * run;
-              dep(0, qa, b, a, v * xr);
-              if (m > 0) dep(0, qb, b, a, v * xi);
+              dep(0, qa, b, a, wr[a][b] * fa);
+              if (m > 0) dep(0, qb, b, a, wr[a][b] * fb);
             }
           }
-          // J_phi at (ib+a, jb+b): m = 0 from v_phi; m >= 1 from the closure
-          // (i/m)(e1 - e0) times r_j, which vanishes on the axis, where m = 1
-          // takes v_phi instead
-          const R dre = e1r - e0r, dim_ = e1i - e0i;
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
             if (a == 2 && !zx) continue;
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
               if (b == 2 && !rx) continue;
-              const R h = R(0.5) * cq * Ss[a][b];
-              if (m == 0) {
-                dep(1, 0, b, a, h * vphi);
-              } else {
-                const bool axis = jb + b == 0;
-                R va = -h * dim_ * (R(1) / (R)m), vb = h * dre * (R(1) / (R)m);
-                if (m == 1) {
-                  va = axis ? h * vphi * emr : va;
-                  vb = axis ? h * vphi * emi : vb;
-                } else {
-                  va = axis ? R(0) : va;
-                  vb = axis ? R(0) : vb;
-                }
-                dep(1, qa, b, a, va);
-                dep(1, qb, b, a, vb);
-              }
+              dep(1, qa, b, a, ws[a][b] * (b == 0 ? pa0 : pa));
+              if (m > 0) dep(1, qb, b, a, ws[a][b] * (b == 0 ? pb0 : pb));
             }
           }
         }
@@ -660,13 +691,13 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
       if ((ib - zlo >= 0) && (ib + 2 - zlo < WZ) && (jb - rlo >= 0) && (jb + 2 - rlo < WR)) {
         double *jw = lds + ((jb - rlo) * WZ + (ib - zlo)) * JS;
         const int rowJ = WZ * JS;
-        deposit([&](int c, int qq, int b, int a, R v) { lds_add(jw + b * rowJ + a * JS + c * NM + qq, (double)v); });
+        deposit([&](int c, int qq, int b, int a, double v) { lds_add(jw + b * rowJ + a * JS + c * NM + qq, v); });
       } else {
         int col[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) col[a] = wrap_once(ib + a, Nz);
-        deposit([&](int c, int qq, int b, int a, R v) {
-          atomic_add(J + (c * NM + qq) * plane + (long long)(jb + b) * Nz + col[a], v);
+        deposit([&](int c, int qq, int b, int a, double v) {
+          atomic_add(J + (c * NM + qq) * plane + (long long)(jb + b) * Nz + col[a], (R)v);
         });
       }
     }
@@ -687,19 +718,33 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
     UZ[p] = un[2];
   }
 
-  // ---- flush the tile's current: one wavefront per (component, plane, row) ----
+  // ---- flush the tile's current (one wavefront per component, plane and
+  // row), clear the window, then stage the next tile's field window ----
+  if (threadIdx.x == 0) ticket = atomicAdd(bt.run[0].work, 1);  // read after the barrier
   __syncthreads();
-  for (int line = wave; line < JS * WR; line += nwave) {  // line = (c NM + q) WR + lr
-    const int cq = line / WR, lr = line - cq * WR;
-    const int row = rlo + lr;
-    if (row < 0 || row > Nr) continue;
-    R *dst = J + cq * plane + (long long)row * Nz;
-    const double *src = lds + lr * WZ * JS + cq;
-    for (int lc = lane; lc < WZ; lc += 64) {
-      const R v = (R)src[lc * JS];
-      if (v != R(0)) atomic_add(dst + wrap_any(zlo + lc, Nz), v);
+  const int nt = ticket;
+  if (n > 0)
+    for (int line = wave; line < JS * WR; line += nwave) {  // line = (c NM + q) WR + lr
+      const int cq = line / WR, lr = line - cq * WR;
+      const int row = rlo + lr;
+      if (row < 0 || row > Nr) continue;  // never deposited to
+      R *dst = J + cq * plane + (long long)row * Nz;
+      double *src = lds + lr * WZ * JS + cq;
+      for (int lc = lane; lc < WZ; lc += 64) {
+        const R v = (R)src[lc * JS];
+        src[lc * JS] = 0.0;
+        if (v != R(0)) atomic_add(dst + wrap_any(zlo + lc, Nz), v);
+      }
     }
-  }
+  if (nt < t_hi)
+    for (int e = threadIdx.x; e < FZ * FR; e += blockDim.x) {
+      R v[FS];
+      stage_load(nt, e, v);
+      stage_store(e, v);
+    }
+  __syncthreads();
+  gt = nt;
+  }  // tiles
 }
 
 // ---------------------------------------------------------------------------
@@ -1358,7 +1403,25 @@ struct PushL {
     if (!set_offsets(b, [](const KRun &k) { return k.np > 0 ? (long long)k.ntz * k.ntr : 0LL; })) return PIC_OK;
     const KRun &k0 = b.run[0];
     const size_t lds = push_lds_bytes(M, k0.Tz, k0.Tr, prec_of<R>());
-    push_kernel<R, M><<<(unsigned)b.off[b.n], 256, lds, s>>>(b);
+    // persistent grid: as many workgroups as are resident at once (a multiple
+    // of 8, one share per XCD), each walking its tiles
+    static size_t lds_seen = 0;
+    static long long resident = 0;
+    if (lds != lds_seen) {
+      int per_cu = 0, cus = 0, dev = 0;
+      int rc = check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, push_kernel<R, M>, 256, lds),
+                     "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+      if (!rc) rc = check(hipGetDevice(&dev), "hipGetDevice");
+      if (!rc) rc = check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
+      if (rc) return rc;
+      resident = (long long)(per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+      resident = resident >= 8 ? resident & ~7LL : resident;
+      lds_seen = lds;
+    }
+    const long long grid = b.off[b.n] < resident ? b.off[b.n] : resident;
+    zero_kernel<<<1, 64, 0, s>>>((uint4 *)b.run[0].work, 1, nullptr, 0);  // tickets from 0
+    if (int rc = check(hipGetLastError(), "zero_kernel")) return rc;
+    push_kernel<R, M><<<(unsigned)grid, 256, lds, s>>>(b);
     return check(hipGetLastError(), "push_kernel");
   }
 };

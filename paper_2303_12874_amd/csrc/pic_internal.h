@@ -62,6 +62,7 @@ struct KRun {
   int ntz, ntr;           // tiles along z and r
   long long n_keys;       // tiles * Tz * Tr
   double *red;            // reduction partials
+  int32_t *work;          // tile ticket counter of the persistent push (run 0's serves a batch)
 };
 
 // ---- push workgroup LDS ---------------------------------------------------------
