@@ -51,9 +51,10 @@ def algorithmic_bytes(run: dict, precision: int) -> dict:
     }
 
 
-def measured_traffic(workload: str, kernel: str):
+def measured_traffic(workload: str, kernel: str, tile: str, sort_interval: int, precision: int):
     """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE
-    counter passes (copy-calibrated), or None when the kernels changed since."""
+    counter passes (copy-calibrated), or None when the kernels changed since or
+    the run's tile, sort interval or precision differ from the profiled ones."""
     try:
         with open(os.path.join(ROOT, "profiles", "hbm_traffic.json")) as f:
             t = json.load(f)
@@ -63,7 +64,10 @@ def measured_traffic(workload: str, kernel: str):
         return None
     if t.get("kernels_sha256") != h:
         return None
-    e = t.get("workloads", {}).get(workload, {}).get(kernel)
+    w = t.get("workloads", {}).get(workload, {})
+    if w.get("settings") != {"tile": tile, "sort_interval": sort_interval, "precision": precision}:
+        return None
+    e = w.get(kernel)
     return None if e is None else e["read_bytes"] + e["write_bytes"]
 
 
@@ -201,9 +205,7 @@ def main(argv=None):
         kernels[ph] = {"avg_ms": ms / n, "launches": n, "GBs": phase_bytes(ph) / (ms * 1e-3) / 1e9}
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
     ach = kernels[dom]["GBs"]
-    default_opts = (args.sort_interval in (0, 8) and args.precision in (0, cfg["precision"])
-                    and args.tile_z == 0 and args.tile_r == 0 and not args.graph and tune is None)
-    traffic = measured_traffic(args.workload, dom) if default_opts else None
+    traffic = measured_traffic(args.workload, dom, "%dx%d" % infos[0]["tile"], sort_k, prec)
     particle_steps = sum(n * s for n, s in zip(nps, per_run))
     value = particle_steps / (elapsed_ms * 1e-3)
     run = runs[0]
