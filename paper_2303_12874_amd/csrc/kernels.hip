@@ -65,6 +65,29 @@ __device__ __forceinline__ int radial_index(R r2, R r) {
   return j;
 }
 
+// 1/sqrt(x) and 1/x for x > 0 from the hardware estimates: FP32 as they are
+// (about an ulp), FP64 with one Newton step (close to correct rounding).  One
+// reciprocal square root replaces a square root and a division.
+template <typename R>
+__device__ __forceinline__ R rsqrt_hw(R x) {
+  if constexpr (std::is_same<R, double>::value) {
+    const double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x * y;
+    return fma(y, fma(-h, y, 0.5), y);
+  } else {
+    return __builtin_amdgcn_rsqf(x);
+  }
+}
+template <typename R>
+__device__ __forceinline__ R rcp_hw(R x) {
+  if constexpr (std::is_same<R, double>::value) {
+    const double y = __builtin_amdgcn_rcp(x);
+    return fma(y, fma(-x, y, 1.0), y);
+  } else {
+    return __builtin_amdgcn_rcpf(x);
+  }
+}
+
 // Relaxed hardware float atomics (no denormal-mode emulation).  The LDS and
 // the global forms use different scopes so that the compiler never merges a
 // workgroup-local and a device-memory update into one flat-address atomic.
@@ -333,14 +356,11 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
     }
     if ((unsigned)i0 >= (unsigned)Nz) i0 = wrap_any(i0, Nz);
     const R x0 = cx, y0 = cy;
-    const R r20 = fma(x0, x0, y0 * y0), r0 = sqrt(r20);
+    const R r20 = fma(x0, x0, y0 * y0);
+    const R ir0 = r20 > R(0) ? rsqrt_hw(r20) : R(0);
+    const R r0 = r20 * ir0;  // the cell index below is exact whatever the last bits of r0
     const int j0 = clampi(radial_index(r20, r0), 0, Nr - 2);
-    R c0 = 1, s0 = 0;
-    if (r0 > R(0)) {
-      const R ir = R(1) / r0;
-      c0 = x0 * ir;
-      s0 = y0 * ir;
-    }
+    const R c0 = r20 > R(0) ? x0 * ir0 : R(1), s0 = y0 * ir0;
 
     // ---- gather E^n and Bbar^n = (B^{n-1/2} + B^{n+1/2})/2 (Eq. (12)) ----
     R fh;
@@ -453,12 +473,11 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
     R um[3], up[3], un[3], tt[3], ss[3], u1[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) um[a] = u[a] - R(0.5) * dt * Ec[a];
-    const R gm = sqrt(R(1) + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
-    const R hb = -R(0.5) * dt / gm;
+    const R hb = -R(0.5) * dt * rsqrt_hw(R(1) + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
 #pragma unroll
     for (int a = 0; a < 3; ++a) tt[a] = hb * Bc[a];
     const R t2 = tt[0] * tt[0] + tt[1] * tt[1] + tt[2] * tt[2];
-    const R sf = R(2) / (R(1) + t2);
+    const R sf = R(2) * rcp_hw(R(1) + t2);
 #pragma unroll
     for (int a = 0; a < 3; ++a) ss[a] = sf * tt[a];
     u1[0] = um[0] + (um[1] * tt[2] - um[2] * tt[1]);
@@ -469,8 +488,8 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
     up[2] = um[2] + (u1[0] * ss[1] - u1[1] * ss[0]);
 #pragma unroll
     for (int a = 0; a < 3; ++a) un[a] = up[a] - R(0.5) * dt * Ec[a];
-    const R g_new = sqrt(R(1) + un[0] * un[0] + un[1] * un[1] + un[2] * un[2]);
-    const R inv_g = R(1) / g_new;
+    const R gg_new = R(1) + un[0] * un[0] + un[1] * un[1] + un[2] * un[2];  // gamma^2
+    const R inv_g = rsqrt_hw(gg_new);
 
     // ---- per-mode work of tracked electrons (FP64), Eq. (16) ----
     if (pidw & kTrackedBit) {
@@ -483,7 +502,7 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
       }
       if (lo < k.n_tracked && k.tracked[lo] == idv) {
         const double g_old = sqrt(1.0 + (double)u[0] * u[0] + (double)u[1] * u[1] + (double)u[2] * u[2]);
-        const double inv = 1.0 / (g_old + (double)g_new);
+        const double inv = 1.0 / (g_old + sqrt((double)gg_new));
         const double v0 = ((double)um[0] + (double)up[0]) * inv;
         const double v1 = ((double)um[1] + (double)up[1]) * inv;
         const double v2 = ((double)um[2] + (double)up[2]) * inv;
@@ -521,8 +540,9 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
     R x1 = x0 + un[0] * inv_g * dt_dr;
     R y1 = y0 + un[1] * inv_g * dt_dr;
     const R Rw = (R)(Nr - 1);
-    R r21 = fma(x1, x1, y1 * y1), r1 = sqrt(r21);
-    if (r1 >= Rw) {  // specular reflection at r = (Nr - 1) dr
+    R r21 = fma(x1, x1, y1 * y1);
+    if (r21 >= Rw * Rw) {  // specular reflection at r = (Nr - 1) dr (Rw^2 is exact)
+      R r1 = sqrt(r21);
       const R nx = x1 / r1, ny = y1 / r1;
       const R sc = (R(2) * Rw - r1) / r1;
       x1 *= sc;
@@ -540,27 +560,20 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
         r1 = sqrt(r21);
       }
     }
+    const R ir1 = r21 > R(0) ? rsqrt_hw(r21) : R(0);
+    const R r1 = r21 * ir1;
     int j1 = clampi(radial_index(r21, r1), j0 - 1, j0 + 1);
     j1 = clampi(j1, 0, Nr - 2);
-    R c1 = 1, s1 = 0;
-    if (r1 > R(0)) {
-      const R ir = R(1) / r1;
-      c1 = x1 * ir;
-      s1 = y1 * ir;
-    }
+    const R c1 = r21 > R(0) ? x1 * ir1 : R(1), s1 = y1 * ir1;
     const R g1 = r1 - (R)j1;
 
     // ---- charge-conserving deposit of J^{n+1/2} ----
     {
       const R xm = R(0.5) * (x0 + x1), ym = R(0.5) * (y0 + y1);
-      const R rm = sqrt(xm * xm + ym * ym);
-      R cmid = 1, smid = 0, vphi = 0;
-      if (rm > R(0)) {
-        const R ir = R(1) / rm;
-        cmid = xm * ir;
-        smid = ym * ir;
-        vphi = (cmid * un[1] - smid * un[0]) * inv_g;
-      }
+      const R rm2 = xm * xm + ym * ym;
+      const R irm = rm2 > R(0) ? rsqrt_hw(rm2) : R(0);
+      const R cmid = rm2 > R(0) ? xm * irm : R(1), smid = ym * irm;
+      const R vphi = rm2 > R(0) ? (cmid * un[1] - smid * un[0]) * inv_g : R(0);
       const int di = clampi(i1 - i0, -1, 1);
       const int oz0 = di < 0 ? 1 : 0, oz1 = oz0 + di;  // cells of the two positions in the 3-node window
       const int ib = i0 - oz0;
