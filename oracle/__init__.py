@@ -65,6 +65,7 @@ def lib():
             "orc_get_particles": (None, [p, p, p, p, p, p, p, p, p]),
             "orc_put_particles": (None, [p, p, p, p, p, p, p, p]),
             "orc_tracked": (i, [p, p, p, p, p]),
+            "orc_cartesian_work": (i, [p, p, p]),
             "orc_kinetic": (d, [p]),
             "orc_add_laser": (i, [p, d, d, d, d, d]),
             "orc_round_to_fp32": (None, [p]),
@@ -187,6 +188,13 @@ class Oracle:
         ga = np.zeros(n)
         lib().orc_tracked(self._h, _ptr(ids), _ptr(W), _ptr(g), _ptr(ga))
         return {"id": ids, "W": W, "gamma": g, "gamma_acc": ga}
+
+    def cartesian_work(self):
+        """W_z and W_perp of the tracked particles (Eq. (17)), slot order."""
+        n = lib().orc_cartesian_work(self._h, None, None)
+        wz, wp = np.zeros(n), np.zeros(n)
+        lib().orc_cartesian_work(self._h, _ptr(wz), _ptr(wp))
+        return {"Wz": wz, "Wperp": wp}
 
     def kinetic(self):
         return lib().orc_kinetic(self._h)

@@ -18,8 +18,7 @@ give the two targets separately:
 
     [k]_E = tan(c k dt/2) / (c dt/2),     [k]_B = sin(c k dt) / (c dt).
 
-The paper fits the coefficients "to desired precision" without giving the
-procedure; the reading used here is a least-squares fit of each operator on
+The paper leaves the fitting procedure and its accuracy open; the reading used here is a least-squares fit of each operator on
 k dz in (0, 2 pi/3] (4000 midpoint samples) under the consistency constraint
 sum_l (2l-1) C_l = 1, solved in the null space of the constraint.
 

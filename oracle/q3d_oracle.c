@@ -67,6 +67,7 @@ typedef struct orc {
   int32_t *slot;      /* tracked slot, -1 if not tracked */
   int ntr;
   double *W;          /* [ntr][M+1] per-mode work */
+  double *Wc;         /* [ntr][2] work of E_z and of E_perp, Eq. (17) */
   double *gam0;       /* [ntr] gamma when tracking started */
   long nstep;
   int freeze_fields;  /* 1: Maxwell update skipped (prescribed fields) */
@@ -144,9 +145,9 @@ orc *orc_create(int Nz, int Nr, int M, double dz, double dr, double dt, int N,
 
 static void free_particles(orc *o) {
   free(o->z); free(o->x); free(o->y); free(o->ux); free(o->uy); free(o->uz);
-  free(o->w); free(o->id); free(o->slot); free(o->W); free(o->gam0);
+  free(o->w); free(o->id); free(o->slot); free(o->W); free(o->Wc); free(o->gam0);
   o->z = o->x = o->y = o->ux = o->uy = o->uz = o->w = NULL;
-  o->id = NULL; o->slot = NULL; o->W = o->gam0 = NULL;
+  o->id = NULL; o->slot = NULL; o->W = o->Wc = o->gam0 = NULL;
   o->np = 0; o->ntr = 0;
 }
 
@@ -650,6 +651,16 @@ static void push_and_deposit(orc *o) {
       double *W = o->W + (size_t)o->slot[p] * (M + 1);
       for (int m = 0; m <= M; ++m)
         W[m] += -dt * (Em[m][0] * v[0] + Em[m][1] * v[1] + Em[m][2] * v[2]);
+      /* the same work split by field direction instead of mode, Eq. (17):
+       * W_z = -e int E_z v_z dt, W_perp = -e int E_perp . v_perp dt */
+      double ez = 0.0, ep = 0.0;
+      for (int m = 0; m <= M; ++m) {
+        ez += Em[m][2];
+        ep += Em[m][0] * v[0] + Em[m][1] * v[1];
+      }
+      double *Wc = o->Wc + (size_t)o->slot[p] * 2;
+      Wc[0] += -dt * ez * v[2];
+      Wc[1] += -dt * ep;
     }
 
     /* move: x^{n+1} = x^n + dt u^{n+1/2} / gamma^{n+1/2}, in cell units */
@@ -797,6 +808,7 @@ int orc_load_plasma(orc *o, int ppc, double n0, double ramp_start, double ramp_l
       }
   o->ntr = n_tracked;
   o->W = (double *)calloc((size_t)(n_tracked > 0 ? n_tracked : 1) * (o->M + 1), sizeof(double));
+  o->Wc = (double *)calloc((size_t)(n_tracked > 0 ? n_tracked : 1) * 2, sizeof(double));
   o->gam0 = (double *)calloc((size_t)(n_tracked > 0 ? n_tracked : 1), sizeof(double));
   if (n_tracked > 0) {
     double *key = (double *)malloc(sizeof(double) * 2 * np);
@@ -841,6 +853,7 @@ int orc_set_particles(orc *o, long np, const double *z, const double *x, const d
   }
   o->ntr = track_all ? (int)np : 0;
   o->W = (double *)calloc((size_t)(o->ntr > 0 ? o->ntr : 1) * (o->M + 1), sizeof(double));
+  o->Wc = (double *)calloc((size_t)(o->ntr > 0 ? o->ntr : 1) * 2, sizeof(double));
   o->gam0 = (double *)calloc((size_t)(o->ntr > 0 ? o->ntr : 1), sizeof(double));
   for (int k = 0; k < o->ntr; ++k)
     o->gam0[k] = sqrt(1.0 + ux[k] * ux[k] + uy[k] * uy[k] + uz[k] * uz[k]);
@@ -885,6 +898,15 @@ int orc_tracked(orc *o, int64_t *ids, double *W, double *gamma, double *gamma_ac
     }
     if (gamma) gamma[k] = sqrt(1.0 + o->ux[p] * o->ux[p] + o->uy[p] * o->uy[p] + o->uz[p] * o->uz[p]);
     if (gamma_acc) gamma_acc[k] = s;
+  }
+  return o->ntr;
+}
+
+/* Work of E_z and of E_perp on the tracked particles (Eq. (17)), slot order. */
+int orc_cartesian_work(orc *o, double *wz, double *wperp) {
+  for (int k = 0; k < o->ntr; ++k) {
+    if (wz) wz[k] = o->Wc[2 * (size_t)k];
+    if (wperp) wperp[k] = o->Wc[2 * (size_t)k + 1];
   }
   return o->ntr;
 }

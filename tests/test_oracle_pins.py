@@ -688,3 +688,83 @@ def test_laser_init_propagates_forward_at_c():
     n = 60
     o.field_step(n)
     assert abs((centroid() - z0) / (n * dt) - 1.0) < 0.02
+
+
+# --------------------------------------------------------------------------
+# Cartesian work split, Eqs. (17)-(21)
+
+
+def test_cartesian_work_splits_the_same_total_as_the_modes():
+    """W_z + W_perp (split by direction, Eq. (17)) and the per-mode work (Eq.
+    (16)) are two partitions of one integral, so their totals agree; the laser
+    does transverse work and the plasma longitudinal work."""
+    o, _, _ = _small_plasma_run()
+    tr, cw = o.tracked(), o.cartesian_work()
+    tot = tr["W"].sum(axis=1)
+    scale = max(1e-3, np.abs(tot).max())
+    assert np.abs(cw["Wz"] + cw["Wperp"] - tot).max() < 1e-13 * scale
+    assert np.abs(cw["Wz"]).max() > 1e-5 and np.abs(cw["Wperp"]).max() > 1e-3
+
+
+@pytest.mark.parametrize("Ex,Ez", [(0.0, 0.05), (0.04, 0.0), (0.03, -0.04)])
+def test_cartesian_work_uniform_field_closed_form(Ex, Ez):
+    """An electron starting at rest in frozen uniform E = (Ex, 0, Ez) moves
+    along -E with u_n = n dt E (q/m = -1); the work telescopes to
+    gamma - 1 = sqrt(1 + (|E| t)^2) - 1 and splits in proportion to Ez^2 and
+    Ex^2 (v is parallel to E)."""
+    Nz, Nr, M = 8, 6, 1
+    dz, dr, dt = 0.5, 0.7, 0.1
+    o = oracle.Oracle(Nz, Nr, M, dz, dr, dt, [1.0], [1.0])
+    zero = np.zeros((Nr + 1, Nz), dtype=complex)
+    for c in range(9):
+        for m in range(M + 1):
+            o.set_field(c, m, zero)
+    o.set_field(oracle.ER, 1, Ex + 0 * zero)
+    o.set_field(oracle.EP, 1, 1j * Ex + 0 * zero)
+    o.set_field(oracle.EZ, 0, Ez + 0 * zero)
+    o.set_flags(freeze_fields=True)
+    rng = np.random.default_rng(5)
+    n = 6
+    o.set_particles(rng.uniform(0, Nz, n), rng.uniform(-1, 1, n), rng.uniform(-1, 1, n), np.zeros(n), np.zeros(n),
+                    np.zeros(n), np.zeros(n))
+    nsteps = 30
+    o.step(nsteps)
+    E2 = Ex * Ex + Ez * Ez
+    gain = math.sqrt(1.0 + E2 * (nsteps * dt) ** 2) - 1.0
+    cw = o.cartesian_work()
+    assert np.allclose(cw["Wz"], gain * Ez * Ez / E2, rtol=1e-13, atol=1e-16)
+    assert np.allclose(cw["Wperp"], gain * Ex * Ex / E2, rtol=1e-13, atol=1e-16)
+
+
+def _resonant_cycle_work(gamma, n0, w0, A, E0=1.0, nq=20001):
+    """<W_z> and <W_perp> of Eq. (19) by quadrature over one betatron period,
+    with the near-focus laser fields of Eq. (18) and the resonant orbit
+    x = A cos(w_b t), theta = w_b t, v_z = c, w_b = w_p / sqrt(2 gamma) (Eq.
+    (1)); c = omega_0 = 1 so k_z = 1; charge -1."""
+    wb = math.sqrt(n0) / math.sqrt(2.0 * gamma)
+    t = np.linspace(0.0, 2.0 * math.pi / wb, nq)
+    x = A * np.cos(wb * t)
+    vx = -A * wb * np.sin(wb * t)
+    env = E0 * np.exp(-(x * x) / (w0 * w0))
+    Ex = env * np.sin(wb * t)
+    Ez = 2.0 * x / (w0 * w0) * env * np.cos(wb * t)
+    trap = lambda y: float(np.sum(0.5 * (y[1:] + y[:-1]) * np.diff(t)))
+    return -trap(Ez * 1.0), -trap(Ex * vx)
+
+
+@pytest.mark.parametrize("gamma,n0,w0", [(50.0, 0.002, 40.0), (400.0, 0.001, 60.0), (10.0, 0.01, 25.0)])
+def test_pukhov_ratio_is_the_resonant_cycle_average(gamma, n0, w0):
+    """Eq. (20) against the quadrature of Eq. (19) for a small amplitude
+    (A = 1e-3 w0): the ratio agrees to the neglected order (A/w0)^2, and the
+    correction of Eq. (21) assigns such an electron's whole laser work to
+    DLA (W*_LWFA ~ 0)."""
+    from oracle import work
+
+    wz, wp = _resonant_cycle_work(gamma, n0, w0, A=1e-3 * w0)
+    f = work.pukhov_ratio(gamma, n0, w0)
+    assert f < 0
+    assert abs(wz / wp - f) < 1e-5 * abs(f)
+    lwfa, dla = work.corrected_work(wz, wp, f)
+    assert abs(lwfa) < 1e-5 * abs(wp)
+    assert abs(dla - (wz + wp)) < 1e-5 * abs(f * wp)
+    assert abs(lwfa + dla - (wz + wp)) < 1e-14 * abs(wp)
