@@ -71,14 +71,14 @@ def measured_traffic(workload: str, kernel: str, tile: str, sort_interval: int, 
     return None if e is None else e["read_bytes"] + e["write_bytes"]
 
 
-def cpu_baseline(runs: list, nsteps: int) -> dict:
+def cpu_baseline(runs: list, nsteps: int, n_coef: int = 16) -> dict:
     """FP64 oracle (as it stands) on the host: nsteps full steps of every run."""
     import oracle
     from oracle import coef
 
     tot, el = 0, 0.0
     for run in runs:
-        dt, CE, CB, _ = coef.solver_setup(16, run["M"], run["dz"], run["dr"])
+        dt, CE, CB, _ = coef.solver_setup(n_coef, run["M"], run["dz"], run["dr"])
         o = workloads.to_oracle(run, dt, CE, CB)
         t0 = time.perf_counter()
         o.step(nsteps)
@@ -107,6 +107,8 @@ def main(argv=None):
                     help="1: tile and sort interval from the library's autotuner (default: on for c4 only)")
     ap.add_argument("--precision", type=int, default=0, choices=[0, 32, 64],
                     help="override the workload's precision (0: as defined)")
+    ap.add_argument("--solver", default="dual", choices=["dual", "yee"],
+                    help="field solver: dual (16 coefficients per operator) or Yee (one)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}), flush=True)
@@ -123,12 +125,15 @@ def main(argv=None):
     W = args.warmup if args.warmup is not None else (8 if multi else 20)
     per_run = [min(n, K) for n in cfg["steps"]] if multi else [K]
     prec = args.precision or cfg["precision"]
+    solver = pic.SOLVER_YEE if args.solver == "yee" else pic.SOLVER_DUAL
+    n_coef = 1 if args.solver == "yee" else 16
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     tune = None
     if args.autotune if args.autotune is not None else multi:
         t0 = time.perf_counter()
-        tune = pic.autotune([workloads.to_rundesc(r) for r in runs], precision=prec, tile_z=args.tile_z,
+        tune = pic.autotune([workloads.to_rundesc(r) for r in runs], precision=prec, solver=solver, n_coef=n_coef,
+                            tile_z=args.tile_z,
                             tile_r=args.tile_r, device="cuda:0")
         torch.cuda.empty_cache()
         args.tile_z, args.tile_r = tune["tile_z"], tune["tile_r"]
@@ -140,7 +145,7 @@ def main(argv=None):
 
     def make(limits):
         return pic.Simulation([workloads.to_rundesc(r, n_steps=n) for r, n in zip(runs, limits)], precision=prec,
-                              sort_interval=args.sort_interval, tile_z=args.tile_z, tile_r=args.tile_r,
+                              solver=solver, n_coef=n_coef, sort_interval=args.sort_interval, tile_z=args.tile_z, tile_r=args.tile_r,
                               use_graph=args.graph, device="cuda:0")
 
     if multi:  # warm up on a context of its own, so that the timed job starts at step 0
@@ -205,14 +210,16 @@ def main(argv=None):
         kernels[ph] = {"avg_ms": ms / n, "launches": n, "GBs": phase_bytes(ph) / (ms * 1e-3) / 1e9}
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
     ach = kernels[dom]["GBs"]
-    traffic = measured_traffic(args.workload, dom, "%dx%d" % infos[0]["tile"], sort_k, prec)
+    traffic = (measured_traffic(args.workload, dom, "%dx%d" % infos[0]["tile"], sort_k, prec)
+               if args.solver == "dual" else None)  # the counters were taken with the dual solver
     particle_steps = sum(n * s for n, s in zip(nps, per_run))
     value = particle_steps / (elapsed_ms * 1e-3)
     run = runs[0]
     config = {"workload": f"{args.workload}: {cfg['desc']}",
               "grid": ", ".join(f"{r['Nz']}x{r['Nr']}" for r in runs), "modes": run["M"] + 1,
               "ppc": run["ppc"], "electrons": sum(nps), "precision": f"fp{prec}",
-              "solver": "dual, 16 coefficients per operator", "dt": [i["dt"] for i in infos] if multi else infos[0]["dt"],
+              "solver": "Yee, one coefficient per operator" if args.solver == "yee"
+              else "dual, 16 coefficients per operator", "dt": [i["dt"] for i in infos] if multi else infos[0]["dt"],
               "sort_interval": sort_k, "tile": "%dx%d" % infos[0]["tile"], "graph": bool(args.graph)}
     if multi:
         config["steps_per_run"] = per_run
@@ -245,7 +252,7 @@ def main(argv=None):
     torch.cuda.empty_cache()
     if args.cpu_steps > 0:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(runs, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(runs, args.cpu_steps, n_coef)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -183,6 +183,31 @@ int pic_step(pic_ctx *ctx, int64_t n_steps);
 int pic_mode_work(pic_ctx *ctx, int32_t run, double *work, double *gamma, double *gamma_acc,
                   int64_t *ids, double *field_energy, double *kinetic);
 
+/* Synchronise and copy out the work on the tracked electrons of one run split
+ * by field direction (Sec. III.B), arrays of n_tracked FP64 values in the
+ * order of pic_mode_work's ids, caller owned, any may be NULL:
+ *   wz     = -sum dt E_z v_z,  wperp = -sum dt E_perp . v_perp, each field
+ *            summed over modes (Eq. (17)), accumulated with the per-mode work;
+ *   f      = -2 sqrt(2 gamma) / (omega_p w0^2), Eq. (20) with c = omega_0 = 1,
+ *            omega_p = sqrt(n0), w0 of pulse 0 and gamma the electron's
+ *            Lorentz factor now;
+ *   w_lwfa = wz - f wperp,  w_dla = (1 + f) wperp (Eq. (21)).
+ * PIC_E_INVALID if f, w_lwfa or w_dla is asked for and the run has no pulse
+ * or n0 <= 0; PIC_E_NUMERIC if a value is not finite.                       */
+int pic_cartesian_work(pic_ctx *ctx, int32_t run, double *wz, double *wperp, double *f, double *w_lwfa,
+                       double *w_dla);
+
+/* Synchronise and reduce the divergence of the energetic electrons of one
+ * run, the quantity Secs. IV.A-IV.B compare between solvers: over electrons
+ * with Lorentz factor >= gamma_min and u_z > 0, with theta_x = atan(u_x/u_z)
+ * and theta_y = atan(u_y/u_z), out[4] (caller owned) receives
+ *   out[0] = sum w,  out[1] = sum w theta_x^2,  out[2] = sum w theta_y^2,
+ *   out[3] = number of electrons counted,
+ * FP64 sums (RMS angle = sqrt(out[1] / out[0])).  The selection compares
+ * |u|^2 with gamma_min^2 - 1.  PIC_E_INVALID if gamma_min < 1 or out is
+ * NULL; PIC_E_NUMERIC if a sum is not finite.                              */
+int pic_divergence(pic_ctx *ctx, int32_t run, double gamma_min, double *out);
+
 /* Synchronise and copy one component of mode m of one run into out, FP64
  * interleaved complex [(Nr+1)][Nz] (2 (Nr+1) Nz doubles; m = 0 has zero
  * imaginary part), physical units.  PIC_E_NOMEM if out_len (in doubles) is

@@ -83,6 +83,8 @@ def _load():
         "pic_init": [C.POINTER(_RunDesc), i32, C.POINTER(_Opts), p, C.POINTER(C.c_size_t), p, C.POINTER(p)],
         "pic_step": [p, i64],
         "pic_mode_work": [p, i32, p, p, p, p, p, p],
+        "pic_cartesian_work": [p, i32, p, p, p, p, p],
+        "pic_divergence": [p, i32, C.c_double, p],
         "pic_fields": [p, i32, i32, i32, p, sz],
         "pic_particles": [p, i32, p, p, p, p, p, p, p, p, sz],
         "pic_coefficients": [p, i32, p, p, p],
@@ -104,6 +106,7 @@ def _load():
 
 _lib = _load()
 EXPORTED = ("pic_solver_setup", "pic_courant_limit", "pic_load_host", "pic_init", "pic_step", "pic_mode_work",
+            "pic_cartesian_work", "pic_divergence",
             "pic_fields", "pic_particles", "pic_coefficients", "pic_run_info_get", "pic_destroy",
             "pic_last_error", "pic_profile", "pic_profile_read", "pic_autotune")
 PHASES = ("sort", "push", "efield", "bfield", "step")  # "step": a whole step replayed from a graph
@@ -323,3 +326,25 @@ class Simulation:
         _check(_lib.pic_mode_work(self._h, run, _ptr(W), _ptr(g), _ptr(ga), _ptr(ids), _ptr(U), _ptr(K)))
         return {"W": W[:nt], "gamma": g[:nt], "gamma_acc": ga[:nt], "id": ids[:nt], "field_energy": U,
                 "kinetic": K[0]}
+
+    def divergence(self, gamma_min=1.0, run=0):
+        """Charge-weighted RMS divergence theta_x = atan(u_x/u_z) (and theta_y)
+        of the electrons with gamma >= gamma_min moving forward, with the raw
+        sums: {"w", "rms_x", "rms_y", "count"}."""
+        out = np.zeros(4)
+        _check(_lib.pic_divergence(self._h, run, float(gamma_min), _ptr(out)))
+        w = out[0]
+        return {"w": w, "rms_x": float(np.sqrt(out[1] / w)) if w > 0 else 0.0,
+                "rms_y": float(np.sqrt(out[2] / w)) if w > 0 else 0.0, "count": int(out[3]),
+                "sum_wtx2": out[1], "sum_wty2": out[2]}
+
+    def cartesian_work(self, run=0, corrected=True):
+        """Work on the tracked electrons by field direction (Eq. (17)); with
+        corrected=True also the Pukhov ratio f (Eq. (20)) and the corrected
+        W*_LWFA, W*_DLA (Eq. (21)) -- the run needs a pulse for those."""
+        nt = self.runs[run].n_tracked
+        out = {k: np.zeros(max(nt, 1)) for k in ("Wz", "Wperp", "f", "W_lwfa", "W_dla")}
+        keys = ("Wz", "Wperp", "f", "W_lwfa", "W_dla") if corrected else ("Wz", "Wperp")
+        _check(_lib.pic_cartesian_work(self._h, run, *[_ptr(out[k]) if k in keys else None
+                                                       for k in ("Wz", "Wperp", "f", "W_lwfa", "W_dla")]))
+        return {k: out[k][:nt] for k in keys}

@@ -68,7 +68,7 @@ struct RunHost {
 struct Layout {
   size_t E, B0, B1, Bbar, J0, J1, rho, pz, pfz, px, py, pux, puy, puz, pw, pid;
   size_t sz, sfz, sx, sy, sux, suy, suz, sw, spid, perm, ccount, cstart, scan;
-  size_t W, tracked, CE, CB, P, red, gam, ids, work, total;
+  size_t W, Wc, tracked, CE, CB, P, red, gam, ids, work, total;
 };
 
 Layout layout_of(const pic_run_desc &d, int prec, int N, int Tz, int Tr, long long n_keys) {
@@ -114,6 +114,7 @@ Layout layout_of(const pic_run_desc &d, int prec, int N, int Tz, int Tr, long lo
   L.cstart = take((size_t)(n_keys + 1) * 4);
   L.scan = take(((size_t)(n_keys + 1) / 256 + 2) * 4 * 2);
   L.W = take((size_t)(d.n_tracked > 0 ? d.n_tracked : 1) * (d.M + 1) * 8);
+  L.Wc = take((size_t)(d.n_tracked > 0 ? d.n_tracked : 1) * 2 * 8);
   L.tracked = take((size_t)(d.n_tracked > 0 ? d.n_tracked : 1) * 4);
   L.CE = take((size_t)N * rs);
   L.CB = take((size_t)N * rs);
@@ -440,6 +441,7 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
     k.ntr = (d.Nr + Tr - 1) / Tr;
     k.n_keys = keys_of(d, Tz, Tr);
     k.W = (double *)(base + L.W);
+    k.Wc = (double *)(base + L.Wc);
     k.tracked = (const int32_t *)(base + L.tracked);
     k.n_tracked = d.n_tracked;
     k.CE = base + L.CE;
@@ -522,7 +524,8 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
     const size_t rs = f64 ? 8 : 4;
     const size_t vecb = (size_t)3 * (2 * d.M + 1) * (size_t)k.plane * rs;
     if ((rc = launch_zero(k.J[0], vecb, s)) || (rc = launch_zero(k.J[1], vecb, s)) ||
-        (rc = launch_zero(k.W, (size_t)(d.n_tracked > 0 ? d.n_tracked : 1) * (d.M + 1) * 8, s)))
+        (rc = launch_zero(k.W, (size_t)(d.n_tracked > 0 ? d.n_tracked : 1) * (d.M + 1) * 8, s)) ||
+        (rc = launch_zero(k.Wc, (size_t)(d.n_tracked > 0 ? d.n_tracked : 1) * 2 * 8, s)))
       break;
     // B[0] = B^0 + (dt/2) curl_E E^0 = B^{-1/2};  B[1] = B^0 - (dt/2) curl_E E^0 = B^{+1/2}
     Batch b = batch_of_one(k);
@@ -1034,6 +1037,67 @@ int pic_mode_work(pic_ctx *ctx, int32_t run, double *work, double *gamma, double
     if (!std::isfinite(acc)) finite = false;
   }
   if (!finite) return fail(PIC_E_NUMERIC, "a diagnostic reduction is not finite");
+  return PIC_OK;
+}
+
+int pic_cartesian_work(pic_ctx *ctx, int32_t run, double *wz, double *wperp, double *f, double *w_lwfa,
+                       double *w_dla) {
+  g_msg[0] = 0;
+  if (!ctx_ok(ctx)) return fail(PIC_E_STATE, "invalid or destroyed context");
+  RunHost *R = get_run(ctx, run);
+  if (!R) return fail(PIC_E_INVALID, "bad run index");
+  const KRun &k = R->k;
+  const pic_run_desc &d = R->d;
+  const bool need_f = f || w_lwfa || w_dla;
+  if (need_f && (d.n_pulses < 1 || !(d.n0 > 0) || !(d.pulse[0].w0 > 0)))
+    return fail(PIC_E_INVALID, "the Pukhov ratio needs a pulse with w0 > 0 and n0 > 0");
+  const int nt = k.n_tracked;
+  if (nt == 0) return PIC_OK;
+  const hipStream_t s = ctx->stream;
+  std::vector<double> Wc((size_t)nt * 2), g((size_t)nt);
+  if (need_f) TRY(launch_tracked_gamma(k, ctx->prec, R->dev_gamma, R->dev_ids, s));
+  TRY(hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize"));
+  TRY(hip_ok(hipMemcpy(Wc.data(), k.Wc, Wc.size() * 8, hipMemcpyDeviceToHost), "D2H"));
+  if (need_f) TRY(hip_ok(hipMemcpy(g.data(), R->dev_gamma, (size_t)nt * 8, hipMemcpyDeviceToHost), "D2H"));
+  const double c = need_f ? -2.0 / (std::sqrt(d.n0) * d.pulse[0].w0 * d.pulse[0].w0) : 0.0;
+  bool finite = true;
+  for (int t = 0; t < nt; ++t) {
+    const double a = Wc[2 * (size_t)t], b = Wc[2 * (size_t)t + 1];
+    if (wz) wz[t] = a;
+    if (wperp) wperp[t] = b;
+    if (!std::isfinite(a) || !std::isfinite(b)) finite = false;
+    if (!need_f) continue;
+    const double ft = c * std::sqrt(2.0 * g[(size_t)t]);
+    if (!std::isfinite(ft)) finite = false;
+    if (f) f[t] = ft;
+    if (w_lwfa) w_lwfa[t] = a - ft * b;
+    if (w_dla) w_dla[t] = (1.0 + ft) * b;
+  }
+  if (!finite) return fail(PIC_E_NUMERIC, "a work value is not finite");
+  return PIC_OK;
+}
+
+int pic_divergence(pic_ctx *ctx, int32_t run, double gamma_min, double *out) {
+  g_msg[0] = 0;
+  if (!ctx_ok(ctx)) return fail(PIC_E_STATE, "invalid or destroyed context");
+  RunHost *R = get_run(ctx, run);
+  if (!R) return fail(PIC_E_INVALID, "bad run index");
+  if (!out) return fail(PIC_E_INVALID, "out is NULL");
+  if (!(gamma_min >= 1.0) || !std::isfinite(gamma_min)) return fail(PIC_E_INVALID, "gamma_min must be >= 1");
+  const KRun &k = R->k;
+  const hipStream_t s = ctx->stream;
+  int nb = 0;
+  static_assert(PIC_MAX_MODES + 1 >= 4, "the reduction buffer holds 4 sums per block");
+  TRY(launch_divergence(k, ctx->prec, gamma_min * gamma_min - 1.0, kRedBlocks, &nb, s));
+  std::vector<double> part((size_t)nb * 4);
+  TRY(hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize"));
+  TRY(hip_ok(hipMemcpy(part.data(), k.red, part.size() * 8, hipMemcpyDeviceToHost), "D2H"));
+  for (int c = 0; c < 4; ++c) {
+    double acc = 0.0;
+    for (int b = 0; b < nb; ++b) acc += part[(size_t)b * 4 + c];
+    out[c] = acc;
+    if (!std::isfinite(acc)) return fail(PIC_E_NUMERIC, "a divergence sum is not finite");
+  }
   return PIC_OK;
 }
 

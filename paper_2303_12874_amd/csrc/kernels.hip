@@ -510,6 +510,16 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
 #pragma unroll
         for (int m = 0; m <= M; ++m)
           W[m] += -k.dt * ((double)Em[m][0] * v0 + (double)Em[m][1] * v1 + (double)Em[m][2] * v2);
+        // the same work split by field direction, Eq. (17)
+        double ez = 0.0, ep = 0.0;
+#pragma unroll
+        for (int m = 0; m <= M; ++m) {
+          ez += (double)Em[m][2];
+          ep += (double)Em[m][0] * v0 + (double)Em[m][1] * v1;
+        }
+        double *Wc = k.Wc + (long long)lo * 2;
+        Wc[0] += -k.dt * ez * v2;
+        Wc[1] += -k.dt * ep;
       }
     }
 
@@ -1158,6 +1168,36 @@ __global__ __launch_bounds__(256) void kinetic_kernel(KRun k) {
   if (tid == 0) k.red[blockIdx.x] = sh[0];
 }
 
+// Charge-weighted divergence sums over electrons with |u|^2 >= u2min and
+// u_z > 0: w, w atan(ux/uz)^2, w atan(uy/uz)^2 and the count, per block.
+template <typename R>
+__global__ __launch_bounds__(256) void divergence_kernel(KRun k, double u2min) {
+  __shared__ double sh[4][256];
+  const int tid = threadIdx.x;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  const R *UX = (const R *)k.pux, *UY = (const R *)k.puy, *UZ = (const R *)k.puz, *W = (const R *)k.pw;
+  for (long long p = (long long)blockIdx.x * blockDim.x + tid; p < k.np; p += (long long)gridDim.x * blockDim.x) {
+    const double ux = UX[p], uy = UY[p], uz = UZ[p];
+    if (!(uz > 0.0) || ux * ux + uy * uy + uz * uz < u2min) continue;
+    const double w = W[p], tx = atan(ux / uz), ty = atan(uy / uz);
+    a0 += w;
+    a1 += w * tx * tx;
+    a2 += w * ty * ty;
+    a3 += 1.0;
+  }
+  sh[0][tid] = a0;
+  sh[1][tid] = a1;
+  sh[2][tid] = a2;
+  sh[3][tid] = a3;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s)
+      for (int c = 0; c < 4; ++c) sh[c][tid] += sh[c][tid + s];
+    __syncthreads();
+  }
+  if (tid < 4) k.red[4 * blockIdx.x + tid] = sh[tid][0];
+}
+
 template <typename R>
 __global__ __launch_bounds__(256) void tracked_gamma_kernel(KRun k, double *gamma, int64_t *ids) {
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1199,16 +1239,40 @@ __device__ __forceinline__ int cell_order(const KRun &k, long long p) {
   return tile * (k.Tz * k.Tr) + local;
 }
 
-// the keys go to the run's spid buffer, free until the gather writes it
+// Key and scatter kernels work on blocks of kSortBlock consecutive electrons
+// (kSortPer per thread).  In the order of the previous sort such a block spans
+// one or two tiles, so keys inside a window of two tiles' cells, starting at
+// the tile of the block's first electron, are counted and ranked in LDS, with
+// one device-memory atomic per cell and block; other keys (the first sort of
+// the loading order, electrons that changed tiles) take a device-memory atomic
+// each.  The keys go to the run's spid buffer, free until the gather writes it.
+constexpr int kSortPer = 8;
+constexpr int kSortBlock = 256 * kSortPer;
+
 template <typename R>
 __global__ __launch_bounds__(256) void sort_key_kernel(const Batch bt) {
+  extern __shared__ int32_t hist[];  // 2 TT counters
   const int rn = batch_run(bt, blockIdx.x);
   const KRun &k = bt.run[rn];
-  const long long p = (long long)(blockIdx.x - bt.off[rn]) * blockDim.x + threadIdx.x;
-  if (p >= k.np) return;
-  const int key = cell_order<R>(k, p);
-  ((int32_t *)k.spid)[p] = key;
-  atomicAdd(&k.cell_count[key], 1);
+  const int TT = k.Tz * k.Tr, HW = 2 * TT;
+  const long long p0 = (long long)(blockIdx.x - bt.off[rn]) * kSortBlock;
+  const int kb = cell_order<R>(k, p0) / TT * TT;  // window start (p0 < np: blocks cover np)
+  for (int d = threadIdx.x; d < HW; d += blockDim.x) hist[d] = 0;
+  __syncthreads();
+  int32_t *keys = (int32_t *)k.spid;
+#pragma unroll
+  for (int q = 0; q < kSortPer; ++q) {
+    const long long p = p0 + q * 256 + threadIdx.x;
+    if (p >= k.np) break;
+    const int key = cell_order<R>(k, p);
+    keys[p] = key;
+    const int d = key - kb;
+    if (d >= 0 && d < HW) atomicAdd(&hist[d], 1);
+    else atomicAdd(&k.cell_count[key], 1);
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < HW; d += blockDim.x)
+    if (hist[d] > 0 && kb + d < k.n_keys) atomicAdd(&k.cell_count[kb + d], hist[d]);
 }
 
 // exclusive scan of 1024-element blocks; block totals to bsum
@@ -1251,15 +1315,39 @@ __global__ __launch_bounds__(256) void copy_i32_kernel(int32_t *dst, const int32
 }
 
 // each electron's entry (id, source index) into its cell's range, in
-// whatever order the atomics run
+// whatever order the atomics run: ranks within the block from LDS atomics,
+// then one device-memory atomic per cell of the window reserves the block's
+// share of the cell (cell_count holds a copy of cell_start, the fill cursor)
 __global__ __launch_bounds__(256) void sort_scatter_kernel(const Batch bt) {
+  extern __shared__ int32_t hist[];  // 2 TT counters, then 2 TT bases
   const int rn = batch_run(bt, blockIdx.x);
   const KRun &k = bt.run[rn];
-  const long long p = (long long)(blockIdx.x - bt.off[rn]) * blockDim.x + threadIdx.x;
-  if (p >= k.np) return;
-  // cell_count holds a copy of cell_start, used as the fill cursor
-  const int pos = atomicAdd(&k.cell_count[((const int32_t *)k.spid)[p]], 1);
-  k.perm[pos] = ((uint64_t)(k.pid[p] & kIdMask) << 32) | (uint64_t)p;
+  const int TT = k.Tz * k.Tr, HW = 2 * TT;
+  int32_t *base = hist + HW;
+  const long long p0 = (long long)(blockIdx.x - bt.off[rn]) * kSortBlock;
+  const int32_t *keys = (const int32_t *)k.spid;
+  const int kb = keys[p0] / TT * TT;  // the window of the key kernel
+  for (int d = threadIdx.x; d < HW; d += blockDim.x) hist[d] = 0;
+  __syncthreads();
+  int key[kSortPer], rank[kSortPer];
+#pragma unroll
+  for (int q = 0; q < kSortPer; ++q) {
+    const long long p = p0 + q * 256 + threadIdx.x;
+    key[q] = p < k.np ? keys[p] : -1;
+    const int d = key[q] - kb;
+    rank[q] = (p < k.np && d >= 0 && d < HW) ? atomicAdd(&hist[d], 1) : -1;
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < HW; d += blockDim.x)
+    base[d] = (hist[d] > 0 && kb + d < k.n_keys) ? atomicAdd(&k.cell_count[kb + d], hist[d]) : 0;
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kSortPer; ++q) {
+    const long long p = p0 + q * 256 + threadIdx.x;
+    if (p >= k.np) break;
+    const int pos = rank[q] >= 0 ? base[key[q] - kb] + rank[q] : atomicAdd(&k.cell_count[key[q]], 1);
+    k.perm[pos] = ((uint64_t)(k.pid[p] & kIdMask) << 32) | (uint64_t)p;
+  }
 }
 
 // entries of one cell [b, e) in ascending id (insertion sort; cells are short)
@@ -1514,6 +1602,15 @@ int launch_kinetic(const KRun &k, int prec, int *nblocks, void *stream) {
   else kinetic_kernel<float><<<nb, 256, 0, (hipStream_t)stream>>>(k);
   return check(hipGetLastError(), "kinetic_kernel");
 }
+int launch_divergence(const KRun &k, int prec, double u2min, int nblocks_max, int *nblocks, void *stream) {
+  long long want = (k.np + 255) / 256;
+  int nb = (int)(want < nblocks_max ? want : nblocks_max);
+  if (nb < 1) nb = 1;
+  *nblocks = nb;
+  if (prec == PIC_PREC_FP64) divergence_kernel<double><<<nb, 256, 0, (hipStream_t)stream>>>(k, u2min);
+  else divergence_kernel<float><<<nb, 256, 0, (hipStream_t)stream>>>(k, u2min);
+  return check(hipGetLastError(), "divergence_kernel");
+}
 int launch_tracked_gamma(const KRun &k, int prec, double *gamma, int64_t *ids, void *stream) {
   if (k.np == 0 || k.n_tracked == 0) return PIC_OK;
   const unsigned blocks = (unsigned)((k.np + 255) / 256);
@@ -1527,10 +1624,11 @@ int launch_sort(Batch &b, int prec, void *stream) {
   int rc;
   for (int i = 0; i < b.n; ++i)
     if ((rc = launch_zero(b.run[i].cell_count, (size_t)(b.run[i].n_keys + 1) * 4, stream))) return rc;
-  const auto pblocks = [](const KRun &k) { return (k.np + 255) / 256; };
+  const auto pblocks = [](const KRun &k) { return (k.np + kSortBlock - 1) / kSortBlock; };
+  const size_t hw = (size_t)2 * b.run[0].Tz * b.run[0].Tr * sizeof(int32_t);  // one 2-tile window
   if (set_offsets(b, pblocks)) {
-    if (prec == PIC_PREC_FP64) sort_key_kernel<double><<<(unsigned)b.off[b.n], 256, 0, s>>>(b);
-    else sort_key_kernel<float><<<(unsigned)b.off[b.n], 256, 0, s>>>(b);
+    if (prec == PIC_PREC_FP64) sort_key_kernel<double><<<(unsigned)b.off[b.n], 256, hw, s>>>(b);
+    else sort_key_kernel<float><<<(unsigned)b.off[b.n], 256, hw, s>>>(b);
     if ((rc = check(hipGetLastError(), "sort_key_kernel"))) return rc;
   }
   for (int i = 0; i < b.n; ++i) {
@@ -1542,7 +1640,7 @@ int launch_sort(Batch &b, int prec, void *stream) {
     if ((rc = check(hipGetLastError(), "copy_i32_kernel"))) return rc;
   }
   if (!set_offsets(b, pblocks)) return PIC_OK;
-  sort_scatter_kernel<<<(unsigned)b.off[b.n], 256, 0, s>>>(b);
+  sort_scatter_kernel<<<(unsigned)b.off[b.n], 256, 2 * hw, s>>>(b);
   if ((rc = check(hipGetLastError(), "sort_scatter_kernel"))) return rc;
   set_offsets(b, [](const KRun &k) { return k.np > 0 ? (long long)k.ntz * k.ntr : 0LL; });
   const size_t lds = (size_t)kSortLdsEntries * sizeof(uint64_t);

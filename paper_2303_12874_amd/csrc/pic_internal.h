@@ -48,6 +48,7 @@ struct KRun {
   void *px, *py, *pux, *puy, *puz, *pw;
   uint32_t *pid;          // particle id | kTrackedBit
   double *W;              // [n_tracked][M+1] per-mode work (FP64)
+  double *Wc;             // [n_tracked][2] work of E_z and of E_perp (FP64)
   const int32_t *tracked; // tracked ids, ascending
   int n_tracked;
   const void *CE, *CB, *P;  // coefficient arrays (real type of the run), P has 2N-1 taps
@@ -118,6 +119,8 @@ int launch_zero(void *ptr, size_t bytes, void *stream);
 int launch_rho(const KRun &k, int prec, void *stream);
 int launch_energy(const KRun &k, int prec, int par, int nblocks_max, int *nblocks, void *stream);
 int launch_kinetic(const KRun &k, int prec, int *nblocks, void *stream);
+// 4 sums per block into k.red (nblocks <= nblocks_max, red holds 4 per block)
+int launch_divergence(const KRun &k, int prec, double u2min, int nblocks_max, int *nblocks, void *stream);
 int launch_tracked_gamma(const KRun &k, int prec, double *gamma, int64_t *ids, void *stream);
 const char *last_device_error();
 

@@ -75,6 +75,8 @@ def test_null_and_destroyed_context():
     assert lib.pic_destroy(None) == pic.PIC_E_STATE
     bogus = ctypes.c_void_p(12345678)
     assert lib.pic_step(bogus, 1) == pic.PIC_E_STATE
+    assert lib.pic_cartesian_work(None, 0, None, None, None, None, None) == pic.PIC_E_STATE
+    assert lib.pic_mode_work(None, 0, None, None, None, None, None, None) == pic.PIC_E_STATE
     assert b"context" in lib.pic_last_error()
 
 

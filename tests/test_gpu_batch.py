@@ -15,7 +15,8 @@ import numpy as np
 import pytest
 
 import workloads
-from test_gpu_parity import TOL64, _pic, _say, _setup, compare_fields, compare_particles, oracle_of
+from test_gpu_parity import (TOL64, _pic, _say, _setup, compare_cartesian_work, compare_fields, compare_particles,
+                             oracle_of)
 
 pytestmark = pytest.mark.gpu
 
@@ -56,6 +57,8 @@ def test_batched_runs_with_step_limits_match_oracles():
         assert np.array_equal(wg["id"], wo["id"])
         scale = max(np.abs(wo["W"]).max(), 1e-300)
         assert np.abs(wg["W"] - wo["W"]).max() / scale < TOL64, i
+        cw = compare_cartesian_work(sim, o, run, TOL64, i)
+        assert max(cw.values()) < TOL64, (i, cw)
     sim.close()
 
 

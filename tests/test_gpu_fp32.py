@@ -54,6 +54,18 @@ def fp32_errors(run, nsteps, sort_interval=0):
     gerr = np.abs(wg["gamma_acc"] - wo["gamma_acc"]) / scale
     werr = np.abs(wg["W"] - wo["W"])
     wtol = 1e-3 * np.abs(wo["W"]).max(axis=0) + 1e-7
+    # the direction split (Eq. (17)) to the per-mode work's bar
+    cg, co = sim.cartesian_work(corrected=False), o.cartesian_work()
+    for k in ("Wz", "Wperp"):
+        assert np.all(np.abs(cg[k] - co[k]) <= 1e-3 * np.abs(co[k]).max() + 1e-7), k
+    # the FP32 instantiation of the divergence reduction on the run's own state
+    from oracle import beam
+
+    pg = sim.particles()
+    dg, rs = sim.divergence(1.0), beam.divergence(pg, 1.0)
+    assert dg["count"] == rs["count"]
+    for k in ("w", "sum_wtx2", "sum_wty2"):
+        assert abs(dg[k] / rs[k] - 1) < 1e-12, k
     sim.close()
     return field_err, gerr, werr, wtol
 

@@ -90,10 +90,59 @@ def oracle_of(run, dt, CE, CB, fp32_start=False):
     return o
 
 
+def compare_cartesian_work(sim, o, run, tol, i=0):
+    """W_z, W_perp (Eq. (17)) against the oracle's accumulators, and f, W*
+    (Eqs. (20)-(21)) against the oracle's formulas applied to the oracle's
+    own W_z, W_perp and gamma.  Returns the worst relative differences."""
+    from oracle import work
+
+    cg = sim.cartesian_work(i, corrected=bool(run["pulses"]))
+    co, to = o.cartesian_work(), o.tracked()
+    scale = max(np.abs(co["Wz"]).max(), np.abs(co["Wperp"]).max(), 1e-300)
+    out = {"Wz": np.abs(cg["Wz"] - co["Wz"]).max() / scale, "Wperp": np.abs(cg["Wperp"] - co["Wperp"]).max() / scale}
+    if run["pulses"]:
+        p = run["pulses"][0]
+        f = work.pukhov_ratio(to["gamma"], run["n0"], p["w0"])
+        lw, dl = work.corrected_work(co["Wz"], co["Wperp"], f)
+        out["f"] = np.abs(cg["f"] / f - 1).max()
+        ws = max(np.abs(lw).max(), np.abs(dl).max(), 1e-300)
+        out["W*"] = max(np.abs(cg["W_lwfa"] - lw).max(), np.abs(cg["W_dla"] - dl).max()) / ws
+    return out
+
+
+def energetic_cut(gamma, lo=0.01, hi=0.03):
+    """A Lorentz-factor cut that keeps the top 1-3 % of the electrons, placed
+    in the middle of the widest gap between neighbouring values there, so that
+    state differences far below the gap cannot move an electron across it."""
+    g = np.sort(gamma)[::-1]
+    a, b = max(1, int(lo * g.size)), max(2, int(hi * g.size))
+    i = a + int(np.argmax(g[a - 1:b - 1] - g[a:b]))
+    return 0.5 * (g[i - 1] + g[i]), g[i - 1] - g[i]
+
+
+def compare_divergence(sim, o, i=0):
+    """The library's divergence sums against the oracle's: on the oracle's own
+    state (physics parity; count exact) and on the library's state (the
+    reduction alone).  Returns (worst relative difference, count)."""
+    from oracle import beam
+
+    po, pg = o.particles(), sim.particles(i)
+    go = np.sqrt(1 + po["ux"] ** 2 + po["uy"] ** 2 + po["uz"] ** 2)
+    cut, gap = energetic_cut(go)
+    dg, ro, rs = sim.divergence(cut, i), beam.divergence(po, cut), beam.divergence(pg, cut)
+    assert dg["count"] == ro["count"] == rs["count"], (dg["count"], ro["count"], rs["count"], gap)
+    worst = 0.0
+    for k in ("w", "sum_wtx2", "sum_wty2"):
+        worst = max(worst, abs(dg[k] / ro[k] - 1), abs(dg[k] / rs[k] - 1))
+    return worst, dg["count"]
+
+
 def run_pair(run, nsteps, precision=64, N=16):
     pic = _pic()
     dt, CE, CB, _ = _setup(N, run["M"], run["dz"], run["dr"])
-    sim = pic.Simulation([workloads.to_rundesc(run)], precision=precision, dt=dt, coef_E=CE, coef_B=CB)
+    solver = pic.SOLVER_YEE if N == 1 else pic.SOLVER_DUAL
+    sim = pic.Simulation([workloads.to_rundesc(run)], precision=precision, solver=solver, n_coef=N, dt=dt, coef_E=CE,
+                         coef_B=CB)
     o = oracle_of(run, dt, CE, CB, fp32_start=(precision == 32))
     sim.step(nsteps)
     o.step(nsteps)
@@ -119,6 +168,8 @@ def test_fp64_small_grid_parity(M):
     assert np.abs(wg["W"] - wo["W"]).max() / scale < TOL64
     # Eq. (16) work identity on the GPU path: sum_m W_m = gamma - gamma_0
     assert np.abs(wg["gamma_acc"] - wg["gamma"]).max() < 1e-13 * max(1.0, wg["gamma"].max())
+    cw = compare_cartesian_work(sim, o, run, TOL64)
+    assert max(cw.values()) < TOL64, cw
     sim.close()
 
 
@@ -141,6 +192,32 @@ def test_fp64_config1_full_parity():
     Uo = np.array([o.field_energy(m) for m in range(run["M"] + 1)])
     assert np.abs(U / Uo - 1).max() < TOL64
     assert abs(wg["kinetic"] / o.kinetic() - 1) < 1e-9
+    cw = compare_cartesian_work(sim, o, run, TOL64)
+    assert max(cw.values()) < TOL64, cw
+    dv, cnt = compare_divergence(sim, o)
+    assert dv < TOL64 and cnt > 100, (dv, cnt)
+    sim.close()
+
+
+@pytest.mark.parametrize("M", [1, 2])
+def test_yee_solver_parity(M):
+    """The Yee solver (one coefficient per operator, no filter) through the
+    same kernels: fields, particles, work and divergence against the oracle
+    run with C^E = C^B = (1)."""
+    _say(f"[gpu] yee M={M}")
+    run = workloads.small(M=M, Nz=64, Nr=12, ppc=2, n_tracked=40)["runs"][0]
+    sim, o = run_pair(run, 30, N=1)
+    worst = compare_fields(sim, o, M, TOL64)
+    bad = {k: v for k, v in worst.items() if v > TOL64}
+    assert not bad, bad
+    dzmax, dxy, du, _ = compare_particles(sim, o, run["Nz"])
+    assert dzmax < TOL64 and dxy < TOL64 and du < TOL64, (dzmax, dxy, du)
+    wg, wo = sim.mode_work(), o.tracked()
+    assert np.abs(wg["W"] - wo["W"]).max() / np.abs(wo["W"]).max() < TOL64
+    cw = compare_cartesian_work(sim, o, run, TOL64)
+    assert max(cw.values()) < TOL64, cw
+    dv, _ = compare_divergence(sim, o)
+    assert dv < TOL64, dv
     sim.close()
 
 

@@ -768,3 +768,36 @@ def test_pukhov_ratio_is_the_resonant_cycle_average(gamma, n0, w0):
     assert abs(lwfa) < 1e-5 * abs(wp)
     assert abs(dla - (wz + wp)) < 1e-5 * abs(f * wp)
     assert abs(lwfa + dla - (wz + wp)) < 1e-14 * abs(wp)
+
+
+# --------------------------------------------------------------------------
+# divergence of the energetic electrons (Secs. IV.A-IV.B)
+
+
+def test_divergence_of_constructed_beam():
+    """Electrons built with chosen angles and energies: the selection keeps
+    exactly those at or above gamma_min moving forward, and the RMS is the
+    charge-weighted RMS of the chosen angles (x and y kept apart)."""
+    from oracle import beam
+
+    rng = np.random.default_rng(11)
+    n = 400
+    th_x = rng.uniform(-0.3, 0.3, n)
+    th_y = rng.uniform(-0.1, 0.1, n)
+    g = rng.choice([5.0, 40.0, 80.0], n)
+    w = rng.uniform(0.5, 2.0, n)
+    # u along (tan th_x, tan th_y, 1) with |u| = sqrt(g^2 - 1)
+    d = np.stack([np.tan(th_x), np.tan(th_y), np.ones(n)])
+    u = d / np.linalg.norm(d, axis=0) * np.sqrt(g * g - 1.0)
+    back = rng.random(n) < 0.1  # some electrons move backward: never counted
+    u[:, back] *= -1.0
+    p = {"ux": u[0], "uy": u[1], "uz": u[2], "w": w}
+    r = beam.divergence(p, 20.0)  # cut between the energies, not on one
+    keep = (g >= 20.0) & ~back
+    assert r["count"] == keep.sum()
+    assert abs(r["rms_x"] - math.sqrt((w[keep] * th_x[keep] ** 2).sum() / w[keep].sum())) < 1e-13
+    assert abs(r["rms_y"] - math.sqrt((w[keep] * th_y[keep] ** 2).sum() / w[keep].sum())) < 1e-13
+    # a symmetric pair at +-theta has RMS theta
+    t = 0.2
+    q = {"ux": [math.sin(t), -math.sin(t)], "uy": [0.0, 0.0], "uz": [math.cos(t)] * 2, "w": [1.0, 3.0]}
+    assert abs(beam.divergence(q, 1.0)["rms_x"] - t) < 1e-15
