@@ -228,7 +228,6 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
   // thousands of FP32 contributions keeps its low bits until the flush
   extern __shared__ __align__(16) unsigned char lds_raw[];
   double *lds = (double *)lds_raw;
-  const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6, nwave = (int)blockDim.x >> 6;
   const int par = bt.par;
   const int TZ = bt.run[0].Tz, TR = bt.run[0].Tr;  // one sort tile for every run of a batch
   const int WZ = TZ + 3, WR = TR + 3;
@@ -257,13 +256,18 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
     const int grow = fr0g + row;
     const bool ok = grow >= 0 && grow <= kg.Nr;
     const long long pl = kg.plane;
-    const long long gg = (long long)(ok ? grow : 0) * kg.Nz + wrap_any(fz0g + col, kg.Nz);
+    // offset inside a plane (32-bit, so that each load is a uniform plane
+    // base plus a per-lane offset); every address is valid (row clamped), so
+    // the loads need no branch
+    const unsigned gg = (unsigned)((ok ? grow : 0) * kg.Nz + wrap_any(fz0g + col, kg.Nz));
     const R *Eg = (const R *)kg.E, *Bg = (const R *)kg.Bbar;
 #pragma unroll
-    for (int cq = 0; cq < FS; ++cq) {
+    for (int cq = 0; cq < 6 * NM; ++cq) {
       const int c = cq / NM, q = cq % NM;
-      v[cq] = (ok && cq < 6 * NM) ? (c < 3 ? Eg : Bg)[(c % 3) * pl * NM + q * pl + gg] : R(0);
+      const R t = ((c < 3 ? Eg : Bg) + ((c % 3) * NM + q) * pl)[gg];
+      v[cq] = ok ? t : R(0);
     }
+    v[6 * NM] = R(0);
   };
   auto stage_store = [&](int e, const R v[FS]) {
 #pragma unroll
@@ -741,22 +745,25 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
     UZ[p] = un[2];
   }
 
-  // ---- flush the tile's current (one wavefront per component, plane and
-  // row), clear the window, then stage the next tile's field window ----
+  // ---- flush the tile's current (each thread a window node, all its
+  // component planes), clear the window, then stage the next tile's field
+  // window ----
   if (threadIdx.x == 0) ticket = atomicAdd(bt.run[0].work, 1);  // read after the barrier
   __syncthreads();
   const int nt = ticket;
   if (n > 0)
-    for (int line = wave; line < JS * WR; line += nwave) {  // line = (c NM + q) WR + lr
-      const int cq = line / WR, lr = line - cq * WR;
+    for (int e = threadIdx.x; e < WZ * WR; e += blockDim.x) {
+      const int lr = e / WZ, lc = e - lr * WZ;
       const int row = rlo + lr;
       if (row < 0 || row > Nr) continue;  // never deposited to
-      R *dst = J + cq * plane + (long long)row * Nz;
-      double *src = lds + lr * WZ * JS + cq;
-      for (int lc = lane; lc < WZ; lc += 64) {
-        const R v = (R)src[lc * JS];
-        src[lc * JS] = 0.0;
-        if (v != R(0)) atomic_add(dst + wrap_any(zlo + lc, Nz), v);
+      // a node that takes current lies in [-1, Nz + 1]; the others hold zero
+      const unsigned off = (unsigned)(row * Nz + wrap_once(zlo + lc, Nz));
+      double *src = lds + e * JS;
+#pragma unroll
+      for (int cq = 0; cq < JS; ++cq) {
+        const R v = (R)src[cq];
+        src[cq] = 0.0;
+        if (v != R(0)) atomic_add(J + cq * plane + off, v);
       }
     }
   if (nt < t_hi)
