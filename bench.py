@@ -104,7 +104,7 @@ def main(argv=None):
     ap.add_argument("--tile-r", type=int, default=0, help="sort tile extent in r (0: library default)")
     ap.add_argument("--graph", action="store_true", help="replay captured steps (per-phase timing then unavailable)")
     ap.add_argument("--autotune", type=int, default=None,
-                    help="1: tile and sort interval from the library's autotuner (default: on for c4 only)")
+                    help="1: tile and sort interval from the library's autotuner (default: on for c4 and c5)")
     ap.add_argument("--precision", type=int, default=0, choices=[0, 32, 64],
                     help="override the workload's precision (0: as defined)")
     ap.add_argument("--solver", default="dual", choices=["dual", "yee"],
@@ -130,7 +130,7 @@ def main(argv=None):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     tune = None
-    if args.autotune if args.autotune is not None else multi:
+    if args.autotune if args.autotune is not None else args.workload in ("c4", "c5"):
         t0 = time.perf_counter()
         tune = pic.autotune([workloads.to_rundesc(r) for r in runs], precision=prec, solver=solver, n_coef=n_coef,
                             tile_z=args.tile_z,

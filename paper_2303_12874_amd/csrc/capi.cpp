@@ -661,8 +661,8 @@ int sort_runs_now(pic_ctx *ctx) {
 }
 
 // Candidate sort tiles of the autotuner (those whose push workgroup fits the LDS).
-constexpr int kTuneTiles[][2] = {{32, 8}, {32, 6}, {32, 4}, {30, 4}, {24, 8}, {24, 4}, {16, 8},
-                                 {16, 4}, {64, 4}, {64, 2}, {48, 4}, {32, 2}};
+constexpr int kTuneTiles[][2] = {{32, 8}, {32, 6}, {32, 4}, {30, 4}, {24, 8}, {24, 4}, {20, 4},
+                                 {16, 8}, {16, 4}, {64, 4}, {64, 2}, {48, 4}, {32, 2}};
 
 // Fold finished marks into the per-phase sums (the stream must be idle).
 int collect_marks(pic_ctx *ctx) {

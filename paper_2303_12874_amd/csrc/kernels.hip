@@ -682,12 +682,16 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
             pa0 = axis_row ? ax_a : pa;
             pb0 = axis_row ? ax_b : pb;
           }
+          // a node past the first two columns (rows) takes current only from
+          // a lane whose electron crossed a z (r) face: the wave skips it when
+          // no lane did, and each other lane masks itself off
 #pragma unroll
           for (int b = 0; b < 3; ++b) {
             if (b == 2 && !rx) continue;
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
               if (a == 1 && !zx) continue;
+              if ((a == 1 && di == 0) || (b == 2 && dj == 0)) continue;
               dep(2, qa, b, a, wz[b][a] * fa);
               if (m > 0) dep(2, qb, b, a, wz[b][a] * fb);
             }
@@ -698,6 +702,7 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
               if (b == 1 && !rx) continue;
+              if ((a == 2 && di == 0) || (b == 1 && dj == 0)) continue;
               dep(0, qa, b, a, wr[a][b] * fa);
               if (m > 0) dep(0, qb, b, a, wr[a][b] * fb);
             }
@@ -708,6 +713,7 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
               if (b == 2 && !rx) continue;
+              if ((a == 2 && di == 0) || (b == 2 && dj == 0)) continue;
               dep(1, qa, b, a, ws[a][b] * (b == 0 ? pa0 : pa));
               if (m > 0) dep(1, qb, b, a, ws[a][b] * (b == 0 ? pb0 : pb));
             }
