@@ -11,6 +11,7 @@ plasmas and pulses stand in for it at the sizes of the benchmark configs.
 from __future__ import annotations
 
 import math
+import numpy as np
 
 LAMBDA0 = 2.0 * math.pi
 SEED_BASE = 2303128740
@@ -96,3 +97,32 @@ def to_oracle(run: dict, dt, CE, CB):
         o.add_laser(p["a0"], p["w0"], p["tau"], p["zc"], run["taper"])
     o.start_fields()
     return o
+
+
+# ---------------------------------------------------------------------------
+# injected electrons for the reduced model of Sec. II (units c = omega_p = 1)
+
+DLA_APP_A = {"a0": 2.8, "kz": 12.14, "vphi": 1.002565, "vg": 0.993583, "R": 3.0, "t_inject": 200.0}
+
+
+def dla_injection(n: int, seed: int, R: float = 3.0, vg: float = 0.993583, t_inject: float = 200.0) -> dict:
+    """Electrons injected into the bubble as App. A describes: injection time
+    uniform over [0, t_inject]; on the y = 0 plane with zeta uniform in
+    [-2R + 0.286, -2R + 0.836] and x uniform in [-r_b, r_b], r_b(zeta) =
+    (R^2 - (zeta + R)^2)^(1/2); gamma uniform in [gamma_g, 2 gamma_g] with
+    gamma_g = (1 - vg^2)^(-1/2); the velocity's angle to the x axis uniform
+    over the angles with v_z >= vg.  Returns t0 and the state (x, zeta, xd,
+    zetad = v_z - 1), FP64, sorted by t0 (so that neighbouring electrons take
+    similar numbers of steps)."""
+    rng = np.random.default_rng(seed)
+    t0 = np.sort(rng.uniform(0.0, t_inject, n))
+    zeta = rng.uniform(-2 * R + 0.286, -2 * R + 0.836, n)
+    rb = np.sqrt(R * R - (zeta + R) ** 2)
+    x = rng.uniform(-1.0, 1.0, n) * rb
+    gg = 1.0 / np.sqrt(1.0 - vg * vg)
+    g = rng.uniform(gg, 2 * gg, n)
+    v = np.sqrt(1.0 - 1.0 / (g * g))
+    amin = np.arcsin(np.minimum(vg / v, 1.0))
+    ang = rng.uniform(amin, np.pi - amin)
+    vz = v * np.sin(ang)
+    return {"t0": t0, "x": x, "zeta": zeta, "xd": v * np.cos(ang), "zetad": vz - 1.0, "gamma": g}
