@@ -91,13 +91,94 @@ def cpu_baseline(runs: list, nsteps: int, n_coef: int = 16) -> dict:
                       f"setup excluded, {el:.1f} s"}
 
 
+# FP64 operations of one Runge-Kutta step of Eq. (8), not counting the three
+# special-function calls (J0, J1, sincos) and the reciprocal square root and
+# division of each of the six right-hand-side evaluations: 48 per evaluation
+# and 170 for the stage combinations and times
+DLA_FLOPS_PER_STEP = 6 * 48 + 170
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def bench_dla(args, torch, pic) -> int:
+    """Electrons of the App. A recipe (injection over 200 / omega_p, model
+    parameters of App. A) integrated to t = 400 / omega_p with h = 0.01 /
+    omega_p; one bench step is one integration of the whole ensemble from the
+    injected state; value = electron-steps/s (Runge-Kutta steps)."""
+    import numpy as np
+
+    A = workloads.DLA_APP_A
+    n, t_end, h = args.electrons, 400.0, 0.01
+    K = args.steps if args.steps is not None else 3
+    W = args.warmup if args.warmup is not None else 1
+    d = workloads.dla_injection(n, workloads.SEED_BASE + 90, R=A["R"], vg=A["vg"], t_inject=A["t_inject"])
+    names = ("t0", "x", "zeta", "xd", "zetad")
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    pristine = {k: torch.tensor(d[k], dtype=torch.float64, device=dev) for k in names}
+    work = {k: torch.empty_like(v) for k, v in pristine.items()}
+    steps_per_electron = np.maximum(0.0, np.ceil((t_end - d["t0"]) / h))
+    total_steps = float(steps_per_electron.sum())
+    model = {k: A[k] for k in ("a0", "kz", "vphi")}
+    stream = torch.cuda.current_stream(dev)
+
+    def once(timed):
+        for k in names:
+            work[k].copy_(pristine[k])
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        pic.dla_integrate(*[work[k] for k in names], t_end, h, **model)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    for _ in range(W):
+        once(False)
+    print(f"# dla warmup {W} done", file=sys.stderr, flush=True)
+    ms = [once(True) for _ in range(K)]
+    avg = sum(ms) / K
+    g = 1.0 / torch.sqrt(-work["zetad"] * (2.0 + work["zetad"]) - work["xd"] ** 2)
+    finite = bool(torch.isfinite(g).all().item())
+    ach = DLA_FLOPS_PER_STEP * total_steps / (avg * 1e-3) / 1e12
+    out = {
+        "metric": "electron-steps/s (reduced model of Eq. (8), fifth-order Runge-Kutta)",
+        "value": total_steps / (avg * 1e-3), "unit": "electron-steps/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": avg, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"dla: {n} electrons injected as in App. A over 200/omega_p, integrated to "
+                               f"t = {t_end:g}/omega_p with h = {h:g}/omega_p",
+                   "model": "a0 2.8, k_z 12.14 omega_p/c, v_phi 1.002565 c, R 3 c/omega_p (App. A)",
+                   "electrons": n, "rk_steps": total_steps},
+        "roofline": {"bound": "alu", "kernel": "dla", "achieved": ach, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "flops_per_step": DLA_FLOPS_PER_STEP, "avg_launch_ms": avg},
+        "state_finite": finite, "max_gamma": float(g.max().item()),
+    }
+    if args.cpu_steps > 0:
+        from oracle import dla
+
+        print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        m = 4096
+        y0 = np.stack([d[k][:m] for k in ("x", "zeta", "xd", "zetad")])
+        nst = 10000 * args.cpu_steps  # about 12 s of host time per unit
+        t0 = time.perf_counter()
+        dla.integrate(dla.params(), np.zeros(m), y0, nst * h, h)
+        el = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": m * nst / el, "unit": "electron-steps/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{nst} steps of {m} of the electrons (numpy, vectorised over electrons), "
+                                         f"{el:.1f} s"}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
                     help="timed steps (default 200; c4: each run its own count, at most --steps)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed steps first (default 20; c4: 8)")
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "dla"],
+                    help="c1..c5: the PIC step; dla: the reduced-model ensemble of Eq. (8)")
+    ap.add_argument("--electrons", type=int, default=262144, help="dla: electrons in the ensemble")
     ap.add_argument("--cpu-steps", type=int, default=1, help="oracle steps for the CPU baseline (0: skip)")
     ap.add_argument("--sort-interval", type=int, default=0)
     ap.add_argument("--tile-z", type=int, default=0, help="sort tile extent in z (0: library default)")
@@ -118,6 +199,8 @@ def main(argv=None):
 
     import paper_2303_12874_amd as pic
 
+    if args.workload == "dla":
+        return bench_dla(args, torch, pic)
     cfg = workloads.config(args.workload)
     runs = cfg["runs"]
     multi = len(runs) > 1

@@ -208,6 +208,35 @@ int pic_cartesian_work(pic_ctx *ctx, int32_t run, double *wz, double *wperp, dou
  * NULL; PIC_E_NUMERIC if a sum is not finite.                              */
 int pic_divergence(pic_ctx *ctx, int32_t run, double gamma_min, double *out);
 
+/* ---- reduced model of Sec. II (independent of any context) -------------- */
+
+/* Parameters of Eq. (8), units c = omega_p = 1 (time 1/omega_p, length
+ * c/omega_p).  The laser mode has wavenumber kz and phase velocity vphi >= 1
+ * (frequency kz vphi, transverse wavenumber kz (vphi^2 - 1)^(1/2)); the
+ * bubble is spherical and moves at c.                                       */
+typedef struct pic_dla_model {
+  double a0;   /* normalised vector potential of the laser                   */
+  double kz;   /* longitudinal wavenumber, > 0                               */
+  double vphi; /* phase velocity, >= 1                                       */
+  double cB;   /* factor on the laser's magnetic terms: 1 for the exact
+                  fields, cos(omega_0 dt / 2) for the time-staggering error of
+                  a Yee-type PIC step (Sec. IV.A)                             */
+  double wake; /* factor on the bubble terms: 1 for the model, 0 laser only  */
+} pic_dla_model;
+
+/* Integrate n electrons of the model (Sec. II, Eq. (8)) with the fifth-order
+ * Dormand-Prince solution at a fixed step (App. A names only an explicit
+ * fifth-order Runge-Kutta method): electron i goes from its injection time
+ * t0[i] to t_end in ceil((t_end - t0[i]) / h) equal steps (none if t0[i] >=
+ * t_end).  Device arrays of n FP64 values, caller owned, updated in place:
+ * x, zeta = z - t, xd = dx/dt, zetad = dzeta/dt (so v_z = zetad + 1; the
+ * state must have speed < 1).  Asynchronous on hip_stream; an electron driven
+ * to a non-physical state, or asked for more than 2^24 steps, ends as NaN.
+ * PIC_E_INVALID on NULL arrays with n > 0, n < 0, h <= 0, a non-finite
+ * t_end or an out-of-range model.                                          */
+int pic_dla_integrate(const pic_dla_model *model, int64_t n, const double *t0, double *x, double *zeta, double *xd,
+                      double *zetad, double t_end, double h, void *hip_stream);
+
 /* Synchronise and copy one component of mode m of one run into out, FP64
  * interleaved complex [(Nr+1)][Nz] (2 (Nr+1) Nz doubles; m = 0 has zero
  * imaginary part), physical units.  PIC_E_NOMEM if out_len (in doubles) is

@@ -64,6 +64,11 @@ class _RunInfo(C.Structure):
 MAX_TUNE = 16
 
 
+class _DlaModel(C.Structure):
+    _fields_ = [("a0", C.c_double), ("kz", C.c_double), ("vphi", C.c_double), ("cB", C.c_double),
+                ("wake", C.c_double)]
+
+
 class _TuneReport(C.Structure):
     _fields_ = [("n", C.c_int32), ("tile_z", C.c_int32 * MAX_TUNE), ("tile_r", C.c_int32 * MAX_TUNE),
                 ("interval", C.c_int32 * MAX_TUNE), ("ms_per_step", C.c_double * MAX_TUNE), ("best", C.c_int32)]
@@ -85,6 +90,7 @@ def _load():
         "pic_mode_work": [p, i32, p, p, p, p, p, p],
         "pic_cartesian_work": [p, i32, p, p, p, p, p],
         "pic_divergence": [p, i32, C.c_double, p],
+        "pic_dla_integrate": [C.POINTER(_DlaModel), C.c_int64, p, p, p, p, p, C.c_double, C.c_double, p],
         "pic_fields": [p, i32, i32, i32, p, sz],
         "pic_particles": [p, i32, p, p, p, p, p, p, p, p, sz],
         "pic_coefficients": [p, i32, p, p, p],
@@ -106,7 +112,7 @@ def _load():
 
 _lib = _load()
 EXPORTED = ("pic_solver_setup", "pic_courant_limit", "pic_load_host", "pic_init", "pic_step", "pic_mode_work",
-            "pic_cartesian_work", "pic_divergence",
+            "pic_cartesian_work", "pic_divergence", "pic_dla_integrate",
             "pic_fields", "pic_particles", "pic_coefficients", "pic_run_info_get", "pic_destroy",
             "pic_last_error", "pic_profile", "pic_profile_read", "pic_autotune")
 PHASES = ("sort", "push", "efield", "bfield", "step")  # "step": a whole step replayed from a graph
@@ -216,6 +222,26 @@ def _make_opts(precision, solver, n_coef, dt=0.0, coef_E=None, coef_B=None, cfl_
             setattr(o, name, a.ctypes.data_as(C.POINTER(C.c_double)))
     o.sort_interval, o.tile_z, o.tile_r, o.use_graph = sort_interval, tile_z, tile_r, int(use_graph)
     return o, keep
+
+
+def dla_integrate(t0, x, zeta, xd, zetad, t_end: float, h: float, a0=2.8, kz=12.14, vphi=1.002565, cB=1.0,
+                  wake=1.0):
+    """Integrate electrons of the reduced model (Sec. II, Eq. (8)) in place with
+    pic_dla_integrate, units c = omega_p = 1.  t0, x, zeta, xd, zetad: FP64
+    contiguous device tensors (torch) of one length; asynchronous on torch's
+    current stream of their device."""
+    import torch  # device memory and streams only
+
+    arrs = (t0, x, zeta, xd, zetad)
+    n = t0.numel()
+    for a in arrs:
+        if not (isinstance(a, torch.Tensor) and a.is_cuda and a.dtype == torch.float64 and a.is_contiguous()
+                and a.numel() == n and a.device == t0.device):
+            raise ValueError("dla_integrate takes contiguous float64 device tensors of one length on one device")
+    m = _DlaModel(a0, kz, vphi, cB, wake)
+    stream = torch.cuda.current_stream(t0.device)
+    _check(_lib.pic_dla_integrate(C.byref(m), n, *[C.c_void_p(a.data_ptr()) for a in arrs], float(t_end), float(h),
+                                  C.c_void_p(stream.cuda_stream)))
 
 
 def autotune(runs: Sequence[RunDesc], precision=PREC_FP64, solver=SOLVER_DUAL, n_coef=16, device="cuda:0",

@@ -1101,6 +1101,20 @@ int pic_divergence(pic_ctx *ctx, int32_t run, double gamma_min, double *out) {
   return PIC_OK;
 }
 
+int pic_dla_integrate(const pic_dla_model *model, int64_t n, const double *t0, double *x, double *zeta, double *xd,
+                      double *zetad, double t_end, double h, void *hip_stream) {
+  g_msg[0] = 0;
+  if (!model || n < 0 || (n > 0 && (!t0 || !x || !zeta || !xd || !zetad)))
+    return fail(PIC_E_INVALID, "bad arrays or count");
+  if (!(h > 0) || !std::isfinite(h) || !std::isfinite(t_end)) return fail(PIC_E_INVALID, "bad step or end time");
+  const pic_dla_model &m = *model;
+  if (!(m.kz > 0) || !std::isfinite(m.kz) || !(m.vphi >= 1.0) || !std::isfinite(m.vphi) || !std::isfinite(m.a0) ||
+      !std::isfinite(m.cB) || !std::isfinite(m.wake))
+    return fail(PIC_E_INVALID, "model out of range (kz > 0, vphi >= 1, finite factors)");
+  TRY(launch_dla(m, (long long)n, t0, x, zeta, xd, zetad, t_end, h, hip_stream));
+  return PIC_OK;
+}
+
 int pic_destroy(pic_ctx *ctx) {
   g_msg[0] = 0;
   if (!ctx_ok(ctx)) return fail(PIC_E_STATE, "invalid or destroyed context");

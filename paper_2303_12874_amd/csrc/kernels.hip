@@ -1576,6 +1576,7 @@ struct EnL {
 }  // namespace
 
 const char *last_device_error() { return g_err; }
+int record_device_error(int hip_status, const char *what) { return check((hipError_t)hip_status, what); }
 
 int launch_push(Batch &b, int prec, void *stream) {
   return dispatch_M<PushL>(prec, b.run[0].M, b, (hipStream_t)stream);

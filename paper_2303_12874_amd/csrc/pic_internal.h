@@ -123,5 +123,10 @@ int launch_kinetic(const KRun &k, int prec, int *nblocks, void *stream);
 int launch_divergence(const KRun &k, int prec, double u2min, int nblocks_max, int *nblocks, void *stream);
 int launch_tracked_gamma(const KRun &k, int prec, double *gamma, int64_t *ids, void *stream);
 const char *last_device_error();
+// record a failed HIP status (as int) with a label for pic_last_error; returns PIC_OK or PIC_E_DEVICE
+int record_device_error(int hip_status, const char *what);
+// reduced-model ensemble (dla.hip): n electrons in place on `stream`
+int launch_dla(const pic_dla_model &m, long long n, const double *t0, double *x, double *zeta, double *xd,
+               double *zetad, double t_end, double h, void *stream);
 
 }  // namespace pic

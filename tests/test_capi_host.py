@@ -156,3 +156,20 @@ def test_autotune_rejects_bad_arguments():
     assert _tune_query(runs, trial_steps=65)[0] == pic.PIC_E_INVALID
     assert _tune_query(runs, precision=16)[0] == pic.PIC_E_INVALID
     assert _tune_query([_desc(M=1), _desc(M=2)])[0] == pic.PIC_E_INVALID
+
+
+def test_dla_integrate_rejects_bad_arguments_without_device():
+    """Validation happens before any device call; n = 0 with valid arguments
+    is a no-op that needs no GPU."""
+    lib = pic._lib
+    good = pic._DlaModel(2.8, 12.14, 1.002565, 1.0, 1.0)
+    assert lib.pic_dla_integrate(ctypes.byref(good), 0, None, None, None, None, None, 100.0, 0.01, None) == pic.PIC_OK
+    dummy = ctypes.c_void_p(4096)
+    for model, n, h, t_end in ((pic._DlaModel(2.8, 12.14, 0.99, 1.0, 1.0), 4, 0.01, 10.0),  # vphi < 1
+                               (pic._DlaModel(2.8, 0.0, 1.002, 1.0, 1.0), 4, 0.01, 10.0),  # kz <= 0
+                               (good, -1, 0.01, 10.0), (good, 4, 0.0, 10.0), (good, 4, 0.01, float("inf"))):
+        assert lib.pic_dla_integrate(ctypes.byref(model), n, dummy, dummy, dummy, dummy, dummy, t_end, h,
+                                     None) == pic.PIC_E_INVALID
+    assert lib.pic_dla_integrate(ctypes.byref(good), 4, None, dummy, dummy, dummy, dummy, 10.0, 0.01,
+                                 None) == pic.PIC_E_INVALID
+    assert lib.pic_dla_integrate(None, 0, None, None, None, None, None, 10.0, 0.01, None) == pic.PIC_E_INVALID
