@@ -232,8 +232,10 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
   const int TZ = bt.run[0].Tz, TR = bt.run[0].Tr;  // one sort tile for every run of a batch
   const int WZ = TZ + 3, WR = TR + 3;
   const long long TT = (long long)TZ * TR;
-  const int nlds = JS * WZ * WR;
-  const int FZ = TZ + 2 + 2 * kFieldMarginZ, FR = TR + 2 + 2 * kFieldMarginR;
+  const int RJ = current_window_row(M, TZ);  // FP64 sums per current-window row (padded)
+  const int nlds = RJ * WR;
+  const int FZ = field_window_z(TZ), FR = field_window_r(TR);
+  const int RF = field_window_row(M, TZ, F64 ? PIC_PREC_FP64 : PIC_PREC_FP32);  // reals per field-window row
   R *fw = (R *)(lds + nlds);
 
   // Persistent: each workgroup takes tiles (of all runs of the batch) from a
@@ -270,8 +272,10 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
     v[6 * NM] = R(0);
   };
   auto stage_store = [&](int e, const R v[FS]) {
+    const int row = e / FZ;
+    R *dst = fw + row * RF + (e - row * FZ) * FS;
 #pragma unroll
-    for (int cq = 0; cq < FS; ++cq) fw[e * FS + cq] = v[cq];
+    for (int cq = 0; cq < FS; ++cq) dst[cq] = v[cq];
   };
 
   // the current window starts at zero; each flush clears what it adds
@@ -401,8 +405,8 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
     const int a0 = fc, h0 = fc + dh;
     const int ri0 = j0 - fr0, rh0 = (mir ? 0 : jh) - fr0, rh1 = jh + 1 - fr0;
     if (h0 >= 0 && a0 + 1 <= FZ - 1 && ri0 >= 0 && rh0 >= 0 && ri0 + 1 <= FR - 1 && rh1 <= FR - 1) {
-      const R *li0 = fw + ri0 * FZ * FS, *li1 = li0 + FZ * FS;  // rows of j0, j0 + 1
-      const R *lh0 = fw + rh0 * FZ * FS, *lh1 = fw + rh1 * FZ * FS;  // half-r rows
+      const R *li0 = fw + ri0 * RF, *li1 = li0 + RF;  // rows of j0, j0 + 1
+      const R *lh0 = fw + rh0 * RF, *lh1 = fw + rh1 * RF;  // half-r rows
       const int A0 = a0 * FS, A1 = A0 + FS, H0 = h0 * FS, H1 = H0 + FS;
       interp4<R, NMP, true, false, int>(lh0 + A0, lh0 + A1, lh1 + A0, lh1 + A1, 1, mir, f0, frh, er);
       interp4<R, NMP, false, false, int>(li0 + A0 + NM, li0 + A1 + NM, li1 + A0 + NM, li1 + A1 + NM, 1, false, f0,
@@ -722,8 +726,8 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
       };
       // the 3 x 3 node window [ib, ib+2] x [jb, jb+2] inside the tile's LDS window?
       if ((ib - zlo >= 0) && (ib + 2 - zlo < WZ) && (jb - rlo >= 0) && (jb + 2 - rlo < WR)) {
-        double *jw = lds + ((jb - rlo) * WZ + (ib - zlo)) * JS;
-        const int rowJ = WZ * JS;
+        double *jw = lds + (jb - rlo) * RJ + (ib - zlo) * JS;
+        const int rowJ = RJ;
         deposit([&](int c, int qq, int b, int a, double v) { lds_add(jw + b * rowJ + a * JS + c * NM + qq, v); });
       } else {
         int col[3];
@@ -764,7 +768,7 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
       if (row < 0 || row > Nr) continue;  // never deposited to
       // a node that takes current lies in [-1, Nz + 1]; the others hold zero
       const unsigned off = (unsigned)(row * Nz + wrap_once(zlo + lc, Nz));
-      double *src = lds + e * JS;
+      double *src = lds + lr * RJ + lc * JS;
 #pragma unroll
       for (int cq = 0; cq < JS; ++cq) {
         const R v = (R)src[cq];

@@ -80,15 +80,28 @@ constexpr int kFieldMarginR = 0;
 constexpr size_t kPushLdsDefault = 81920;  // default tile choice: two workgroups per CU
 constexpr size_t kPushLdsMax = 163840;     // gfx950 LDS per workgroup
 
-inline int field_window_z(int Tz) { return Tz + 2 + 2 * kFieldMarginZ; }
-inline int field_window_r(int Tr) { return Tr + 2 + 2 * kFieldMarginR; }
-inline size_t current_window_words(int M, int Tz, int Tr) {
-  return (size_t)3 * (2 * M + 1) * (Tz + 3) * (Tr + 3);
+// Both windows are row-padded: the wavefront's lanes work on consecutive cells
+// of the tile (z fastest, then the next row), and a row stride congruent to
+// Tz nodes modulo the 256-byte bank width keeps those lanes on distinct banks
+// when a wavefront spans two rows.
+constexpr int kBankBytes = 256;  // 64 LDS banks of 4 bytes
+constexpr int field_window_z(int Tz) { return Tz + 2 + 2 * kFieldMarginZ; }
+constexpr int field_window_r(int Tr) { return Tr + 2 + 2 * kFieldMarginR; }
+constexpr int pos_mod(int a, int m) { return ((a % m) + m) % m; }
+// FP64 sums per current-window row: (Tz + 3) nodes of 3 NM, plus the pad
+constexpr int current_window_row(int M, int Tz) {
+  return 3 * (2 * M + 1) * (Tz + 3) + pos_mod(-3 * 3 * (2 * M + 1), kBankBytes / 8);
 }
+// reals per field-window row: field_window_z nodes of 6 NM + 1, plus the pad
+constexpr int field_window_row(int M, int Tz, int precision) {
+  return (6 * (2 * M + 1) + 1) * field_window_z(Tz) +
+         pos_mod(-(field_window_z(Tz) - Tz) * (6 * (2 * M + 1) + 1),
+                 kBankBytes / (precision == PIC_PREC_FP64 ? 8 : 4));
+}
+inline size_t current_window_words(int M, int Tz, int Tr) { return (size_t)current_window_row(M, Tz) * (Tr + 3); }
 inline size_t push_lds_bytes(int M, int Tz, int Tr, int precision) {
   const size_t w = precision == PIC_PREC_FP64 ? 8 : 4;
-  return current_window_words(M, Tz, Tr) * 8 +
-         (size_t)(6 * (2 * M + 1) + 1) * field_window_z(Tz) * field_window_r(Tr) * w;
+  return current_window_words(M, Tz, Tr) * 8 + (size_t)field_window_row(M, Tz, precision) * field_window_r(Tr) * w;
 }
 
 // ---- batched launches ---------------------------------------------------------
