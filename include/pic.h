@@ -286,14 +286,15 @@ typedef struct pic_tune_report {
  * measurement (neither changes the physics, only the summation order of the
  * deposit).  For every candidate tile whose push workgroup fits the LDS
  * (the tile in opts, if set, is the only candidate) a trial context is built
- * in device_workspace on hip_stream; after one untimed step and a timed sort,
- * trial_steps steps (4..64) are timed one by one with HIP events, t_k at k
- * steps after the sort, and K = argmin (t_sort + sum_{k<K} t_k) / K.  The
- * fastest (tile, K) is written to opts->tile_z, tile_r, sort_interval; the
- * trial contexts are destroyed.  With device_workspace NULL only the bytes
- * needed (the largest trial context) are written to *workspace_bytes.
- * report may be NULL.  Times are those of the early, still cold plasma of
- * the trial, which the caller should keep in mind for long runs.            */
+ * in device_workspace on hip_stream; after trial_steps untimed steps and a
+ * timed sort, trial_steps steps (4..64) are timed one by one with HIP
+ * events, t_k at k steps after the sort, and K = argmin (t_sort +
+ * sum_{k<K} t_k) / K.  The fastest (tile, K) is written to opts->tile_z,
+ * tile_r, sort_interval; the trial contexts are destroyed.  With
+ * device_workspace NULL only the bytes needed (the largest trial context)
+ * are written to *workspace_bytes.  report may be NULL.  Times are those of
+ * the early plasma of the trial, which the caller should keep in mind for
+ * long runs.                                                                */
 int pic_autotune(const pic_run_desc *runs, int32_t n_runs, pic_opts *opts, void *device_workspace,
                  size_t *workspace_bytes, void *hip_stream, int32_t trial_steps, pic_tune_report *report);
 

@@ -78,6 +78,10 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (or python -m "
                           "paper_2303_12874_amd.build)")
+    # The device memory and streams the library is handed come from torch, so
+    # it must bind to the HIP runtime torch loads: load torch first, or the
+    # dynamic linker picks the system runtime and the process holds two.
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     i32, i64, d, p, sz = C.c_int32, C.c_int64, C.c_double, C.c_void_p, C.c_size_t
     dp = C.POINTER(C.c_double)

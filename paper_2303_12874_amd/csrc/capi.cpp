@@ -764,9 +764,10 @@ int pic_autotune(const pic_run_desc *runs, int32_t n_runs, pic_opts *opts, void 
     pic_ctx *ctx = nullptr;
     size_t b = *workspace_bytes;
     if ((rc = pic_init(rd.data(), n_runs, &o, device_workspace, &b, hip_stream, &ctx))) break;
-    // one untimed step (kernels loaded, caches warm), then a timed sort: the
-    // timed steps start from a freshly sorted state
-    rc = pic_step(ctx, 1);
+    // T untimed steps (kernels loaded, caches warm, the electrons and the
+    // pulse no longer in their loaded state), then a timed sort: the timed
+    // steps start from a freshly sorted state
+    rc = pic_step(ctx, T);
     if (!rc) rc = hip_ok(hipEventRecord(ev[0], s), "hipEventRecord");
     if (!rc) rc = sort_runs_now(ctx);
     if (!rc) rc = hip_ok(hipEventRecord(ev[1], s), "hipEventRecord");

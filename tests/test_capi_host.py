@@ -173,3 +173,18 @@ def test_dla_integrate_rejects_bad_arguments_without_device():
     assert lib.pic_dla_integrate(ctypes.byref(good), 4, None, dummy, dummy, dummy, dummy, 10.0, 0.01,
                                  None) == pic.PIC_E_INVALID
     assert lib.pic_dla_integrate(None, 0, None, None, None, None, None, 10.0, 0.01, None) == pic.PIC_E_INVALID
+
+
+def test_library_binds_to_the_runtime_torch_loads():
+    """Importing the package before torch must not bring a second HIP runtime
+    into the process: the library receives torch's device memory and streams,
+    so it has to bind to the runtime torch loads."""
+    import subprocess
+    import sys
+
+    code = ("import paper_2303_12874_amd, torch\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "print(len({l.split()[-1] for l in maps if 'libamdhip64' in l}))\n")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "1", out.stdout
