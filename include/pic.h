@@ -208,6 +208,22 @@ int pic_cartesian_work(pic_ctx *ctx, int32_t run, double *wz, double *wperp, dou
  * NULL; PIC_E_NUMERIC if a sum is not finite.                              */
 int pic_divergence(pic_ctx *ctx, int32_t run, double gamma_min, double *out);
 
+/* ---- checkpoint and restore ------------------------------------------------ */
+
+/* Synchronise and copy the whole state of the context (every run: fields,
+ * currents, electrons in their current order, the tile ranges of the last
+ * sort, tracked work, step counts) into host_buf, caller owned.  With
+ * host_buf NULL only *bytes is written (size query).  PIC_E_NOMEM if *bytes
+ * is short.                                                                 */
+int pic_checkpoint(pic_ctx *ctx, void *host_buf, size_t *bytes);
+
+/* Load a checkpoint into a context created by pic_init with the same runs and
+ * options (checked: run descriptors, precision, sort tile and interval,
+ * solver coefficients); stepping then continues where the checkpointed
+ * context was.  PIC_E_INVALID if the checkpoint does not belong to such a
+ * context; nothing is changed then.                                         */
+int pic_restore(pic_ctx *ctx, const void *host_buf, size_t bytes);
+
 /* ---- reduced model of Sec. II (independent of any context) -------------- */
 
 /* Parameters of Eq. (8), units c = omega_p = 1 (time 1/omega_p, length

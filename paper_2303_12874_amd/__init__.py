@@ -94,6 +94,8 @@ def _load():
         "pic_mode_work": [p, i32, p, p, p, p, p, p],
         "pic_cartesian_work": [p, i32, p, p, p, p, p],
         "pic_divergence": [p, i32, C.c_double, p],
+        "pic_checkpoint": [p, p, C.POINTER(C.c_size_t)],
+        "pic_restore": [p, p, sz],
         "pic_dla_integrate": [C.POINTER(_DlaModel), C.c_int64, p, p, p, p, p, C.c_double, C.c_double, p],
         "pic_fields": [p, i32, i32, i32, p, sz],
         "pic_particles": [p, i32, p, p, p, p, p, p, p, p, sz],
@@ -116,7 +118,7 @@ def _load():
 
 _lib = _load()
 EXPORTED = ("pic_solver_setup", "pic_courant_limit", "pic_load_host", "pic_init", "pic_step", "pic_mode_work",
-            "pic_cartesian_work", "pic_divergence", "pic_dla_integrate",
+            "pic_cartesian_work", "pic_divergence", "pic_dla_integrate", "pic_checkpoint", "pic_restore",
             "pic_fields", "pic_particles", "pic_coefficients", "pic_run_info_get", "pic_destroy",
             "pic_last_error", "pic_profile", "pic_profile_read", "pic_autotune")
 PHASES = ("sort", "push", "efield", "bfield", "step")  # "step": a whole step replayed from a graph
@@ -356,6 +358,19 @@ class Simulation:
         _check(_lib.pic_mode_work(self._h, run, _ptr(W), _ptr(g), _ptr(ga), _ptr(ids), _ptr(U), _ptr(K)))
         return {"W": W[:nt], "gamma": g[:nt], "gamma_acc": ga[:nt], "id": ids[:nt], "field_energy": U,
                 "kinetic": K[0]}
+
+    def checkpoint(self) -> bytes:
+        """The whole state of the context as bytes (pic_checkpoint)."""
+        n = C.c_size_t(0)
+        _check(_lib.pic_checkpoint(self._h, None, C.byref(n)))
+        buf = (C.c_ubyte * n.value)()
+        _check(_lib.pic_checkpoint(self._h, buf, C.byref(n)))
+        return bytes(buf)
+
+    def restore(self, blob: bytes):
+        """Continue from a checkpoint of a context with the same runs and options."""
+        buf = (C.c_ubyte * len(blob)).from_buffer_copy(blob)
+        _check(_lib.pic_restore(self._h, buf, len(blob)))
 
     def divergence(self, gamma_min=1.0, run=0):
         """Charge-weighted RMS divergence theta_x = atan(u_x/u_z) (and theta_y)

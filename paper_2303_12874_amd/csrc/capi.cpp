@@ -1116,6 +1116,147 @@ int pic_dla_integrate(const pic_dla_model *model, int64_t n, const double *t0, d
   return PIC_OK;
 }
 
+// ---- checkpoint / restore --------------------------------------------------
+// Layout: header, then per run its descriptor, step count, initial tracked
+// gamma and coefficients (for validation), then the device state in a fixed
+// order: E, B at both half steps, Bbar, both J buffers, rho, the particle
+// arrays in their current (sorted) order, the tile ranges of the last sort,
+// and the tracked work.
+
+}  // extern "C"
+
+namespace {
+
+struct CkptHeader {
+  char magic[8];
+  int32_t version, n_runs, precision, tile_z, tile_r, sort_interval;
+};
+
+struct Seg {
+  void *dev;
+  size_t bytes;
+};
+
+std::vector<Seg> state_segments(const RunHost &R, int prec) {
+  const KRun &k = R.k;
+  const pic_run_desc &d = R.d;
+  const size_t rs = prec == PIC_PREC_FP64 ? 8 : 4;
+  const size_t NM = (size_t)(2 * d.M + 1);
+  const size_t vec = 3 * NM * (size_t)k.plane * rs;
+  const size_t np = (size_t)k.np;
+  const size_t nt = (size_t)(d.n_tracked > 0 ? d.n_tracked : 0);
+  std::vector<Seg> s = {{k.E, vec}, {k.B[0], vec}, {k.B[1], vec}, {k.Bbar, vec}, {k.J[0], vec}, {k.J[1], vec},
+                        {k.rho, NM * (size_t)k.plane * 8}, {k.pz, np * (prec == PIC_PREC_FP64 ? 8 : 4)}};
+  if (prec != PIC_PREC_FP64) s.push_back({k.pfz, np * 4});
+  for (void *p : {k.px, k.py, k.pux, k.puy, k.puz, k.pw}) s.push_back({p, np * rs});
+  s.push_back({k.pid, np * 4});
+  s.push_back({k.cell_start, (size_t)(k.n_keys + 1) * 4});
+  s.push_back({k.W, nt * (size_t)(d.M + 1) * 8});
+  s.push_back({k.Wc, nt * 2 * 8});
+  return s;
+}
+
+size_t run_meta_bytes(const RunHost &R) {
+  return sizeof(pic_run_desc) + sizeof(int64_t) + (R.gam0.size() + R.CE.size() + R.CB.size()) * sizeof(double);
+}
+
+size_t checkpoint_bytes(pic_ctx *ctx) {
+  size_t n = sizeof(CkptHeader);
+  for (const RunHost &R : ctx->runs) {
+    n += run_meta_bytes(R);
+    for (const Seg &g : state_segments(R, ctx->prec)) n += g.bytes;
+  }
+  return n;
+}
+
+CkptHeader header_of(pic_ctx *ctx) {
+  CkptHeader h;
+  std::memset(&h, 0, sizeof h);
+  std::memcpy(h.magic, "PICCKPT1", 8);
+  h.version = 1;
+  h.n_runs = (int32_t)ctx->runs.size();
+  h.precision = ctx->prec;
+  h.tile_z = ctx->runs.empty() ? 0 : ctx->runs[0].k.Tz;
+  h.tile_r = ctx->runs.empty() ? 0 : ctx->runs[0].k.Tr;
+  h.sort_interval = ctx->sort_interval;
+  return h;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pic_checkpoint(pic_ctx *ctx, void *host_buf, size_t *bytes) {
+  g_msg[0] = 0;
+  if (!ctx_ok(ctx)) return fail(PIC_E_STATE, "invalid or destroyed context");
+  if (!bytes) return fail(PIC_E_INVALID, "bytes is NULL");
+  const size_t need = checkpoint_bytes(ctx);
+  if (!host_buf) {
+    *bytes = need;
+    return PIC_OK;
+  }
+  if (*bytes < need) return fail(PIC_E_NOMEM, "buffer of %zu bytes, %zu needed", *bytes, need);
+  TRY(hip_ok(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize"));
+  unsigned char *o = (unsigned char *)host_buf;
+  const CkptHeader h = header_of(ctx);
+  std::memcpy(o, &h, sizeof h);
+  o += sizeof h;
+  for (const RunHost &R : ctx->runs) {
+    std::memcpy(o, &R.d, sizeof(pic_run_desc));
+    o += sizeof(pic_run_desc);
+    std::memcpy(o, &R.steps, sizeof(int64_t));
+    o += sizeof(int64_t);
+    for (const std::vector<double> *v : {&R.gam0, &R.CE, &R.CB}) {
+      if (!v->empty()) std::memcpy(o, v->data(), v->size() * sizeof(double));
+      o += v->size() * sizeof(double);
+    }
+    for (const Seg &g : state_segments(R, ctx->prec)) {
+      if (g.bytes) TRY(hip_ok(hipMemcpy(o, g.dev, g.bytes, hipMemcpyDeviceToHost), "D2H"));
+      o += g.bytes;
+    }
+  }
+  *bytes = need;
+  return PIC_OK;
+}
+
+int pic_restore(pic_ctx *ctx, const void *host_buf, size_t bytes) {
+  g_msg[0] = 0;
+  if (!ctx_ok(ctx)) return fail(PIC_E_STATE, "invalid or destroyed context");
+  if (!host_buf) return fail(PIC_E_INVALID, "buffer is NULL");
+  const size_t need = checkpoint_bytes(ctx);
+  if (bytes != need) return fail(PIC_E_INVALID, "checkpoint of %zu bytes, this context takes %zu", bytes, need);
+  const unsigned char *p = (const unsigned char *)host_buf;
+  const CkptHeader h = header_of(ctx);
+  if (std::memcmp(p, &h, sizeof h) != 0)
+    return fail(PIC_E_INVALID, "checkpoint header does not match this context (runs, precision, tile, interval)");
+  // validate every run before any device copy
+  const unsigned char *q = p + sizeof h;
+  for (const RunHost &R : ctx->runs) {
+    if (std::memcmp(q, &R.d, sizeof(pic_run_desc)) != 0) return fail(PIC_E_INVALID, "run descriptors differ");
+    q += sizeof(pic_run_desc) + sizeof(int64_t) + R.gam0.size() * sizeof(double);
+    for (const std::vector<double> *v : {&R.CE, &R.CB}) {
+      if (!v->empty() && std::memcmp(q, v->data(), v->size() * sizeof(double)) != 0)
+        return fail(PIC_E_INVALID, "solver coefficients differ");
+      q += v->size() * sizeof(double);
+    }
+    for (const Seg &g : state_segments(R, ctx->prec)) q += g.bytes;
+  }
+  TRY(hip_ok(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize"));
+  q = p + sizeof h;
+  for (RunHost &R : ctx->runs) {
+    q += sizeof(pic_run_desc);
+    std::memcpy(&R.steps, q, sizeof(int64_t));
+    q += sizeof(int64_t);
+    if (!R.gam0.empty()) std::memcpy(R.gam0.data(), q, R.gam0.size() * sizeof(double));
+    q += (R.gam0.size() + R.CE.size() + R.CB.size()) * sizeof(double);
+    for (const Seg &g : state_segments(R, ctx->prec)) {
+      if (g.bytes) TRY(hip_ok(hipMemcpy(g.dev, q, g.bytes, hipMemcpyHostToDevice), "H2D"));
+      q += g.bytes;
+    }
+  }
+  return PIC_OK;
+}
+
 int pic_destroy(pic_ctx *ctx) {
   g_msg[0] = 0;
   if (!ctx_ok(ctx)) return fail(PIC_E_STATE, "invalid or destroyed context");

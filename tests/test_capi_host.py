@@ -76,6 +76,9 @@ def test_null_and_destroyed_context():
     bogus = ctypes.c_void_p(12345678)
     assert lib.pic_step(bogus, 1) == pic.PIC_E_STATE
     assert lib.pic_cartesian_work(None, 0, None, None, None, None, None) == pic.PIC_E_STATE
+    n = ctypes.c_size_t(0)
+    assert lib.pic_checkpoint(None, None, ctypes.byref(n)) == pic.PIC_E_STATE
+    assert lib.pic_restore(None, None, 0) == pic.PIC_E_STATE
     assert lib.pic_mode_work(None, 0, None, None, None, None, None, None) == pic.PIC_E_STATE
     assert b"context" in lib.pic_last_error()
 
