@@ -821,6 +821,30 @@ __global__ __launch_bounds__(kFieldTile) void efield_kernel(const Batch bt) {
   R *Jn = (R *)k.J[par ^ 1];
   R *E = (R *)k.E;
   R *sBp = lds, *sBr = lds + W * NMP, *sJr = lds + 2 * W * NMP, *sJp = lds + 3 * W * NMP;
+  // the thread's own-column operands (a column past Nz reads column Nz - 1
+  // and is dropped after the barrier).  In FP32 they are loaded first, to be
+  // in flight while the rows are staged; in FP64 that costs more in
+  // registers than it gains, and they are loaded after the barrier.
+  constexpr bool kEarly = sizeof(R) == 4;
+  const int i = i0 + t;
+  const bool live = i < Nz;
+  const long long ic = live ? i : Nz - 1;
+  R er[NMP], ep[NMP], ez[NMP], bz[NMP], bzm[NMP], bpm[NMP], jz[NMP];
+  auto load_own = [&]() {
+    load_node<R, NMP>(E + 0 * cstride, plane, row + ic, er);
+    load_node<R, NMP>(E + 1 * cstride, plane, row + ic, ep);
+    load_node<R, NMP>(E + 2 * cstride, plane, row + ic, ez);
+    load_node<R, NMP>(B + 2 * cstride, plane, row + ic, bz);
+    load_node<R, NMP>(Jc + 2 * cstride, plane, row + ic, jz);
+    if (j > 0) {
+      load_node<R, NMP>(B + 2 * cstride, plane, row - Nz + ic, bzm);
+      load_node<R, NMP>(B + 1 * cstride, plane, row - Nz + ic, bpm);
+    } else {
+#pragma unroll
+      for (int s = 0; s < NMP; ++s) bzm[s] = bpm[s] = R(0);
+    }
+  };
+  if constexpr (kEarly) load_own();
   for (int r = t; r < W; r += kFieldTile) {
     const int col = wrap_any(i0 - N + r, Nz);
     R v[NMP];
@@ -834,8 +858,8 @@ __global__ __launch_bounds__(kFieldTile) void efield_kernel(const Batch bt) {
     store_rec<R, NMP>(sJp + r * NMP, v);
   }
   __syncthreads();
-  const int i = i0 + t;
-  if (i >= Nz) return;
+  if (!live) return;
+  if constexpr (!kEarly) load_own();
   const R dt = (R)k.dt, dr = (R)k.dr, idz = (R)(1.0 / k.dz);
   const R *CB = (const R *)k.CB, *P = (const R *)k.P;
   // physical current = raw deposit * factor of the row
@@ -881,19 +905,6 @@ __global__ __launch_bounds__(kFieldTile) void efield_kernel(const Batch bt) {
     }
   }
 
-  R er[NMP], ep[NMP], ez[NMP], bz[NMP], bzm[NMP], bpm[NMP], jz[NMP];
-  load_node<R, NMP>(E + 0 * cstride, plane, row + i, er);
-  load_node<R, NMP>(E + 1 * cstride, plane, row + i, ep);
-  load_node<R, NMP>(E + 2 * cstride, plane, row + i, ez);
-  load_node<R, NMP>(B + 2 * cstride, plane, row + i, bz);
-  load_node<R, NMP>(Jc + 2 * cstride, plane, row + i, jz);
-  if (j > 0) {
-    load_node<R, NMP>(B + 2 * cstride, plane, row - Nz + i, bzm);
-    load_node<R, NMP>(B + 1 * cstride, plane, row - Nz + i, bpm);
-  } else {
-#pragma unroll
-    for (int s = 0; s < NMP; ++s) bzm[s] = bpm[s] = R(0);
-  }
   const R *bpc = sBp + c0 * NMP, *brc = sBr + c0 * NMP;
 #pragma unroll
   for (int m = 0; m <= M; ++m) {
