@@ -22,8 +22,29 @@ namespace {
 constexpr double kDlaMaxSteps = 16777216.0;  // steps per electron, 2^24
 
 struct Model {
-  double a0, kz, vphi, w0, kperp, kk, cB, wake;
+  double a0, kz, vphi, w0, kperp, kk, kpz, cB, wake;  // kk = (kperp/kz)^2, kpz = kperp/kz
 };
+
+// J0(s) and J1(s)/s from their power series in q = s^2/4,
+//   J0 = sum_k (-q)^k / (k!)^2,   J1/s = (1/2) sum_k (-q)^k / (k! (k+1)!),
+// 15 terms: absolute error below 1e-15 for |s| <= 3, which covers electrons
+// inside the bubble (k_perp x <= 3); beyond it the library's j0, j1 are used.
+constexpr int kBesselTerms = 15;
+constexpr double kBesselSeriesMax = 3.0;
+struct BesselSeries {
+  double j0[kBesselTerms], j1s[kBesselTerms];
+};
+constexpr BesselSeries make_bessel_series() {
+  BesselSeries c{};
+  double f = 1.0;  // k!
+  for (int k = 0; k < kBesselTerms; ++k) {
+    if (k > 0) f *= k;
+    const double sg = (k % 2 == 0) ? 1.0 : -1.0;
+    c.j0[k] = sg / (f * f);
+    c.j1s[k] = 0.5 * sg / (f * f * (k + 1));
+  }
+  return c;
+}
 
 // d/dt (x, zeta, xd, zetad) at time t
 __device__ __forceinline__ void dla_rhs(const Model &m, double t, const double y[4], double d[4]) {
@@ -35,12 +56,28 @@ __device__ __forceinline__ void dla_rhs(const Model &m, double t, const double y
   double sn, cs;
   sincos(m.kz * xi, &sn, &cs);
   const double s = m.kperp * x;
-  const double j0v = j0(s), j1v = j1(s);
-  const double j1p = fabs(s) < 1e-4 ? 0.5 - 0.1875 * s * s : j0v - j1v / s;  // J1'(s)
+  double j0v, j1v, j1p;  // J0(s), J1(s), J1'(s) = J0 - J1/s
+  if (fabs(s) <= kBesselSeriesMax) {
+    constexpr BesselSeries C = make_bessel_series();
+    const double q = 0.25 * s * s;
+    double a = C.j0[kBesselTerms - 1], b = C.j1s[kBesselTerms - 1];
+#pragma unroll
+    for (int k = kBesselTerms - 2; k >= 0; --k) {
+      a = fma(a, q, C.j0[k]);
+      b = fma(b, q, C.j1s[k]);
+    }
+    j0v = a;
+    j1v = b * s;
+    j1p = a - b;
+  } else {
+    j0v = j0(s);
+    j1v = j1(s);
+    j1p = j0v - j1v / s;
+  }
   const double amp = m.a0 * ig;
   const double mag = m.cB * m.kz * (j0v + m.kk * j1p) * sn;  // magnetic terms, per unit velocity
   const double gx = amp * (m.w0 * j0v * sn - zd * mag) - m.wake * 0.5 * wb2 * (1.0 + zd) * x;
-  const double gz = -amp * ((m.kperp / m.kz) * m.w0 * j1v * cs - u * mag) - m.wake * wb2 * (zeta - 0.5 * x * u);
+  const double gz = -amp * (m.kpz * m.w0 * j1v * cs - u * mag) - m.wake * wb2 * (zeta - 0.5 * x * u);
   const double gv = gx * u + gz * zd;  // gamma-dot / gamma
   d[0] = u;
   d[1] = w;
@@ -114,7 +151,8 @@ int launch_dla(const pic_dla_model &d, long long n, const double *t0, double *x,
   m.vphi = d.vphi;
   m.w0 = d.kz * d.vphi;
   m.kperp = sqrt(m.w0 * m.w0 - d.kz * d.kz);
-  m.kk = (m.kperp / d.kz) * (m.kperp / d.kz);
+  m.kpz = m.kperp / d.kz;
+  m.kk = m.kpz * m.kpz;
   m.cB = d.cB;
   m.wake = d.wake;
   const unsigned blocks = (unsigned)((n + 255) / 256);

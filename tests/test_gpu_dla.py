@@ -97,3 +97,17 @@ def test_dla_edge_cases():
     assert _worst(_run_gpu(pic, one, 10.0, 0.01), _oracle(one, 10.0, 0.01)) < TOL
     empty = {k: v[:0].copy() for k, v in d.items()}
     assert _run_gpu(pic, empty, 10.0, 0.01).shape == (4, 0)
+
+
+def test_dla_outside_the_series_range():
+    """Electrons at |k_perp x| from 2.5 to 6 (the kernel's Bessel functions
+    switch from their power series to the library's at 3) match the oracle."""
+    _say("[gpu] dla outside the series range")
+    pic = _pic()
+    d = workloads.dla_injection(256, 14, t_inject=5.0)
+    kperp = dla.params()["kperp"]
+    d["x"] = np.linspace(2.5, 6.0, 256) / kperp * np.where(np.arange(256) % 2 == 0, 1.0, -1.0)
+    g = _run_gpu(pic, d, 8.0, 0.005)
+    o = _oracle(d, 8.0, 0.005)
+    assert np.isfinite(g).all()
+    assert _worst(g, o) < TOL
