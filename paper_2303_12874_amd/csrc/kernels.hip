@@ -1406,27 +1406,69 @@ __device__ __forceinline__ void sort_tile(const KRun &k, uint64_t *ent, long lon
   __syncthreads();
   const int chunk = (n + 255) / 256;
   const int t = threadIdx.x;
+  // the gather, kG rounds at a time: every load of the group is issued
+  // before its stores, so that the rounds' memory latencies overlap (the
+  // source and destination buffers are distinct)
+  constexpr bool F64 = std::is_same<R, double>::value;
+  using Zw = typename std::conditional<F64, double, int>::type;  // the z word
+  constexpr int kG = 4;
+  const Zw *__restrict__ PZ = (const Zw *)k.pz;
+  const float *__restrict__ PF = (const float *)k.pfz;
+  const R *__restrict__ PX = (const R *)k.px, *__restrict__ PY = (const R *)k.py;
+  const R *__restrict__ PUX = (const R *)k.pux, *__restrict__ PUY = (const R *)k.puy;
+  const R *__restrict__ PUZ = (const R *)k.puz, *__restrict__ PW = (const R *)k.pw;
+  const uint32_t *__restrict__ PID = k.pid;
+  Zw *__restrict__ SZ = (Zw *)k.sz;
+  float *__restrict__ SF = (float *)k.sfz;
+  R *__restrict__ SX = (R *)k.sx, *__restrict__ SY = (R *)k.sy, *__restrict__ SUX = (R *)k.sux;
+  R *__restrict__ SUY = (R *)k.suy, *__restrict__ SUZ = (R *)k.suz, *__restrict__ SW = (R *)k.sw;
+  uint32_t *__restrict__ SID = k.spid;
   int base = 0;
-  for (int it = 0; it < chunk; ++it) {
-    const int cnt = round_count(n, chunk, it);
-    const int d = beg + base + t;
-    base += cnt;
-    if (t >= cnt) continue;
-    const long long s = (long long)(ent[t * chunk + it] & 0xffffffffu);
-    if (s >= k.np) continue;
-    if constexpr (std::is_same<R, double>::value) {
-      ((double *)k.sz)[d] = ((const double *)k.pz)[s];
-    } else {
-      ((int *)k.sz)[d] = ((const int *)k.pz)[s];
-      ((float *)k.sfz)[d] = ((const float *)k.pfz)[s];
+  for (int it0 = 0; it0 < chunk; it0 += kG) {
+    int dd[kG];
+    long long ss[kG];
+    bool ok[kG];
+#pragma unroll
+    for (int g = 0; g < kG; ++g) {
+      const int it = it0 + g;
+      const int cnt = it < chunk ? round_count(n, chunk, it) : 0;
+      dd[g] = beg + base + t;
+      base += cnt;
+      ss[g] = t < cnt ? (long long)(ent[t * chunk + it] & 0xffffffffu) : -1;
+      ok[g] = ss[g] >= 0 && ss[g] < k.np;
     }
-    ((R *)k.sx)[d] = ((const R *)k.px)[s];
-    ((R *)k.sy)[d] = ((const R *)k.py)[s];
-    ((R *)k.sux)[d] = ((const R *)k.pux)[s];
-    ((R *)k.suy)[d] = ((const R *)k.puy)[s];
-    ((R *)k.suz)[d] = ((const R *)k.puz)[s];
-    ((R *)k.sw)[d] = ((const R *)k.pw)[s];
-    k.spid[d] = k.pid[s];
+    Zw vz[kG];
+    float vf[kG];
+    R vx[kG], vy[kG], vux[kG], vuy[kG], vuz[kG], vw[kG];
+    uint32_t vid[kG];
+#pragma unroll
+    for (int g = 0; g < kG; ++g) {
+      if (!ok[g]) continue;
+      const long long q = ss[g];
+      vz[g] = PZ[q];
+      if constexpr (!F64) vf[g] = PF[q];
+      vx[g] = PX[q];
+      vy[g] = PY[q];
+      vux[g] = PUX[q];
+      vuy[g] = PUY[q];
+      vuz[g] = PUZ[q];
+      vw[g] = PW[q];
+      vid[g] = PID[q];
+    }
+#pragma unroll
+    for (int g = 0; g < kG; ++g) {
+      if (!ok[g]) continue;
+      const int d = dd[g];
+      SZ[d] = vz[g];
+      if constexpr (!F64) SF[d] = vf[g];
+      SX[d] = vx[g];
+      SY[d] = vy[g];
+      SUX[d] = vux[g];
+      SUY[d] = vuy[g];
+      SUZ[d] = vuz[g];
+      SW[d] = vw[g];
+      SID[d] = vid[g];
+    }
   }
 }
 
