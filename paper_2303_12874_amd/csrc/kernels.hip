@@ -761,27 +761,59 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
   if (threadIdx.x == 0) ticket = atomicAdd(bt.run[0].work, 1);  // read after the barrier
   __syncthreads();
   const int nt = ticket;
-  if (n > 0)
-    for (int e = threadIdx.x; e < WZ * WR; e += blockDim.x) {
-      const int lr = e / WZ, lc = e - lr * WZ;
-      const int row = rlo + lr;
-      if (row < 0 || row > Nr) continue;  // never deposited to
-      // a node that takes current lies in [-1, Nz + 1]; the others hold zero
-      const unsigned off = (unsigned)(row * Nz + wrap_once(zlo + lc, Nz));
-      double *src = lds + lr * RJ + lc * JS;
+  if constexpr (!F64) {
+    // FP32: the first half of the wavefronts flush the current window while
+    // the other half stage the next tile's field window (separate LDS
+    // regions), so that the two phases' memory traffic overlaps
+    const int split = (int)(blockDim.x >> 7) << 6;
+    if ((int)threadIdx.x < split) {
+      if (n > 0)
+        for (int e = threadIdx.x; e < WZ * WR; e += split) {
+          const int lr = e / WZ, lc = e - lr * WZ;
+          const int row = rlo + lr;
+          if (row < 0 || row > Nr) continue;  // never deposited to
+          // a node that takes current lies in [-1, Nz + 1]; the others hold zero
+          const unsigned off = (unsigned)(row * Nz + wrap_once(zlo + lc, Nz));
+          double *src = lds + lr * RJ + lc * JS;
 #pragma unroll
-      for (int cq = 0; cq < JS; ++cq) {
-        const R v = (R)src[cq];
-        src[cq] = 0.0;
-        if (v != R(0)) atomic_add(J + cq * plane + off, v);
+          for (int cq = 0; cq < JS; ++cq) {
+            const R v = (R)src[cq];
+            src[cq] = 0.0;
+            if (v != R(0)) atomic_add(J + cq * plane + off, v);
+          }
+        }
+    } else if (nt < t_hi) {
+      for (int e = (int)threadIdx.x - split; e < FZ * FR; e += (int)blockDim.x - split) {
+        R v[FS];
+        stage_load(nt, e, v);
+        stage_store(e, v);
       }
     }
-  if (nt < t_hi)
-    for (int e = threadIdx.x; e < FZ * FR; e += blockDim.x) {
-      R v[FS];
-      stage_load(nt, e, v);
-      stage_store(e, v);
-    }
+  } else {
+    // FP64: the flush (FP64 device atomics) dominates; every thread flushes,
+    // then stages
+    if (n > 0)
+      for (int e = threadIdx.x; e < WZ * WR; e += blockDim.x) {
+        const int lr = e / WZ, lc = e - lr * WZ;
+        const int row = rlo + lr;
+        if (row < 0 || row > Nr) continue;  // never deposited to
+        // a node that takes current lies in [-1, Nz + 1]; the others hold zero
+        const unsigned off = (unsigned)(row * Nz + wrap_once(zlo + lc, Nz));
+        double *src = lds + lr * RJ + lc * JS;
+#pragma unroll
+        for (int cq = 0; cq < JS; ++cq) {
+          const R v = (R)src[cq];
+          src[cq] = 0.0;
+          if (v != R(0)) atomic_add(J + cq * plane + off, v);
+        }
+      }
+    if (nt < t_hi)
+      for (int e = threadIdx.x; e < FZ * FR; e += blockDim.x) {
+        R v[FS];
+        stage_load(nt, e, v);
+        stage_store(e, v);
+      }
+  }
   __syncthreads();
   gt = nt;
   }  // tiles
