@@ -856,7 +856,7 @@ __global__ __launch_bounds__(kFieldTile) void efield_kernel(const Batch bt) {
   // the thread's own-column operands (a column past Nz reads column Nz - 1
   // and is dropped after the barrier).  In FP32 they are loaded first, to be
   // in flight while the rows are staged; in FP64 that costs more in
-  // registers than it gains, and they are loaded after the barrier.
+  // registers than it gains, and they are loaded after the z operators.
   constexpr bool kEarly = sizeof(R) == 4;
   const int i = i0 + t;
   const bool live = i < Nz;
@@ -891,7 +891,6 @@ __global__ __launch_bounds__(kFieldTile) void efield_kernel(const Batch bt) {
   }
   __syncthreads();
   if (!live) return;
-  if constexpr (!kEarly) load_own();
   const R dt = (R)k.dt, dr = (R)k.dr, idz = (R)(1.0 / k.dz);
   const R *CB = (const R *)k.CB, *P = (const R *)k.P;
   // physical current = raw deposit * factor of the row
@@ -936,6 +935,9 @@ __global__ __launch_bounds__(kFieldTile) void efield_kernel(const Batch bt) {
       pjp[s] += pl * (b1[s] + b2[s]);
     }
   }
+  // (FP64: the own-column operands are loaded only now, after the z
+  // operators, so that they and the operators' sums are not all live at once)
+  if constexpr (!kEarly) load_own();
 
   const R *bpc = sBp + c0 * NMP, *brc = sBr + c0 * NMP;
 #pragma unroll
