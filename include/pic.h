@@ -13,6 +13,11 @@
  *   E and B with distinct z-difference operators D_E, D_B (Eq. (9)) whose
  *   coefficients satisfy the dispersion condition Eq. (11) and the
  *   Lorentz-force condition Eq. (15).
+ * Around the step: FP64 diagnostics (per-mode work Eq. (16), work by field
+ * direction and the Pukhov-corrected estimate Eqs. (17), (20)-(21), field
+ * and kinetic energy, beam divergence), checkpoint and restore, a measuring
+ * autotuner of the sort tile and interval, and, independent of any
+ * context, the ensemble integrator of the reduced model of Sec. II (Eq. (8)).
  *
  * Units: c = omega_0 = 1 (omega_0 the laser frequency), lengths in c/omega_0
  * (the laser wavelength is 2 pi), time in 1/omega_0, fields in
@@ -102,7 +107,8 @@ typedef struct pic_run_desc {
   pic_pulse pulse[PIC_MAX_PULSES];
   double taper;     /* laser taper length at the box ends (0: none)           */
   uint64_t seed;    /* counter-based SplitMix64 seed of the loading           */
-  int32_t n_tracked;/* electrons whose per-mode work is accumulated (FP64)    */
+  int32_t n_tracked;/* electrons whose work is accumulated (FP64), per mode
+                       and by field direction                                 */
   int64_t n_steps;  /* steps this run takes in total (0: no limit); pic_step
                        leaves a run alone once it has taken them, so runs of
                        one context can end at different times                 */
@@ -130,7 +136,8 @@ typedef struct pic_run_info {
   double dt;             /* time step in use                                 */
   double courant_limit;  /* largest stable c dt / dz for these coefficients  */
   int64_t n_particles;   /* electrons in the run                             */
-  int64_t steps_done;    /* steps taken since pic_init                       */
+  int64_t steps_done;    /* steps taken (those of a restored checkpoint
+                            included)                                        */
   int32_t n_coef;        /* coefficients per operator                        */
   int32_t n_tracked;
   int32_t tile_z;        /* sort tile in use (cells along z and r)           */

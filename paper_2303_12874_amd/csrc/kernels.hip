@@ -119,18 +119,6 @@ struct RecVec {
 };
 
 template <typename R, int NMP>
-__device__ __forceinline__ void load_rec(const R *__restrict__ p, R out[NMP]) {
-  using T = RecVec<R, NMP>;
-  const typename T::V *q = reinterpret_cast<const typename T::V *>(p);
-#pragma unroll
-  for (int a = 0; a < T::nv; ++a) {
-    const typename T::V x = q[a];
-    const R *xs = reinterpret_cast<const R *>(&x);
-#pragma unroll
-    for (int b = 0; b < T::per; ++b) out[a * T::per + b] = xs[b];
-  }
-}
-template <typename R, int NMP>
 __device__ __forceinline__ void store_rec(R *__restrict__ p, const R in[NMP]) {
   using T = RecVec<R, NMP>;
   typename T::V *q = reinterpret_cast<typename T::V *>(p);
@@ -824,12 +812,6 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
 // the rows whose z differences or z filter need neighbours (+-N columns) are
 // first staged in LDS with coalesced record loads, every other operand is a
 // record of the thread's own column.
-
-// complex (re, im) helpers on records
-template <typename R>
-struct Cx {
-  R re, im;
-};
 
 template <typename R, int M>
 __global__ __launch_bounds__(kFieldTile) void efield_kernel(const Batch bt) {
