@@ -315,3 +315,27 @@ def test_cell_sort_after_steps_bit_exact():
     o.step(8)
     assert np.array_equal(sim.particles()["id"], _oracle_order(o, 16, 4))
     sim.close()
+
+
+def test_fp64_edge_case_largest_operators_ragged_grid_no_tracking():
+    """The extremes at once: 32 coefficients per operator (the most the ABI
+    takes), modes 0..3 (the most), no tracked electrons, a 70 x 13 grid that
+    neither tile dimension divides (16 x 8 tiles), and a sort every step."""
+    _say("[gpu] fp64 edge case: N=32, M=3, 70x13, no tracking, sort every step")
+    pic = _pic()
+    run = workloads.small(M=3, Nz=70, Nr=13, ppc=2, n_tracked=0)["runs"][0]
+    dt, CE, CB, _ = _setup(32, 3, run["dz"], run["dr"])
+    sim = pic.Simulation([workloads.to_rundesc(run)], dt=dt, coef_E=CE, coef_B=CB, n_coef=32, tile_z=16, tile_r=8,
+                         sort_interval=1)
+    o = oracle_of(run, dt, CE, CB)
+    sim.step(12)
+    o.step(12)
+    worst = compare_fields(sim, o, run["M"], TOL64)
+    bad = {k: v for k, v in worst.items() if v > TOL64}
+    assert not bad, bad
+    dzmax, dxy, du, _ = compare_particles(sim, o, run["Nz"])
+    assert dzmax < TOL64 and dxy < TOL64 and du < TOL64, (dzmax, dxy, du)
+    w = sim.mode_work()
+    assert w["W"].shape == (0, 4) and w["id"].size == 0
+    assert all(v.size == 0 for v in sim.cartesian_work().values())
+    sim.close()
