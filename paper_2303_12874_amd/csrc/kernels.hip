@@ -850,7 +850,16 @@ __global__ __launch_bounds__(kFieldTile) void efield_kernel(const Batch bt) {
     load_node<R, NMP>(E + 2 * cstride, plane, row + ic, ez);
     load_node<R, NMP>(B + 2 * cstride, plane, row + ic, bz);
     load_node<R, NMP>(Jc + 2 * cstride, plane, row + ic, jz);
-    if (j > 0) {
+    // half row j-1 (unused in row 0).  FP64 loads it without a branch, row 0
+    // reading its own row: the branch leaves part of the two arrays in scratch
+    // memory there (24 bytes; 0.158 -> 0.154 ms at 4096 x 256, modes 0..2).
+    // FP32 keeps the branch, measured faster (0.391 -> 0.377 ms at
+    // 8192 x 512, modes 0..3) despite 12 bytes of scratch.
+    if constexpr (!kEarly) {
+      const long long rowm = j > 0 ? row - Nz : row;
+      load_node<R, NMP>(B + 2 * cstride, plane, rowm + ic, bzm);
+      load_node<R, NMP>(B + 1 * cstride, plane, rowm + ic, bpm);
+    } else if (j > 0) {
       load_node<R, NMP>(B + 2 * cstride, plane, row - Nz + ic, bzm);
       load_node<R, NMP>(B + 1 * cstride, plane, row - Nz + ic, bpm);
     } else {
