@@ -71,6 +71,8 @@ def lib():
             "orc_round_to_fp32": (None, [p]),
             "orc_cell_order": (None, [p, i, i, p]),
             "orc_filter_taps": (dp, [p]),
+            "orc_set_exact_jz": (None, [p, i]),
+            "orc_inverse_filter": (i, [p, p, p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(_lib, name)
@@ -207,6 +209,21 @@ class Oracle:
         """Taps p_l, l = -(N-1)..N-1, of the z filter the oracle applies to J_r, J_phi."""
         ptr = lib().orc_filter_taps(self._h)
         return np.array([ptr[k] for k in range(2 * self.CB.size - 1)])
+
+    def set_exact_jz(self, on=True):
+        """Charge conservation by J_z <- P^{-1} J_z with J_r, J_phi unfiltered
+        (Gauss's law then holds with rho itself) instead of filtering J_r, J_phi."""
+        lib().orc_set_exact_jz(self._h, int(on))
+
+    def inverse_filter(self, line):
+        """P^{-1} of one periodic complex z line of Nz values (DFT)."""
+        a = np.ascontiguousarray(line, dtype=np.complex128)
+        if a.shape != (self.Nz,):
+            raise ValueError("line of Nz values expected")
+        out = np.zeros_like(a)
+        if lib().orc_inverse_filter(self._h, _ptr(a), _ptr(out)) != 0:
+            raise ValueError("P has a non-positive symbol on this grid")
+        return out
 
     def round_to_fp32(self):
         lib().orc_round_to_fp32(self._h)

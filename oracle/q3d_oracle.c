@@ -12,7 +12,10 @@
  *   Sec. III.A, Eq. (9)   Faraday and Ampere with distinct z-difference
  *                         operators: D_E acts on E, D_B acts on B.
  *   Sec. III.A, Eq. (10)  Gauss's law uses D_B; the dispersion relation is
- *                         [w]_t^2 = [k]_B [k]_E.
+ *                         [w]_t^2 = [k]_B [k]_E.  The deposited current is
+ *                         made to conserve charge with D_B either by the z
+ *                         filter P on J_r, J_phi or, as a switch, by P^{-1}
+ *                         on J_z (a DFT on each periodic z line).
  *   Sec. III.A, Eq. (12)  the force uses E^n and the time average
  *                         (B^{n-1/2} + B^{n+1/2})/2; B is kept at half steps.
  *   Sec. II,   Eq. (6)    relativistic Lorentz force, integrated with Boris.
@@ -72,6 +75,7 @@ typedef struct orc {
   long nstep;
   int freeze_fields;  /* 1: Maxwell update skipped (prescribed fields) */
   int deposit_rho;    /* 1: deposit rho after every step */
+  int exact_jz;       /* 1: J_z <- P^{-1} J_z, J_r and J_phi unfiltered */
 } orc;
 
 /* ------------------------------------------------------------------------ */
@@ -164,6 +168,8 @@ void orc_set_flags(orc *o, int freeze_fields, int deposit_rho) {
   o->deposit_rho = deposit_rho;
 }
 
+void orc_set_exact_jz(orc *o, int on) { o->exact_jz = on; }
+
 long orc_num_particles(const orc *o) { return o->np; }
 long orc_num_steps(const orc *o) { return o->nstep; }
 const double *orc_filter_taps(const orc *o) { return o->P; }
@@ -226,6 +232,41 @@ static cplx filterP(const orc *o, const cplx *f, int m, int j, int i) {
   return s;
 }
 
+/* The inverse of P on one periodic z line of Nz values, by the discrete
+ * Fourier transform: P is a circulant convolution whose symbol at
+ * k_q dz = 2 pi q / Nz is P_q = sum_l p_l cos(2 pi q l / Nz) (real, as
+ * p_{-l} = p_l), so the line is transformed, divided by P_q and transformed
+ * back.  A plain O(Nz^2) DFT.  Returns -1 if some P_q <= 0 (not invertible
+ * as a positive filter).                                                   */
+static int inverse_filter_line(const orc *o, const cplx *in, cplx *out) {
+  const int Nz = o->Nz;
+  cplx *tw = (cplx *)malloc(sizeof(cplx) * (size_t)Nz);  /* e^{-2 pi i k / Nz} */
+  cplx *X = (cplx *)malloc(sizeof(cplx) * (size_t)Nz);
+  int rc = 0;
+  for (int k = 0; k < Nz; ++k) tw[k] = cexp(-2.0 * ORC_PI * I * (double)k / (double)Nz);
+  for (int q = 0; q < Nz; ++q) {
+    cplx sum = 0.0;
+    for (int i = 0; i < Nz; ++i) sum += in[i] * tw[(long)q * i % Nz];
+    double Pq = 0.0;
+    for (int l = -(o->N - 1); l <= o->N - 1; ++l) Pq += o->P[l + o->N - 1] * creal(tw[wrapz(o, q * l)]);
+    if (!(Pq > 0.0)) rc = -1;
+    X[q] = sum / Pq;
+  }
+  for (int i = 0; i < Nz; ++i) {
+    cplx sum = 0.0;
+    for (int q = 0; q < Nz; ++q) sum += X[q] * conj(tw[(long)q * i % Nz]);
+    out[i] = sum / (double)Nz;
+  }
+  free(tw);
+  free(X);
+  return rc;
+}
+
+/* P^{-1} applied to one interleaved complex line of Nz values.              */
+int orc_inverse_filter(orc *o, const double *in, double *out) {
+  return inverse_filter_line(o, (const cplx *)in, (cplx *)out);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Faraday: Bout = Bin - tau * curl_E(E), mode by mode (d/dphi -> i m).      */
 /* Axis rules (reading; the paper defers to the quasi-3D algorithm paper):  */
@@ -271,7 +312,10 @@ static void faraday(orc *o, cplx *Bout[3], cplx *Bin[3], cplx *E[3], double tau)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Ampere: E += dt * (curl_B(B) - J'), with J' = (P J_r, P J_phi, J_z).      */
+/* Ampere: E += dt * (curl_B(B) - J'), with J' = (P J_r, P J_phi, J_z), or  */
+/* with exact_jz set J' = (J_r, J_phi, P^{-1} J_z): both satisfy the D_B     */
+/* continuity equation, since D_B = D_Yee o P and the deposit satisfies the  */
+/* two-point one.                                                            */
 /* Axis rules: m = 0: E_phi(axis) = 0 and E_z(axis) uses the flux of B_phi  */
 /* through the disc of radius dr/2, i.e. 4 B_phi(1/2)/dr;  m = 1: E_z = 0,  */
 /* E_phi uses -dB_z/dr = -2 B_z(1/2)/dr (B_z^1 vanishes linearly);          */
@@ -280,6 +324,12 @@ static void faraday(orc *o, cplx *Bout[3], cplx *Bin[3], cplx *E[3], double tau)
 static void ampere(orc *o, cplx *B[3]) {
   const int Nz = o->Nz, Nr = o->Nr;
   const double dr = o->dr, dt = o->dt;
+  cplx *jz = o->J[CZ];
+  if (o->exact_jz) {
+    jz = (cplx *)malloc(o->nf * sizeof(cplx));
+    for (int m = 0; m <= o->M; ++m)
+      for (int j = 0; j <= Nr; ++j) inverse_filter_line(o, o->J[CZ] + ix(o, m, j, 0), jz + ix(o, m, j, 0));
+  }
   for (int m = 0; m <= o->M; ++m) {
     const cplx im = I * (double)m;
     for (int j = 0; j <= Nr; ++j) {
@@ -289,7 +339,7 @@ static void ampere(orc *o, cplx *B[3]) {
         if (j < Nr) {
           double rh = (j + 0.5) * dr;
           cplx cr = im / rh * B[CZ][k] - D_B(o, B[CP], m, j, i);
-          cplx jr = filterP(o, o->J[CR], m, j, i);
+          cplx jr = o->exact_jz ? o->J[CR][k] : filterP(o, o->J[CR], m, j, i);
           o->E[CR][k] += dt * (cr - jr);
         } else {
           o->E[CR][k] = 0.0;
@@ -301,7 +351,7 @@ static void ampere(orc *o, cplx *B[3]) {
           cplx cp;
           if (j == 0) cp = D_B(o, B[CR], m, 0, i) - 2.0 * B[CZ][ix(o, m, 0, i)] / dr;
           else cp = D_B(o, B[CR], m, j, i) - (B[CZ][ix(o, m, j, i)] - B[CZ][ix(o, m, j - 1, i)]) / dr;
-          cplx jp = filterP(o, o->J[CP], m, j, i);
+          cplx jp = o->exact_jz ? o->J[CP][k] : filterP(o, o->J[CP], m, j, i);
           o->E[CP][k] += dt * (cp - jp);
         }
         /* E_z at (i+1/2, j) */
@@ -312,17 +362,19 @@ static void ampere(orc *o, cplx *B[3]) {
           if (j == 0) cz = 4.0 * B[CP][ix(o, m, 0, i)] / dr;
           else cz = ((j + 0.5) * B[CP][ix(o, m, j, i)] - (j - 0.5) * B[CP][ix(o, m, j - 1, i)]) / (j * dr)
                     - im / (j * dr) * B[CR][k];
-          o->E[CZ][k] += dt * (cz - o->J[CZ][k]);
+          o->E[CZ][k] += dt * (cz - jz[k]);
         }
       }
     }
   }
+  if (jz != o->J[CZ]) free(jz);
 }
 
 /* ------------------------------------------------------------------------ */
 /* Gauss residual of Eq. (10): G = D_B E_z + (1/r) d(r E_r)/dr + (i m/r) E_phi
- * - P rho, on nodes where Gauss's law is evolved (interior rows; axis row
- * for m = 0 only).  Written into out as interleaved complex [Nr+1][Nz].    */
+ * - P rho (- rho with exact_jz), on nodes where Gauss's law is evolved
+ * (interior rows; axis row for m = 0 only).  Written into out as
+ * interleaved complex [Nr+1][Nz].                                          */
 int orc_gauss_residual(orc *o, int m, double *out) {
   if (m < 0 || m > o->M) return -1;
   const int Nz = o->Nz, Nr = o->Nr;
@@ -332,12 +384,13 @@ int orc_gauss_residual(orc *o, int m, double *out) {
   for (int j = 0; j <= Nr; ++j)
     for (int i = 0; i < Nz; ++i) {
       cplx v = 0.0;
+      const cplx q = o->exact_jz ? o->rho[ix(o, m, j, i)] : filterP(o, o->rho, m, j, i);
       if (j == 0 && m == 0) {
-        v = D_B(o, o->E[CZ], m, 0, i) + 4.0 * o->E[CR][ix(o, m, 0, i)] / dr - filterP(o, o->rho, m, 0, i);
+        v = D_B(o, o->E[CZ], m, 0, i) + 4.0 * o->E[CR][ix(o, m, 0, i)] / dr - q;
       } else if (j >= 1 && j < Nr) {
         v = D_B(o, o->E[CZ], m, j, i)
             + ((j + 0.5) * o->E[CR][ix(o, m, j, i)] - (j - 0.5) * o->E[CR][ix(o, m, j - 1, i)]) / (j * dr)
-            + im / (j * dr) * o->E[CP][ix(o, m, j, i)] - filterP(o, o->rho, m, j, i);
+            + im / (j * dr) * o->E[CP][ix(o, m, j, i)] - q;
       }
       g[(size_t)j * Nz + i] = v;
     }
