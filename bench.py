@@ -190,6 +190,8 @@ def main(argv=None):
                     help="override the workload's precision (0: as defined)")
     ap.add_argument("--solver", default="dual", choices=["dual", "yee"],
                     help="field solver: dual (16 coefficients per operator) or Yee (one)")
+    ap.add_argument("--current", default="filter", choices=["filter", "exact"],
+                    help="charge conservation with D_B: z filter on J_r, J_phi (default) or P^-1 on J_z")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}), flush=True)
@@ -210,13 +212,14 @@ def main(argv=None):
     prec = args.precision or cfg["precision"]
     solver = pic.SOLVER_YEE if args.solver == "yee" else pic.SOLVER_DUAL
     n_coef = 1 if args.solver == "yee" else 16
+    current = pic.CURRENT_EXACT_JZ if args.current == "exact" else pic.CURRENT_FILTER
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     tune = None
     if args.autotune if args.autotune is not None else args.workload in ("c4", "c5"):
         t0 = time.perf_counter()
         tune = pic.autotune([workloads.to_rundesc(r) for r in runs], precision=prec, solver=solver, n_coef=n_coef,
-                            tile_z=args.tile_z,
+                            current=current, tile_z=args.tile_z,
                             tile_r=args.tile_r, device="cuda:0")
         torch.cuda.empty_cache()
         args.tile_z, args.tile_r = tune["tile_z"], tune["tile_r"]
@@ -229,7 +232,7 @@ def main(argv=None):
     def make(limits):
         return pic.Simulation([workloads.to_rundesc(r, n_steps=n) for r, n in zip(runs, limits)], precision=prec,
                               solver=solver, n_coef=n_coef, sort_interval=args.sort_interval, tile_z=args.tile_z, tile_r=args.tile_r,
-                              use_graph=args.graph, device="cuda:0")
+                              use_graph=args.graph, current=current, device="cuda:0")
 
     if multi:  # warm up on a context of its own, so that the timed job starts at step 0
         warm = make([0] * len(runs))
@@ -294,7 +297,7 @@ def main(argv=None):
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
     ach = kernels[dom]["GBs"]
     traffic = (measured_traffic(args.workload, dom, "%dx%d" % infos[0]["tile"], sort_k, prec)
-               if args.solver == "dual" else None)  # the counters were taken with the dual solver
+               if args.solver == "dual" and args.current == "filter" else None)  # the counters' settings
     particle_steps = sum(n * s for n, s in zip(nps, per_run))
     value = particle_steps / (elapsed_ms * 1e-3)
     run = runs[0]
@@ -302,7 +305,9 @@ def main(argv=None):
               "grid": ", ".join(f"{r['Nz']}x{r['Nr']}" for r in runs), "modes": run["M"] + 1,
               "ppc": run["ppc"], "electrons": sum(nps), "precision": f"fp{prec}",
               "solver": "Yee, one coefficient per operator" if args.solver == "yee"
-              else "dual, 16 coefficients per operator", "dt": [i["dt"] for i in infos] if multi else infos[0]["dt"],
+              else "dual, 16 coefficients per operator",
+              "current": "P^-1 on J_z" if args.current == "exact" else "z filter on J_r, J_phi",
+              "dt": [i["dt"] for i in infos] if multi else infos[0]["dt"],
               "sort_interval": sort_k, "tile": "%dx%d" % infos[0]["tile"], "graph": bool(args.graph)}
     if multi:
         config["steps_per_run"] = per_run

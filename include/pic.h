@@ -57,6 +57,17 @@ extern "C" {
                             FP64 only in setup, reductions and tracked work   */
 #define PIC_SOLVER_DUAL 0 /* N-coefficient operators fitted to Eqs. (11), (15)  */
 #define PIC_SOLVER_YEE 1  /* the two-point (one-coefficient) Yee operator      */
+/* How the deposited current is made to conserve charge with D_B (Sec. III.A:
+ * the solver conserves charge, with Gauss's law written with [k]_B,
+ * Eq. (10)).  D_B is the two-point difference after a symmetric z filter P
+ * with taps p_l = sum_{l' > |l|} C^B_{l'}.                                   */
+#define PIC_CURRENT_FILTER 0   /* P on J_r and J_phi, J_z as deposited: keeps
+                                  div_B E - P rho constant (default)          */
+#define PIC_CURRENT_EXACT_JZ 1 /* P^{-1} on J_z, J_r and J_phi as deposited:
+                                  keeps div_B E - rho constant; P^{-1} is
+                                  applied as the symmetric stencil of
+                                  pic_jz_inverse_taps                          */
+#define PIC_MAX_JZ_TAPS 128    /* one-sided taps of that stencil, at most     */
 
 /* ---- field components for pic_fields ------------------------------------ */
 #define PIC_ER 0   /* E_r   at (z_i,       r_{j+1/2}), time n                  */
@@ -127,6 +138,7 @@ typedef struct pic_opts {
   int32_t tile_z, tile_r; /* sort tile in cells; 0 -> default                 */
   int32_t use_graph;    /* 1: capture each distinct step (the launches of all
                            runs) once as a hipGraph and replay it             */
+  int32_t current;      /* PIC_CURRENT_FILTER (0) or PIC_CURRENT_EXACT_JZ    */
 } pic_opts;
 
 typedef struct pic_ctx pic_ctx;
@@ -160,6 +172,20 @@ int pic_solver_setup(int32_t solver, int32_t n_coef, int32_t M, double dz, doubl
 /* Courant limit (largest stable c dt / dz) of given coefficients.           */
 int pic_courant_limit(int32_t n_coef, const double *coef_E, const double *coef_B, int32_t M,
                       double dz, double dr, double *courant_limit);
+
+/* The inverse of the z filter P of coef_B (n_coef values) as a symmetric
+ * stencil: taps[l] = h_l = h_{-l}, l = 0..*n_taps-1, with
+ * sum_l h_l p_{k-l} = delta_k on the infinite line.  h is the Fourier
+ * series of 1/P(k), P(k) = sum_l p_l cos(l k dz), computed in FP64 from 8192
+ * samples of P, and cut after the last tap above 2^-53 (precision
+ * PIC_PREC_FP64) or 2^-24 (PIC_PREC_FP32) times h_0: the taps decay
+ * geometrically, so the cut changes P^{-1} by about that fraction, and on a
+ * periodic line of any length the stencil (wrapped) is P^{-1} to that
+ * accuracy.  taps: PIC_MAX_JZ_TAPS doubles, caller owned.  PIC_E_INVALID if
+ * P(k) <= 0 for some k (P has no inverse; some fits with many coefficients
+ * do this near k dz = pi) or if more than PIC_MAX_JZ_TAPS taps are needed.  */
+int pic_jz_inverse_taps(int32_t n_coef, const double *coef_B, int32_t precision, double *taps,
+                        int32_t *n_taps);
 
 /* The electrons pic_init loads for `run`, on the host, in FP64: positions in
  * cell units (z in dz, x and y in dr), weights w (charge -w), ids.  Arrays of

@@ -20,6 +20,8 @@ LIB_PATH = os.path.join(_HERE, "libpic.so")
 PIC_OK, PIC_E_INVALID, PIC_E_CFL, PIC_E_NOMEM, PIC_E_STATE, PIC_E_DEVICE, PIC_E_NUMERIC = 0, -1, -2, -3, -4, -5, -6
 PREC_FP64, PREC_FP32 = 64, 32
 SOLVER_DUAL, SOLVER_YEE = 0, 1
+CURRENT_FILTER, CURRENT_EXACT_JZ = 0, 1  # P on J_r, J_phi; or P^{-1} on J_z
+MAX_JZ_TAPS = 128
 (ER, EPHI, EZ, BR, BPHI, BZ, JR, JPHI, JZ, RHO, BR_OLD, BPHI_OLD, BZ_OLD, BR_NEW, BPHI_NEW,
  BZ_NEW) = range(16)
 MAX_PULSES = 2
@@ -51,7 +53,7 @@ class _Opts(C.Structure):
         ("fit_band", C.c_double), ("cfl_fraction", C.c_double), ("dt", C.c_double),
         ("coef_E", C.POINTER(C.c_double)), ("coef_B", C.POINTER(C.c_double)),
         ("sort_interval", C.c_int32), ("tile_z", C.c_int32), ("tile_r", C.c_int32),
-        ("use_graph", C.c_int32),
+        ("use_graph", C.c_int32), ("current", C.c_int32),
     ]
 
 
@@ -88,6 +90,7 @@ def _load():
     sigs = {
         "pic_solver_setup": [i32, i32, i32, d, d, d, d, dp, dp, dp, dp],
         "pic_courant_limit": [i32, dp, dp, i32, d, d, dp],
+        "pic_jz_inverse_taps": [i32, dp, i32, dp, C.POINTER(C.c_int32)],
         "pic_load_host": [C.POINTER(_RunDesc), p, p, p, p, p, p, C.POINTER(C.c_int64)],
         "pic_init": [C.POINTER(_RunDesc), i32, C.POINTER(_Opts), p, C.POINTER(C.c_size_t), p, C.POINTER(p)],
         "pic_step": [p, i64],
@@ -117,9 +120,9 @@ def _load():
 
 
 _lib = _load()
-EXPORTED = ("pic_solver_setup", "pic_courant_limit", "pic_load_host", "pic_init", "pic_step", "pic_mode_work",
-            "pic_cartesian_work", "pic_divergence", "pic_dla_integrate", "pic_checkpoint", "pic_restore",
-            "pic_fields", "pic_particles", "pic_coefficients", "pic_run_info_get", "pic_destroy",
+EXPORTED = ("pic_solver_setup", "pic_courant_limit", "pic_jz_inverse_taps", "pic_load_host", "pic_init", "pic_step",
+            "pic_mode_work", "pic_cartesian_work", "pic_divergence", "pic_dla_integrate", "pic_checkpoint",
+            "pic_restore", "pic_fields", "pic_particles", "pic_coefficients", "pic_run_info_get", "pic_destroy",
             "pic_last_error", "pic_profile", "pic_profile_read", "pic_autotune")
 PHASES = ("sort", "push", "efield", "bfield", "step")  # "step": a whole step replayed from a graph
 
@@ -195,6 +198,17 @@ def courant_limit(coef_E, coef_B, M, dz, dr):
     return out.value
 
 
+def jz_inverse_taps(coef_B, precision=PREC_FP64):
+    """Taps h_0..h_{n-1} of the stencil the library uses for P^{-1} with the
+    exact J_z correction (pic_jz_inverse_taps)."""
+    cb = np.ascontiguousarray(coef_B, dtype=np.float64)
+    h = np.zeros(MAX_JZ_TAPS)
+    n = C.c_int32()
+    dp = C.POINTER(C.c_double)
+    _check(_lib.pic_jz_inverse_taps(cb.size, cb.ctypes.data_as(dp), precision, h.ctypes.data_as(dp), C.byref(n)))
+    return h[:n.value].copy()
+
+
 def load_host(run: RunDesc):
     """Electrons the library loads for `run` (host, FP64, cell units)."""
     rd = run.to_c()
@@ -216,7 +230,7 @@ def workspace_bytes(runs: Sequence[RunDesc], precision=PREC_FP64, solver=SOLVER_
 
 
 def _make_opts(precision, solver, n_coef, dt=0.0, coef_E=None, coef_B=None, cfl_fraction=0.0, fit_band=0.0,
-               sort_interval=0, tile_z=0, tile_r=0, use_graph=False):
+               sort_interval=0, tile_z=0, tile_r=0, use_graph=False, current=CURRENT_FILTER):
     o = _Opts()
     o.precision, o.solver, o.n_coef = precision, solver, n_coef
     o.fit_band, o.cfl_fraction, o.dt = fit_band, cfl_fraction, dt
@@ -227,6 +241,7 @@ def _make_opts(precision, solver, n_coef, dt=0.0, coef_E=None, coef_B=None, cfl_
             keep.append(a)
             setattr(o, name, a.ctypes.data_as(C.POINTER(C.c_double)))
     o.sort_interval, o.tile_z, o.tile_r, o.use_graph = sort_interval, tile_z, tile_r, int(use_graph)
+    o.current = current
     return o, keep
 
 

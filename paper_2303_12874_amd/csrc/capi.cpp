@@ -57,6 +57,7 @@ struct RunHost {
   int N = 1;
   double dt = 0, nu_lim = 0;
   std::vector<double> CE, CB, P;
+  std::vector<double> H;  // taps of P^{-1} (exact J_z correction), else empty
   std::vector<double> gam0;
   int64_t steps = 0;
   size_t offset = 0, bytes = 0;
@@ -68,7 +69,7 @@ struct RunHost {
 struct Layout {
   size_t E, B0, B1, Bbar, J0, J1, rho, pz, pfz, px, py, pux, puy, puz, pw, pid;
   size_t sz, sfz, sx, sy, sux, suy, suz, sw, spid, perm, ccount, cstart, scan;
-  size_t W, Wc, tracked, CE, CB, P, red, gam, ids, work, total;
+  size_t W, Wc, tracked, CE, CB, P, H, red, gam, ids, work, total;
 };
 
 Layout layout_of(const pic_run_desc &d, int prec, int N, int Tz, int Tr, long long n_keys) {
@@ -119,6 +120,7 @@ Layout layout_of(const pic_run_desc &d, int prec, int N, int Tz, int Tr, long lo
   L.CE = take((size_t)N * rs);
   L.CB = take((size_t)N * rs);
   L.P = take((size_t)(2 * N - 1) * rs);
+  L.H = take((size_t)PIC_MAX_JZ_TAPS * rs);
   L.red = take((size_t)kRedBlocks * (PIC_MAX_MODES + 1) * 8);
   L.work = take(16);
   L.gam = take((size_t)(d.n_tracked > 0 ? d.n_tracked : 1) * 8);
@@ -292,6 +294,20 @@ int pic_courant_limit(int32_t n_coef, const double *coef_E, const double *coef_B
   return PIC_OK;
 }
 
+int pic_jz_inverse_taps(int32_t n_coef, const double *coef_B, int32_t precision, double *taps, int32_t *n_taps) {
+  g_msg[0] = 0;
+  if (n_coef < 1 || n_coef > PIC_MAX_COEF || !coef_B || !taps || !n_taps ||
+      (precision != PIC_PREC_FP64 && precision != PIC_PREC_FP32))
+    return fail(PIC_E_INVALID, "bad arguments");
+  int nh = 0;
+  const int rc = jz_inverse_taps(coef_B, n_coef, precision == PIC_PREC_FP64 ? 0x1p-53 : 0x1p-24, PIC_MAX_JZ_TAPS,
+                                 taps, &nh);
+  if (rc == 1) return fail(PIC_E_INVALID, "the z filter of these coefficients has P(k) <= 0: no inverse");
+  if (rc == 2) return fail(PIC_E_INVALID, "the inverse z filter needs more than %d taps", PIC_MAX_JZ_TAPS);
+  *n_taps = nh;
+  return PIC_OK;
+}
+
 int pic_load_host(const pic_run_desc *run, double *z, double *x, double *y, double *w, int64_t *id,
                   int64_t *tracked_ids, int64_t *n_out) {
   g_msg[0] = 0;
@@ -317,6 +333,8 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
     return fail(PIC_E_INVALID, "cfl_fraction or dt out of range");
   if ((o.coef_E == nullptr) != (o.coef_B == nullptr)) return fail(PIC_E_INVALID, "give both coef_E and coef_B");
   if (o.sort_interval < 0 || o.tile_z < 0 || o.tile_r < 0) return fail(PIC_E_INVALID, "negative sort options");
+  if (o.current != PIC_CURRENT_FILTER && o.current != PIC_CURRENT_EXACT_JZ)
+    return fail(PIC_E_INVALID, "current must be PIC_CURRENT_FILTER or PIC_CURRENT_EXACT_JZ");
   for (int i = 0; i < n_runs; ++i) {
     TRY(validate_run(runs[i], i, N));
     if (runs[i].M != runs[0].M) return fail(PIC_E_INVALID, "all runs of one context must share M");
@@ -390,6 +408,20 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
       R.P[(size_t)(N - 1 + l)] = p;
       R.P[(size_t)(N - 1 - l)] = p;
     }
+    // P^{-1} as a cut symmetric stencil for the exact J_z correction
+    R.H.clear();
+    if (o.current == PIC_CURRENT_EXACT_JZ) {
+      double h[PIC_MAX_JZ_TAPS];
+      int nh = 0;
+      const int hr = jz_inverse_taps(R.CB.data(), N, f64 ? 0x1p-53 : 0x1p-24, PIC_MAX_JZ_TAPS, h, &nh);
+      if (hr) {
+        rc = fail(PIC_E_INVALID, hr == 1 ? "run %d: the z filter has P(k) <= 0, so J_z cannot be corrected exactly"
+                                         : "run %d: the inverse z filter needs more than the maximum of taps",
+                  i);
+        break;
+      }
+      R.H.assign(h, h + nh);
+    }
     // ---- device view ----
     const Layout &L = lays[(size_t)i];
     unsigned char *base = ctx->ws + offs[(size_t)i];
@@ -447,6 +479,8 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
     k.CE = base + L.CE;
     k.CB = base + L.CB;
     k.P = base + L.P;
+    k.H = base + L.H;
+    k.NH = (int)R.H.size();
     k.red = (double *)(base + L.red);
     k.work = (int32_t *)(base + L.work);
     R.dev_gamma = (double *)(base + L.gam);
@@ -454,11 +488,15 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
 
     // ---- coefficients ----
     if (f64) {
-      if ((rc = upload(base + L.CE, R.CE, s)) || (rc = upload(base + L.CB, R.CB, s)) || (rc = upload(base + L.P, R.P, s)))
+      if ((rc = upload(base + L.CE, R.CE, s)) || (rc = upload(base + L.CB, R.CB, s)) || (rc = upload(base + L.P, R.P, s)) ||
+          (!R.H.empty() && (rc = upload(base + L.H, R.H, s))))
         break;
     } else {
-      std::vector<float> a(R.CE.begin(), R.CE.end()), b(R.CB.begin(), R.CB.end()), c(R.P.begin(), R.P.end());
-      if ((rc = upload(base + L.CE, a, s)) || (rc = upload(base + L.CB, b, s)) || (rc = upload(base + L.P, c, s))) break;
+      std::vector<float> a(R.CE.begin(), R.CE.end()), b(R.CB.begin(), R.CB.end()), c(R.P.begin(), R.P.end()),
+          hf(R.H.begin(), R.H.end());
+      if ((rc = upload(base + L.CE, a, s)) || (rc = upload(base + L.CB, b, s)) || (rc = upload(base + L.P, c, s)) ||
+          (!hf.empty() && (rc = upload(base + L.H, hf, s))))
+        break;
       if ((rc = hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize"))) break;
     }
     // ---- electrons (host FP64 loading, then the run's precision) ----

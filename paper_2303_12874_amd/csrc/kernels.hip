@@ -812,8 +812,13 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
 // the rows whose z differences or z filter need neighbours (+-N columns) are
 // first staged in LDS with coalesced record loads, every other operand is a
 // record of the thread's own column.
+//
+// The E update takes the deposited current through one of two z stencils
+// that make it conserve charge with D_B = D_Yee o P: the filter P (2N-1
+// taps) on J_r and J_phi (kExact false), or P^{-1} (2 NH - 1 taps) on J_z
+// with J_r and J_phi as deposited (kExact true).
 
-template <typename R, int M>
+template <typename R, int M, bool kExact>
 __global__ __launch_bounds__(kFieldTile) void efield_kernel(const Batch bt) {
   constexpr int NMP = 2 * (M + 1);
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -828,6 +833,8 @@ __global__ __launch_bounds__(kFieldTile) void efield_kernel(const Batch bt) {
   const int i0 = (blk - j * ncol) * kFieldTile;
   const int t = threadIdx.x;
   const int W = kFieldTile + 2 * N;  // staged columns i0-N .. i0+kFieldTile+N-1
+  const int NH = k.NH;               // exact: J_z staged over i0-NH+1 .. i0+kFieldTile+NH-2
+  const int WH = kFieldTile + 2 * (NH - 1);
   const long long plane = k.plane, cstride = plane * (NMP - 1);  // NM planes per component
   const long long row = (long long)j * Nz;
   const R *B = (const R *)k.B[par ^ 1];  // B^{n+1/2}
@@ -835,6 +842,7 @@ __global__ __launch_bounds__(kFieldTile) void efield_kernel(const Batch bt) {
   R *Jn = (R *)k.J[par ^ 1];
   R *E = (R *)k.E;
   R *sBp = lds, *sBr = lds + W * NMP, *sJr = lds + 2 * W * NMP, *sJp = lds + 3 * W * NMP;
+  R *sJz = lds + 2 * W * NMP;  // exact: in place of sJr, sJp
   // the thread's own-column operands (a column past Nz reads column Nz - 1
   // and is dropped after the barrier).  In FP32 they are loaded first, to be
   // in flight while the rows are staged; in FP64 that costs more in
@@ -844,12 +852,18 @@ __global__ __launch_bounds__(kFieldTile) void efield_kernel(const Batch bt) {
   const bool live = i < Nz;
   const long long ic = live ? i : Nz - 1;
   R er[NMP], ep[NMP], ez[NMP], bz[NMP], bzm[NMP], bpm[NMP], jz[NMP];
+  R pjr[NMP], pjp[NMP];  // J_r, J_phi as the update takes them
   auto load_own = [&]() {
     load_node<R, NMP>(E + 0 * cstride, plane, row + ic, er);
     load_node<R, NMP>(E + 1 * cstride, plane, row + ic, ep);
     load_node<R, NMP>(E + 2 * cstride, plane, row + ic, ez);
     load_node<R, NMP>(B + 2 * cstride, plane, row + ic, bz);
-    load_node<R, NMP>(Jc + 2 * cstride, plane, row + ic, jz);
+    if constexpr (kExact) {
+      load_node<R, NMP>(Jc + 0 * cstride, plane, row + ic, pjr);
+      load_node<R, NMP>(Jc + 1 * cstride, plane, row + ic, pjp);
+    } else {
+      load_node<R, NMP>(Jc + 2 * cstride, plane, row + ic, jz);
+    }
     // half row j-1 (unused in row 0).  FP64 loads it without a branch, row 0
     // reading its own row: the branch leaves part of the two arrays in scratch
     // memory there (24 bytes; 0.158 -> 0.154 ms at 4096 x 256, modes 0..2).
@@ -875,11 +889,20 @@ __global__ __launch_bounds__(kFieldTile) void efield_kernel(const Batch bt) {
     store_rec<R, NMP>(sBp + r * NMP, v);
     load_node<R, NMP>(B + 0 * cstride, plane, row + col, v);  // B_r
     store_rec<R, NMP>(sBr + r * NMP, v);
-    load_node<R, NMP>(Jc + 0 * cstride, plane, row + col, v);  // J_r
-    store_rec<R, NMP>(sJr + r * NMP, v);
-    load_node<R, NMP>(Jc + 1 * cstride, plane, row + col, v);  // J_phi
-    store_rec<R, NMP>(sJp + r * NMP, v);
+    if constexpr (!kExact) {
+      load_node<R, NMP>(Jc + 0 * cstride, plane, row + col, v);  // J_r
+      store_rec<R, NMP>(sJr + r * NMP, v);
+      load_node<R, NMP>(Jc + 1 * cstride, plane, row + col, v);  // J_phi
+      store_rec<R, NMP>(sJp + r * NMP, v);
+    }
   }
+  if constexpr (kExact)
+    for (int r = t; r < WH; r += kFieldTile) {
+      const int col = wrap_any(i0 - (NH - 1) + r, Nz);
+      R v[NMP];
+      load_node<R, NMP>(Jc + 2 * cstride, plane, row + col, v);  // J_z
+      store_rec<R, NMP>(sJz + r * NMP, v);
+    }
   __syncthreads();
   if (!live) return;
   const R dt = (R)k.dt, dr = (R)k.dr, idz = (R)(1.0 / k.dz);
@@ -895,9 +918,9 @@ __global__ __launch_bounds__(kFieldTile) void efield_kernel(const Batch bt) {
   const int c0 = t + N;  // LDS index of column i
 
   // z operators on the staged rows, all modes at once
-  R dbp[NMP], dbr[NMP], pjr[NMP], pjp[NMP];
+  R dbp[NMP], dbr[NMP];
 #pragma unroll
-  for (int s = 0; s < NMP; ++s) dbp[s] = dbr[s] = pjr[s] = pjp[s] = R(0);
+  for (int s = 0; s < NMP; ++s) dbp[s] = dbr[s] = R(0);
   for (int l = 1; l <= N; ++l) {  // D_B: sum_l C^B_l (g_{i+l-1/2} - g_{i-l+1/2})
     const R cb = CB[l - 1];
     const R *ap = sBp + (c0 + l - 1) * NMP, *am = sBp + (c0 - l) * NMP;
@@ -908,22 +931,34 @@ __global__ __launch_bounds__(kFieldTile) void efield_kernel(const Batch bt) {
       dbr[s] += cb * (bp_[s] - bm[s]);
     }
   }
-  {
+  if constexpr (kExact) {  // symmetric stencil of P^{-1} on J_z
+    const R *H = (const R *)k.H;
+    const int ch = t + NH - 1;  // LDS index of column i in the J_z rows
+    const R h0 = H[0];
+#pragma unroll
+    for (int s = 0; s < NMP; ++s) jz[s] = h0 * sJz[ch * NMP + s];
+    for (int l = 1; l < NH; ++l) {
+      const R hl = H[l];
+      const R *a1 = sJz + (ch + l) * NMP, *a2 = sJz + (ch - l) * NMP;
+#pragma unroll
+      for (int s = 0; s < NMP; ++s) jz[s] += hl * (a1[s] + a2[s]);
+    }
+  } else {
     const R p0 = P[N - 1];
 #pragma unroll
     for (int s = 0; s < NMP; ++s) {
       pjr[s] = p0 * sJr[c0 * NMP + s];
       pjp[s] = p0 * sJp[c0 * NMP + s];
     }
-  }
-  for (int l = 1; l < N; ++l) {  // symmetric filter P
-    const R pl = P[N - 1 + l];
-    const R *a1 = sJr + (c0 + l) * NMP, *a2 = sJr + (c0 - l) * NMP;
-    const R *b1 = sJp + (c0 + l) * NMP, *b2 = sJp + (c0 - l) * NMP;
+    for (int l = 1; l < N; ++l) {  // symmetric filter P
+      const R pl = P[N - 1 + l];
+      const R *a1 = sJr + (c0 + l) * NMP, *a2 = sJr + (c0 - l) * NMP;
+      const R *b1 = sJp + (c0 + l) * NMP, *b2 = sJp + (c0 - l) * NMP;
 #pragma unroll
-    for (int s = 0; s < NMP; ++s) {
-      pjr[s] += pl * (a1[s] + a2[s]);
-      pjp[s] += pl * (b1[s] + b2[s]);
+      for (int s = 0; s < NMP; ++s) {
+        pjr[s] += pl * (a1[s] + a2[s]);
+        pjp[s] += pl * (b1[s] + b2[s]);
+      }
     }
   }
   // (FP64: the own-column operands are loaded only now, after the z
@@ -1625,8 +1660,16 @@ template <typename R, int M>
 struct EL {
   static int run(Batch &b, hipStream_t s) {
     set_offsets(b, [](const KRun &k) { return (long long)((k.Nz + kFieldTile - 1) / kFieldTile) * (k.Nr + 1); });
-    const size_t lds = (size_t)4 * (kFieldTile + 2 * b.run[0].N) * 2 * (M + 1) * sizeof(R);
-    efield_kernel<R, M><<<(unsigned)b.off[b.n], kFieldTile, lds, s>>>(b);
+    const size_t rec = (size_t)2 * (M + 1) * sizeof(R);
+    const size_t wb = (size_t)(kFieldTile + 2 * b.run[0].N);
+    if (b.run[0].NH > 0) {  // all runs of a context share the option; their tap counts differ
+      int nh = 0;
+      for (int r = 0; r < b.n; ++r) nh = b.run[r].NH > nh ? b.run[r].NH : nh;
+      const size_t lds = (2 * wb + (size_t)(kFieldTile + 2 * (nh - 1))) * rec;
+      efield_kernel<R, M, true><<<(unsigned)b.off[b.n], kFieldTile, lds, s>>>(b);
+    } else {
+      efield_kernel<R, M, false><<<(unsigned)b.off[b.n], kFieldTile, 4 * wb * rec, s>>>(b);
+    }
     return check(hipGetLastError(), "efield_kernel");
   }
 };

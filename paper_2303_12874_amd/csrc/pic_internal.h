@@ -21,6 +21,9 @@ double radial_lambda(int m, int nr);
 double radial_lambda_max(int M);
 bool stable_at(const double *CE, const double *CB, int N, int M, double dz, double dr, double nu);
 double courant_limit_of(const double *CE, const double *CB, int N, int M, double dz, double dr);
+// taps h_0..h_{nh-1} of the inverse of the z filter of CB, cut below eps h_0;
+// 0, or 1 if P(k) <= 0 somewhere, or 2 if more than max_taps are needed
+int jz_inverse_taps(const double *CB, int N, double eps, int max_taps, double *h, int *nh);
 double courant_limit_fitted(int solver, int N, int M, double dz, double dr, double band);
 int64_t run_particle_count(const pic_run_desc &r);
 void load_electrons(const pic_run_desc &r, double *z, double *x, double *y, double *w, int64_t *id,
@@ -52,6 +55,8 @@ struct KRun {
   const int32_t *tracked; // tracked ids, ascending
   int n_tracked;
   const void *CE, *CB, *P;  // coefficient arrays (real type of the run), P has 2N-1 taps
+  const void *H;            // taps h_0..h_{NH-1} of P^{-1} (exact J_z correction)
+  int NH;                   // 0: the current is filtered by P instead
   // sort scratch
   void *sz, *sfz, *sx, *sy, *sux, *suy, *suz, *sw;  // second particle buffer
   uint32_t *spid;

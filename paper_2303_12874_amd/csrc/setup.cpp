@@ -256,6 +256,46 @@ static double courant_limit_search(int solver, int N, int M, double dz, double d
   return lo;
 }
 
+// Inverse of the z filter P (taps p_l = sum_{l' > |l|} C^B_{l'}).  P is a
+// convolution with symbol P(k) = p_0 + 2 sum_{l >= 1} p_l cos(l k dz), a
+// positive trigonometric polynomial for the usual fits, so 1/P(k) is smooth
+// and its Fourier coefficients h_l decay geometrically: h is P^{-1} on the
+// infinite line, and a cut where the taps fall below eps h_0 leaves an error
+// of that order.  h_l = (1/K) sum_q cos(2 pi q l / K) / P(2 pi q / K) with
+// K = 8192 samples (the aliasing of the K-periodic series is h_{K-l}, nil),
+// summed in the host's extended precision so that the rounding of the sums
+// stays far below the FP64 cut.
+int jz_inverse_taps(const double *CB, int N, double eps, int max_taps, double *h, int *nh) {
+  using X = long double;
+  constexpr int K = 8192;
+  std::vector<X> p((size_t)N, 0.0L);  // p_0 .. p_{N-1}
+  for (int l = 0; l < N; ++l)
+    for (int lp = l + 1; lp <= N; ++lp) p[(size_t)l] += CB[lp - 1];
+  std::vector<X> cs(K), inv(K);
+  const X two_pi = 2.0L * 3.141592653589793238462643383279502884L;
+  for (int k = 0; k < K; ++k) cs[(size_t)k] = std::cos(two_pi * k / K);
+  for (int q = 0; q < K; ++q) {
+    X P = p[0];
+    for (int l = 1; l < N; ++l) P += 2.0L * p[(size_t)l] * cs[(size_t)((long long)l * q % K)];
+    if (!(P > 0.0L)) return 1;
+    inv[(size_t)q] = 1.0L / P;
+  }
+  const int scan = 2 * max_taps;  // taps examined beyond the cut
+  std::vector<double> hh((size_t)scan);
+  for (int l = 0; l < scan; ++l) {
+    X acc = 0.0L;
+    for (int q = 0; q < K; ++q) acc += cs[(size_t)((long long)l * q % K)] * inv[(size_t)q];
+    hh[(size_t)l] = (double)(acc / K);
+  }
+  int n = 1;
+  for (int l = 1; l < scan; ++l)
+    if (std::fabs(hh[(size_t)l]) > eps * std::fabs(hh[0])) n = l + 1;
+  if (n > max_taps) return 2;
+  for (int l = 0; l < n; ++l) h[l] = hh[(size_t)l];
+  *nh = n;
+  return 0;
+}
+
 // ---------------------------------------------------------------------------
 // loading: counter-based SplitMix64; draw d of electron pid is output number
 // 4 pid + d + 1 of the stream seeded with `seed`.

@@ -109,6 +109,46 @@ def test_yee_setup_is_textbook():
     assert abs(lim - 1 / math.sqrt(1 + lam0 * (dz / dr) ** 2 / 4)) < 1e-9
 
 
+@pytest.mark.parametrize("M", [0, 1, 2, 3])
+def test_jz_inverse_taps_invert_the_filter(M):
+    """The stencil of the exact J_z correction against the oracle's P^{-1} (a
+    DFT on a periodic line, no cut) applied to a unit impulse, and against the
+    forward filter by direct convolution; FP32 cuts it shorter."""
+    dz = workloads.LAMBDA0 / 16
+    _, _, _, cb = pic.solver_setup(M, dz, 4 * dz)
+    h = pic.jz_inverse_taps(cb, pic.PREC_FP64)
+    nh = h.size
+    assert 1 < nh <= pic.MAX_JZ_TAPS
+    Nz = 512
+    o = oracle.Oracle(Nz, 4, 0, dz, 4 * dz, 0.5 * dz, cb, cb)
+    delta = np.zeros(Nz, dtype=complex)
+    delta[0] = 1.0
+    ref = o.inverse_filter(delta).real  # periodic P^{-1}: ref[l] = h_l
+    # both sides round: the oracle's 512-term DFT sums to a few units of 1e-15
+    assert np.abs(ref[:nh] - h).max() < 1e-14 * abs(h[0])
+    assert np.abs(ref[nh:Nz - nh + 1]).max() <= 2 * 2.0 ** -53 * abs(h[0])
+    full = np.concatenate([h[:0:-1], h])  # h_{-(nh-1)} .. h_{nh-1}
+    p = o.filter_taps()
+    conv = np.convolve(full, p)
+    centre = (conv.size - 1) // 2
+    e = np.zeros(conv.size)
+    e[centre] = 1.0
+    assert np.abs(conv - e).max() < 1e-14
+    h32 = pic.jz_inverse_taps(cb, pic.PREC_FP32)
+    assert h32.size < nh and np.array_equal(h32, h[:h32.size])
+    assert np.abs(ref[h32.size:Nz - h32.size + 1]).max() <= 2.0 ** -24 * abs(h[0])
+
+
+def test_jz_inverse_taps_yee_and_refusal():
+    assert list(pic.jz_inverse_taps([1.0])) == [1.0]
+    # a 32-coefficient fit whose filter changes sign near k dz = 0.93 pi
+    _, CB = coef.fit(32, 0.75)
+    with pytest.raises(pic.PicError):
+        pic.jz_inverse_taps(CB)
+    with pytest.raises(pic.PicError):
+        pic.jz_inverse_taps(np.ones(40))
+
+
 @pytest.mark.parametrize("name", ["c1", "small"])
 def test_loader_bit_exact_with_oracle(name):
     run = (workloads.config("c1") if name == "c1" else workloads.small(M=2, Nz=48, Nr=9, ppc=3))["runs"][0]
