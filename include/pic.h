@@ -112,8 +112,13 @@ typedef struct pic_run_desc {
   int32_t ppc;      /* electrons per cell, >= 1 (loaded for r < (Nr-1) dr)    */
   double dz, dr;    /* cell sizes                                             */
   double n0;        /* electron density (units of n_c)                        */
-  double ramp_start, ramp_len; /* linear up-ramp of the density along z
-                                  (ramp_len = 0: uniform)                     */
+  double ramp_start, ramp_len; /* linear up-ramp of the density along z,
+                                  0 at ramp_start to n0 at ramp_start +
+                                  ramp_len (ramp_len = 0: none)               */
+  double down_start, down_len; /* linear down-ramp, n0 at down_start to 0 at
+                                  down_start + down_len (down_len = 0: none);
+                                  the profile of App. A is up-ramp, plateau,
+                                  down-ramp                                   */
   int32_t n_pulses; /* 0..PIC_MAX_PULSES                                      */
   pic_pulse pulse[PIC_MAX_PULSES];
   double taper;     /* laser taper length at the box ends (0: none)           */

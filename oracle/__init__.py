@@ -60,7 +60,7 @@ def lib():
             "orc_field_step": (None, [p, i]),
             "orc_start_fields": (None, [p]),
             "orc_splitmix64": (u64, [u64, u64]),
-            "orc_load_plasma": (i, [p, i, d, d, d, u64, i]),
+            "orc_load_plasma": (i, [p, i, d, d, d, u64, i, d, d]),
             "orc_set_particles": (i, [p, l, p, p, p, p, p, p, p, i]),
             "orc_get_particles": (None, [p, p, p, p, p, p, p, p, p]),
             "orc_put_particles": (None, [p, p, p, p, p, p, p, p]),
@@ -159,9 +159,10 @@ class Oracle:
     def np(self):
         return lib().orc_num_particles(self._h)
 
-    def load_plasma(self, ppc, n0, ramp_start=0.0, ramp_len=0.0, seed=0, n_tracked=0):
+    def load_plasma(self, ppc, n0, ramp_start=0.0, ramp_len=0.0, seed=0, n_tracked=0, down_start=0.0,
+                    down_len=0.0):
         r = lib().orc_load_plasma(self._h, int(ppc), float(n0), float(ramp_start), float(ramp_len),
-                                  int(seed) & (2**64 - 1), int(n_tracked))
+                                  int(seed) & (2**64 - 1), int(n_tracked), float(down_start), float(down_len))
         if r != 0:
             raise ValueError("bad plasma load")
 

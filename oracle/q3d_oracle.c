@@ -818,12 +818,14 @@ static int cmp_track(const void *a, const void *b) {
 
 /* Cold electrons, ppc per cell in cells iz = 0..Nz-1, ir = 0..Nr-2, at
  * uniform-random (z, r, phi) in the cell; density n(z) = n0 times a linear
- * up-ramp over [ramp_start, ramp_start + ramp_len] (physical z) enters the
+ * up-ramp over [ramp_start, ramp_start + ramp_len] and a linear down-ramp
+ * over [down_start, down_start + down_len] (physical z; App. A's profile is
+ * up-ramp, plateau, down-ramp; a zero length means no ramp) enters the
  * weight w = n(z) 2 pi r dr dr dz / ppc (r physical), so that the density is
  * uniform in r.  Particle pid = (iz (Nr-1) + ir) ppc + s.  The n_tracked
  * particles with the smallest (draw 3, pid) are tracked.                    */
 int orc_load_plasma(orc *o, int ppc, double n0, double ramp_start, double ramp_len, uint64_t seed,
-                    int n_tracked) {
+                    int n_tracked, double down_start, double down_len) {
   free_particles(o);
   const int Nz = o->Nz, nrc = o->Nr - 1;
   long np = (long)Nz * nrc * ppc;
@@ -851,6 +853,12 @@ int orc_load_plasma(orc *o, int ppc, double n0, double ramp_start, double ramp_l
           if (f < 0.0) f = 0.0;
           if (f > 1.0) f = 1.0;
           n = n0 * f;
+        }
+        if (down_len > 0.0) {
+          double g = 1.0 - (zc * o->dz - down_start) / down_len;
+          if (g < 0.0) g = 0.0;
+          if (g > 1.0) g = 1.0;
+          n *= g;
         }
         o->z[pid] = zc;
         o->x[pid] = rc * cos(phi);

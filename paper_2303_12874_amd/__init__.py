@@ -42,6 +42,7 @@ class _RunDesc(C.Structure):
         ("Nz", C.c_int32), ("Nr", C.c_int32), ("M", C.c_int32), ("ppc", C.c_int32),
         ("dz", C.c_double), ("dr", C.c_double), ("n0", C.c_double),
         ("ramp_start", C.c_double), ("ramp_len", C.c_double),
+        ("down_start", C.c_double), ("down_len", C.c_double),
         ("n_pulses", C.c_int32), ("pulse", _Pulse * MAX_PULSES), ("taper", C.c_double),
         ("seed", C.c_uint64), ("n_tracked", C.c_int32), ("n_steps", C.c_int64),
     ]
@@ -156,6 +157,8 @@ class RunDesc:
     n0: float = 0.0
     ramp_start: float = 0.0
     ramp_len: float = 0.0
+    down_start: float = 0.0
+    down_len: float = 0.0
     pulses: List[Pulse] = field(default_factory=list)
     taper: float = 0.0
     seed: int = 0
@@ -166,6 +169,7 @@ class RunDesc:
         r = _RunDesc()
         r.Nz, r.Nr, r.M, r.ppc = self.Nz, self.Nr, self.M, self.ppc
         r.dz, r.dr, r.n0, r.ramp_start, r.ramp_len = self.dz, self.dr, self.n0, self.ramp_start, self.ramp_len
+        r.down_start, r.down_len = self.down_start, self.down_len
         if len(self.pulses) > MAX_PULSES:
             raise ValueError("at most %d pulses" % MAX_PULSES)
         r.n_pulses = len(self.pulses)

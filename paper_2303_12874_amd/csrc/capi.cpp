@@ -179,7 +179,9 @@ int validate_run(const pic_run_desc &r, int i, int N) {
   if (r.Nz < 2 * N) return fail(PIC_E_INVALID, "run %d: Nz=%d shorter than the %d-tap stencil", i, r.Nz, 2 * N);
   if (!(r.dz > 0) || !(r.dr > 0) || !std::isfinite(r.dz) || !std::isfinite(r.dr))
     return fail(PIC_E_INVALID, "run %d: cell sizes must be positive", i);
-  if (!(r.n0 >= 0) || !(r.ramp_len >= 0)) return fail(PIC_E_INVALID, "run %d: density must be >= 0", i);
+  if (!(r.n0 >= 0) || !(r.ramp_len >= 0) || !(r.down_len >= 0) || !std::isfinite(r.ramp_start) ||
+      !std::isfinite(r.down_start))
+    return fail(PIC_E_INVALID, "run %d: density must be >= 0 and ramps finite", i);
   if (r.n_pulses < 0 || r.n_pulses > PIC_MAX_PULSES) return fail(PIC_E_INVALID, "run %d: n_pulses out of range", i);
   if (r.n_pulses > 0 && r.M < 1) return fail(PIC_E_INVALID, "run %d: a laser needs M >= 1", i);
   for (int p = 0; p < r.n_pulses; ++p)

@@ -314,7 +314,7 @@ static inline double draw(uint64_t seed, int64_t pid, int d) {
 int64_t run_particle_count(const pic_run_desc &r) { return (int64_t)r.Nz * (r.Nr - 1) * r.ppc; }
 
 // Cold electrons: ppc per cell for r < (Nr-1) dr at uniform-random (z, r, phi)
-// in the cell; the density n(z) (with its linear up-ramp) and the annulus
+// in the cell; the density n(z) (with its linear up- and down-ramps) and the annulus
 // volume enter the weight w = n 2 pi r dr dr dz / ppc, so the density is
 // uniform in r.  The n_tracked electrons with the smallest (draw 3, pid) are
 // tracked; tracked ids are returned ascending.
@@ -347,6 +347,11 @@ void load_electrons(const pic_run_desc &r, double *z, double *x, double *y, doub
             double f = (zc * r.dz - r.ramp_start) / r.ramp_len;
             f = f < 0.0 ? 0.0 : (f > 1.0 ? 1.0 : f);
             n = r.n0 * f;
+          }
+          if (r.down_len > 0.0) {
+            double g = 1.0 - (zc * r.dz - r.down_start) / r.down_len;
+            g = g < 0.0 ? 0.0 : (g > 1.0 ? 1.0 : g);
+            n *= g;
           }
           if (z) z[pid] = zc;
           if (x) x[pid] = rc * std::cos(phi);

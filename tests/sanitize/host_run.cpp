@@ -24,6 +24,8 @@ int main() {
     d.n0 = 0.01;
     d.ramp_start = 2.0;
     d.ramp_len = 6.0;
+    d.down_start = 10.0;
+    d.down_len = 4.0;
     d.n_pulses = M >= 1 ? 1 : 0;
     d.pulse[0].a0 = 1.0;
     d.pulse[0].w0 = 6.0;

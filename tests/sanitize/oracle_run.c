@@ -21,7 +21,8 @@ void orc_deposit_rho(orc *o);
 void orc_step(orc *o, int nsteps);
 void orc_field_step(orc *o, int nsteps);
 void orc_start_fields(orc *o);
-int orc_load_plasma(orc *o, int ppc, double n0, double ramp_start, double ramp_len, uint64_t seed, int n_tracked);
+int orc_load_plasma(orc *o, int ppc, double n0, double ramp_start, double ramp_len, uint64_t seed, int n_tracked,
+                    double down_start, double down_len);
 int orc_tracked(orc *o, int64_t *ids, double *W, double *gamma, double *gamma_acc);
 int orc_cartesian_work(orc *o, double *wz, double *wperp);
 double orc_kinetic(orc *o);
@@ -32,7 +33,7 @@ static int run(int M, int N, const double *C) {
   const int Nz = 24, Nr = 8;
   orc *o = orc_create(Nz, Nr, M, 0.4, 1.6, 0.15, N, C, C);
   if (!o) return 1;
-  if (orc_load_plasma(o, 2, 0.02, 2.0, 4.0, 7u, 12)) return 2;
+  if (orc_load_plasma(o, 2, 0.02, 2.0, 4.0, 7u, 12, 8.0, 3.0)) return 2;
   if (M >= 1 && orc_add_laser(o, 1.5, 4.0, 3.0, 4.8, 1.0)) return 3;
   orc_start_fields(o);
   orc_set_flags(o, 0, 1);

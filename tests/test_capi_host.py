@@ -161,14 +161,16 @@ def test_loader_bit_exact_with_oracle(name):
     assert np.array_equal(L["tracked"], o.tracked()["id"])
 
 
-def test_loader_ramp_bit_exact():
+def test_loader_ramps_bit_exact():
+    """Up-ramp, plateau and down-ramp (App. A's profile)."""
     run = dict(workloads.small(M=1, Nz=40, Nr=6, ppc=2)["runs"][0])
-    run.update(ramp_start=1.0, ramp_len=10.0)
+    run.update(ramp_start=1.0, ramp_len=5.0, down_start=9.0, down_len=4.0)
     L = pic.load_host(workloads.to_rundesc(run))
-    o = oracle.Oracle(run["Nz"], run["Nr"], run["M"], run["dz"], run["dr"], 0.3, [1.0], [1.0])
-    o.load_plasma(run["ppc"], run["n0"], run["ramp_start"], run["ramp_len"], run["seed"], run["n_tracked"])
+    o = workloads.to_oracle(run, 0.3, [1.0], [1.0])
     assert np.array_equal(L["w"], o.particles()["w"])
-    assert (L["w"] == 0).any() and (L["w"] > 0).any()
+    z = L["z"] * run["dz"]
+    assert (L["w"][z < 1.0] == 0).all() and (L["w"][z > 13.0] == 0).all()
+    assert (L["w"][(z > 6.0) & (z < 9.0)] > 0).all()
 
 
 def _tune_query(runs, trial_steps=16, **kw):

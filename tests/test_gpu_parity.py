@@ -81,7 +81,8 @@ def oracle_of(run, dt, CE, CB, fp32_start=False):
     """The oracle of a run; with fp32_start its initial particles and E^0, B^0
     are first rounded as the FP32 library stores them."""
     o = oracle.Oracle(run["Nz"], run["Nr"], run["M"], run["dz"], run["dr"], dt, CE, CB)
-    o.load_plasma(run["ppc"], run["n0"], run["ramp_start"], run["ramp_len"], run["seed"], run["n_tracked"])
+    o.load_plasma(run["ppc"], run["n0"], run["ramp_start"], run["ramp_len"], run["seed"], run["n_tracked"],
+                  run.get("down_start", 0.0), run.get("down_len", 0.0))
     for p in run["pulses"]:
         o.add_laser(p["a0"], p["w0"], p["tau"], p["zc"], run["taper"])
     if fp32_start:
@@ -170,6 +171,22 @@ def test_fp64_small_grid_parity(M):
     assert np.abs(wg["gamma_acc"] - wg["gamma"]).max() < 1e-13 * max(1.0, wg["gamma"].max())
     cw = compare_cartesian_work(sim, o, run, TOL64)
     assert max(cw.values()) < TOL64, cw
+    sim.close()
+
+
+def test_fp64_density_ramps_parity():
+    """App. A's density profile (up-ramp, plateau, down-ramp) in a short box:
+    12 steps, modes 0..1, to the FP64 bar."""
+    _say("[gpu] fp64 density ramps")
+    run = workloads.small(M=1, Nz=96, Nr=12, ppc=2, n_tracked=40)["runs"][0]
+    L = run["Nz"] * run["dz"]
+    run.update(ramp_start=0.1 * L, ramp_len=0.2 * L, down_start=0.55 * L, down_len=0.3 * L)
+    sim, o = run_pair(run, 12)
+    worst = compare_fields(sim, o, run["M"], TOL64)
+    bad = {k: v for k, v in worst.items() if v > TOL64}
+    assert not bad, bad
+    dzmax, dxy, du, _ = compare_particles(sim, o, run["Nz"])
+    assert dzmax < TOL64 and dxy < TOL64 and du < TOL64, (dzmax, dxy, du)
     sim.close()
 
 

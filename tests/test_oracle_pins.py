@@ -72,6 +72,33 @@ def test_loader_matches_independent_draws():
     assert list(o.tracked()["id"]) == tracked
 
 
+def test_density_profile_up_plateau_down():
+    """App. A's profile (up-ramp, plateau, down-ramp): the density each
+    electron carries, w / (2 pi r dr dr dz / ppc), is 0 before the up-ramp and
+    after the down-ramp, n0 on the plateau, and on each ramp a straight line
+    through its end points (a least-squares line through the electrons on it
+    has the ramp's slope and passes through them to rounding)."""
+    Nz, Nr, ppc, dz, dr, n0 = 120, 4, 3, 0.5, 1.0, 0.03
+    up0, upl, dn0, dnl = 5.0, 12.0, 35.0, 18.0
+    o = oracle.Oracle(Nz, Nr, 0, dz, dr, 0.1, [1.0], [1.0])
+    o.load_plasma(ppc, n0, up0, upl, seed=3, down_start=dn0, down_len=dnl)
+    P = o.particles()
+    z = P["z"] * dz
+    r = np.hypot(P["x"], P["y"]) * dr
+    n = P["w"] / (2 * math.pi * r * dr * dz / ppc)
+    assert np.all(n[z < up0] == 0) and np.all(n[z > dn0 + dnl] == 0)
+    plateau = (z > up0 + upl) & (z < dn0)
+    assert np.abs(n[plateau] / n0 - 1).max() < 1e-14
+    for lo, ln, slope in ((up0, upl, n0 / upl), (dn0, dnl, -n0 / dnl)):
+        on = (z > lo) & (z < lo + ln)
+        assert on.sum() > 50
+        A = np.vstack([z[on] - lo, np.ones(on.sum())]).T
+        (k, c), *_ = np.linalg.lstsq(A, n[on], rcond=None)
+        assert abs(k / slope - 1) < 1e-12
+        assert np.abs(A @ [k, c] - n[on]).max() < 1e-14 * n0
+        assert abs(c - (0.0 if slope > 0 else n0)) < 1e-14 * n0
+
+
 # --------------------------------------------------------------------------
 # coefficient fit (Sec. III.A, Eqs. (11), (15))
 

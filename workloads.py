@@ -82,6 +82,7 @@ def to_rundesc(run: dict, n_steps: int = 0):
 
     return pic.RunDesc(Nz=run["Nz"], Nr=run["Nr"], M=run["M"], ppc=run["ppc"], dz=run["dz"], dr=run["dr"],
                        n0=run["n0"], ramp_start=run["ramp_start"], ramp_len=run["ramp_len"],
+                       down_start=run.get("down_start", 0.0), down_len=run.get("down_len", 0.0),
                        pulses=[pic.Pulse(**p) for p in run["pulses"]], taper=run["taper"], seed=run["seed"],
                        n_tracked=run["n_tracked"], n_steps=n_steps)
 
@@ -92,7 +93,8 @@ def to_oracle(run: dict, dt, CE, CB):
 
     o = oracle.Oracle(run["Nz"], run["Nr"], run["M"], run["dz"], run["dr"], dt, CE, CB)
     if run["ppc"] > 0:
-        o.load_plasma(run["ppc"], run["n0"], run["ramp_start"], run["ramp_len"], run["seed"], run["n_tracked"])
+        o.load_plasma(run["ppc"], run["n0"], run["ramp_start"], run["ramp_len"], run["seed"], run["n_tracked"],
+                      run.get("down_start", 0.0), run.get("down_len", 0.0))
     for p in run["pulses"]:
         o.add_laser(p["a0"], p["w0"], p["tau"], p["zc"], run["taper"])
     o.start_fields()
