@@ -191,8 +191,10 @@ int validate_run(const pic_run_desc &r, int i, int N) {
   if (np > (int64_t)kIdMask) return fail(PIC_E_INVALID, "run %d: %lld electrons exceed the id range", i, (long long)np);
   if (r.n_tracked < 0 || r.n_tracked > np) return fail(PIC_E_INVALID, "run %d: n_tracked out of range", i);
   if (r.n_steps < 0) return fail(PIC_E_INVALID, "run %d: n_steps < 0", i);
-  if ((int64_t)(r.Nr + 1) * r.Nz * (2 * r.M + 1) * 3 > ((int64_t)1 << 40))
-    return fail(PIC_E_INVALID, "run %d: grid too large", i);
+  // the kernels address a node inside a plane with 32-bit signed offsets
+  if ((int64_t)(r.Nr + 1) * r.Nz > (int64_t)INT32_MAX)
+    return fail(PIC_E_INVALID, "run %d: (Nr+1) Nz = %lld nodes per plane exceed 2^31 - 1", i,
+                (long long)(r.Nr + 1) * r.Nz);
   return PIC_OK;
 }
 

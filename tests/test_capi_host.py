@@ -43,6 +43,19 @@ def test_invalid_descriptor_is_rejected_without_device(field, value):
     assert e.value.code == pic.PIC_E_INVALID
 
 
+def test_plane_beyond_32_bit_offsets_is_rejected():
+    """The largest plane the kernels address with 32-bit offsets is accepted
+    (size query only), one node more is not."""
+    Nz = 65536
+    ok = _desc(Nz=Nz, Nr=(2**31 - 1) // Nz - 1, ppc=0, n_tracked=0)
+    assert pic.workspace_bytes([ok]) > 0
+    bad = _desc(Nz=Nz, Nr=(2**31 - 1) // Nz, ppc=0, n_tracked=0)
+    assert (bad.Nr + 1) * bad.Nz > 2**31 - 1
+    with pytest.raises(pic.PicError) as e:
+        pic.workspace_bytes([bad])
+    assert e.value.code == pic.PIC_E_INVALID
+
+
 def test_bad_options_rejected():
     d = _desc()
     for kw in (dict(precision=16), dict(solver=7), dict(n_coef=0), dict(n_coef=99)):
