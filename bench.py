@@ -99,6 +99,29 @@ DLA_FLOPS_PER_STEP = 6 * 48 + 170
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 
+def copy_bandwidth(torch, dev, nbytes: int = 1 << 30, reps: int = 10) -> float:
+    """Achievable HBM bandwidth on this device (GB/s): a device-to-device copy
+    of nbytes (read + write counted), timed with events over `reps` copies
+    after two untimed ones.  Measured after the timed region, beside the
+    published peak the roofline is priced against."""
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    y = torch.empty_like(x)
+    for _ in range(2):
+        y.copy_(x)
+    s = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record(s)
+    torch.cuda.synchronize()
+    bw = 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return bw
+
+
 def bench_dla(args, torch, pic) -> int:
     """Electrons of the App. A recipe (injection over 200 / omega_p, model
     parameters of App. A) integrated to t = 400 / omega_p with h = 0.01 /
@@ -338,6 +361,9 @@ def main(argv=None):
     sim.close()
     del sim
     torch.cuda.empty_cache()
+    copy_bw = copy_bandwidth(torch, dev)
+    out["roofline"]["measured_peak"] = copy_bw  # 1 GiB device copy on this GPU
+    out["roofline"]["frac_of_measured_peak"] = ach / copy_bw
     if args.cpu_steps > 0:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(runs, args.cpu_steps, n_coef)
