@@ -256,8 +256,9 @@ int pic_divergence(pic_ctx *ctx, int32_t run, double gamma_min, double *out);
 int pic_checkpoint(pic_ctx *ctx, void *host_buf, size_t *bytes);
 
 /* Load a checkpoint into a context created by pic_init with the same runs and
- * options (checked: run descriptors, precision, sort tile and interval,
- * solver coefficients); stepping then continues where the checkpointed
+ * options (checked: format version, run descriptors, precision, sort tile
+ * and interval, current correction, solver coefficients); stepping then
+ * continues where the checkpointed
  * context was.  PIC_E_INVALID if the checkpoint does not belong to such a
  * context; nothing is changed then.                                         */
 int pic_restore(pic_ctx *ctx, const void *host_buf, size_t bytes);

@@ -139,6 +139,7 @@ struct pic_ctx {
   hipStream_t stream = nullptr;
   unsigned char *ws = nullptr;
   int sort_interval = 0;
+  int current = PIC_CURRENT_FILTER;
   std::vector<RunHost> runs;
   // per-phase event timing
   bool profiling = false;
@@ -371,6 +372,7 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
   ctx->ws = (unsigned char *)device_workspace;
   ctx->sort_interval = o.sort_interval > 0 ? o.sort_interval : kDefaultSortInterval;
   ctx->use_graph = o.use_graph != 0;
+  ctx->current = o.current;
   ctx->runs.resize((size_t)n_runs);
   const hipStream_t s = ctx->stream;
   const bool f64 = o.precision == PIC_PREC_FP64;
@@ -1171,7 +1173,7 @@ namespace {
 
 struct CkptHeader {
   char magic[8];
-  int32_t version, n_runs, precision, tile_z, tile_r, sort_interval;
+  int32_t version, n_runs, precision, tile_z, tile_r, sort_interval, current;
 };
 
 struct Seg {
@@ -1215,12 +1217,13 @@ CkptHeader header_of(pic_ctx *ctx) {
   CkptHeader h;
   std::memset(&h, 0, sizeof h);
   std::memcpy(h.magic, "PICCKPT1", 8);
-  h.version = 1;
+  h.version = 2;
   h.n_runs = (int32_t)ctx->runs.size();
   h.precision = ctx->prec;
   h.tile_z = ctx->runs.empty() ? 0 : ctx->runs[0].k.Tz;
   h.tile_r = ctx->runs.empty() ? 0 : ctx->runs[0].k.Tr;
   h.sort_interval = ctx->sort_interval;
+  h.current = ctx->current;
   return h;
 }
 
@@ -1270,7 +1273,8 @@ int pic_restore(pic_ctx *ctx, const void *host_buf, size_t bytes) {
   const unsigned char *p = (const unsigned char *)host_buf;
   const CkptHeader h = header_of(ctx);
   if (std::memcmp(p, &h, sizeof h) != 0)
-    return fail(PIC_E_INVALID, "checkpoint header does not match this context (runs, precision, tile, interval)");
+    return fail(PIC_E_INVALID,
+                "checkpoint header does not match this context (version, runs, precision, tile, interval, current)");
   // validate every run before any device copy
   const unsigned char *q = p + sizeof h;
   for (const RunHost &R : ctx->runs) {

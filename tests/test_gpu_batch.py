@@ -123,3 +123,38 @@ def test_autotune_reports_candidates_and_choice_keeps_parity():
         bad = {k: v for k, v in worst.items() if v > TOL64}
         assert not bad, (i, bad)
     sim.close()
+
+
+def test_empty_run_beside_a_full_one():
+    """A run with no electrons (ppc = 0: a laser in vacuum) in one context with
+    a populated run: the empty run's fields match its oracle (the current
+    stays zero), its diagnostics are empty or zero, and the populated run
+    matches its own oracle."""
+    _say("[gpu] empty run beside a full one")
+    pic = _pic()
+    empty = workloads.small(M=2, Nz=64, Nr=12, ppc=2, seed=11, n_tracked=0)["runs"][0]
+    empty["ppc"] = 0
+    full = workloads.small(M=2, Nz=80, Nr=10, ppc=2, seed=12, n_tracked=20)["runs"][0]
+    dt, CE, CB, _ = _setup(16, 2, full["dz"], full["dr"])
+    sim = pic.Simulation([workloads.to_rundesc(empty), workloads.to_rundesc(full)], dt=dt, coef_E=CE, coef_B=CB)
+    assert sim.info(0)["n_particles"] == 0
+    sim.step(15)
+    o = oracle_of(empty, dt, CE, CB)
+    o.step(15)
+    worst = compare_fields(sim, o, 2, TOL64, run=0)
+    bad = {k: v for k, v in worst.items() if v > TOL64}
+    assert not bad, bad
+    assert all(np.abs(sim.fields(c, m, 0)).max() == 0 for c in (pic.JR, pic.JPHI, pic.JZ, pic.RHO) for m in range(3))
+    assert np.abs(sim.fields(pic.EPHI, 1, 0)).max() > 0.1  # the laser is there
+    assert sim.particles(0)["z"].size == 0
+    mw = sim.mode_work(0)
+    assert mw["id"].size == 0 and mw["kinetic"] == 0.0
+    assert sim.divergence(1.0, 0)["count"] == 0
+    o = oracle_of(full, dt, CE, CB)
+    o.step(15)
+    worst = compare_fields(sim, o, 2, TOL64, run=1)
+    bad = {k: v for k, v in worst.items() if v > TOL64}
+    assert not bad, bad
+    dzmax, dxy, du, _ = compare_particles(sim, o, full["Nz"], run=1)
+    assert dzmax < TOL64 and dxy < TOL64 and du < TOL64, (dzmax, dxy, du)
+    sim.close()

@@ -80,3 +80,28 @@ def test_fp32_batched_restore_and_mismatch():
     assert np.array_equal(c.fields(2, 0, 0), before)
     for s in (a, b, c):
         s.close()
+
+
+def test_exact_jz_restore_and_mode_mismatch():
+    """A context with the exact J_z correction restores its own checkpoint
+    and continues like the original; a context that filters the current
+    instead refuses it."""
+    _say("[gpu] checkpoint exact J_z")
+    pic = _pic()
+    run = workloads.small(M=1, Nz=64, Nr=12, ppc=2, n_tracked=10)["runs"][0]
+    dt, CE, CB, _ = _setup(16, 1, run["dz"], run["dr"])
+    mk = lambda cur: pic.Simulation([workloads.to_rundesc(run)], dt=dt, coef_E=CE, coef_B=CB, sort_interval=4,
+                                    current=cur)
+    a = mk(pic.CURRENT_EXACT_JZ)
+    a.step(9)
+    blob = a.checkpoint()
+    a.step(6)
+    b = mk(pic.CURRENT_EXACT_JZ)
+    b.restore(blob)
+    b.step(6)
+    assert _max_rel(a, b) < 1e-12
+    c = mk(pic.CURRENT_FILTER)
+    with pytest.raises(pic.PicError):
+        c.restore(blob)
+    for s in (a, b, c):
+        s.close()
