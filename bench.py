@@ -199,7 +199,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=None,
                     help="timed steps (default 200; c4: each run its own count, at most --steps)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed steps first (default 20; c4: 8)")
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "dla"],
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "cv32", "cv128", "dla"],
                     help="c1..c5: the PIC step; dla: the reduced-model ensemble of Eq. (8)")
     ap.add_argument("--electrons", type=int, default=262144, help="dla: electrons in the ensemble")
     ap.add_argument("--cpu-steps", type=int, default=1, help="oracle steps for the CPU baseline (0: skip)")

@@ -64,6 +64,20 @@ def config(name: str) -> dict:
         return dict(name=name, runs=[run], precision=32, steps=5000,
                     desc="8192x512 r-z grid, modes 0..3, 16 ppc (~67M electrons), n=0.003 n_c, two pulses a0=3 "
                          "and 1.5 one plasma period apart")
+    if name in ("cv32", "cv128"):
+        # the cost comparison of converged runs (Sec. IV.B): the dual solver
+        # at about 30 points per wavelength against Yee at about 120 with half
+        # the electrons per cell; same box (256 x 16 lambda), same radial cell
+        ppl = 32 if name == "cv32" else 128
+        dz = LAMBDA0 / ppl
+        run = dict(Nz=256 * ppl, Nr=128, M=2, ppc=4 if ppl == 32 else 2, dz=dz, dr=LAMBDA0 / 8, n0=0.01,
+                   ramp_start=0.0, ramp_len=0.0,
+                   pulses=[dict(a0=1.0, w0=8 * LAMBDA0, tau=10 * LAMBDA0, zc=22 * LAMBDA0)], taper=2 * LAMBDA0,
+                   seed=SEED_BASE + 60, n_tracked=1000)
+        return dict(name=name, runs=[run], precision=32, steps=200,
+                    desc=f"{256 * ppl}x128 r-z grid ({ppl} points per lambda, dr = lambda/8), modes 0..2, "
+                         f"{run['ppc']} ppc: the {'dual' if ppl == 32 else 'Yee'} side of the converged-run cost "
+                         "comparison")
     raise KeyError(name)
 
 
