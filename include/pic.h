@@ -31,6 +31,11 @@
  * library never frees caller memory.  No C++ exception crosses this ABI;
  * every call returns PIC_OK (0) or a negative PIC_E_* code, and
  * pic_last_error() (thread local) describes the last failure.
+ *
+ * Threads: calls on different contexts may run on different threads at once
+ * (the state the library shares between contexts -- the registry of live
+ * contexts and the memo of fitted Courant limits -- is locked, and its
+ * per-launch caches are thread local); calls on one context must not overlap.
  */
 #ifndef PIC_H
 #define PIC_H

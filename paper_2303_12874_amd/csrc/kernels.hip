@@ -1635,19 +1635,23 @@ struct PushL {
     const KRun &k0 = b.run[0];
     const size_t lds = push_lds_bytes(M, k0.Tz, k0.Tr, prec_of<R>());
     // persistent grid: as many workgroups as are resident at once (a multiple
-    // of 8, one share per XCD), each walking its tiles
-    static size_t lds_seen = 0;
-    static long long resident = 0;
-    if (lds != lds_seen) {
-      int per_cu = 0, cus = 0, dev = 0;
+    // of 8, one share per XCD), each walking its tiles; the occupancy query
+    // is cached per thread for the last (device, LDS size)
+    static thread_local size_t lds_seen = 0;
+    static thread_local int dev_seen = -1;
+    static thread_local long long resident = 0;
+    int dev = 0;
+    if (int rc = check(hipGetDevice(&dev), "hipGetDevice")) return rc;
+    if (lds != lds_seen || dev != dev_seen) {
+      int per_cu = 0, cus = 0;
       int rc = check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, push_kernel<R, M>, 256, lds),
                      "hipOccupancyMaxActiveBlocksPerMultiprocessor");
-      if (!rc) rc = check(hipGetDevice(&dev), "hipGetDevice");
       if (!rc) rc = check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
       if (rc) return rc;
       resident = (long long)(per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
       resident = resident >= 8 ? resident & ~7LL : resident;
       lds_seen = lds;
+      dev_seen = dev;
     }
     const long long grid = b.off[b.n] < resident ? b.off[b.n] : resident;
     zero_kernel<<<1, 64, 0, s>>>((uint4 *)b.run[0].work, 1, nullptr, 0);  // tickets from 0

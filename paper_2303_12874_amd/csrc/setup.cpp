@@ -4,6 +4,7 @@
 #include "pic_internal.h"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -198,12 +199,14 @@ double radial_lambda(int m, int nr) {
 }
 
 double radial_lambda_max(int M) {
-  static double cache[PIC_MAX_MODES + 1] = {0, 0, 0, 0};
+  // every mode's eigenvalue, computed once (thread-safe static initialisation)
+  static const std::array<double, PIC_MAX_MODES + 1> lam = [] {
+    std::array<double, PIC_MAX_MODES + 1> v{};
+    for (int m = 0; m <= PIC_MAX_MODES; ++m) v[(size_t)m] = radial_lambda(m, 32);
+    return v;
+  }();
   double out = 0.0;
-  for (int m = 0; m <= M; ++m) {
-    if (cache[m] == 0.0) cache[m] = radial_lambda(m, 32);
-    out = std::max(out, cache[m]);
-  }
+  for (int m = 0; m <= M; ++m) out = std::max(out, lam[(size_t)m]);
   return out;
 }
 
