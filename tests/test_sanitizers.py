@@ -1,10 +1,14 @@
-"""Host code under AddressSanitizer and UndefinedBehaviorSanitizer (CPU only).
+"""Host code under AddressSanitizer, UndefinedBehaviorSanitizer and
+ThreadSanitizer (CPU only).
 
 The C oracle and the library's host set-up code (setup.cpp: coefficient fit,
 Courant limit, electron loading, laser fields) are built with gcc / g++ and
 -fsanitize=address,undefined, and driven over modes 0..3 by the small
 programs in tests/sanitize/.  Any out-of-bounds access, leak or undefined
-behaviour aborts the run.  (Device code is not built with sanitizers here.)
+behaviour aborts the run.  The host set-up code is also built with
+-fsanitize=thread and called from several threads at once, since contexts may
+be created on different threads.  (Device code is not built with sanitizers
+here.)
 """
 import os
 import shutil
@@ -16,12 +20,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SAN = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g", "-O1"]
 
 
-def _build_and_run(cmd, exe, tmp_path):
+def _build_and_run(cmd, exe, tmp_path, env_extra=None):
     if shutil.which(cmd[0]) is None:
         pytest.skip(f"{cmd[0]} not available")
     r = subprocess.run(cmd + ["-o", str(exe)], capture_output=True, text=True, timeout=600)
     assert r.returncode == 0, r.stderr[-3000:]
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1", UBSAN_OPTIONS="print_stacktrace=1")
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1", UBSAN_OPTIONS="print_stacktrace=1",
+               **(env_extra or {}))
     env.pop("LD_PRELOAD", None)
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=600, env=env)
     assert r.returncode == 0 and "runtime error" not in r.stderr, (r.returncode, r.stderr[-3000:])
@@ -40,3 +45,11 @@ def test_host_setup_under_sanitizers(tmp_path):
                           os.path.join(ROOT, "paper_2303_12874_amd", "csrc", "setup.cpp")], tmp_path / "host_run",
                          tmp_path)
     assert "host ok" in out
+
+
+def test_host_setup_from_threads_under_thread_sanitizer(tmp_path):
+    out = _build_and_run(["g++", "-std=c++17", "-fsanitize=thread", "-fno-omit-frame-pointer", "-g", "-O1", "-pthread",
+                          "-I", os.path.join(ROOT, "include"), os.path.join(ROOT, "tests", "sanitize", "host_threads.cpp"),
+                          os.path.join(ROOT, "paper_2303_12874_amd", "csrc", "setup.cpp")], tmp_path / "host_threads",
+                         tmp_path, {"TSAN_OPTIONS": "halt_on_error=1"})
+    assert "threads ok" in out
