@@ -10,6 +10,9 @@
   the filtered current (Eq. (10)) stays constant to within a bound derived
   from the FP32 arithmetic of the E update and of the push's radius, and the
   tracked work sums over modes to the change of gamma (Eq. (16)).
+* the six-run FP32 scan (34 M electrons, 24 x 8 tiles, sort every 16 steps,
+  captured-graph steps): the smallest run against the oracle at the FP32
+  bounds, every run against the same Gauss-law and work-identity checks.
 """
 import numpy as np
 import pytest
@@ -22,23 +25,7 @@ pytestmark = pytest.mark.gpu
 
 def _gauss(sim, pic, run, CB, taps, m):
     """div_B E - P rho of mode m from the library's arrays (interior rows)."""
-    N = CB.size
-    dz, dr, Nr = run["dz"], run["dr"], run["Nr"]
-    Er, Ep, Ez, rho = (sim.fields(c, m) for c in (pic.ER, pic.EPHI, pic.EZ, pic.RHO))
-    dbz = np.zeros_like(Ez)
-    for l in range(1, N + 1):
-        dbz += CB[l - 1] * (np.roll(Ez, -(l - 1), axis=1) - np.roll(Ez, l, axis=1))
-    dbz /= dz
-    prho = np.zeros_like(rho)
-    for l in range(-(N - 1), N):
-        prho += taps[l + N - 1] * np.roll(rho, -l, axis=1)
-    G = np.zeros_like(Er)
-    j = np.arange(1, Nr)[:, None]
-    G[1:Nr] = (dbz[1:Nr] + ((j + 0.5) * Er[1:Nr] - (j - 0.5) * Er[0:Nr - 1]) / (j * dr)
-               + 1j * m / (j * dr) * Ep[1:Nr] - prho[1:Nr])
-    if m == 0:
-        G[0] = dbz[0] + 4 * Er[0] / dr - prho[0]
-    return G, max(np.abs(Er).max(), np.abs(Ep).max(), np.abs(Ez).max())
+    return _gauss_run(sim, pic, run, CB, taps, m, 0)
 
 
 def test_fp64_4096x256_two_steps_match_oracle():
@@ -102,3 +89,82 @@ def test_fp32_8192x512_invariants():
     gmax = max(1.0, w["gamma"].max())
     assert np.abs(w["gamma_acc"] - w["gamma"]).max() <= 1e-6 * gmax
     sim.close()
+
+
+def test_fp32_six_run_scan_full_size_graph():
+    """The six-run FP32 scan (12..64 points per wavelength, 34 M electrons) in
+    the launch configuration of the benchmark (tile 24 x 8, sort every 16
+    steps) with captured-graph steps: four steps, then
+      * the smallest run (3072 x 48, 577 k electrons) against the FP64 oracle
+        from the same FP32-rounded start, at the FP32 per-quantity bounds;
+      * every run: Gauss's law with the filtered current drifts by no more
+        than the FP32 bound of the 8192 x 512 test, and the tracked work sums
+        over modes to the change of gamma."""
+    _say("[gpu] full size six-run scan fp32, graph")
+    from test_gpu_fp32 import EBTOL, JTOL
+    from test_gpu_parity import FIELD_PAIRS
+
+    pic = _pic()
+    cfg = workloads.config("c4")
+    runs = cfg["runs"]
+    sim = pic.Simulation([workloads.to_rundesc(r) for r in runs], precision=pic.PREC_FP32, tile_z=24, tile_r=8,
+                         sort_interval=16, use_graph=True)
+    nsteps = 4
+    G0 = []
+    for i, run in enumerate(runs):
+        CE, CB, taps = sim.coefficients(i)
+        G0.append([_gauss_run(sim, pic, run, CB, taps, m, i) for m in range(run["M"] + 1)])
+    sim.step(nsteps)
+    u = 2.0 ** -24
+    for i, run in enumerate(runs):
+        CE, CB, taps = sim.coefficients(i)
+        dt = sim.info(i)["dt"]
+        M, dz, dr = run["M"], run["dz"], run["dr"]
+        S = 2 * np.abs(CB).sum() / dz + 4 / dr + M / dr
+        rows = np.arange(run["Nr"] + 1)[:, None]
+        for m in range(M + 1):
+            G1, emax = _gauss_run(sim, pic, run, CB, taps, m, i)
+            jmax = max(np.abs(sim.fields(c, m, i)).max() for c in (pic.JR, pic.JPHI, pic.JZ))
+            rho_r = (rows * np.abs(sim.fields(pic.RHO, m, i))).max()
+            bound = nsteps * 2 * np.sqrt(2) * u * ((max(emax, G0[i][m][1]) + dt * jmax) * S
+                                                    + rho_r * np.abs(taps).sum())
+            dG = np.abs(G1 - G0[i][m][0]).max()
+            assert dG <= bound, (i, m, dG, bound)
+        w = sim.mode_work(i)
+        assert np.abs(w["gamma_acc"] - w["gamma"]).max() <= 1e-6 * max(1.0, w["gamma"].max()), i
+    # the smallest run against the oracle
+    run = runs[0]
+    CE, CB, _ = sim.coefficients(0)
+    o = oracle_of(run, sim.info(0)["dt"], CE, CB, fp32_start=True)
+    o.step(nsteps)
+    for name, comp, ocomp in FIELD_PAIRS:
+        for m in range(run["M"] + 1):
+            g, r = sim.fields(comp, m, 0), o.get_field(ocomp, m)
+            err = np.linalg.norm(g - r) / np.linalg.norm(r)
+            assert err <= (JTOL if name.startswith("J") else EBTOL), (name, m, err)
+    wg, wo = sim.mode_work(0), o.tracked()
+    assert np.array_equal(wg["id"], wo["id"])
+    gerr = np.abs(wg["gamma_acc"] - wo["gamma_acc"]) / np.maximum(wo["gamma_acc"] - 1.0, 1e-3)
+    assert np.percentile(gerr, 99) <= 1e-4 and gerr.max() <= 1e-3
+    sim.close()
+
+
+def _gauss_run(sim, pic, run, CB, taps, m, i):
+    """div_B E - P rho of mode m of run i from the library's arrays."""
+    N = CB.size
+    dz, dr, Nr = run["dz"], run["dr"], run["Nr"]
+    Er, Ep, Ez, rho = (sim.fields(c, m, i) for c in (pic.ER, pic.EPHI, pic.EZ, pic.RHO))
+    dbz = np.zeros_like(Ez)
+    for l in range(1, N + 1):
+        dbz += CB[l - 1] * (np.roll(Ez, -(l - 1), axis=1) - np.roll(Ez, l, axis=1))
+    dbz /= dz
+    prho = np.zeros_like(rho)
+    for l in range(-(N - 1), N):
+        prho += taps[l + N - 1] * np.roll(rho, -l, axis=1)
+    G = np.zeros_like(Er)
+    j = np.arange(1, Nr)[:, None]
+    G[1:Nr] = (dbz[1:Nr] + ((j + 0.5) * Er[1:Nr] - (j - 0.5) * Er[0:Nr - 1]) / (j * dr)
+               + 1j * m / (j * dr) * Ep[1:Nr] - prho[1:Nr])
+    if m == 0:
+        G[0] = dbz[0] + 4 * Er[0] / dr - prho[0]
+    return G, max(np.abs(Er).max(), np.abs(Ep).max(), np.abs(Ez).max())
