@@ -10,6 +10,8 @@
   the filtered current (Eq. (10)) stays constant to within a bound derived
   from the FP32 arithmetic of the E update and of the push's radius, and the
   tracked work sums over modes to the change of gamma (Eq. (16)).
+  Sampled outputs the oracle computes one by one: the gather and push of
+  3600 electrons from the library's own field and electron state.
 * the six-run FP32 scan (34 M electrons, 24 x 8 tiles, sort every 16 steps,
   captured-graph steps): the smallest run against the oracle at the FP32
   bounds, every run against the same Gauss-law and work-identity checks.
@@ -168,3 +170,65 @@ def _gauss_run(sim, pic, run, CB, taps, m, i):
     if m == 0:
         G[0] = dbz[0] + 4 * Er[0] / dr - prho[0]
     return G, max(np.abs(Er).max(), np.abs(Ep).max(), np.abs(Ez).max())
+
+
+def test_fp32_8192x512_sampled_push_matches_oracle():
+    """Sampled parity at full size: after two steps of the 8192 x 512 FP32 run
+    (67 M electrons, the benchmark's 16 x 4 tiles), the library's E^n and
+    time-averaged B^n are loaded into an FP64 oracle grid, and for 3600
+    sampled electrons (random ones, the closest to the axis, the most
+    energetic) the oracle's gather and Boris push (Eqs. (6), (12)) from the
+    electron's stored state are compared with the library's next step.  Both
+    start from the same FP32 values; the bounds are those of FP32 arithmetic
+    with a 10x margin: momenta within 1e-5 (|u| + dt |E| + 1e-3), the
+    transverse position within 1e-6 (|x| + 1) cells and z within 2e-6 cells
+    (its FP32 offset)."""
+    _say("[gpu] full size 8192x512 fp32, sampled push against the oracle")
+    import oracle
+
+    pic = _pic()
+    run = workloads.config("c5")["runs"][0]
+    sim = pic.Simulation([workloads.to_rundesc(run)], precision=pic.PREC_FP32, tile_z=16, tile_r=4,
+                         sort_interval=16)
+    sim.step(2)  # the next step sorts nothing: the storage order is kept
+    P0 = sim.particles()
+    Nz, Nr, M, dz, dr = run["Nz"], run["Nr"], run["M"], run["dz"], run["dr"]
+    CE, CB, _ = sim.coefficients()
+    dt = sim.info()["dt"]
+    o = oracle.Oracle(Nz, Nr, M, dz, dr, dt, CE, CB)
+    for m in range(M + 1):
+        for gc, oc in ((pic.ER, oracle.ER), (pic.EPHI, oracle.EP), (pic.EZ, oracle.EZ)):
+            o.set_field(oc, m, sim.fields(gc, m))
+        for gc, oo, on in ((pic.BR, oracle.BOR, oracle.BR), (pic.BPHI, oracle.BOP, oracle.BP),
+                           (pic.BZ, oracle.BOZ, oracle.BZ)):
+            b = sim.fields(gc, m)  # Bbar^n: both half steps set to it, so the oracle gathers it
+            o.set_field(oo, m, b)
+            o.set_field(on, m, b)
+    sim.step(1)
+    P1 = sim.particles()
+    assert np.array_equal(P0["id"], P1["id"])
+    rng = np.random.default_rng(2303)
+    r0 = np.hypot(P0["x"], P0["y"])
+    u0 = np.sqrt(P0["ux"] ** 2 + P0["uy"] ** 2 + P0["uz"] ** 2)
+    pick = np.unique(np.concatenate([rng.choice(P0["z"].size, 3000, replace=False), np.argsort(r0)[:300],
+                                     np.argsort(u0)[-300:]]))
+    pick = pick[r0[pick] < Nr - 3]  # away from the reflecting wall
+    lib = oracle.lib()
+    worst = {"u": 0.0, "xy": 0.0, "z": 0.0}
+    for p in pick:
+        EB = o.gather(P0["z"][p], P0["x"][p], P0["y"][p])
+        u = np.array([P0["ux"][p], P0["uy"][p], P0["uz"][p]])
+        E, B = np.ascontiguousarray(EB[:3]), np.ascontiguousarray(EB[3:])
+        lib.orc_boris(u.ctypes.data, E.ctypes.data, B.ctypes.data, dt)
+        g = np.sqrt(1.0 + u @ u)
+        x1, y1 = P0["x"][p] + dt * u[0] / g / dr, P0["y"][p] + dt * u[1] / g / dr
+        z1 = (P0["z"][p] + dt * u[2] / g / dz) % Nz
+        ug = np.array([P1["ux"][p], P1["uy"][p], P1["uz"][p]])
+        du = np.abs(ug - u).max() / (1e-5 * (np.abs(u).max() + dt * np.abs(E).max() + 1e-3))
+        dxy = max(abs(P1["x"][p] - x1), abs(P1["y"][p] - y1)) / (1e-6 * (max(abs(x1), abs(y1)) + 1))
+        dzc = abs(P1["z"][p] - z1)
+        dzc = min(dzc, Nz - dzc) / 2e-6
+        worst = {"u": max(worst["u"], du), "xy": max(worst["xy"], dxy), "z": max(worst["z"], dzc)}
+    _say(f"  {pick.size} electrons; worst error / bound: {worst}")
+    assert max(worst.values()) <= 1.0, worst
+    sim.close()
