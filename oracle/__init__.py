@@ -56,6 +56,7 @@ def lib():
             "orc_boris": (None, [p, p, p, d]),
             "orc_deposit_rho": (None, [p]),
             "orc_deposit_one": (None, [p, d, d, d, d, d, d, d, d]),
+            "orc_deposit_add": (None, [p, d, d, d, d, d, d, d, d]),
             "orc_step": (None, [p, i]),
             "orc_field_step": (None, [p, i]),
             "orc_start_fields": (None, [p]),
@@ -153,6 +154,10 @@ class Oracle:
 
     def deposit_one(self, q, p0, p1, vphi=0.0):
         lib().orc_deposit_one(self._h, q, *map(float, p0), *map(float, p1), float(vphi))
+
+    def deposit_add(self, q, p0, p1, vphi=0.0):
+        """Add one particle's move from p0 to p1 (z, x, y in cell units) to J."""
+        lib().orc_deposit_add(self._h, q, *map(float, p0), *map(float, p1), float(vphi))
 
     # --- particles ------------------------------------------------------
     @property

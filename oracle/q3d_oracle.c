@@ -647,9 +647,10 @@ void orc_deposit_rho(orc *o) { deposit_rho_all(o); }
 /* Charge-conserving current of one particle alone (for brute-force pins):
  * clears J, deposits the move (z0,x0,y0) -> (z1,x1,y1) with charge q and
  * azimuthal velocity vphi (used only where J_phi is deposited directly).    */
-void orc_deposit_one(orc *o, double q, double z0, double x0, double y0, double z1, double x1,
+/* Adds the current of one particle's move to o->J (orc_deposit_one clears
+ * the current first).                                                       */
+void orc_deposit_add(orc *o, double q, double z0, double x0, double y0, double z1, double x1,
                      double y1, double vphi) {
-  for (int c = 0; c < 3; ++c) memset(o->J[c], 0, o->nf * sizeof(cplx));
   double r20 = fma(x0, x0, y0 * y0), r0 = sqrt(r20);
   double r21 = fma(x1, x1, y1 * y1), r1 = sqrt(r21);
   int j0 = radial_index(r20, r0), j1 = radial_index(r21, r1);
@@ -660,6 +661,12 @@ void orc_deposit_one(orc *o, double q, double z0, double x0, double y0, double z
   double cm = 1, sm = 0;
   if (rm > 0) { cm = xm / rm; sm = ym / rm; }
   deposit_particle(o, q, z0, r0, j0, c0, s0, z1, r1, j1, c1, s1, vphi, cm, sm);
+}
+
+void orc_deposit_one(orc *o, double q, double z0, double x0, double y0, double z1, double x1,
+                     double y1, double vphi) {
+  for (int c = 0; c < 3; ++c) memset(o->J[c], 0, o->nf * sizeof(cplx));
+  orc_deposit_add(o, q, z0, x0, y0, z1, x1, y1, vphi);
 }
 
 /* ------------------------------------------------------------------------ */

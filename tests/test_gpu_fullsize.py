@@ -172,8 +172,8 @@ def _gauss_run(sim, pic, run, CB, taps, m, i):
     return G, max(np.abs(Er).max(), np.abs(Ep).max(), np.abs(Ez).max())
 
 
-def test_fp32_8192x512_sampled_push_matches_oracle():
-    """Sampled parity at full size: after two steps of the 8192 x 512 FP32 run
+def test_fp32_8192x512_sampled_step_matches_oracle():
+    """Sampled parity at full size, gather + push and deposit: after two steps of the 8192 x 512 FP32 run
     (67 M electrons, the benchmark's 16 x 4 tiles), the library's E^n and
     time-averaged B^n are loaded into an FP64 oracle grid, and for 3600
     sampled electrons (random ones, the closest to the axis, the most
@@ -182,7 +182,10 @@ def test_fp32_8192x512_sampled_push_matches_oracle():
     start from the same FP32 values; the bounds are those of FP32 arithmetic
     with a 10x margin: momenta within 1e-5 (|u| + dt |E| + 1e-3), the
     transverse position within 1e-6 (|x| + 1) cells and z within 2e-6 cells
-    (its FP32 offset)."""
+    (its FP32 offset).  The deposit of the same step is checked on node
+    patches (below) within 1e-5 of the largest current there: each
+    electron's FP32 offset difference is exact to ~2^-24 cells, and a node
+    sums a few hundred of them."""
     _say("[gpu] full size 8192x512 fp32, sampled push against the oracle")
     import oracle
 
@@ -231,4 +234,32 @@ def test_fp32_8192x512_sampled_push_matches_oracle():
         worst = {"u": max(worst["u"], du), "xy": max(worst["xy"], dxy), "z": max(worst["z"], dzc)}
     _say(f"  {pick.size} electrons; worst error / bound: {worst}")
     assert max(worst.values()) <= 1.0, worst
+
+    # the deposit of that step on 12 patches of 8 x 6 nodes (two on the axis):
+    # every electron whose old cell is within reach of a patch is deposited
+    # by the oracle from the library's own old and new states, and the current
+    # on the patch is compared with the library's J of the step
+    z0, z1 = P0["z"], P1["z"].copy()
+    z1 += np.where(z1 - z0 > Nz / 2, -Nz, 0.0) + np.where(z1 - z0 < -Nz / 2, Nz, 0.0)  # undo the periodic wrap
+    i0, j0 = np.floor(z0).astype(np.int64), np.floor(r0).astype(np.int64)
+    patches = [(300 + 650 * k, rs) for k, rs in enumerate((0, 0, 40, 120, 200, 300, 400, 480, 60, 250, 350, 10))]
+    for zs, rs in patches:
+        sel = np.nonzero((i0 >= zs - 3) & (i0 <= zs + 7 + 2) & (j0 >= rs - 3) & (j0 <= rs + 5 + 2))[0]
+        for p in sel:
+            xm, ym = 0.5 * (P0["x"][p] + P1["x"][p]), 0.5 * (P0["y"][p] + P1["y"][p])
+            rm = np.hypot(xm, ym)
+            u1 = np.array([P1["ux"][p], P1["uy"][p], P1["uz"][p]])
+            vphi = (xm / rm * u1[1] - ym / rm * u1[0]) / np.sqrt(1.0 + u1 @ u1) if rm > 0 else 0.0
+            o.deposit_add(-P0["w"][p], (z0[p], P0["x"][p], P0["y"][p]), (z1[p], P1["x"][p], P1["y"][p]), vphi)
+    jworst = 0.0
+    for gc, oc in ((pic.JR, oracle.JR), (pic.JPHI, oracle.JP), (pic.JZ, oracle.JZ)):
+        for m in range(M + 1):
+            g, r = sim.fields(gc, m), o.get_field(oc, m)
+            if gc == pic.JZ and m >= 1:
+                r[0] = 0.0  # the m >= 1 J_z vanishes on the axis
+            gp = np.concatenate([g[rs:rs + 6, zs:zs + 8].ravel() for zs, rs in patches])
+            rp = np.concatenate([r[rs:rs + 6, zs:zs + 8].ravel() for zs, rs in patches])
+            jworst = max(jworst, np.abs(gp - rp).max() / (1e-5 * np.abs(rp).max()))
+    _say(f"  deposit on {len(patches)} patches: worst error / (1e-5 max|J|) = {jworst:.3f}")
+    assert jworst <= 1.0, jworst
     sim.close()
