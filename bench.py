@@ -202,7 +202,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "cv32", "cv128", "dla"],
                     help="c1..c5: the PIC step; dla: the reduced-model ensemble of Eq. (8)")
     ap.add_argument("--electrons", type=int, default=262144, help="dla: electrons in the ensemble")
-    ap.add_argument("--cpu-steps", type=int, default=1, help="oracle steps for the CPU baseline (0: skip)")
+    ap.add_argument("--cpu-steps", type=int, default=None,
+                    help="oracle steps for the CPU baseline (0: skip; default: about 10-30 s of host work)")
     ap.add_argument("--sort-interval", type=int, default=0)
     ap.add_argument("--tile-z", type=int, default=0, help="sort tile extent in z (0: library default)")
     ap.add_argument("--tile-r", type=int, default=0, help="sort tile extent in r (0: library default)")
@@ -216,6 +217,8 @@ def main(argv=None):
     ap.add_argument("--current", default="filter", choices=["filter", "exact"],
                     help="charge conservation with D_B: z filter on J_r, J_phi (default) or P^-1 on J_z")
     args = ap.parse_args(argv)
+    if args.cpu_steps is None:  # a bounded oracle sample of about 10-30 s on one host core
+        args.cpu_steps = {"c1": 200, "c3": 200, "c2": 3, "c4": 1, "c5": 1, "cv32": 3, "cv128": 1, "dla": 1}[args.workload]
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}), flush=True)
         return 2
