@@ -46,6 +46,13 @@ constexpr BesselSeries make_bessel_series() {
   return c;
 }
 
+// J0 and J1 beyond the series' range (electrons outside the bubble), out of
+// line so that the main path is not allocated around the library's code
+__device__ __noinline__ void bessel_far(double s, double *a, double *b) {
+  *a = j0(s);
+  *b = j1(s);
+}
+
 // d/dt (x, zeta, xd, zetad) at time t
 __device__ __forceinline__ void dla_rhs(const Model &m, double t, const double y[4], double d[4]) {
   const double x = y[0], zeta = y[1], u = y[2], w = y[3];
@@ -70,8 +77,7 @@ __device__ __forceinline__ void dla_rhs(const Model &m, double t, const double y
     j1v = b * s;
     j1p = a - b;
   } else {
-    j0v = j0(s);
-    j1v = j1(s);
+    bessel_far(s, &j0v, &j1v);
     j1p = j0v - j1v / s;
   }
   const double amp = m.a0 * ig;
