@@ -99,6 +99,23 @@ DLA_FLOPS_PER_STEP = 6 * 48 + 170
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 
+def work_split(sim, M: int) -> dict:
+    """Energy gain of the tracked electrons of run 0 split by azimuthal mode
+    (Eq. (16)): m = 0 is the wake's work, m = 1 the laser's.  Sums over all
+    tracked electrons and over the 1% with the largest gamma."""
+    import numpy as np
+
+    w = sim.mode_work(0)
+    W, g = w["W"], w["gamma"]
+    top = np.argsort(g)[-max(1, g.size // 100):]
+    return {"tracked": int(g.size), "steps": int(sim.info(0)["steps_done"]),
+            "gamma_max": float(g.max()), "gamma_mean": float(g.mean()),
+            "W_sum_by_mode": [float(v) for v in W.sum(axis=0)],
+            "top1pct": {"gamma_min": float(g[top].min()), "W_mean_by_mode": [float(v) for v in W[top].mean(axis=0)],
+                        "laser_share": float(W[top, 1].sum() / max(W[top].sum(), 1e-300)) if M >= 1 else 0.0},
+            "identity_max_err": float(np.abs(w["gamma_acc"] - g).max())}
+
+
 def copy_bandwidth(torch, dev, nbytes: int = 1 << 30, reps: int = 10) -> float:
     """Achievable HBM bandwidth on this device (GB/s): a device-to-device copy
     of nbytes (read + write counted), timed with events over `reps` copies
@@ -216,6 +233,8 @@ def main(argv=None):
                     help="field solver: dual (16 coefficients per operator) or Yee (one)")
     ap.add_argument("--current", default="filter", choices=["filter", "exact"],
                     help="charge conservation with D_B: z filter on J_r, J_phi (default) or P^-1 on J_z")
+    ap.add_argument("--work-split", action="store_true",
+                    help="after the timed steps, report the tracked electrons' energy gain split by mode (Eq. (16))")
     args = ap.parse_args(argv)
     if args.cpu_steps is None:  # a bounded oracle sample of about 10-30 s on one host core
         args.cpu_steps = {"c1": 200, "c3": 200, "c2": 3, "c4": 1, "c5": 1, "cv32": 3, "cv128": 1, "dla": 1}[args.workload]
@@ -361,6 +380,8 @@ def main(argv=None):
         "kernels": kernels,
         "state_finite": finite,
     }
+    if args.work_split:
+        out["work_split"] = work_split(sim, run["M"])
     sim.close()
     del sim
     torch.cuda.empty_cache()
