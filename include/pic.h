@@ -186,8 +186,9 @@ int pic_courant_limit(int32_t n_coef, const double *coef_E, const double *coef_B
 /* The inverse of the z filter P of coef_B (n_coef values) as a symmetric
  * stencil: taps[l] = h_l = h_{-l}, l = 0..*n_taps-1, with
  * sum_l h_l p_{k-l} = delta_k on the infinite line.  h is the Fourier
- * series of 1/P(k), P(k) = sum_l p_l cos(l k dz), computed in FP64 from 8192
- * samples of P, and cut after the last tap above 2^-53 (precision
+ * series of 1/P(k), P(k) = sum_l p_l cos(l k dz), summed in the host's
+ * extended precision over 8192 samples of P and rounded to FP64, and cut
+ * after the last tap above 2^-53 (precision
  * PIC_PREC_FP64) or 2^-24 (PIC_PREC_FP32) times h_0: the taps decay
  * geometrically, so the cut changes P^{-1} by about that fraction, and on a
  * periodic line of any length the stencil (wrapped) is P^{-1} to that
@@ -210,7 +211,11 @@ int pic_load_host(const pic_run_desc *run, double *z, double *x, double *y, doub
  * into device_workspace on hip_stream.  With device_workspace == NULL only
  * *workspace_bytes is written (size query, no device call).  Otherwise
  * *workspace_bytes must be at least the queried size; the buffer must stay
- * allocated until pic_destroy.  *out receives the context.                   */
+ * allocated until pic_destroy.  *out receives the context.  Errors:
+ * PIC_E_INVALID for a bad descriptor or option (with PIC_CURRENT_EXACT_JZ
+ * also when a run's filter has no inverse stencil, see pic_jz_inverse_taps),
+ * PIC_E_CFL for a dt above the Courant limit of the coefficients,
+ * PIC_E_NOMEM for a short workspace, PIC_E_DEVICE for a failed HIP call.    */
 int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts,
              void *device_workspace, size_t *workspace_bytes, void *hip_stream, pic_ctx **out);
 
