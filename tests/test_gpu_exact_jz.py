@@ -147,3 +147,23 @@ def test_fp32_exact_jz_per_quantity_bounds():
     gerr = np.abs(wg["gamma_acc"] - wo["gamma_acc"]) / scale
     assert np.percentile(gerr, 99) <= 1e-4 and gerr.max() <= 1e-3
     sim.close()
+
+
+@pytest.mark.parametrize("M", [0, 2, 3])
+def test_fp32_exact_jz_small_grid_bounds(M):
+    """The FP32 instantiations of the other mode counts, 70 columns, 40 steps,
+    at the FP32 per-quantity bounds."""
+    _say(f"[gpu] exact J_z fp32 M={M}")
+    pic = _pic()
+    run = workloads.small(M=M, Nz=70, Nr=12, ppc=2, n_tracked=40)["runs"][0]
+    sim, o = _pair(run, 40, precision=pic.PREC_FP32)
+    for name, comp, ocomp in FIELD_PAIRS:
+        for m in range(M + 1):
+            g, r = sim.fields(comp, m), o.get_field(ocomp, m)
+            nr = np.linalg.norm(r)
+            err = np.linalg.norm(g - r) / nr if nr > 0 else np.linalg.norm(g)
+            assert err <= (JTOL if name.startswith("J") else EBTOL), (name, m, err)
+    wg, wo = sim.mode_work(), o.tracked()
+    gerr = np.abs(wg["gamma_acc"] - wo["gamma_acc"]) / np.maximum(wo["gamma_acc"] - 1.0, 1e-3)
+    assert gerr.max() <= 1e-3
+    sim.close()

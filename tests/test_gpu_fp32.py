@@ -65,7 +65,10 @@ def fp32_errors(run, nsteps, sort_interval=0):
     dg, rs = sim.divergence(1.0), beam.divergence(pg, 1.0)
     assert dg["count"] == rs["count"]
     for k in ("w", "sum_wtx2", "sum_wty2"):
-        assert abs(dg[k] / rs[k] - 1) < 1e-12, k
+        if rs["count"] == 0:  # nothing selected (no laser: the cold plasma has no forward electron)
+            assert dg[k] == 0.0 and rs[k] == 0.0, k
+        else:
+            assert abs(dg[k] / rs[k] - 1) < 1e-12, k
     sim.close()
     return field_err, gerr, werr, wtol
 
@@ -84,7 +87,7 @@ def test_fp32_config3_per_quantity_bounds():
     assert np.all(werr <= wtol)
 
 
-@pytest.mark.parametrize("M", [2, 3])
+@pytest.mark.parametrize("M", [0, 2, 3])
 def test_fp32_small_grid_bounds(M):
     _say(f"[gpu] fp32 small grid M={M}")
     run = workloads.small(M=M, Nz=64, Nr=12, ppc=2, n_tracked=40)["runs"][0]
