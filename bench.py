@@ -71,6 +71,13 @@ def measured_traffic(workload: str, kernel: str, tile: str, sort_interval: int, 
     return None if e is None else e["read_bytes"] + e["write_bytes"]
 
 
+# default oracle steps of the CPU baseline per workload: a bounded sample of
+# about 10-30 s on one host core (one step of the 67 M-electron run is the
+# smallest whole-step sample, about 47 s)
+CPU_STEPS = {"c1": 200, "c3": 200, "c2": 3, "c4": 1, "c5": 1, "cv32": 3, "cv128": 1, "dla": 1}
+WORKLOADS = ("c1", "c2", "c3", "c4", "c5", "cv32", "cv128", "dla")
+
+
 def cpu_baseline(runs: list, nsteps: int, n_coef: int = 16) -> dict:
     """FP64 oracle (as it stands) on the host: nsteps full steps of every run."""
     import oracle
@@ -216,7 +223,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=None,
                     help="timed steps (default 200; c4: each run its own count, at most --steps)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed steps first (default 20; c4: 8)")
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "cv32", "cv128", "dla"],
+    ap.add_argument("--workload", default="c2", choices=WORKLOADS,
                     help="c1..c5: the PIC step; dla: the reduced-model ensemble of Eq. (8)")
     ap.add_argument("--electrons", type=int, default=262144, help="dla: electrons in the ensemble")
     ap.add_argument("--cpu-steps", type=int, default=None,
@@ -236,8 +243,8 @@ def main(argv=None):
     ap.add_argument("--work-split", action="store_true",
                     help="after the timed steps, report the tracked electrons' energy gain split by mode (Eq. (16))")
     args = ap.parse_args(argv)
-    if args.cpu_steps is None:  # a bounded oracle sample of about 10-30 s on one host core
-        args.cpu_steps = {"c1": 200, "c3": 200, "c2": 3, "c4": 1, "c5": 1, "cv32": 3, "cv128": 1, "dla": 1}[args.workload]
+    if args.cpu_steps is None:
+        args.cpu_steps = CPU_STEPS[args.workload]
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}), flush=True)
         return 2
