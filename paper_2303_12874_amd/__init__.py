@@ -79,8 +79,7 @@ class _TuneReport(C.Structure):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (or python -m "
-                          "paper_2303_12874_amd.build)")
+        raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2303_12874_amd.build")
     # The device memory and streams the library is handed come from torch, so
     # it must bind to the HIP runtime torch loads: load torch first, or the
     # dynamic linker picks the system runtime and the process holds two.
