@@ -356,3 +356,25 @@ def test_fp64_edge_case_largest_operators_ragged_grid_no_tracking():
     assert w["W"].shape == (0, 4) and w["id"].size == 0
     assert all(v.size == 0 for v in sim.cartesian_work().values())
     sim.close()
+
+
+def test_fp64_smallest_grid_and_all_electrons_tracked():
+    """The smallest grid the library accepts (Nz = 2N = 32 columns, so the
+    16-coefficient stencils reach round the whole periodic line; Nr = 4, one
+    tile row, electrons loaded in the three cells below the reflecting
+    radius) with every electron tracked: fields, electrons and every
+    electron's work against the oracle at the FP64 bar."""
+    _say("[gpu] fp64 smallest grid, all electrons tracked")
+    run = workloads.small(M=1, Nz=32, Nr=4, ppc=3, n_tracked=0)["runs"][0]
+    run["n_tracked"] = 32 * 3 * 3
+    sim, o = run_pair(run, 25)
+    worst = compare_fields(sim, o, run["M"], TOL64)
+    bad = {k: v for k, v in worst.items() if v > TOL64}
+    assert not bad, bad
+    dzmax, dxy, du, _ = compare_particles(sim, o, run["Nz"])
+    assert dzmax < TOL64 and dxy < TOL64 and du < TOL64, (dzmax, dxy, du)
+    wg, wo = sim.mode_work(), o.tracked()
+    assert wg["id"].size == run["n_tracked"] and np.array_equal(wg["id"], wo["id"])
+    assert np.abs(wg["W"] - wo["W"]).max() <= TOL64 * max(np.abs(wo["W"]).max(), 1e-300)
+    assert np.abs(wg["gamma_acc"] - wg["gamma"]).max() < 1e-13 * max(1.0, wg["gamma"].max())
+    sim.close()
