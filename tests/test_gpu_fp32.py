@@ -97,3 +97,14 @@ def test_fp32_small_grid_bounds(M):
     check_fields(field_err)
     assert gerr.max() <= 1e-3
     assert np.all(werr <= wtol)
+
+
+def test_fp32_smallest_grid_bounds():
+    """The smallest grid accepted (32 x 4) in FP32, every electron tracked."""
+    _say("[gpu] fp32 smallest grid")
+    run = workloads.small(M=1, Nz=32, Nr=4, ppc=3, n_tracked=0)["runs"][0]
+    run["n_tracked"] = 32 * 3 * 3
+    field_err, gerr, werr, wtol = fp32_errors(run, 25)
+    check_fields(field_err)
+    assert gerr.max() <= 1e-3
+    assert np.all(werr <= wtol)
