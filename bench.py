@@ -3,16 +3,21 @@
 One bench step = one time step of the whole hot path (cell sort when due,
 gather + push + deposit, E update with the filtered current, B update) on a
 synthetic LWFA-shaped plasma, with every input resident in HBM.  Prints one
-JSON line.  The default workload is the 4096 x 256, modes 0..2, 8 ppc FP64
-run; --workload c5 selects the 8192 x 512, modes 0..3, 16 ppc FP32 run, and
---workload c4 the six-run FP32 convergence scan (12..64 points per
-wavelength) stepped as one batch, each run for its own number of steps.
+JSON line.  The default workload is the largest single-GPU one: the 8192 x
+512, modes 0..3, 16 ppc FP32 run (67 M electrons, tile and sort interval from
+the library's autotuner); after its timed region the plain FP64 path is timed
+on the same workload, and the FP32 state's difference from the FP64 state
+after the same steps is reported beside the FP32 bounds the tests hold
+against the FP64 oracle.  --workload c2 selects the 4096 x 256, modes 0..2,
+8 ppc FP64 run, --workload c4 the six-run FP32 convergence scan (12..64
+points per wavelength) stepped as one batch, each run for its own number of
+steps.
 
 Per-kernel durations come from HIP events the library records around each
 launch on its own stream (pic_profile); the roofline object prices the
 dominant kernel's algorithmic bytes against the MI355X HBM peak.  The CPU
 baseline times the FP64 oracle (test infrastructure) on a bounded sample of
-the same workload on the host.
+the same workload on the host, on one core and on every usable core.
 """
 from __future__ import annotations
 
@@ -71,31 +76,116 @@ def measured_traffic(workload: str, kernel: str, tile: str, sort_interval: int, 
     return None if e is None else e["read_bytes"] + e["write_bytes"]
 
 
-# default oracle steps of the CPU baseline per workload: a bounded sample of
-# about 10-30 s on one host core (one step of the 67 M-electron run is the
-# smallest whole-step sample, about 47 s)
-CPU_STEPS = {"c1": 200, "c3": 200, "c2": 3, "c4": 1, "c5": 1, "cv32": 3, "cv128": 1, "dla": 1}
 WORKLOADS = ("c1", "c2", "c3", "c4", "c5", "cv32", "cv128", "dla")
 
 
-def cpu_baseline(runs: list, nsteps: int, n_coef: int = 16) -> dict:
-    """FP64 oracle (as it stands) on the host: nsteps full steps of every run."""
-    import oracle
+def _oracle_sample(workload: str, n_coef: int) -> tuple:
+    """The serial FP64 oracle over the workload's bounded CPU sample
+    (workloads.cpu_sample): (particle-steps, seconds of stepping)."""
+    import oracle  # noqa: F401  (test infrastructure: the CPU baseline only)
     from oracle import coef
 
+    smp = workloads.cpu_sample(workload)
     tot, el = 0, 0.0
-    for run in runs:
+    for run in smp["runs"]:
         dt, CE, CB, _ = coef.solver_setup(n_coef, run["M"], run["dz"], run["dr"])
         o = workloads.to_oracle(run, dt, CE, CB)
         t0 = time.perf_counter()
-        o.step(nsteps)
+        o.step(smp["steps"])
         el += time.perf_counter() - t0
-        tot += o.np * nsteps
+        tot += o.np * smp["steps"]
         del o
-    what = "the same run" if len(runs) == 1 else f"each of the {len(runs)} runs"
-    return {"value": tot / el, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nsteps} full step(s) of {what} ({tot // nsteps} electrons), serial C oracle, "
-                      f"setup excluded, {el:.1f} s"}
+    return tot, el
+
+
+def host_cpu() -> tuple:
+    """(usable host cores, CPU model name)"""
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return cores, model
+
+
+def cpu_baseline(workload: str, n_coef: int = 16, max_procs: int = 16) -> dict:
+    """The FP64 oracle as it stands (serial C) on the workload's bounded
+    sample: once on one core, then as one process per usable host core (at
+    most max_procs), all running the same sample at once; the all-core value
+    is their summed particle-steps over the wall time of the slowest."""
+    cores, model = host_cpu()
+    smp = workloads.cpu_sample(workload)
+    tot1, el1 = _oracle_sample(workload, n_coef)
+    one = {"value": tot1 / el1, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+           "sample": f"{smp['desc']}: {tot1} particle-steps, serial C oracle, setup excluded, {el1:.1f} s",
+           "cpu": model}
+    nproc = max(1, min(cores, max_procs))
+    if nproc == 1:
+        return dict(one, all_cores=dict(one))
+    import subprocess
+
+    cmd = [sys.executable, os.path.abspath(__file__), "--oracle-sample", workload, "--n-coef", str(n_coef)]
+    procs = [subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, text=True,
+                              env=dict(os.environ, OMP_NUM_THREADS="1")) for _ in range(nproc)]
+    res = []
+    for p in procs:
+        out, _ = p.communicate()
+        if p.returncode != 0:
+            raise RuntimeError(f"oracle sample process failed ({p.returncode})")
+        res.append(json.loads(out.strip().splitlines()[-1]))
+    tot = sum(r["particle_steps"] for r in res)
+    wall = max(r["seconds"] for r in res)
+    one["all_cores"] = {"value": tot / wall, "unit": "particle-steps/s", "cores": nproc, "kind": "oracle",
+                        "sample": f"{nproc} concurrent processes of the serial oracle, each on the same sample "
+                                  f"({smp['desc']}); summed particle-steps over the slowest one's "
+                                  f"{wall:.1f} s of stepping",
+                        "cpu": model, "host_cores": cores}
+    return one
+
+
+# The FP32 form's error bounds against the FP64 oracle (started from the same
+# FP32-rounded state), as the GPU tests hold them: per field array and mode
+# (relative L2), per tracked electron (gamma, relative to max(gamma - 1,
+# 1e-3)) and per mode (work).
+FP32_BOUNDS = {"E_B_l2": 1e-4, "J_l2": 3e-4, "tracked_gamma_p99": 1e-4, "tracked_gamma_max": 1e-3,
+               "mode_work": "1e-3 max_p |W_m| + 1e-7",
+               "held_by": "tests/test_gpu_fp32.py (256x64, 100 steps), tests/test_gpu_fullsize.py (8192x512 prefix, "
+                          "six-run scan), tests/test_gpu_vs_stored_oracle.py"}
+
+
+def fp32_vs_fp64(pic, s32, s64, run: dict) -> dict:
+    """Difference of the FP32 state from the FP64 state of the same workload
+    after the same steps (run 0): relative L2 of every E, Bbar and J array
+    and mode, and the tracked electrons' gamma and per-mode work."""
+    import numpy as np
+
+    comps = [("E_r", pic.ER), ("E_phi", pic.EPHI), ("E_z", pic.EZ), ("Bbar_r", pic.BR), ("Bbar_phi", pic.BPHI),
+             ("Bbar_z", pic.BZ), ("J_r", pic.JR), ("J_phi", pic.JPHI), ("J_z", pic.JZ)]
+    l2 = {}
+    for name, c in comps:
+        for m in range(run["M"] + 1):
+            a, b = s32.fields(c, m), s64.fields(c, m)
+            nb = np.linalg.norm(b)
+            l2[f"{name}/m{m}"] = float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
+    w32, w64 = s32.mode_work(0), s64.mode_work(0)
+    ok = bool(np.array_equal(w32["id"], w64["id"]))
+    g = np.abs(w32["gamma_acc"] - w64["gamma_acc"]) / np.maximum(w64["gamma_acc"] - 1.0, 1e-3)
+    wtol = 1e-3 * np.abs(w64["W"]).max(axis=0) + 1e-7
+    eb = {k: v for k, v in l2.items() if not k.startswith("J")}
+    jj = {k: v for k, v in l2.items() if k.startswith("J")}
+    return {"steps": int(s32.info(0)["steps_done"]), "field_l2": l2,
+            "E_B_l2_worst": max(eb.values()), "J_l2_worst": max(jj.values()),
+            "tracked_ids_equal": ok, "tracked_gamma_p99": float(np.percentile(g, 99)) if g.size else 0.0,
+            "tracked_gamma_max": float(g.max()) if g.size else 0.0,
+            "mode_work_max_over_tol": float((np.abs(w32["W"] - w64["W"]) / wtol).max()) if g.size else 0.0}
 
 
 # FP64 operations of one Runge-Kutta step of Eq. (8), not counting the three
@@ -200,13 +290,13 @@ def bench_dla(args, torch, pic) -> int:
                      "flops_per_step": DLA_FLOPS_PER_STEP, "avg_launch_ms": avg},
         "state_finite": finite, "max_gamma": float(g.max().item()),
     }
-    if args.cpu_steps > 0:
+    if args.cpu_baseline:
         from oracle import dla
 
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         m = 4096
         y0 = np.stack([d[k][:m] for k in ("x", "zeta", "xd", "zetad")])
-        nst = 10000 * args.cpu_steps  # about 12 s of host time per unit
+        nst = 10000  # about 12 s of host time
         t0 = time.perf_counter()
         dla.integrate(dla.params(), np.zeros(m), y0, nst * h, h)
         el = time.perf_counter() - t0
@@ -223,11 +313,16 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=None,
                     help="timed steps (default 200; c4: each run its own count, at most --steps)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed steps first (default 20; c4: 8)")
-    ap.add_argument("--workload", default="c2", choices=WORKLOADS,
+    ap.add_argument("--workload", default="c5", choices=WORKLOADS,
                     help="c1..c5: the PIC step; dla: the reduced-model ensemble of Eq. (8)")
     ap.add_argument("--electrons", type=int, default=262144, help="dla: electrons in the ensemble")
-    ap.add_argument("--cpu-steps", type=int, default=None,
-                    help="oracle steps for the CPU baseline (0: skip; default: about 10-30 s of host work)")
+    ap.add_argument("--cpu-baseline", type=int, default=1,
+                    help="1: time the oracle on the workload's bounded sample, on one core and on all host cores")
+    ap.add_argument("--fp64-beside", type=int, default=None,
+                    help="FP32 workloads: 1 also times the FP64 path on the same workload and reports the FP32 "
+                         "result's difference from it (default on for FP32 runs)")
+    ap.add_argument("--oracle-sample", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--n-coef", type=int, default=16, help=argparse.SUPPRESS)
     ap.add_argument("--sort-interval", type=int, default=0)
     ap.add_argument("--tile-z", type=int, default=0, help="sort tile extent in z (0: library default)")
     ap.add_argument("--tile-r", type=int, default=0, help="sort tile extent in r (0: library default)")
@@ -243,10 +338,13 @@ def main(argv=None):
     ap.add_argument("--work-split", action="store_true",
                     help="after the timed steps, report the tracked electrons' energy gain split by mode (Eq. (16))")
     args = ap.parse_args(argv)
-    if args.cpu_steps is None:
-        args.cpu_steps = CPU_STEPS[args.workload]
+    if args.oracle_sample:  # a child process of the all-core CPU baseline: no GPU is touched
+        tot, el = _oracle_sample(args.oracle_sample, args.n_coef)
+        print(json.dumps({"particle_steps": tot, "seconds": el}), flush=True)
+        return 0
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}), flush=True)
+        print(json.dumps({"error": "this benchmark runs on one GPU only (--gpus 1); the multi-GPU sharding of "
+                                   "the path is a design, not built"}), flush=True)
         return 2
 
     import torch
@@ -281,43 +379,50 @@ def main(argv=None):
               f"{args.sort_interval}; {tune['candidates']}", file=sys.stderr, flush=True)
     sort_k = args.sort_interval or 8
 
-    def make(limits):
-        return pic.Simulation([workloads.to_rundesc(r, n_steps=n) for r, n in zip(runs, limits)], precision=prec,
-                              solver=solver, n_coef=n_coef, sort_interval=args.sort_interval, tile_z=args.tile_z, tile_r=args.tile_r,
-                              use_graph=args.graph, current=current, device="cuda:0")
+    def timed(prec_, tile_z, tile_r, sort_interval):
+        """Build the job (multi-run jobs warm up on a context of their own, so
+        that the timed job starts at step 0), take W untimed steps (single
+        run), then time K steps with HIP events on the library's stream."""
+        def make(limits):
+            return pic.Simulation([workloads.to_rundesc(r, n_steps=n) for r, n in zip(runs, limits)],
+                                  precision=prec_, solver=solver, n_coef=n_coef, sort_interval=sort_interval,
+                                  tile_z=tile_z, tile_r=tile_r, use_graph=args.graph, current=current,
+                                  device="cuda:0")
 
-    if multi:  # warm up on a context of its own, so that the timed job starts at step 0
-        warm = make([0] * len(runs))
-        warm.step(W)
+        if multi:
+            warm = make([0] * len(runs))
+            warm.step(W)
+            torch.cuda.synchronize()
+            warm.close()
+            del warm
+            torch.cuda.empty_cache()
+        t_init = time.perf_counter()
+        sim_ = make(per_run if multi else [0])
         torch.cuda.synchronize()
-        warm.close()
-        del warm
-        torch.cuda.empty_cache()
-    t_init = time.perf_counter()
-    sim = make(per_run if multi else [0])
-    torch.cuda.synchronize()
-    t_init = time.perf_counter() - t_init
-    infos = [sim.info(i) for i in range(len(runs))]
+        t_init = time.perf_counter() - t_init
+        infos_ = [sim_.info(i) for i in range(len(runs))]
+        print(f"# fp{prec_} init {t_init:.1f} s, {sum(i['n_particles'] for i in infos_)} electrons in {len(runs)} "
+              f"run(s), dt {[round(i['dt'], 5) for i in infos_]}", file=sys.stderr, flush=True)
+        if not multi:
+            sim_.step(W)
+            torch.cuda.synchronize()
+        print(f"# fp{prec_} warmup {W} steps done", file=sys.stderr, flush=True)
+        sim_.profile(True)
+        stream = torch.cuda.current_stream(dev)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        sim_.step(K)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_ = ev0.elapsed_time(ev1)
+        phases_ = sim_.profile_read()
+        sim_.profile(False)
+        print(f"# fp{prec_} timed {K} steps: {ms_:.2f} ms", file=sys.stderr, flush=True)
+        return sim_, ms_, phases_, infos_
+
+    sim, elapsed_ms, phases, infos = timed(prec, args.tile_z, args.tile_r, args.sort_interval)
     nps = [inf["n_particles"] for inf in infos]
-    print(f"# init {t_init:.1f} s, {sum(nps)} electrons in {len(runs)} run(s), dt {[round(i['dt'], 5) for i in infos]}",
-          file=sys.stderr, flush=True)
-    if not multi:
-        sim.step(W)
-        torch.cuda.synchronize()
-    print(f"# warmup {W} steps done", file=sys.stderr, flush=True)
-
-    sim.profile(True)
-    stream = torch.cuda.current_stream(dev)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    sim.step(K)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    elapsed_ms = ev0.elapsed_time(ev1)
-    phases = sim.profile_read()
-    sim.profile(False)
-    print(f"# timed {K} steps: {elapsed_ms:.2f} ms", file=sys.stderr, flush=True)
 
     # sanity of the state after the run (FP64 reductions)
     finite = True
@@ -389,15 +494,29 @@ def main(argv=None):
     }
     if args.work_split:
         out["work_split"] = work_split(sim, run["M"])
+    if args.fp64_beside if args.fp64_beside is not None else prec == 32:
+        # the plain FP64 path on the same workload (library default tile and
+        # sort interval), timed the same way, after the FP32 timed region; then
+        # the FP32 state's difference from the FP64 state after the same steps
+        sim64, ms64, ph64, inf64 = timed(64, 0, 0, 0)
+        v64 = particle_steps / (ms64 * 1e-3)
+        out["fp64"] = {"value": v64, "unit": "particle-steps/s", "ms_per_step": ms64 / K,
+                       "tile": "%dx%d" % inf64[0]["tile"], "sort_interval": 8,
+                       "kernels": {ph: {"avg_ms": ms / n, "launches": n} for ph, (ms, n) in ph64.items() if n}}
+        out["fp32_over_fp64"] = value / v64
+        out["fp32_error"] = {"vs_fp64_gpu": fp32_vs_fp64(pic, sim, sim64, runs[0]),
+                             "stated_bounds_vs_fp64_oracle": FP32_BOUNDS}
+        sim64.close()
+        del sim64
     sim.close()
     del sim
     torch.cuda.empty_cache()
     copy_bw = copy_bandwidth(torch, dev)
     out["roofline"]["measured_peak"] = copy_bw  # 1 GiB device copy on this GPU
     out["roofline"]["frac_of_measured_peak"] = ach / copy_bw
-    if args.cpu_steps > 0:
+    if args.cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(runs, args.cpu_steps, n_coef)
+        out["cpu_baseline"] = cpu_baseline(args.workload, n_coef)
     print(json.dumps(out), flush=True)
     return 0
 

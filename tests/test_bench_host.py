@@ -47,6 +47,29 @@ def test_measured_traffic_only_for_the_profiled_build_and_settings():
     assert bench.measured_traffic("c2", "push", st["tile"], st["sort_interval"], 32) is None
 
 
-def test_cpu_baseline_sample_sizes_cover_every_workload():
-    assert set(bench.CPU_STEPS) == set(bench.WORKLOADS)
-    assert all(n >= 1 for n in bench.CPU_STEPS.values())
+def test_cpu_baseline_sample_covers_every_pic_workload():
+    """Every PIC workload has a bounded oracle sample; the 67 M-electron run's
+    is a slab of the same physics (radius, modes, ppc, density, pulses)."""
+    for name in bench.WORKLOADS:
+        if name == "dla":
+            continue
+        smp = workloads.cpu_sample(name)
+        assert smp["steps"] >= 1 and smp["runs"]
+    full, slab = workloads.config("c5")["runs"][0], workloads.cpu_sample("c5")["runs"][0]
+    assert slab["Nz"] == 512 and slab["Nz"] < full["Nz"]
+    for k in ("Nr", "M", "ppc", "dz", "dr", "n0", "seed", "taper"):
+        assert slab[k] == full[k], k
+    assert len(slab["pulses"]) == 2
+    for p in slab["pulses"]:
+        assert 0 < p["zc"] < slab["Nz"] * slab["dz"]
+
+
+def test_cpu_baseline_all_cores_leg():
+    """The all-core leg runs one oracle process per core on the same sample
+    and sums their particle-steps (here on the smallest workload)."""
+    out = bench.cpu_baseline("c1", max_procs=2)
+    assert out["cores"] == 1 and out["kind"] == "oracle" and out["value"] > 0
+    ac = out["all_cores"]
+    assert ac["kind"] == "oracle" and ac["value"] > 0 and 1 <= ac["cores"] <= 2
+    assert out["cpu"] == ac["cpu"]
+

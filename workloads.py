@@ -81,6 +81,26 @@ def config(name: str) -> dict:
     raise KeyError(name)
 
 
+def cpu_sample(name: str) -> dict:
+    """The bounded sample of a workload that the CPU baseline times with the
+    oracle: {"runs", "steps", "desc"}.  Whole steps of the workload's own runs,
+    except for the 67 M-electron run, whose one step takes the serial oracle
+    about 50 s and 8 GB: its sample is a slab of 512 of its 8192 columns (same
+    radius, modes, electrons per cell, density and pulses, the leading pulse
+    inside the slab), 4.2 M electrons."""
+    cfg = config(name)
+    if name != "c5":
+        steps = {"c1": 200, "c3": 200, "c2": 3, "c4": 1, "cv32": 3, "cv128": 1}[name]
+        return dict(runs=cfg["runs"], steps=steps, desc=f"{steps} full step(s) of the workload")
+    run = dict(cfg["runs"][0])
+    run["Nz"] = 512
+    lp = _lp(run["n0"])
+    run["pulses"] = [dict(p, zc=20 * LAMBDA0 - k * lp) for k, p in enumerate(run["pulses"])]
+    return dict(runs=[run], steps=3,
+                desc="3 steps of a 512-column slab of the workload (512x512, modes 0..3, 16 ppc, 4.2M electrons, "
+                     "both pulses)")
+
+
 def small(name="tiny", M=1, Nz=64, Nr=12, ppc=2, n0=0.02, a0=1.5, seed=99, n_tracked=64) -> dict:
     """Small grids that still span several sort tiles and a ragged radial tile."""
     dz = LAMBDA0 / 16
