@@ -460,6 +460,85 @@ def test_P5_betatron_frequency():
     assert abs(2 * math.pi / period / wb - 1.0) < 1e-3
 
 
+def _betatron_in_wave(w0, n0, E0, T, dt, electrons):
+    """Test electrons (w = 0, tracked) in the ion channel E_r^0 = (n0/2) r
+    and a weak vacuum plane wave of frequency w0 (k = w0, E_x = B_y =
+    E0 sin(w0 (z - t))) placed in the m = 1 arrays.  electrons: rows (z, x,
+    y, ux, uy, uz), lengths in c/omega_0.  The fields are prescribed on the
+    grid every step (E at t^n, both B half steps at t^n, so the gathered time
+    average is B(t^n)).  Returns the laser-mode work W_1 of each electron."""
+    Nz, Nr, dr = 32, 8, 1.0
+    dz = 2 * math.pi / w0 / 16  # 16 points per laser wavelength, two wavelengths in the periodic box
+    o = oracle.Oracle(Nz, Nr, 1, dz, dr, dt, [1.0], [1.0])
+    o.set_field(oracle.ER, 0, (0.5 * n0 * (np.arange(Nr + 1) + 0.5) * dr)[:, None] * np.ones((1, Nz)))
+    o.set_flags(freeze_fields=True)
+    e = np.array(electrons, dtype=float)
+    o.set_particles(e[:, 0] / dz, e[:, 1] / dr, e[:, 2] / dr, e[:, 3], e[:, 4], e[:, 5], np.zeros(len(e)))
+    zi = np.arange(Nz) * dz
+    one = np.ones((Nr + 1, 1))
+    for n in range(int(round(T / dt))):
+        ev = E0 * np.sin(w0 * (zi - n * dt))[None, :] * one
+        bv = E0 * np.sin(w0 * (zi + 0.5 * dz - n * dt))[None, :] * one
+        # x-polarised plane wave in mode form: E_r^1 = E, E_phi^1 = iE, B_r^1 = -iB, B_phi^1 = B
+        o.set_field(oracle.ER, 1, ev)
+        o.set_field(oracle.EP, 1, 1j * ev)
+        for c_old, c_new, v in ((oracle.BOR, oracle.BR, -1j * bv), (oracle.BOP, oracle.BP, bv)):
+            o.set_field(c_old, 1, v)
+            o.set_field(c_new, 1, v)
+        o.step(1)
+    return o.tracked()["W"][:, 1]
+
+
+def test_P5_betatron_resonance_eq1():
+    """The second half of P5, Eq. (1): (1 - beta_z) omega_0 = omega_p / sqrt(2 gamma).
+    gamma = 3 electrons on small betatron orbits (K = gamma omega_beta x_beta
+    = 0.09, so that beta_z stays that of the straight orbit) in the channel
+    of n0 = 0.02, and a weak x-polarised laser in the m = 1 arrays, scanned
+    in omega_0 over 0.6..1.4 (bins of 0.04).  Per laser phase (two, a quarter
+    period apart) one electron oscillates in the plane at 30 degrees to the
+    polarisation, through the axis, and one circles the axis (a helical
+    orbit, on which a wrong sign of the azimuthal factor e^{i m phi} of the
+    gather reverses the work).  After 8 betatron periods:
+      * the laser-mode work W_1, combined over the two phases, peaks in the
+        bin of the resonance Eq. (1) predicts (omega_0 = 1.009);
+      * every electron's signed W_1 follows the textbook linear theory of a
+        harmonic transverse orbit at constant beta_z, W_1 = E0 omega_beta
+        A_x int_0^T sin(phi - (1 - beta_z) omega_0 t) sin(omega_beta t) dt
+        (A_x the orbit's x amplitude), to within 8% of the largest W_1 (grid
+        interpolation of the laser, and the laser's own small push on the
+        orbit)."""
+    gamma0, n0, xb, E0, dt = 3.0, 0.02, 0.5, 1e-5, 0.25
+    ang = math.radians(30.0)
+    wb = math.sqrt(n0) / math.sqrt(2 * gamma0)  # Eq. (1)
+    uz = math.sqrt(gamma0**2 - 1.0)
+    bz = uz / gamma0
+    w_res = wb / (1.0 - bz)
+    T = 8 * 2 * math.pi / wb
+    ws = np.round(np.arange(0.6, 1.4001, 0.04), 10)
+    t = np.linspace(0.0, round(T / dt) * dt, 200001)
+    u_circ = gamma0 * xb * wb  # circular orbit of radius xb at omega_beta
+    W, L = [], []
+    for w0 in ws:
+        z0 = [3.0, 3.0 + 0.5 * math.pi / w0]
+        els = []
+        for z in z0:
+            els.append((z, xb * math.cos(ang), xb * math.sin(ang), 0.0, 0.0, uz))  # planar, through the axis
+            els.append((z, xb, 0.0, 0.0, u_circ, uz))  # circular
+        W.append(_betatron_in_wave(w0, n0, E0, T, dt, els))
+        lin = []
+        for z in z0:
+            for Ax, uy in ((xb * math.cos(ang), 0.0), (xb, u_circ)):
+                g = math.sqrt(1.0 + uy * uy + uz * uz)
+                lin.append(E0 * wb * Ax * np.trapezoid(np.sin(w0 * z - (1 - uz / g) * w0 * t) * np.sin(wb * t), t))
+        L.append(lin)
+    W, L = np.array(W), np.array(L)
+    amp = np.hypot(W[:, 0], W[:, 2]) + np.hypot(W[:, 1], W[:, 3])
+    peak = ws[int(np.argmax(amp))]
+    assert abs(peak - w_res) <= 0.04 + 1e-12, (peak, w_res)
+    assert np.abs(W - L).max() <= 0.08 * np.abs(L).max(), np.abs(W - L).max() / np.abs(L).max()
+    assert amp.max() > 5 * np.median(amp)  # a resonance, not a flat response
+
+
 # --------------------------------------------------------------------------
 # plasma run: P6 (Gauss), P7 (work), P9 (stability)
 
@@ -518,19 +597,154 @@ def test_P7_vacuum_laser_does_no_wake_work():
     assert np.abs(tr["W"][:, 1]).max() > 1e-3
 
 
+def _filter_taps(C):
+    """p_l = sum_{l' > |l|} C_{l'}, l = -(N-1)..N-1: D = D_Yee o P for the
+    staggered difference with coefficients C (written out here from that
+    definition, independently of the oracle's own taps)."""
+    N = len(C)
+    return np.array([sum(C[lp - 1] for lp in range(abs(l) + 1, N + 1)) for l in range(-(N - 1), N)])
+
+
+def _zfilter(p, f):
+    N = (len(p) + 1) // 2
+    out = np.zeros_like(f)
+    for l in range(-(N - 1), N):
+        out += p[l + N - 1] * np.roll(f, -l, axis=1)
+    return out
+
+
 @pytest.mark.slow
-def test_P9_vacuum_long_run_bounded():
+@pytest.mark.parametrize("N", [16, 1])
+def test_P9_long_run_leapfrog_energy_is_conserved(N):
+    """P9, long-run stability at 0.95 of the Courant limit, as an exact
+    invariant.  With D_E = D_Yee o P_E and D_B = D_Yee o P_B (Eq. (9); P_X the
+    symmetric z filters of C^E, C^B), the curls of Faraday's and Ampere's laws
+    are each other's adjoints in the metric that weights E_r, E_phi, B_z by
+    P_E and E_z, B_r, B_phi by P_B (and by the cell volumes), so the leapfrog
+    keeps
+        H = <E^n, P E^n>_V + <B^{n-1/2}, P B^{n+1/2}>_V
+    constant per mode (the m >= 1 axis values of E_phi and B_r, which only the
+    gather reads, excluded).  A laser pulse plus random noise on every node
+    (all wavenumbers, up to k dz = pi, where the fit no longer holds) runs
+    10^4 steps: H stays constant to 1e-12 (rounding), so nothing grows at the
+    Courant-limited dt.  The naive field energy sum |E|^2 + |Bbar|^2 is not
+    invariant: its ratio to H oscillates by (omega dt)^2 terms, up to 10% for
+    the noise near the Courant limit here (checked bounded).  The Yee case (N = 1, P = identity) is the textbook
+    leapfrog energy."""
     Nz, Nr, M = 64, 12, 3
     dz = LAMBDA0 / 16
     dr = 4 * dz
-    dt, CE, CB, _ = setup_cached(16, M, dz, dr)
+    dt, CE, CB, _ = setup_cached(N, M, dz, dr)
     o = oracle.Oracle(Nz, Nr, M, dz, dr, dt, CE, CB)
     o.add_laser(1.0, 3 * LAMBDA0, 2 * LAMBDA0, 2 * LAMBDA0, taper=LAMBDA0)
+    rng = np.random.default_rng(11)
+    for c in (oracle.ER, oracle.EP, oracle.EZ):
+        for m in range(M + 1):
+            f = o.get_field(c, m)
+            f += 1e-3 * (rng.normal(size=f.shape) + (1j * rng.normal(size=f.shape) if m else 0.0))
+            o.set_field(c, m, f)
     o.start_fields()
-    U0 = sum(o.field_energy(m) for m in range(M + 1))
-    o.field_step(3000)
-    U1 = sum(o.field_energy(m) for m in range(M + 1))
-    assert abs(U1 / U0 - 1.0) < 1e-2
+    o.field_step(1)  # the first step enforces the axis and wall values the noise broke
+    PE, PB = _filter_taps(CE), _filter_taps(CB)
+    j = np.arange(Nr + 1)
+    Vn = np.where(j == 0, math.pi * dr * dr * dz / 4, 2 * math.pi * j * dr * dr * dz)[:, None]
+    Vh = np.where(j < Nr, 2 * math.pi * (j + 0.5) * dr * dr * dz, 0.0)[:, None]
+
+    def ip(a, b, V):
+        return float(np.real(np.sum(np.conj(a) * b * V)))
+
+    def H(m):
+        E = [o.get_field(c, m) for c in (oracle.ER, oracle.EP, oracle.EZ)]
+        Bo = [o.get_field(c, m) for c in (oracle.BOR, oracle.BOP, oracle.BOZ)]
+        Bn = [o.get_field(c, m) for c in (oracle.BR, oracle.BP, oracle.BZ)]
+        Vn_ = Vn.copy()
+        if m >= 1:
+            Vn_[0] = 0.0
+        return (ip(E[0], _zfilter(PE, E[0]), Vh) + ip(E[1], _zfilter(PE, E[1]), Vn_)
+                + ip(E[2], _zfilter(PB, E[2]), Vn_) + ip(Bo[0], _zfilter(PB, Bn[0]), Vn_)
+                + ip(Bo[1], _zfilter(PB, Bn[1]), Vh) + ip(Bo[2], _zfilter(PE, Bn[2]), Vh))
+
+    H0 = [H(m) for m in range(M + 1)]
+    U0 = [o.field_energy(m) for m in range(M + 1)]
+    worst, uratio = 0.0, []
+    for _ in range(10):
+        o.field_step(1000)
+        for m in range(M + 1):
+            worst = max(worst, abs(H(m) / H0[m] - 1.0))
+            uratio.append(o.field_energy(m) / U0[m])
+    assert worst < 1e-12, worst
+    assert max(abs(r - 1.0) for r in uratio) < 0.2
+
+
+@pytest.mark.parametrize("comp", [oracle.ER, oracle.EP, oracle.EZ, oracle.BOR, oracle.BOP, oracle.BOZ])
+@pytest.mark.parametrize("m", [0, 1, 2])
+def test_field_energy_is_the_volume_integral(comp, m):
+    """U_m (the oracle's field energy) against the closed form of
+    (1/2) int |F|^2 dV for one component of one mode,
+    F = Re(a exp(-r^2/w^2) cos(k z) e^{i m phi}), on a cylinder wide enough
+    for the Gaussian: int_phi Re(...)^2 dphi = 2 pi a^2 (m = 0) or pi |a|^2
+    (m >= 1), int r exp(-2 r^2/w^2) dr = w^2/4, and the mean of cos^2 over
+    whole periods is 1/2, so U = (1/2) (2 pi a^2 or pi |a|^2) (w^2/4) (L/2).
+    Each component sits at its own staggered place (E_r, B_phi, B_z at
+    half-integer r; E_z, B_r, B_phi at half-integer z) and takes that place's
+    volume; B enters as the time average of its two half steps.  The sum over
+    z is exact; over r the rule is second order: the error falls 4x per
+    halving of dr and its Richardson extrapolation is below 1e-5.  A wrong
+    mode weight, or a node's volume given to a half-integer row, fails."""
+    Nz, dz, R, w = 16, 0.3, 12.0, 2.5
+    amp = (0.7 + 0.4j) if m else 0.7
+    half_r = comp in (oracle.ER, oracle.BOP, oracle.BOZ)
+    half_z = comp in (oracle.EZ, oracle.BOR, oracle.BOP)
+    new_half = {oracle.BOR: oracle.BR, oracle.BOP: oracle.BP, oracle.BOZ: oracle.BZ}
+    L = Nz * dz
+    ang = 2 * math.pi * abs(amp) ** 2 if m == 0 else math.pi * abs(amp) ** 2
+    exact = 0.5 * ang * (w * w / 4) * (L / 2)
+    err = []
+    for Nr in (24, 48, 96):
+        dr = R / Nr
+        o = oracle.Oracle(Nz, Nr, m, dz, dr, 0.1, [1.0], [1.0])
+        r = (np.arange(Nr + 1) + (0.5 if half_r else 0.0)) * dr
+        z = (np.arange(Nz) + (0.5 if half_z else 0.0)) * dz
+        f = amp * np.exp(-r**2 / w**2)[:, None] * np.cos(4 * math.pi * z / L)[None, :]
+        o.set_field(comp, m, f)
+        if comp in new_half:
+            o.set_field(new_half[comp], m, f)
+        err.append(o.field_energy(m) / exact - 1.0)
+    assert abs(err[0]) < 1e-2
+    assert 3.8 < err[0] / err[1] < 4.2 and 3.8 < err[1] / err[2] < 4.2, err
+    assert abs((4 * err[2] - err[1]) / 3) < 1e-5, err
+
+
+def test_m1_axis_current_is_charge_density_times_velocity():
+    """The m = 1 azimuthal current on the axis node.  On the axis a smooth
+    transverse field has F_r^1 = F_x - i F_y and F_phi^1 = i F_r^1, so the
+    current of electrons moving with one velocity v there is
+    J_phi^1(0) = i rho^0(0) (v_x - i v_y), rho^0 the charge density.  A ring
+    of N evenly spaced electrons around the axis, within one cell of it, each
+    depositing its azimuthal velocity v_phi = -v_x sin(phi) + v_y cos(phi) of
+    that v (no move, so the closure term is zero), gives exactly that on the
+    axis node (for N >= 3): the check holds the axis term's mode factor
+    c_1 = 2, the sign of its phase e^{-i phi} and its node volume."""
+    Nz, Nr, M = 10, 6, 2
+    dz, dr, dt = 0.4, 1.3, 0.35
+    o = oracle.Oracle(Nz, Nr, M, dz, dr, dt, [1.0], [1.0])
+    rng = np.random.default_rng(3)
+    for N in (3, 5, 8):
+        r0, z0 = rng.uniform(0.05, 0.95), rng.uniform(3, 5)
+        vx, vy = rng.normal(size=2) * 0.3
+        q = -0.6
+        ph = 2 * math.pi * (np.arange(N) + rng.uniform()) / N
+        xs, ys = r0 * np.cos(ph), r0 * np.sin(ph)
+        for k in range(N):
+            p = (z0, xs[k], ys[k])
+            vphi = -vx * math.sin(ph[k]) + vy * math.cos(ph[k])
+            (o.deposit_one if k == 0 else o.deposit_add)(q, p, p, vphi)
+        Jp1 = o.get_field(oracle.JP, 1)
+        o.set_particles(np.full(N, z0), xs, ys, np.zeros(N), np.zeros(N), np.zeros(N), np.full(N, -q))
+        o.deposit_rho()
+        want = 1j * o.get_field(oracle.RHO, 0)[0] * (vx - 1j * vy)
+        assert np.abs(want).max() > 0.1
+        assert np.abs(Jp1[0] - want).max() <= 1e-14 * np.abs(want).max(), N
 
 
 # --------------------------------------------------------------------------
@@ -649,12 +863,16 @@ def test_wall_reflection_is_specular():
 # P4 on the grid: gather of E^n and the Eq. (12) average of B, dual vs Yee
 
 
-def _grid_orbit(N, nsteps=190, a0=0.5):
+def _grid_orbit(N, nu=0.9341, a0=0.5):
+    """An electron at rest run over by a Gaussian x-polarised pulse on the
+    grid (the full loop: solver, gather, push); returns the largest
+    |gamma - u_z - 1| (0 for the exact plane-wave orbit) and the final u.
+    The same physical time at any nu = c dt / dz."""
     Nz, Nr, M = 192, 64, 1
     dz = LAMBDA0 / 16
     dr = 4 * dz
-    nu = 0.9341
     dt = nu * dz
+    nsteps = int(round(190 * 0.9341 / nu))
     CE, CB = coef.fit(N, nu)
     o = oracle.Oracle(Nz, Nr, M, dz, dr, dt, CE, CB)
     L = Nz * dz
@@ -688,11 +906,26 @@ def _grid_orbit(N, nsteps=190, a0=0.5):
 
 @pytest.mark.slow
 def test_P4_grid_orbit_dual_beats_yee():
+    """P4 on the grid, dual against Yee at the same (dz, dt), then at half the
+    dt.  The dual coefficients remove the dispersion error (Eq. (11)) and the
+    E/B time-staggering error (Eq. (15)) at the dt they are fitted for, so
+    what is left of the dual error is the interpolation floor of the grid
+    (O((k dz)^2), the S-tilde of Eq. (13)): it does not change when dt is
+    halved at fixed dz.  Yee's error is larger at every dt; its excess over
+    that floor is dominated by the staggering factor cos(omega dt / 2) of the
+    Lorentz force, second order in dt, so halving dt cuts it about 4x (the
+    survey expected Yee's error to grow as dt falls, through its dispersion;
+    at 16 points per wavelength the staggering term dominates instead)."""
     e_dual, u_dual = _grid_orbit(16)
     e_yee, _ = _grid_orbit(1)
     assert np.abs(u_dual).max() < 0.05  # the pulse has passed and left it nearly at rest
     assert e_dual < 2e-3
     assert e_yee > 3.0 * e_dual
+    e_dual2, _ = _grid_orbit(16, 0.9341 / 2)
+    e_yee2, _ = _grid_orbit(1, 0.9341 / 2)
+    assert abs(e_dual2 / e_dual - 1.0) < 0.1, (e_dual, e_dual2)  # flat: the floor
+    assert e_yee2 > e_dual2
+    assert 3.0 < (e_yee - e_dual) / (e_yee2 - e_dual2) < 6.0, (e_yee, e_yee2, e_dual, e_dual2)
 
 
 def test_laser_init_propagates_forward_at_c():
