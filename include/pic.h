@@ -149,6 +149,15 @@ typedef struct pic_opts {
   int32_t use_graph;    /* 1: capture each distinct step (the launches of all
                            runs) once as a hipGraph and replay it             */
   int32_t current;      /* PIC_CURRENT_FILTER (0) or PIC_CURRENT_EXACT_JZ    */
+  /* Per-run set-up, for a context of runs on different cells (a resolution
+   * scan): arrays over the runs in their order, caller owned, read during
+   * pic_init only; NULL leaves each run to the shared dt / coef_E / coef_B
+   * above.  run_dt[i] > 0 is run i's dt (PIC_E_CFL above its limit);
+   * run_coef_E, run_coef_B (both or neither) hold n_coef values per run,
+   * run i's at [i * n_coef].                                                 */
+  const double *run_dt;
+  const double *run_coef_E;
+  const double *run_coef_B;
 } pic_opts;
 
 typedef struct pic_ctx pic_ctx;
@@ -207,8 +216,19 @@ int pic_load_host(const pic_run_desc *run, double *z, double *x, double *y, doub
 
 /* ---- device life cycle --------------------------------------------------- */
 
-/* Validate, set up (coefficients, dt, loading, laser) and upload n_runs runs
- * into device_workspace on hip_stream.  With device_workspace == NULL only
+/* Set up and upload n_runs runs: the problem of Sec. II and App. A (a laser
+ * driving a wake in an under-dense plasma) in the quasi-3D representation of
+ * Sec. III.B.  Per run:
+ *   - the dual operators' coefficients C^E, C^B fitted to Eqs. (11) and (15)
+ *     (Sec. III.A), and dt at cfl_fraction of the Courant limit they and the
+ *     modes 0..M allow (or the caller's dt / coefficients);
+ *   - cold electrons over immobile ions with the density profile of App. A
+ *     (up-ramp, plateau, down-ramp), loaded on the host;
+ *   - E^0 and B^0 of the pulses of Eq. (18) in the m = 1 arrays, and the
+ *     half-step B^{-1/2}, B^{+1/2} of the staggering of Eq. (12);
+ *   - the first cell sort.
+ * Validate, set up and upload n_runs runs into device_workspace on
+ * hip_stream.  With device_workspace == NULL only
  * *workspace_bytes is written (size query, no device call).  Otherwise
  * *workspace_bytes must be at least the queried size; the buffer must stay
  * allocated until pic_destroy.  *out receives the context.  Errors:
@@ -219,7 +239,18 @@ int pic_load_host(const pic_run_desc *run, double *z, double *x, double *y, doub
 int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts,
              void *device_workspace, size_t *workspace_bytes, void *hip_stream, pic_ctx **out);
 
-/* Enqueue n_steps steps of every run on the context's stream (asynchronous).*/
+/* Enqueue n_steps time steps of every run on the context's stream
+ * (asynchronous).  One step is the loop of Sec. III: gather of E^n and of
+ * the time average (B^{n-1/2} + B^{n+1/2})/2 of Eq. (12) at each electron
+ * from the modes F = Re sum_m F^m e^{i m phi} (Sec. III.B); the relativistic
+ * push of Eq. (6) (Boris), with the per-mode work of Eq. (16) accumulated on
+ * tracked electrons; the charge-conserving deposit of J^{n+1/2} into the
+ * mode arrays; and the dual-solver update of Eq. (9), Ampere's law with D_B
+ * and the current made to conserve charge with it (Gauss's law with [k]_B,
+ * Eq. (10)), then Faraday's law with D_E.  A cell sort precedes every
+ * sort_interval-th step.  Runs that have taken their n_steps are left
+ * alone.  Errors found on the device (a cell sort that met inconsistent
+ * data) are reported by the next synchronising call.                       */
 int pic_step(pic_ctx *ctx, int64_t n_steps);
 
 /* Synchronise the stream and copy out FP64 diagnostics of one run (any
@@ -248,12 +279,14 @@ int pic_cartesian_work(pic_ctx *ctx, int32_t run, double *wz, double *wperp, dou
 /* Synchronise and reduce the divergence of the energetic electrons of one
  * run, the quantity Secs. IV.A-IV.B compare between solvers: over electrons
  * with Lorentz factor >= gamma_min and u_z > 0, with theta_x = atan(u_x/u_z)
- * and theta_y = atan(u_y/u_z), out[4] (caller owned) receives
+ * and theta_y = atan(u_y/u_z), out[6] (caller owned) receives
  *   out[0] = sum w,  out[1] = sum w theta_x^2,  out[2] = sum w theta_y^2,
  *   out[3] = number of electrons counted,
- * FP64 sums (RMS angle = sqrt(out[1] / out[0])).  The selection compares
- * |u|^2 with gamma_min^2 - 1.  PIC_E_INVALID if gamma_min < 1 or out is
- * NULL; PIC_E_NUMERIC if a sum is not finite.                              */
+ *   out[4] = sqrt(out[1] / out[0]), out[5] = sqrt(out[2] / out[0]): the
+ *            charge-weighted RMS angles (0 when no electron is counted),
+ * FP64 sums.  The selection compares |u|^2 with gamma_min^2 - 1.
+ * PIC_E_INVALID if gamma_min < 1 or out is NULL; PIC_E_NUMERIC if a sum is
+ * not finite.                                                              */
 int pic_divergence(pic_ctx *ctx, int32_t run, double gamma_min, double *out);
 
 /* ---- checkpoint and restore ------------------------------------------------ */
@@ -302,10 +335,13 @@ typedef struct pic_dla_model {
 int pic_dla_integrate(const pic_dla_model *model, int64_t n, const double *t0, double *x, double *zeta, double *xd,
                       double *zetad, double t_end, double h, void *hip_stream);
 
-/* Synchronise and copy one component of mode m of one run into out, FP64
- * interleaved complex [(Nr+1)][Nz] (2 (Nr+1) Nz doubles; m = 0 has zero
- * imaginary part), physical units.  PIC_E_NOMEM if out_len (in doubles) is
- * short.                                                                    */
+/* Synchronise and copy one component of mode m of one run into out: the
+ * amplitude F^m(r, z) of F = Re sum_m F^m e^{i m phi} (Sec. III.B), the
+ * per-mode fields whose work Eq. (16) separates (m = 0 the wake, m = 1 the
+ * laser), at the staggered places listed with PIC_ER..PIC_BZ_NEW.  FP64 interleaved complex
+ * [(Nr+1)][Nz] (2 (Nr+1) Nz doubles; m = 0 has zero imaginary part),
+ * physical units, FP64 also for FP32 runs.  PIC_E_NOMEM if out_len (in
+ * doubles) is short; PIC_E_STATE if a cell sort met inconsistent data.      */
 int pic_fields(pic_ctx *ctx, int32_t run, int32_t comp, int32_t m, double *out, size_t out_len);
 
 /* Synchronise and copy the electrons of one run in device order (FP64, cell

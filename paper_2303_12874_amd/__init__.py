@@ -55,6 +55,8 @@ class _Opts(C.Structure):
         ("coef_E", C.POINTER(C.c_double)), ("coef_B", C.POINTER(C.c_double)),
         ("sort_interval", C.c_int32), ("tile_z", C.c_int32), ("tile_r", C.c_int32),
         ("use_graph", C.c_int32), ("current", C.c_int32),
+        ("run_dt", C.POINTER(C.c_double)), ("run_coef_E", C.POINTER(C.c_double)),
+        ("run_coef_B", C.POINTER(C.c_double)),
     ]
 
 
@@ -233,14 +235,19 @@ def workspace_bytes(runs: Sequence[RunDesc], precision=PREC_FP64, solver=SOLVER_
 
 
 def _make_opts(precision, solver, n_coef, dt=0.0, coef_E=None, coef_B=None, cfl_fraction=0.0, fit_band=0.0,
-               sort_interval=0, tile_z=0, tile_r=0, use_graph=False, current=CURRENT_FILTER):
+               sort_interval=0, tile_z=0, tile_r=0, use_graph=False, current=CURRENT_FILTER, run_dt=None,
+               run_coef_E=None, run_coef_B=None):
+    """pic_opts.  run_dt: one dt per run; run_coef_E / run_coef_B: one
+    coefficient vector per run (sequences over the runs)."""
     o = _Opts()
     o.precision, o.solver, o.n_coef = precision, solver, n_coef
     o.fit_band, o.cfl_fraction, o.dt = fit_band, cfl_fraction, dt
     keep = []
-    for name, val in (("coef_E", coef_E), ("coef_B", coef_B)):
+    for name, val in (("coef_E", coef_E), ("coef_B", coef_B), ("run_dt", run_dt), ("run_coef_E", run_coef_E),
+                      ("run_coef_B", run_coef_B)):
         if val is not None:
-            a = np.ascontiguousarray(val, dtype=np.float64)
+            a = np.ascontiguousarray(np.concatenate([np.ravel(v) for v in val]) if name.startswith("run_coef")
+                                     else val, dtype=np.float64)
             keep.append(a)
             setattr(o, name, a.ctypes.data_as(C.POINTER(C.c_double)))
     o.sort_interval, o.tile_z, o.tile_r, o.use_graph = sort_interval, tile_z, tile_r, int(use_graph)
@@ -394,11 +401,9 @@ class Simulation:
         """Charge-weighted RMS divergence theta_x = atan(u_x/u_z) (and theta_y)
         of the electrons with gamma >= gamma_min moving forward, with the raw
         sums: {"w", "rms_x", "rms_y", "count"}."""
-        out = np.zeros(4)
+        out = np.zeros(6)
         _check(_lib.pic_divergence(self._h, run, float(gamma_min), _ptr(out)))
-        w = out[0]
-        return {"w": w, "rms_x": float(np.sqrt(out[1] / w)) if w > 0 else 0.0,
-                "rms_y": float(np.sqrt(out[2] / w)) if w > 0 else 0.0, "count": int(out[3]),
+        return {"w": out[0], "rms_x": float(out[4]), "rms_y": float(out[5]), "count": int(out[3]),
                 "sum_wtx2": out[1], "sum_wty2": out[2]}
 
     def cartesian_work(self, run=0, corrected=True):

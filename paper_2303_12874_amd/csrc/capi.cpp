@@ -122,7 +122,7 @@ Layout layout_of(const pic_run_desc &d, int prec, int N, int Tz, int Tr, long lo
   L.P = take((size_t)(2 * N - 1) * rs);
   L.H = take((size_t)PIC_MAX_JZ_TAPS * rs);
   L.red = take((size_t)kRedBlocks * (PIC_MAX_MODES + 1) * 8);
-  L.work = take(16);
+  L.work = take(32);  // tile ticket (16 bytes), then the sort's flag word
   L.gam = take((size_t)(d.n_tracked > 0 ? d.n_tracked : 1) * 8);
   L.ids = take((size_t)(d.n_tracked > 0 ? d.n_tracked : 1) * 8);
   L.total = o;
@@ -337,6 +337,11 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
   if (o.cfl_fraction < 0 || o.cfl_fraction > 1 || o.dt < 0 || !std::isfinite(o.dt))
     return fail(PIC_E_INVALID, "cfl_fraction or dt out of range");
   if ((o.coef_E == nullptr) != (o.coef_B == nullptr)) return fail(PIC_E_INVALID, "give both coef_E and coef_B");
+  if ((o.run_coef_E == nullptr) != (o.run_coef_B == nullptr))
+    return fail(PIC_E_INVALID, "give both run_coef_E and run_coef_B");
+  if (o.run_dt)
+    for (int i = 0; i < n_runs; ++i)
+      if (!(o.run_dt[i] > 0) || !std::isfinite(o.run_dt[i])) return fail(PIC_E_INVALID, "run_dt[%d] out of range", i);
   if (o.sort_interval < 0 || o.tile_z < 0 || o.tile_r < 0) return fail(PIC_E_INVALID, "negative sort options");
   if (o.current != PIC_CURRENT_FILTER && o.current != PIC_CURRENT_EXACT_JZ)
     return fail(PIC_E_INVALID, "current must be PIC_CURRENT_FILTER or PIC_CURRENT_EXACT_JZ");
@@ -388,15 +393,18 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
     // ---- coefficients and dt (Sec. III.A) ----
     R.CE.assign(N, 1.0);
     R.CB.assign(N, 1.0);
-    if (o.coef_E) {
-      R.CE.assign(o.coef_E, o.coef_E + N);
-      R.CB.assign(o.coef_B, o.coef_B + N);
+    const double *ce = o.run_coef_E ? o.run_coef_E + (size_t)i * N : o.coef_E;
+    const double *cb = o.run_coef_B ? o.run_coef_B + (size_t)i * N : o.coef_B;
+    const double dt_fix = o.run_dt ? o.run_dt[i] : o.dt;
+    if (ce) {
+      R.CE.assign(ce, ce + N);
+      R.CB.assign(cb, cb + N);
       R.nu_lim = courant_limit_of(R.CE.data(), R.CB.data(), N, d.M, d.dz, d.dr);
-      R.dt = o.dt > 0 ? o.dt : frac * R.nu_lim * d.dz;
-    } else if (o.dt > 0) {
-      if (N > 1) fit_dual(N, o.dt / d.dz, band, R.CE.data(), R.CB.data());
+      R.dt = dt_fix > 0 ? dt_fix : frac * R.nu_lim * d.dz;
+    } else if (dt_fix > 0) {
+      if (N > 1) fit_dual(N, dt_fix / d.dz, band, R.CE.data(), R.CB.data());
       R.nu_lim = courant_limit_of(R.CE.data(), R.CB.data(), N, d.M, d.dz, d.dr);
-      R.dt = o.dt;
+      R.dt = dt_fix;
     } else {
       R.nu_lim = courant_limit_fitted(o.solver, N, d.M, d.dz, d.dr, band);
       R.dt = frac * R.nu_lim * d.dz;
@@ -489,6 +497,7 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
     k.NH = (int)R.H.size();
     k.red = (double *)(base + L.red);
     k.work = (int32_t *)(base + L.work);
+    k.flags = (uint32_t *)(base + L.work + 16);
     R.dev_gamma = (double *)(base + L.gam);
     R.dev_ids = (int64_t *)(base + L.ids);
 
@@ -567,7 +576,7 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
     }
     const size_t rs = f64 ? 8 : 4;
     const size_t vecb = (size_t)3 * (2 * d.M + 1) * (size_t)k.plane * rs;
-    if ((rc = launch_zero(k.J[0], vecb, s)) || (rc = launch_zero(k.J[1], vecb, s)) ||
+    if ((rc = launch_zero(k.work, 32, s)) || (rc = launch_zero(k.J[0], vecb, s)) || (rc = launch_zero(k.J[1], vecb, s)) ||
         (rc = launch_zero(k.W, (size_t)(d.n_tracked > 0 ? d.n_tracked : 1) * (d.M + 1) * 8, s)) ||
         (rc = launch_zero(k.Wc, (size_t)(d.n_tracked > 0 ? d.n_tracked : 1) * 2 * 8, s)))
       break;
@@ -861,6 +870,23 @@ int pic_autotune(const pic_run_desc *runs, int32_t n_runs, pic_opts *opts, void 
   return PIC_OK;
 }
 
+// After a synchronisation of the context's stream: PIC_E_STATE if a cell
+// sort of any run has raised an integrity flag (the flags are sticky).
+int check_sort_flags(pic_ctx *ctx) {
+  for (size_t i = 0; i < ctx->runs.size(); ++i) {
+    uint32_t f = 0;
+    TRY(hip_ok(hipMemcpyAsync(&f, ctx->runs[i].k.flags, sizeof f, hipMemcpyDeviceToHost, ctx->stream),
+               "hipMemcpyAsync"));
+    TRY(hip_ok(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize"));
+    if (f) {
+      char msg[320];
+      sort_flags_text(f, (int)i, msg, sizeof msg);
+      return fail(PIC_E_STATE, "%s", msg);
+    }
+  }
+  return PIC_OK;
+}
+
 int pic_profile(pic_ctx *ctx, int32_t enable) {
   g_msg[0] = 0;
   if (!ctx_ok(ctx)) return fail(PIC_E_STATE, "invalid or destroyed context");
@@ -916,6 +942,7 @@ int pic_fields(pic_ctx *ctx, int32_t run, int32_t comp, int32_t m, double *out, 
   if (!ctx_ok(ctx)) return fail(PIC_E_STATE, "invalid or destroyed context");
   RunHost *R = get_run(ctx, run);
   if (!R) return fail(PIC_E_INVALID, "bad run index");
+  TRY(check_sort_flags(ctx));
   if (comp < 0 || comp > PIC_BZ_NEW || m < 0 || m > R->d.M || !out) return fail(PIC_E_INVALID, "bad component or mode");
   const KRun &k = R->k;
   const size_t plane = (size_t)k.plane;
@@ -990,6 +1017,7 @@ int pic_particles(pic_ctx *ctx, int32_t run, double *z, double *x, double *y, do
   if (!ctx_ok(ctx)) return fail(PIC_E_STATE, "invalid or destroyed context");
   RunHost *R = get_run(ctx, run);
   if (!R) return fail(PIC_E_INVALID, "bad run index");
+  TRY(check_sort_flags(ctx));
   const KRun &k = R->k;
   const size_t np = (size_t)k.np;
   if (out_len < np) return fail(PIC_E_NOMEM, "buffers hold %zu, %zu needed", out_len, np);
@@ -1033,6 +1061,7 @@ int pic_mode_work(pic_ctx *ctx, int32_t run, double *work, double *gamma, double
   if (!ctx_ok(ctx)) return fail(PIC_E_STATE, "invalid or destroyed context");
   RunHost *R = get_run(ctx, run);
   if (!R) return fail(PIC_E_INVALID, "bad run index");
+  TRY(check_sort_flags(ctx));
   const KRun &k = R->k;
   const hipStream_t s = ctx->stream;
   const int M = k.M;
@@ -1091,6 +1120,7 @@ int pic_cartesian_work(pic_ctx *ctx, int32_t run, double *wz, double *wperp, dou
   if (!ctx_ok(ctx)) return fail(PIC_E_STATE, "invalid or destroyed context");
   RunHost *R = get_run(ctx, run);
   if (!R) return fail(PIC_E_INVALID, "bad run index");
+  TRY(check_sort_flags(ctx));
   const KRun &k = R->k;
   const pic_run_desc &d = R->d;
   const bool need_f = f || w_lwfa || w_dla;
@@ -1127,6 +1157,7 @@ int pic_divergence(pic_ctx *ctx, int32_t run, double gamma_min, double *out) {
   if (!ctx_ok(ctx)) return fail(PIC_E_STATE, "invalid or destroyed context");
   RunHost *R = get_run(ctx, run);
   if (!R) return fail(PIC_E_INVALID, "bad run index");
+  TRY(check_sort_flags(ctx));
   if (!out) return fail(PIC_E_INVALID, "out is NULL");
   if (!(gamma_min >= 1.0) || !std::isfinite(gamma_min)) return fail(PIC_E_INVALID, "gamma_min must be >= 1");
   const KRun &k = R->k;
@@ -1143,6 +1174,9 @@ int pic_divergence(pic_ctx *ctx, int32_t run, double gamma_min, double *out) {
     out[c] = acc;
     if (!std::isfinite(acc)) return fail(PIC_E_NUMERIC, "a divergence sum is not finite");
   }
+  // charge-weighted RMS angles; 0 when no electron passes the cut
+  out[4] = out[0] > 0 ? std::sqrt(out[1] / out[0]) : 0.0;
+  out[5] = out[0] > 0 ? std::sqrt(out[2] / out[0]) : 0.0;
   return PIC_OK;
 }
 
@@ -1234,6 +1268,7 @@ extern "C" {
 int pic_checkpoint(pic_ctx *ctx, void *host_buf, size_t *bytes) {
   g_msg[0] = 0;
   if (!ctx_ok(ctx)) return fail(PIC_E_STATE, "invalid or destroyed context");
+  TRY(check_sort_flags(ctx));
   if (!bytes) return fail(PIC_E_INVALID, "bytes is NULL");
   const size_t need = checkpoint_bytes(ctx);
   if (!host_buf) {

@@ -1434,6 +1434,10 @@ __global__ __launch_bounds__(256) void sort_scatter_kernel(const Batch bt) {
     const long long p = p0 + q * 256 + threadIdx.x;
     if (p >= k.np) break;
     const int pos = rank[q] >= 0 ? base[key[q] - kb] + rank[q] : atomicAdd(&k.cell_count[key[q]], 1);
+    if (const uint32_t f = sort_index_flags(pos, k.np, kSortBadSlot)) {
+      atomicOr(k.flags, f);
+      continue;
+    }
     k.perm[pos] = ((uint64_t)(k.pid[p] & kIdMask) << 32) | (uint64_t)p;
   }
 }
@@ -1496,6 +1500,7 @@ __device__ __forceinline__ void sort_tile(const KRun &k, uint64_t *ent, long lon
       base += cnt;
       ss[g] = t < cnt ? (long long)(ent[t * chunk + it] & 0xffffffffu) : -1;
       ok[g] = ss[g] >= 0 && ss[g] < k.np;
+      if (t < cnt && !ok[g]) atomicOr(k.flags, sort_index_flags(ss[g], k.np, kSortBadSource));
     }
     Zw vz[kG];
     float vf[kG];
@@ -1543,6 +1548,11 @@ __global__ __launch_bounds__(256) void sort_tile_kernel(const Batch bt) {
   const long long c0 = (long long)(blockIdx.x - bt.off[rn]) * TT;
   const int beg = k.cell_start[c0], end = k.cell_start[c0 + TT];
   const int n = end - beg;
+  if (threadIdx.x == 0) {
+    uint32_t f = sort_tile_flags(beg, end, k.np);
+    if (blockIdx.x == bt.off[rn]) f |= sort_count_flags(k.cell_start[k.n_keys], k.np);  // one block per run
+    if (f) atomicOr(k.flags, f);
+  }
   if (n <= 0 || beg < 0 || end > k.np) return;
   if (n <= kSortLdsEntries) {
     uint64_t *ent = (uint64_t *)lds_raw;

@@ -30,6 +30,24 @@ void load_electrons(const pic_run_desc &r, double *z, double *x, double *y, doub
                     int64_t *tracked);
 void laser_fields(const pic_run_desc &r, double *E, double *B);
 
+// ---- integrity of the cell sort ----------------------------------------------
+// The sort kernels raise these bits in the run's flag word (device memory,
+// zeroed by pic_init) where data would otherwise send them out of range, and
+// skip that access; the calls that synchronise report a raised bit as
+// PIC_E_STATE.  A raised bit means electrons were lost or duplicated.
+constexpr uint32_t kSortBadCount = 1u;   // the cell counts do not sum to the electrons
+constexpr uint32_t kSortBadTile = 2u;    // a tile's electron range is not inside [0, np]
+constexpr uint32_t kSortBadSlot = 4u;    // a ranked entry's slot is outside [0, np)
+constexpr uint32_t kSortBadSource = 8u;  // an entry names an electron outside [0, np)
+// (constexpr functions are host and device functions alike)
+constexpr uint32_t sort_count_flags(long long total, long long np) { return total != np ? kSortBadCount : 0u; }
+constexpr uint32_t sort_tile_flags(long long beg, long long end, long long np) {
+  return (beg < 0 || end < beg || end > np) ? kSortBadTile : 0u;
+}
+constexpr uint32_t sort_index_flags(long long i, long long np, uint32_t bit) { return (i < 0 || i >= np) ? bit : 0u; }
+// message for raised bits (host): writes at most n bytes, returns the bits
+uint32_t sort_flags_text(uint32_t flags, int run, char *buf, size_t n);
+
 // ---- device view of one run ---------------------------------------------------
 // Field storage: component-major planes of (Nr+1) x Nz reals, z fastest; a
 // component holds NM = 2M+1 planes: q = 0 is Re(m=0), q = 2m-1 / 2m are Re / Im
@@ -69,6 +87,7 @@ struct KRun {
   long long n_keys;       // tiles * Tz * Tr
   double *red;            // reduction partials
   int32_t *work;          // tile ticket counter of the persistent push (run 0's serves a batch)
+  uint32_t *flags;        // cell-sort integrity bits (kSort*), sticky
 };
 
 // ---- push workgroup LDS ---------------------------------------------------------

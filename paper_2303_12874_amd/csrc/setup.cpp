@@ -7,6 +7,7 @@
 #include <array>
 #include <cmath>
 #include <complex>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -437,6 +438,24 @@ void laser_fields(const pic_run_desc &r, double *E, double *B) {
         }
       }
   }
+}
+
+uint32_t sort_flags_text(uint32_t flags, int run, char *buf, size_t n) {
+  if (!buf || n == 0) return flags;
+  buf[0] = 0;
+  if (!flags) return 0;
+  int w = std::snprintf(buf, n, "run %d: the cell sort met inconsistent data and skipped it (electrons lost or "
+                        "duplicated):", run);
+  const struct {
+    uint32_t bit;
+    const char *what;
+  } names[] = {{kSortBadCount, " cell counts do not sum to the electrons;"},
+               {kSortBadTile, " a tile's electron range out of bounds;"},
+               {kSortBadSlot, " a sorted slot out of bounds;"},
+               {kSortBadSource, " a source electron out of bounds;"}};
+  for (const auto &nm : names)
+    if ((flags & nm.bit) && w >= 0 && (size_t)w < n) w += std::snprintf(buf + w, n - (size_t)w, "%s", nm.what);
+  return flags;
 }
 
 }  // namespace pic

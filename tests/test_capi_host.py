@@ -68,6 +68,20 @@ def test_bad_options_rejected():
         pic.workspace_bytes([d], coef_E=[1.0], coef_B=None)
 
 
+def test_per_run_options_are_checked():
+    """run_dt must be positive and finite for every run; run_coef_E and
+    run_coef_B come together (checked before any device call)."""
+    runs = [_desc(Nz=64), _desc(Nz=96)]
+    assert pic.workspace_bytes(runs, run_dt=[0.2, 0.15]) > 0
+    for bad in ([0.2, 0.0], [0.2, -1.0], [0.2, float("nan")]):
+        with pytest.raises(pic.PicError) as e:
+            pic.workspace_bytes(runs, run_dt=bad)
+        assert e.value.code == pic.PIC_E_INVALID
+    with pytest.raises(pic.PicError) as e:
+        pic.workspace_bytes(runs, run_coef_E=[np.ones(16), np.ones(16)])
+    assert e.value.code == pic.PIC_E_INVALID
+
+
 def test_runs_must_share_modes():
     with pytest.raises(pic.PicError) as e:
         pic.workspace_bytes([_desc(M=1), _desc(M=2)])

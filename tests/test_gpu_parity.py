@@ -133,7 +133,7 @@ def compare_divergence(sim, o, i=0):
     dg, ro, rs = sim.divergence(cut, i), beam.divergence(po, cut), beam.divergence(pg, cut)
     assert dg["count"] == ro["count"] == rs["count"], (dg["count"], ro["count"], rs["count"], gap)
     worst = 0.0
-    for k in ("w", "sum_wtx2", "sum_wty2"):
+    for k in ("w", "sum_wtx2", "sum_wty2", "rms_x", "rms_y"):  # the RMS angles come from the library itself
         worst = max(worst, abs(dg[k] / ro[k] - 1), abs(dg[k] / rs[k] - 1))
     return worst, dg["count"]
 
@@ -393,4 +393,54 @@ def test_fp64_many_electrons_per_cell():
     assert not bad, bad
     dzmax, dxy, du, _ = compare_particles(sim, o, run["Nz"])
     assert dzmax < TOL64 and dxy < TOL64 and du < TOL64, (dzmax, dxy, du)
+    sim.close()
+
+
+def test_fp64_electrons_outside_their_tile_window():
+    """The push's other path: an electron that has moved out of its sort
+    tile's LDS windows since the last sort gathers from and deposits to
+    device memory directly.  A strong, long pulse (a0 = 4) over the whole
+    small box drives the electrons forward at nearly c, the tiles are 8 x 1
+    cells (the field window reaches one column past the tile in z and no row
+    past it in r) and nothing is re-sorted after the first sort: over 32
+    steps more than half of the electron-steps (checked here from the
+    oracle's own trajectories) take that path.  FP64 bar, every array and
+    electron, and the tracked work."""
+    _say("[gpu] fp64 electrons outside their tile windows")
+    pic = _pic()
+    run = workloads.small(M=2, Nz=64, Nr=12, ppc=2, a0=4.0, n_tracked=64)["runs"][0]
+    run["pulses"] = [dict(a0=4.0, w0=3 * workloads.LAMBDA0, tau=6 * workloads.LAMBDA0, zc=2 * workloads.LAMBDA0)]
+    Tz, Tr, nsteps = 8, 1, 32
+    dt, CE, CB, _ = _setup(16, run["M"], run["dz"], run["dr"])
+    sim = pic.Simulation([workloads.to_rundesc(run)], dt=dt, coef_E=CE, coef_B=CB, tile_z=Tz, tile_r=Tr,
+                         sort_interval=1000)
+    o = oracle_of(run, dt, CE, CB)
+    Nz = run["Nz"]
+
+    def cells(P):
+        r = np.sqrt(P["x"] ** 2 + P["y"] ** 2)
+        return np.floor(P["z"]).astype(np.int64) % Nz, np.floor(r).astype(np.int64)
+
+    iz0, ir0 = cells(o.particles())
+    tz0, tr0 = iz0 // Tz, ir0 // Tr
+    outside = total = 0
+    for _ in range(nsteps):
+        iz, ir = cells(o.particles())
+        dzc = (iz - tz0 * Tz) % Nz
+        dzc = np.where(dzc > Nz // 2, dzc - Nz, dzc)
+        inside = (dzc >= -1) & (dzc <= Tz) & (ir >= tr0 * Tr) & (ir < tr0 * Tr + Tr)
+        outside += int((~inside).sum())
+        total += inside.size
+        o.step(1)
+    _say(f"  {outside / total:.2f} of the electron-steps outside their tile's windows")
+    assert outside > 0.5 * total
+    sim.step(nsteps)
+    worst = compare_fields(sim, o, run["M"], TOL64)
+    bad = {k: v for k, v in worst.items() if v > TOL64}
+    assert not bad, bad
+    dzmax, dxy, du, _ = compare_particles(sim, o, Nz)
+    assert dzmax < TOL64 and dxy < TOL64 and du < TOL64, (dzmax, dxy, du)
+    wg, wo = sim.mode_work(), o.tracked()
+    assert np.array_equal(wg["id"], wo["id"])
+    assert np.abs(wg["W"] - wo["W"]).max() <= TOL64 * max(np.abs(wo["W"]).max(), 1e-300)
     sim.close()

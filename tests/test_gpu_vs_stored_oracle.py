@@ -1,0 +1,160 @@
+"""Parity at the benchmark sizes against stored FP64 oracle results.
+
+The serial oracle needs about 15 minutes of one core for 200 steps of the
+4096 x 256 run or 20 steps of the 8192 x 512 run, too long for a test, so
+``tests/golden/make_oracle_fixtures.py`` (which calls only the oracle) ran
+it once and stored, per run, a seeded sample of every field array and mode
+(random nodes, the two rows nearest the axis, the nodes where the array is
+largest) with each array's largest value and L2 norm over the whole grid,
+every tracked electron's work, and, for the FP64 run, a sample of electrons.
+The library runs the same workload from the same description, with the
+oracle's dt and coefficients, in the launch configuration the benchmark
+uses, and is compared on the stored sample:
+
+* 4096 x 256, modes 0..2, FP64, 200 steps (the FP64 parity horizon; 30 x 4
+  tiles, sort every 8 steps): every sampled node of every array and mode,
+  every sampled electron and every tracked electron's work within 1e-10 of
+  the array's (momenta's, work's) largest value;
+* 8192 x 512, modes 0..3, FP32, 20 steps (16 x 4 tiles, sort every 16, so
+  one sort inside), and every run of the six-run FP32 scan, 20 steps each in
+  one batched context with captured-graph steps (24 x 8 tiles, sort every
+  16): the FP32 per-quantity bounds, each sampled array and mode within the
+  L2 bound (1e-4 for E and B, 3e-4 for J, relative over the sample) and
+  within the max-norm bound below, tracked gamma (p99, max) and per-mode
+  work as in the small-grid FP32 tests.
+
+Max-norm bound for FP32 (largest sampled |library - oracle| over the
+array's largest |oracle|): 1e-3 for E and B, 3e-3 for J.  The L2 bounds hold
+the bulk of an array; this one holds its worst node, where a node's error is
+not averaged with its neighbours' (J: an electron's FP32 offset difference is
+rounded to ~2^-24 cells against moves of 1e-2..1e-1 cell, 1e-5..1e-4 of its
+own current, and the few electrons of a lightly loaded node do not average
+it down).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+from test_gpu_fp32 import EBTOL, JTOL
+from test_gpu_parity import FIELD_PAIRS, TOL64, _pic, _say
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+MAXTOL_EB, MAXTOL_J = 1e-3, 3e-3
+LIB_COMP = {name: comp for name, comp, _ in FIELD_PAIRS}
+
+
+def _fixture(tag):
+    path = os.path.join(GOLDEN, f"oracle_{tag}.npz")
+    if not os.path.exists(path):
+        pytest.fail(f"missing stored oracle result {path}: run tests/golden/make_oracle_fixtures.py")
+    return dict(np.load(path, allow_pickle=False))
+
+
+def _field_errors(sim, fx, M, run=0):
+    """{(name, m): (sampled relative L2, sampled max over array max)}"""
+    out = {}
+    for name in fx["field_names"]:
+        name = str(name)
+        for m in range(M + 1):
+            key = f"{name}/m{m}"
+            idx, ref = fx[f"idx:{key}"], fx[f"val:{key}"]
+            g = sim.fields(LIB_COMP[name], m, run).ravel()[idx]
+            nr = np.linalg.norm(ref)
+            l2 = np.linalg.norm(g - ref) / nr if nr > 0 else np.linalg.norm(g)
+            amax = fx[f"max:{key}"]
+            mx = np.abs(g - ref).max() / amax if amax > 0 else np.abs(g).max()
+            out[(name, m)] = (float(l2), float(mx))
+    return out
+
+
+def _tracked(sim, fx, run=0):
+    """The library's tracked work of the stored electrons (same ids)."""
+    w = sim.mode_work(run)
+    pos = np.searchsorted(w["id"], fx["tracked_id"])
+    assert w["id"].size == int(fx["tracked_total"])
+    assert np.array_equal(w["id"][pos], fx["tracked_id"])
+    return {k: w[k][pos] for k in ("W", "gamma", "gamma_acc")}
+
+
+def _check_fp32(sim, fx, M, run, label):
+    errs = _field_errors(sim, fx, M, run)
+    worst_l2 = max(errs.items(), key=lambda kv: kv[1][0])
+    worst_mx = max(errs.items(), key=lambda kv: kv[1][1])
+    _say(f"  {label}: worst L2 {worst_l2[0]} {worst_l2[1][0]:.2e}, worst max {worst_mx[0]} {worst_mx[1][1]:.2e}")
+    for (name, m), (l2, mx) in errs.items():
+        isj = name.startswith("J")
+        assert l2 <= (JTOL if isj else EBTOL), (label, name, m, l2)
+        assert mx <= (MAXTOL_J if isj else MAXTOL_EB), (label, name, m, mx)
+    t = _tracked(sim, fx, run)
+    scale = np.maximum(fx["tracked_gamma_acc"] - 1.0, 1e-3)
+    gerr = np.abs(t["gamma_acc"] - fx["tracked_gamma_acc"]) / scale
+    wtol = 1e-3 * fx["tracked_W_absmax"] + 1e-7
+    werr = np.abs(t["W"] - fx["tracked_W"]) / wtol
+    _say(f"  {label}: gamma p99 {np.percentile(gerr, 99):.2e} max {gerr.max():.2e}; work max/tol {werr.max():.2e}")
+    assert np.percentile(gerr, 99) <= 1e-4 and gerr.max() <= 1e-3, label
+    assert werr.max() <= 1.0, label
+
+
+def test_fp64_4096x256_200_steps_match_stored_oracle():
+    _say("[gpu] 4096x256 fp64, 200 steps against the stored oracle")
+    pic = _pic()
+    fx = _fixture("c2_200")
+    run = workloads.config("c2")["runs"][0]
+    sim = pic.Simulation([workloads.to_rundesc(run)], dt=float(fx["dt"]), coef_E=fx["coef_E"], coef_B=fx["coef_B"],
+                         tile_z=30, tile_r=4, sort_interval=8)
+    sim.step(int(fx["steps"]))
+    errs = _field_errors(sim, fx, run["M"])
+    worst = max(errs.items(), key=lambda kv: kv[1][1])
+    _say(f"  worst array {worst[0]}: {worst[1][1]:.2e} of its largest value")
+    bad = {k: v[1] for k, v in errs.items() if v[1] > TOL64}
+    assert not bad, bad
+    P = sim.particles()
+    order = np.argsort(P["id"])
+    pos = order[np.searchsorted(P["id"], fx["p_id"], sorter=order)]
+    assert np.array_equal(P["id"][pos], fx["p_id"])
+    dz = np.abs(P["z"][pos] - fx["p_z"])
+    dz = np.minimum(dz, run["Nz"] - dz)
+    dxy = max(np.abs(P[k][pos] - fx[f"p_{k}"]).max() for k in ("x", "y"))
+    du = max(np.abs(P[k][pos] - fx[f"p_{k}"]).max() for k in ("ux", "uy", "uz")) / float(fx["p_umax"])
+    _say(f"  electrons: z {dz.max():.2e} cells, x/y {dxy:.2e} cells, u {du:.2e} of the largest")
+    assert dz.max() < TOL64 and dxy < TOL64 and du < TOL64
+    t = _tracked(sim, fx)
+    wmax = max(np.abs(fx["tracked_W"]).max(), 1e-300)
+    assert np.abs(t["W"] - fx["tracked_W"]).max() <= TOL64 * wmax
+    assert np.abs(t["gamma_acc"] - fx["tracked_gamma_acc"]).max() <= TOL64 * np.abs(fx["tracked_gamma_acc"]).max()
+    sim.close()
+
+
+def test_fp32_8192x512_20_steps_match_stored_oracle():
+    _say("[gpu] 8192x512 fp32, 20 steps against the stored oracle")
+    pic = _pic()
+    fx = _fixture("c5_20")
+    run = workloads.config("c5")["runs"][0]
+    sim = pic.Simulation([workloads.to_rundesc(run)], precision=pic.PREC_FP32, dt=float(fx["dt"]),
+                         coef_E=fx["coef_E"], coef_B=fx["coef_B"], tile_z=16, tile_r=4, sort_interval=16)
+    sim.step(int(fx["steps"]))
+    _check_fp32(sim, fx, run["M"], 0, "8192x512")
+    sim.close()
+
+
+def test_fp32_six_run_scan_each_run_matches_stored_oracle():
+    _say("[gpu] six-run fp32 scan, graph steps, every run against its stored oracle")
+    pic = _pic()
+    runs = workloads.config("c4")["runs"]
+    fxs = [_fixture(f"c4_r{k}_20") for k in range(len(runs))]
+    nsteps = int(fxs[0]["steps"])
+    sim = pic.Simulation([workloads.to_rundesc(r, n_steps=nsteps) for r in runs], precision=pic.PREC_FP32,
+                         run_dt=[float(f["dt"]) for f in fxs], run_coef_E=[f["coef_E"] for f in fxs],
+                         run_coef_B=[f["coef_B"] for f in fxs], tile_z=24, tile_r=8, sort_interval=16,
+                         use_graph=True)
+    for k, f in enumerate(fxs):
+        assert sim.info(k)["dt"] == float(f["dt"])
+    sim.step(nsteps + 5)  # each run stops at its own limit
+    for k, (run, fx) in enumerate(zip(runs, fxs)):
+        assert sim.info(k)["steps_done"] == nsteps
+        _check_fp32(sim, fx, run["M"], k, f"run {k} ({run['Nz']}x{run['Nr']})")
+    sim.close()

@@ -53,3 +53,14 @@ def test_host_setup_from_threads_under_thread_sanitizer(tmp_path):
                           os.path.join(ROOT, "paper_2303_12874_amd", "csrc", "setup.cpp")], tmp_path / "host_threads",
                          tmp_path, {"TSAN_OPTIONS": "halt_on_error=1"})
     assert "threads ok" in out
+
+
+def test_cell_sort_integrity_flags_on_host(tmp_path):
+    """The checks the sort kernels make (which bit a bad tile range, slot,
+    source or count raises) and the message the synchronising calls return,
+    built for the host under the sanitizers."""
+    out = _build_and_run(["g++", "-std=c++17", *SAN, "-I", os.path.join(ROOT, "include"),
+                          os.path.join(ROOT, "tests", "sanitize", "sort_flags.cpp"),
+                          os.path.join(ROOT, "paper_2303_12874_amd", "csrc", "setup.cpp")], tmp_path / "sort_flags",
+                         tmp_path)
+    assert "sort flags ok" in out
