@@ -199,8 +199,8 @@ __device__ __forceinline__ int batch_run(const Batch &b, long long g) {
 //    Bbar_z, each NM planes) and one pad;
 //  * the current of the whole tile over the node window [z0-1, z0+Tz+2) x
 //    [r0-1, r0+Tr+2) (every move of less than one cell from a cell of the
-//    tile stays inside it), records of 3 NM FP64 sums, added to the global
-//    arrays once.
+//    tile stays inside it), records of 3 NM sums in the run's real type,
+//    added to the global arrays once.
 // An electron that drifted out of either window since the last sort gathers
 // from, or deposits to, global memory directly.
 template <typename R, int M>
@@ -209,22 +209,23 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
   constexpr int NMP = 2 * (M + 1);    // reals per field record in registers
   constexpr int FS = 6 * NM + 1;      // reals per field-window node, odd: lanes in
                                       // consecutive nodes hit distinct LDS banks
-  constexpr int JS = 3 * NM;          // FP64 sums per current-window node
+  constexpr int JS = 3 * NM;          // sums per current-window node
   constexpr bool F64 = std::is_same<R, double>::value;
-  // the tile current is accumulated in FP64 for both precisions: the LDS
-  // double-precision atomic add is the fast one on gfx950, and the sum of
-  // thousands of FP32 contributions keeps its low bits until the flush
+  constexpr int PREC = F64 ? PIC_PREC_FP64 : PIC_PREC_FP32;
+  // the tile current is summed in the run's real type (ds_add_f64 or
+  // ds_add_f32): a tile's node sums a few hundred contributions, far fewer
+  // than would let FP32 rounding approach the FP32 form's current bound
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  double *lds = (double *)lds_raw;
+  R *lds = (R *)lds_raw;
   const int par = bt.par;
   const int TZ = bt.run[0].Tz, TR = bt.run[0].Tr;  // one sort tile for every run of a batch
   const int WZ = TZ + 3, WR = TR + 3;
   const long long TT = (long long)TZ * TR;
-  const int RJ = current_window_row(M, TZ);  // FP64 sums per current-window row (padded)
+  const int RJ = current_window_row(M, TZ, PREC);  // sums per current-window row (padded)
   const int nlds = RJ * WR;
   const int FZ = field_window_z(TZ), FR = field_window_r(TR);
-  const int RF = field_window_row(M, TZ, F64 ? PIC_PREC_FP64 : PIC_PREC_FP32);  // reals per field-window row
-  R *fw = (R *)(lds + nlds);
+  const int RF = field_window_row(M, TZ, PREC);  // reals per field-window row
+  R *fw = (R *)(lds_raw + current_window_bytes(M, TZ, TR, PREC));
 
   // Persistent: each workgroup takes tiles (of all runs of the batch) from a
   // ticket counter, zero before the launch, until none are left; the dealing
@@ -267,7 +268,7 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
   };
 
   // the current window starts at zero; each flush clears what it adds
-  for (int e = threadIdx.x; e < nlds; e += blockDim.x) lds[e] = 0.0;
+  for (int e = threadIdx.x; e < nlds; e += blockDim.x) lds[e] = R(0);
   if (gt < t_hi)
     for (int e = threadIdx.x; e < FZ * FR; e += blockDim.x) {
       R v[FS];
@@ -427,15 +428,16 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
     }
 
     // ---- reconstruct Re sum_m F^m e^{i m phi}, rotate to Cartesian ----
-    R Em[M + 1][3];
+    // Ecyl[m] = (E_r, E_phi, E_z) of mode m at the electron's azimuth (kept
+    // for the per-mode work of tracked electrons); the modes are summed in
+    // cylindrical components and rotated to (x, y) once.
+    R Ecyl[M + 1][3];
     R Ec[3], Bc[3];
     {
-      Em[0][0] = er[0] * c0 - ep[0] * s0;
-      Em[0][1] = er[0] * s0 + ep[0] * c0;
-      Em[0][2] = ez[0];
-      Bc[0] = br[0] * c0 - bp[0] * s0;
-      Bc[1] = br[0] * s0 + bp[0] * c0;
-      Bc[2] = bz[0];
+      Ecyl[0][0] = er[0];
+      Ecyl[0][1] = ep[0];
+      Ecyl[0][2] = ez[0];
+      R Er = er[0], Ep = ep[0], Ez = ez[0], Br = br[0], Bp = bp[0], Bz = bz[0];
       R ere = 1, eim = 0;
 #pragma unroll
       for (int m = 1; m <= M; ++m) {
@@ -444,24 +446,22 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
         ere = nre;
         eim = nim;
         const int a = 2 * m, b = 2 * m + 1;
-        const R Fr = er[a] * ere - er[b] * eim, Fp = ep[a] * ere - ep[b] * eim;
-        Em[m][0] = Fr * c0 - Fp * s0;
-        Em[m][1] = Fr * s0 + Fp * c0;
-        Em[m][2] = ez[a] * ere - ez[b] * eim;
-        const R Gr = br[a] * ere - br[b] * eim, Gp = bp[a] * ere - bp[b] * eim;
-        Bc[0] += Gr * c0 - Gp * s0;
-        Bc[1] += Gr * s0 + Gp * c0;
-        Bc[2] += bz[a] * ere - bz[b] * eim;
+        Ecyl[m][0] = er[a] * ere - er[b] * eim;
+        Ecyl[m][1] = ep[a] * ere - ep[b] * eim;
+        Ecyl[m][2] = ez[a] * ere - ez[b] * eim;
+        Er += Ecyl[m][0];
+        Ep += Ecyl[m][1];
+        Ez += Ecyl[m][2];
+        Br += br[a] * ere - br[b] * eim;
+        Bp += bp[a] * ere - bp[b] * eim;
+        Bz += bz[a] * ere - bz[b] * eim;
       }
-      Ec[0] = Em[0][0];
-      Ec[1] = Em[0][1];
-      Ec[2] = Em[0][2];
-#pragma unroll
-      for (int m = 1; m <= M; ++m) {
-        Ec[0] += Em[m][0];
-        Ec[1] += Em[m][1];
-        Ec[2] += Em[m][2];
-      }
+      Ec[0] = Er * c0 - Ep * s0;
+      Ec[1] = Er * s0 + Ep * c0;
+      Ec[2] = Ez;
+      Bc[0] = Br * c0 - Bp * s0;
+      Bc[1] = Br * s0 + Bp * c0;
+      Bc[2] = Bz;
     }
 
     // ---- Boris, q/m = -1 (Eq. (6)) ----
@@ -503,15 +503,15 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
         const double v1 = ((double)um[1] + (double)up[1]) * inv;
         const double v2 = ((double)um[2] + (double)up[2]) * inv;
         double *W = k.W + (long long)lo * (M + 1);
-#pragma unroll
-        for (int m = 0; m <= M; ++m)
-          W[m] += -k.dt * ((double)Em[m][0] * v0 + (double)Em[m][1] * v1 + (double)Em[m][2] * v2);
         // the same work split by field direction, Eq. (17)
         double ez = 0.0, ep = 0.0;
 #pragma unroll
         for (int m = 0; m <= M; ++m) {
-          ez += (double)Em[m][2];
-          ep += (double)Em[m][0] * v0 + (double)Em[m][1] * v1;
+          const double fr = Ecyl[m][0], fp = Ecyl[m][1], fz = Ecyl[m][2];
+          const double ex = fr * c0 - fp * s0, ey = fr * s0 + fp * c0;  // mode m's E in (x, y)
+          W[m] += -k.dt * (ex * v0 + ey * v1 + fz * v2);
+          ez += fz;
+          ep += ex * v0 + ey * v1;
         }
         double *Wc = k.Wc + (long long)lo * 2;
         Wc[0] += -k.dt * ez * v2;
@@ -581,149 +581,182 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
       const R cmid = rm2 > R(0) ? xm * irm : R(1), smid = ym * irm;
       const R vphi = rm2 > R(0) ? (cmid * un[1] - smid * un[0]) * inv_g : R(0);
       const int di = clampi(i1 - i0, -1, 1);
-      const int oz0 = di < 0 ? 1 : 0, oz1 = oz0 + di;  // cells of the two positions in the 3-node window
-      const int ib = i0 - oz0;
       const int dj = j1 - j0;
-      const int or0 = dj < 0 ? 1 : 0, or1 = or0 + dj;
-      const int jb = j0 - or0;
-      // the third node column (row) of the window carries current only for an
-      // electron that crossed a z (r) cell face; skip it when no lane did
-      const bool zx = __any(di != 0), rx = __any(dj != 0);
-      R Sz0[3], Sz1[3], Sr0[3], Sr1[3];
       const R g0 = fr;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        Sz0[a] = (a == oz0) ? R(1) - f0 : ((a == oz0 + 1) ? f0 : R(0));
-        Sz1[a] = (a == oz1) ? R(1) - f1 : ((a == oz1 + 1) ? f1 : R(0));
-        Sr0[a] = (a == or0) ? R(1) - g0 : ((a == or0 + 1) ? g0 : R(0));
-        Sr1[a] = (a == or1) ? R(1) - g1 : ((a == or1 + 1) ? g1 : R(0));
-      }
-      R Wz[3][3], Wr[3][3], Ss[3][3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-          Wz[a][b] = (Sz1[a] - Sz0[a]) * (Sr0[b] + Sr1[b]) * R(0.5);
-          Wr[a][b] = (Sr1[b] - Sr0[b]) * (Sz0[a] + Sz1[a]) * R(0.5);
-          Ss[a][b] = Sz0[a] * Sr0[b] + Sz1[a] * Sr1[b];
-        }
-      // the whole deposit, into `dep(c, plane, b, a, v)`: component c (0 r,
-      // 1 phi, 2 z), window node (ib + a, jb + b)
-      // Node weights, shared by every mode (in FP64 for both precisions: each
-      // contribution is then one FP64 product of a node weight and a mode
-      // coefficient): J_z at face (ib+a+1/2, jb+b) carries minus the running
-      // sum of Wz behind it, J_r at (ib+a, jb+b+1/2) minus the running sum of
-      // Wr below it, J_phi at node (ib+a, jb+b) half the summed shape.
-      double wz[3][2], wr[3][2], ws[3][3];
-#pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        R run = 0;
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          run += Wz[a][b];
-          wz[b][a] = -(double)run;
-        }
-      }
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        R run = 0;
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          run += Wr[a][b];
-          wr[a][b] = -(double)run;
-        }
-#pragma unroll
-        for (int b = 0; b < 3; ++b) ws[a][b] = (double)(R(0.5) * Ss[a][b]);
-      }
-      const bool axis_row = jb == 0;  // row b = 0 of the window is the axis
-      // the whole deposit, into `dep(c, plane, b, a, v)`: component c (0 r,
-      // 1 phi, 2 z), window node (ib + a, jb + b)
-      auto deposit = [&](auto &&dep) {
-        // e^{-i m phi} at the old, new and mid positions, by recurrence
-        R e0r = 1, e0i = 0, e1r = 1, e1i = 0, emr = 1, emi = 0;
+      // Mode coefficients, mode by mode with e^{-i m phi} of the old and new
+      // positions by recurrence: the flux phase cq xi, xi = (e0 + e1)/2, of
+      // J_z and J_r; for J_phi, m = 0 takes cq v_phi, m >= 1 the closure
+      // cq (i/m)(e1 - e0) (its factor r_j and the node volume cancel into the
+      // row factor of the E update), which is zero on the axis row, where
+      // m = 1 takes cq v_phi e_mid instead (cq = c_m q).
+      auto for_modes = [&](bool axis_row, auto &&body) {
+        R e0r = 1, e0i = 0, e1r = 1, e1i = 0;
 #pragma unroll
         for (int m = 0; m <= M; ++m) {
           if (m > 0) {
-            R tr_ = e0r * c0 + e0i * s0, ti = e0i * c0 - e0r * s0;
-            e0r = tr_;
-            e0i = ti;
-            tr_ = e1r * c1 + e1i * s1;
-            ti = e1i * c1 - e1r * s1;
-            e1r = tr_;
-            e1i = ti;
-            tr_ = emr * cmid + emi * smid;
-            ti = emi * cmid - emr * smid;
-            emr = tr_;
-            emi = ti;
+            R t = e0r * c0 + e0i * s0;
+            e0i = e0i * c0 - e0r * s0;
+            e0r = t;
+            t = e1r * c1 + e1i * s1;
+            e1i = e1i * c1 - e1r * s1;
+            e1r = t;
           }
           const R cq = (m == 0 ? R(1) : R(2)) * q;
-          const int qa = m == 0 ? 0 : 2 * m - 1, qb = 2 * m;
-          // mode coefficients: the flux phase cq xi for J_z and J_r; for
-          // J_phi, m = 0 takes cq v_phi, m >= 1 the closure cq (i/m)(e1 - e0)
-          // times r_j (zero on the axis row, where m = 1 takes cq v_phi e_mid)
-          const double fa = (double)(cq * (R(0.5) * (e0r + e1r))), fb = (double)(cq * (R(0.5) * (e0i + e1i)));
-          double pa, pb, pa0, pb0;
+          const R fa = cq * (R(0.5) * (e0r + e1r)), fb = cq * (R(0.5) * (e0i + e1i));
+          R pa, pb, pa0, pb0;
           if (m == 0) {
-            pa = pa0 = (double)(cq * vphi);
-            pb = pb0 = 0.0;
+            pa = pa0 = cq * vphi;
+            pb = pb0 = R(0);
           } else {
-            pa = (double)(-cq * (e1i - e0i) * (R(1) / (R)m));
-            pb = (double)(cq * (e1r - e0r) * (R(1) / (R)m));
-            const double ax_a = m == 1 ? (double)(cq * vphi * emr) : 0.0;
-            const double ax_b = m == 1 ? (double)(cq * vphi * emi) : 0.0;
-            pa0 = axis_row ? ax_a : pa;
-            pb0 = axis_row ? ax_b : pb;
+            pa = -cq * (e1i - e0i) * (R(1) / (R)m);
+            pb = cq * (e1r - e0r) * (R(1) / (R)m);
+            pa0 = axis_row ? (m == 1 ? cq * vphi * cmid : R(0)) : pa;
+            pb0 = axis_row ? (m == 1 ? -cq * vphi * smid : R(0)) : pb;
           }
-          // a node past the first two columns (rows) takes current only from
-          // a lane whose electron crossed a z (r) face: the wave skips it when
-          // no lane did, and each other lane masks itself off
-#pragma unroll
-          for (int b = 0; b < 3; ++b) {
-            if (b == 2 && !rx) continue;
-#pragma unroll
-            for (int a = 0; a < 2; ++a) {
-              if (a == 1 && !zx) continue;
-              if ((a == 1 && di == 0) || (b == 2 && dj == 0)) continue;
-              dep(2, qa, b, a, wz[b][a] * fa);
-              if (m > 0) dep(2, qb, b, a, wz[b][a] * fb);
+          body(m, m == 0 ? 0 : 2 * m - 1, 2 * m, fa, fb, pa, pb, pa0, pb0);
+        }
+      };
+      if (!__any(di != 0 || dj != 0)) {
+        // No electron of the wavefront left its cell: each deposits on the
+        // 2 x 2 nodes (i0 + a, j0 + b) of its cell.  J_z at (i0+1/2, j0+b)
+        // carries (f1 - f0) times the mean radial shape of row b, J_r at
+        // (i0+a, j0+1/2) (g1 - g0) times the mean axial shape of column a,
+        // J_phi at (i0+a, j0+b) half the summed shape (the 2D Esirkepov
+        // weights of a move inside one cell).
+        const R df = f1 - f0, dg = g1 - g0;
+        const R sz0 = R(1) - f0, sz1 = R(1) - f1, sr0 = R(1) - g0, sr1 = R(1) - g1;
+        const R wz0 = df * (R(0.5) * (sr0 + sr1)), wz1 = df * (R(0.5) * (g0 + g1));
+        const R wr0 = dg * (R(0.5) * (sz0 + sz1)), wr1 = dg * (R(0.5) * (f0 + f1));
+        const R w00 = R(0.5) * (sz0 * sr0 + sz1 * sr1), w10 = R(0.5) * (f0 * sr0 + f1 * sr1);
+        const R w01 = R(0.5) * (sz0 * g0 + sz1 * g1), w11 = R(0.5) * (f0 * g0 + f1 * g1);
+        auto deposit = [&](auto &&dep) {
+          for_modes(j0 == 0, [&](int m, int qa, int qb, R fa, R fb, R pa, R pb, R pa0, R pb0) {
+            dep(2, qa, 0, 0, wz0 * fa);
+            dep(2, qa, 1, 0, wz1 * fa);
+            dep(0, qa, 0, 0, wr0 * fa);
+            dep(0, qa, 0, 1, wr1 * fa);
+            dep(1, qa, 0, 0, w00 * pa0);
+            dep(1, qa, 0, 1, w10 * pa0);
+            dep(1, qa, 1, 0, w01 * pa);
+            dep(1, qa, 1, 1, w11 * pa);
+            if (m > 0) {
+              dep(2, qb, 0, 0, wz0 * fb);
+              dep(2, qb, 1, 0, wz1 * fb);
+              dep(0, qb, 0, 0, wr0 * fb);
+              dep(0, qb, 0, 1, wr1 * fb);
+              dep(1, qb, 0, 0, w00 * pb0);
+              dep(1, qb, 0, 1, w10 * pb0);
+              dep(1, qb, 1, 0, w01 * pb);
+              dep(1, qb, 1, 1, w11 * pb);
             }
+          });
+        };
+        if ((i0 - zlo >= 0) && (i0 + 1 - zlo < WZ) && (j0 - rlo >= 0) && (j0 + 1 - rlo < WR)) {
+          R *jw = lds + (j0 - rlo) * RJ + (i0 - zlo) * JS;
+          deposit([&](int c, int qq, int b, int a, R v) { lds_add(jw + b * RJ + a * JS + c * NM + qq, v); });
+        } else {
+          const int col1 = wrap_once(i0 + 1, Nz);
+          deposit([&](int c, int qq, int b, int a, R v) {
+            atomic_add(J + (c * NM + qq) * plane + (long long)(j0 + b) * Nz + (a ? col1 : i0), v);
+          });
+        }
+      } else {
+        // General move: the 3 x 3 node window [ib, ib+2] x [jb, jb+2] that
+        // holds both positions; shapes S0, S1 on it, the 2D Esirkepov weights
+        // Wz = dSz (Sr0 + Sr1)/2, Wr = dSr (Sz0 + Sz1)/2, and the fluxes minus
+        // their running sums.
+        const int oz0 = di < 0 ? 1 : 0, oz1 = oz0 + di;  // cells of the two positions in the window
+        const int ib = i0 - oz0;
+        const int or0 = dj < 0 ? 1 : 0, or1 = or0 + dj;
+        const int jb = j0 - or0;
+        // the third node column (row) of the window carries current only for an
+        // electron that crossed a z (r) cell face; skip it when no lane did
+        const bool zx = __any(di != 0), rx = __any(dj != 0);
+        R Sz0[3], Sz1[3], Sr0[3], Sr1[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          Sz0[a] = (a == oz0) ? R(1) - f0 : ((a == oz0 + 1) ? f0 : R(0));
+          Sz1[a] = (a == oz1) ? R(1) - f1 : ((a == oz1 + 1) ? f1 : R(0));
+          Sr0[a] = (a == or0) ? R(1) - g0 : ((a == or0 + 1) ? g0 : R(0));
+          Sr1[a] = (a == or1) ? R(1) - g1 : ((a == or1 + 1) ? g1 : R(0));
+        }
+        // J_z at face (ib+a+1/2, jb+b): minus the running sum of Wz behind it;
+        // J_r at (ib+a, jb+b+1/2): minus the running sum of Wr below it;
+        // J_phi at node (ib+a, jb+b): half the summed shape
+        R wz[3][2], wr[3][2], ws[3][3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          R run = 0;
+#pragma unroll
+          for (int a = 0; a < 2; ++a) {
+            run += (Sz1[a] - Sz0[a]) * (Sr0[b] + Sr1[b]) * R(0.5);
+            wz[b][a] = -run;
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          R run = 0;
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            run += (Sr1[b] - Sr0[b]) * (Sz0[a] + Sz1[a]) * R(0.5);
+            wr[a][b] = -run;
           }
 #pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            if (a == 2 && !zx) continue;
-#pragma unroll
-            for (int b = 0; b < 2; ++b) {
-              if (b == 1 && !rx) continue;
-              if ((a == 2 && di == 0) || (b == 1 && dj == 0)) continue;
-              dep(0, qa, b, a, wr[a][b] * fa);
-              if (m > 0) dep(0, qb, b, a, wr[a][b] * fb);
-            }
-          }
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            if (a == 2 && !zx) continue;
+          for (int b = 0; b < 3; ++b) ws[a][b] = R(0.5) * (Sz0[a] * Sr0[b] + Sz1[a] * Sr1[b]);
+        }
+        // the whole deposit, into `dep(c, plane, b, a, v)`: component c (0 r,
+        // 1 phi, 2 z), window node (ib + a, jb + b).  A node past the first
+        // two columns (rows) takes current only from a lane whose electron
+        // crossed a z (r) face: the wave skips it when no lane did, and each
+        // other lane masks itself off.
+        auto deposit = [&](auto &&dep) {
+          for_modes(jb == 0, [&](int m, int qa, int qb, R fa, R fb, R pa, R pb, R pa0, R pb0) {
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
               if (b == 2 && !rx) continue;
-              if ((a == 2 && di == 0) || (b == 2 && dj == 0)) continue;
-              dep(1, qa, b, a, ws[a][b] * (b == 0 ? pa0 : pa));
-              if (m > 0) dep(1, qb, b, a, ws[a][b] * (b == 0 ? pb0 : pb));
-            }
-          }
-        }
-      };
-      // the 3 x 3 node window [ib, ib+2] x [jb, jb+2] inside the tile's LDS window?
-      if ((ib - zlo >= 0) && (ib + 2 - zlo < WZ) && (jb - rlo >= 0) && (jb + 2 - rlo < WR)) {
-        double *jw = lds + (jb - rlo) * RJ + (ib - zlo) * JS;
-        const int rowJ = RJ;
-        deposit([&](int c, int qq, int b, int a, double v) { lds_add(jw + b * rowJ + a * JS + c * NM + qq, v); });
-      } else {
-        int col[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) col[a] = wrap_once(ib + a, Nz);
-        deposit([&](int c, int qq, int b, int a, double v) {
-          atomic_add(J + (c * NM + qq) * plane + (long long)(jb + b) * Nz + col[a], (R)v);
-        });
+              for (int a = 0; a < 2; ++a) {
+                if (a == 1 && !zx) continue;
+                if ((a == 1 && di == 0) || (b == 2 && dj == 0)) continue;
+                dep(2, qa, b, a, wz[b][a] * fa);
+                if (m > 0) dep(2, qb, b, a, wz[b][a] * fb);
+              }
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              if (a == 2 && !zx) continue;
+#pragma unroll
+              for (int b = 0; b < 2; ++b) {
+                if (b == 1 && !rx) continue;
+                if ((a == 2 && di == 0) || (b == 1 && dj == 0)) continue;
+                dep(0, qa, b, a, wr[a][b] * fa);
+                if (m > 0) dep(0, qb, b, a, wr[a][b] * fb);
+              }
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              if (a == 2 && !zx) continue;
+#pragma unroll
+              for (int b = 0; b < 3; ++b) {
+                if (b == 2 && !rx) continue;
+                if ((a == 2 && di == 0) || (b == 2 && dj == 0)) continue;
+                dep(1, qa, b, a, ws[a][b] * (b == 0 ? pa0 : pa));
+                if (m > 0) dep(1, qb, b, a, ws[a][b] * (b == 0 ? pb0 : pb));
+              }
+            }
+          });
+        };
+        if ((ib - zlo >= 0) && (ib + 2 - zlo < WZ) && (jb - rlo >= 0) && (jb + 2 - rlo < WR)) {
+          R *jw = lds + (jb - rlo) * RJ + (ib - zlo) * JS;
+          deposit([&](int c, int qq, int b, int a, R v) { lds_add(jw + b * RJ + a * JS + c * NM + qq, v); });
+        } else {
+          int col[3];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) col[a] = wrap_once(ib + a, Nz);
+          deposit([&](int c, int qq, int b, int a, R v) {
+            atomic_add(J + (c * NM + qq) * plane + (long long)(jb + b) * Nz + col[a], v);
+          });
+        }
       }
     }
 
@@ -762,11 +795,11 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
           if (row < 0 || row > Nr) continue;  // never deposited to
           // a node that takes current lies in [-1, Nz + 1]; the others hold zero
           const unsigned off = (unsigned)(row * Nz + wrap_once(zlo + lc, Nz));
-          double *src = lds + lr * RJ + lc * JS;
+          R *src = lds + lr * RJ + lc * JS;
 #pragma unroll
           for (int cq = 0; cq < JS; ++cq) {
-            const R v = (R)src[cq];
-            src[cq] = 0.0;
+            const R v = src[cq];
+            src[cq] = R(0);
             if (v != R(0)) atomic_add(J + cq * plane + off, v);
           }
         }
@@ -787,11 +820,11 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
         if (row < 0 || row > Nr) continue;  // never deposited to
         // a node that takes current lies in [-1, Nz + 1]; the others hold zero
         const unsigned off = (unsigned)(row * Nz + wrap_once(zlo + lc, Nz));
-        double *src = lds + lr * RJ + lc * JS;
+        R *src = lds + lr * RJ + lc * JS;
 #pragma unroll
         for (int cq = 0; cq < JS; ++cq) {
-          const R v = (R)src[cq];
-          src[cq] = 0.0;
+          const R v = src[cq];
+          src[cq] = R(0);
           if (v != R(0)) atomic_add(J + cq * plane + off, v);
         }
       }

@@ -92,7 +92,7 @@ struct KRun {
 
 // ---- push workgroup LDS ---------------------------------------------------------
 // One push workgroup per sort tile of Tz x Tr cells.  Its LDS holds
-//  * the tile's current window, FP64 for both precisions, 3 components x NM
+//  * the tile's current window in the run's real type, 3 components x NM
 //    planes x (Tz+3) x (Tr+3) nodes from cell (z0-1, r0-1): every move of
 //    less than a cell from a cell of the tile deposits inside it;
 //  * the field window of E and Bbar, records of 6 components x NM planes
@@ -112,9 +112,11 @@ constexpr int kBankBytes = 256;  // 64 LDS banks of 4 bytes
 constexpr int field_window_z(int Tz) { return Tz + 2 + 2 * kFieldMarginZ; }
 constexpr int field_window_r(int Tr) { return Tr + 2 + 2 * kFieldMarginR; }
 constexpr int pos_mod(int a, int m) { return ((a % m) + m) % m; }
-// FP64 sums per current-window row: (Tz + 3) nodes of 3 NM, plus the pad
-constexpr int current_window_row(int M, int Tz) {
-  return 3 * (2 * M + 1) * (Tz + 3) + pos_mod(-3 * 3 * (2 * M + 1), kBankBytes / 8);
+// Sums per current-window row: (Tz + 3) nodes of 3 NM, plus the pad.  The
+// tile current is summed in the run's real type (FP64 or FP32 LDS atomics).
+constexpr int current_window_row(int M, int Tz, int precision) {
+  return 3 * (2 * M + 1) * (Tz + 3) +
+         pos_mod(-3 * 3 * (2 * M + 1), kBankBytes / (precision == PIC_PREC_FP64 ? 8 : 4));
 }
 // reals per field-window row: field_window_z nodes of 6 NM + 1, plus the pad
 constexpr int field_window_row(int M, int Tz, int precision) {
@@ -122,10 +124,17 @@ constexpr int field_window_row(int M, int Tz, int precision) {
          pos_mod(-(field_window_z(Tz) - Tz) * (6 * (2 * M + 1) + 1),
                  kBankBytes / (precision == PIC_PREC_FP64 ? 8 : 4));
 }
-inline size_t current_window_words(int M, int Tz, int Tr) { return (size_t)current_window_row(M, Tz) * (Tr + 3); }
+constexpr size_t current_window_words(int M, int Tz, int Tr, int precision) {
+  return (size_t)current_window_row(M, Tz, precision) * (Tr + 3);
+}
+// bytes of the current window, rounded up to 16 so that the field window after it is aligned
+constexpr size_t current_window_bytes(int M, int Tz, int Tr, int precision) {
+  const size_t w = precision == PIC_PREC_FP64 ? 8 : 4;
+  return (current_window_words(M, Tz, Tr, precision) * w + 15) / 16 * 16;
+}
 inline size_t push_lds_bytes(int M, int Tz, int Tr, int precision) {
   const size_t w = precision == PIC_PREC_FP64 ? 8 : 4;
-  return current_window_words(M, Tz, Tr) * 8 + (size_t)field_window_row(M, Tz, precision) * field_window_r(Tr) * w;
+  return current_window_bytes(M, Tz, Tr, precision) + (size_t)field_window_row(M, Tz, precision) * field_window_r(Tr) * w;
 }
 
 // ---- batched launches ---------------------------------------------------------
