@@ -158,6 +158,17 @@ typedef struct pic_opts {
   const double *run_dt;
   const double *run_coef_E;
   const double *run_coef_B;
+  /* 1 (PIC_PREC_FP64 only): bitwise reproducible steps.  The deposit's sums,
+   * whose order the atomics choose, are taken exactly in integers: each
+   * contribution v (|v| <= 4 |q|, q the largest electron charge of the run)
+   * is scaled by a power of two 2^K with 4 |q| 2^K <= 2^30 and split into
+   * a = rint(v 2^K) and b = rint((v 2^K - a) 2^31), both summed with 64-bit
+   * integer atomics, and each node's current is a 2^-K + b 2^-(K+31) in
+   * FP64 (quantisation below 2^-62 of the largest contribution).  Results
+   * are then the same whatever the order of the atomics, the sort tile and
+   * interval, and with or without captured graphs; the deposit costs more
+   * (about twice the LDS and more arithmetic).  PIC_E_INVALID in FP32.      */
+  int32_t deterministic;
 } pic_opts;
 
 typedef struct pic_ctx pic_ctx;
@@ -300,7 +311,8 @@ int pic_checkpoint(pic_ctx *ctx, void *host_buf, size_t *bytes);
 
 /* Load a checkpoint into a context created by pic_init with the same runs and
  * options (checked: format version, run descriptors, precision, sort tile
- * and interval, current correction, solver coefficients); stepping then
+ * and interval, current correction, deterministic mode, solver
+ * coefficients); stepping then
  * continues where the checkpointed
  * context was.  PIC_E_INVALID if the checkpoint does not belong to such a
  * context; nothing is changed then.                                         */

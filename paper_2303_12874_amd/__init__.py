@@ -56,7 +56,7 @@ class _Opts(C.Structure):
         ("sort_interval", C.c_int32), ("tile_z", C.c_int32), ("tile_r", C.c_int32),
         ("use_graph", C.c_int32), ("current", C.c_int32),
         ("run_dt", C.POINTER(C.c_double)), ("run_coef_E", C.POINTER(C.c_double)),
-        ("run_coef_B", C.POINTER(C.c_double)),
+        ("run_coef_B", C.POINTER(C.c_double)), ("deterministic", C.c_int32),
     ]
 
 
@@ -236,7 +236,7 @@ def workspace_bytes(runs: Sequence[RunDesc], precision=PREC_FP64, solver=SOLVER_
 
 def _make_opts(precision, solver, n_coef, dt=0.0, coef_E=None, coef_B=None, cfl_fraction=0.0, fit_band=0.0,
                sort_interval=0, tile_z=0, tile_r=0, use_graph=False, current=CURRENT_FILTER, run_dt=None,
-               run_coef_E=None, run_coef_B=None):
+               run_coef_E=None, run_coef_B=None, deterministic=False):
     """pic_opts.  run_dt: one dt per run; run_coef_E / run_coef_B: one
     coefficient vector per run (sequences over the runs)."""
     o = _Opts()
@@ -252,6 +252,7 @@ def _make_opts(precision, solver, n_coef, dt=0.0, coef_E=None, coef_B=None, cfl_
             setattr(o, name, a.ctypes.data_as(C.POINTER(C.c_double)))
     o.sort_interval, o.tile_z, o.tile_r, o.use_graph = sort_interval, tile_z, tile_r, int(use_graph)
     o.current = current
+    o.deterministic = int(bool(deterministic))
     return o, keep
 
 

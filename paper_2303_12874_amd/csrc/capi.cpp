@@ -69,10 +69,10 @@ struct RunHost {
 struct Layout {
   size_t E, B0, B1, Bbar, J0, J1, rho, pz, pfz, px, py, pux, puy, puz, pw, pid;
   size_t sz, sfz, sx, sy, sux, suy, suz, sw, spid, perm, ccount, cstart, scan;
-  size_t W, Wc, tracked, CE, CB, P, H, red, gam, ids, work, total;
+  size_t W, Wc, tracked, CE, CB, P, H, red, gam, ids, work, Jfix, total;
 };
 
-Layout layout_of(const pic_run_desc &d, int prec, int N, int Tz, int Tr, long long n_keys) {
+Layout layout_of(const pic_run_desc &d, int prec, int N, int Tz, int Tr, long long n_keys, bool det) {
   const size_t rs = prec == PIC_PREC_FP64 ? 8 : 4;
   const int NM = 2 * d.M + 1;  // mode planes per component
   const size_t plane = (size_t)(d.Nr + 1) * d.Nz;
@@ -125,6 +125,8 @@ Layout layout_of(const pic_run_desc &d, int prec, int N, int Tz, int Tr, long lo
   L.work = take(32);  // tile ticket (16 bytes), then the sort's flag word
   L.gam = take((size_t)(d.n_tracked > 0 ? d.n_tracked : 1) * 8);
   L.ids = take((size_t)(d.n_tracked > 0 ? d.n_tracked : 1) * 8);
+  // deterministic mode: an integer pair (2 x 8 bytes) per value of J
+  L.Jfix = det ? take((size_t)2 * 3 * NM * plane * 8) : 0;
   L.total = o;
   (void)Tz;
   (void)Tr;
@@ -140,6 +142,7 @@ struct pic_ctx {
   unsigned char *ws = nullptr;
   int sort_interval = 0;
   int current = PIC_CURRENT_FILTER;
+  bool det = false;  // deterministic mode: integer deposit sums
   std::vector<RunHost> runs;
   // per-phase event timing
   bool profiling = false;
@@ -190,6 +193,9 @@ int validate_run(const pic_run_desc &r, int i, int N) {
       return fail(PIC_E_INVALID, "run %d: pulse %d needs w0 > 0 and tau > 0", i, p);
   const int64_t np = run_particle_count(r);
   if (np > (int64_t)kIdMask) return fail(PIC_E_INVALID, "run %d: %lld electrons exceed the id range", i, (long long)np);
+  // the push addresses a particle array with 32-bit byte offsets
+  if (np * 8 > (int64_t)UINT32_MAX)
+    return fail(PIC_E_INVALID, "run %d: %lld electrons exceed the 2^29 a run may hold", i, (long long)np);
   if (r.n_tracked < 0 || r.n_tracked > np) return fail(PIC_E_INVALID, "run %d: n_tracked out of range", i);
   if (r.n_steps < 0) return fail(PIC_E_INVALID, "run %d: n_steps < 0", i);
   // the kernels address a node inside a plane with 32-bit signed offsets
@@ -206,16 +212,17 @@ int validate_run(const pic_run_desc &r, int i, int N) {
 int choose_tiles(const pic_opts &o, int M, int *Tz, int *Tr) {
   *Tz = o.tile_z > 0 ? o.tile_z : 32;
   *Tr = o.tile_r > 0 ? o.tile_r : 8;
-  auto over = [&] { return push_lds_bytes(M, *Tz, *Tr, o.precision) > kPushLdsDefault; };
+  const bool det = o.deterministic != 0;
+  auto over = [&] { return push_lds_bytes(M, *Tz, *Tr, o.precision, det) > kPushLdsDefault; };
   while (over()) {
     if (o.tile_r <= 0 && *Tr > 4) *Tr /= 2;
     else if (o.tile_z <= 0 && *Tz > 16) *Tz -= 2;
     else if (o.tile_r <= 0 && *Tr > 1) *Tr /= 2;
     else break;
   }
-  if (push_lds_bytes(M, *Tz, *Tr, o.precision) > kPushLdsMax)
+  if (push_lds_bytes(M, *Tz, *Tr, o.precision, det) > kPushLdsMax)
     return fail(PIC_E_INVALID, "tile %dx%d needs %zu bytes of LDS (limit %zu)", *Tz, *Tr,
-                push_lds_bytes(M, *Tz, *Tr, o.precision), kPushLdsMax);
+                push_lds_bytes(M, *Tz, *Tr, o.precision, det), kPushLdsMax);
   return PIC_OK;
 }
 
@@ -345,6 +352,9 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
   if (o.sort_interval < 0 || o.tile_z < 0 || o.tile_r < 0) return fail(PIC_E_INVALID, "negative sort options");
   if (o.current != PIC_CURRENT_FILTER && o.current != PIC_CURRENT_EXACT_JZ)
     return fail(PIC_E_INVALID, "current must be PIC_CURRENT_FILTER or PIC_CURRENT_EXACT_JZ");
+  if (o.deterministic != 0 && o.deterministic != 1) return fail(PIC_E_INVALID, "deterministic must be 0 or 1");
+  if (o.deterministic && o.precision != PIC_PREC_FP64)
+    return fail(PIC_E_INVALID, "the deterministic mode is for PIC_PREC_FP64 runs");
   for (int i = 0; i < n_runs; ++i) {
     TRY(validate_run(runs[i], i, N));
     if (runs[i].M != runs[0].M) return fail(PIC_E_INVALID, "all runs of one context must share M");
@@ -357,7 +367,7 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
   std::vector<size_t> offs;
   size_t total = 0;
   for (int i = 0; i < n_runs; ++i) {
-    lays.push_back(layout_of(runs[i], o.precision, N, Tz, Tr, keys_of(runs[i], Tz, Tr)));
+    lays.push_back(layout_of(runs[i], o.precision, N, Tz, Tr, keys_of(runs[i], Tz, Tr), o.deterministic != 0));
     offs.push_back(total);
     total = align_up(total + lays.back().total);
   }
@@ -378,13 +388,14 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
   ctx->sort_interval = o.sort_interval > 0 ? o.sort_interval : kDefaultSortInterval;
   ctx->use_graph = o.use_graph != 0;
   ctx->current = o.current;
+  ctx->det = o.deterministic != 0;
   ctx->runs.resize((size_t)n_runs);
   const hipStream_t s = ctx->stream;
   const bool f64 = o.precision == PIC_PREC_FP64;
   const double band = o.fit_band > 0 ? o.fit_band : 2.0 * kPi / 3.0;
   const double frac = o.cfl_fraction > 0 ? o.cfl_fraction : 0.95;
 
-  int rc = prepare_kernels(o.precision, runs[0].M, Tz, Tr);
+  int rc = prepare_kernels(o.precision, runs[0].M, Tz, Tr, ctx->det);
   for (int i = 0; i < n_runs && rc == PIC_OK; ++i) {
     RunHost &R = ctx->runs[(size_t)i];
     R.d = runs[i];
@@ -498,6 +509,8 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
     k.red = (double *)(base + L.red);
     k.work = (int32_t *)(base + L.work);
     k.flags = (uint32_t *)(base + L.work + 16);
+    k.Jfix = ctx->det ? (unsigned long long *)(base + L.Jfix) : nullptr;
+    k.qscale = 1.0;
     R.dev_gamma = (double *)(base + L.gam);
     R.dev_ids = (int64_t *)(base + L.ids);
 
@@ -521,6 +534,18 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
     load_electrons(d, z.data(), x.data(), y.data(), w.data(), ids.data(), tr.empty() ? nullptr : tr.data());
     std::vector<uint32_t> pid(np);
     for (int64_t p = 0; p < np; ++p) pid[(size_t)p] = (uint32_t)ids[(size_t)p];
+    if (ctx->det) {
+      // 2^K with 4 max|q| 2^K < 2^30: every scaled contribution fits the
+      // integer split of the deterministic deposit (|contribution| <= 4 |q|)
+      double wmax = 0.0;
+      for (int64_t p = 0; p < np; ++p) wmax = std::max(wmax, std::fabs(w[(size_t)p]));
+      int e = 0;
+      if (wmax > 0) std::frexp(wmax, &e);
+      k.qscale = wmax > 0 ? std::ldexp(1.0, 28 - e) : 1.0;
+      if ((rc = launch_zero(k.Jfix, lays[(size_t)i].Jfix ? (size_t)2 * 3 * (2 * d.M + 1) * (size_t)k.plane * 8 : 0,
+                            s)))
+        break;
+    }
     for (size_t t = 0; t < tr.size(); ++t) pid[(size_t)tr[t]] |= kTrackedBit;
     std::vector<int32_t> tr32(tr.begin(), tr.end());
     R.gam0.assign(tr.size(), 1.0);  // cold start
@@ -646,6 +671,7 @@ int step_batch(pic_ctx *ctx, const std::vector<int> &ids) {
   std::memset(&b, 0, sizeof b);  // every byte defined: the batch is a capture key
   b.n = (int)ids.size();
   b.par = par;
+  b.det = ctx->det ? 1 : 0;
   for (int i = 0; i < b.n; ++i) {
     const RunHost &R = ctx->runs[(size_t)ids[(size_t)i]];
     b.run[i] = R.k;
@@ -657,7 +683,10 @@ int step_batch(pic_ctx *ctx, const std::vector<int> &ids) {
   auto launches = [&](bool events) {
     auto ph = [&](int phase, auto &&f) { return events ? timed(ctx, phase, f) : f(); };
     if (sort) TRY(ph(PIC_PHASE_SORT, [&] { return launch_sort(b, prec, s); }));
-    TRY(ph(PIC_PHASE_PUSH, [&] { return launch_push(b, prec, s); }));
+    TRY(ph(PIC_PHASE_PUSH, [&] {
+      const int rc = launch_push(b, prec, s);
+      return (rc || !b.det) ? rc : launch_fix_convert(b, s);  // deterministic: the integer sums into J
+    }));
     TRY(ph(PIC_PHASE_EFIELD, [&] { return launch_efield(b, prec, s); }));
     TRY(ph(PIC_PHASE_BFIELD, [&] { return launch_bfield(b, prec, s); }));
     return PIC_OK;
@@ -778,7 +807,8 @@ int pic_autotune(const pic_run_desc *runs, int32_t n_runs, pic_opts *opts, void 
     cand.push_back({Tz, Tr});
   } else {
     for (const auto &t : kTuneTiles)
-      if (push_lds_bytes(rd[0].M, t[0], t[1], opts->precision) <= kPushLdsMax && cand.size() < PIC_MAX_TUNE)
+      if (push_lds_bytes(rd[0].M, t[0], t[1], opts->precision, opts->deterministic != 0) <= kPushLdsMax &&
+          cand.size() < PIC_MAX_TUNE)
         cand.push_back({t[0], t[1]});
   }
   pic_opts o = *opts;
@@ -1207,7 +1237,7 @@ namespace {
 
 struct CkptHeader {
   char magic[8];
-  int32_t version, n_runs, precision, tile_z, tile_r, sort_interval, current;
+  int32_t version, n_runs, precision, tile_z, tile_r, sort_interval, current, deterministic;
 };
 
 struct Seg {
@@ -1251,13 +1281,14 @@ CkptHeader header_of(pic_ctx *ctx) {
   CkptHeader h;
   std::memset(&h, 0, sizeof h);
   std::memcpy(h.magic, "PICCKPT1", 8);
-  h.version = 2;
+  h.version = 3;
   h.n_runs = (int32_t)ctx->runs.size();
   h.precision = ctx->prec;
   h.tile_z = ctx->runs.empty() ? 0 : ctx->runs[0].k.Tz;
   h.tile_r = ctx->runs.empty() ? 0 : ctx->runs[0].k.Tr;
   h.sort_interval = ctx->sort_interval;
   h.current = ctx->current;
+  h.deterministic = ctx->det ? 1 : 0;
   return h;
 }
 
@@ -1309,7 +1340,8 @@ int pic_restore(pic_ctx *ctx, const void *host_buf, size_t bytes) {
   const CkptHeader h = header_of(ctx);
   if (std::memcmp(p, &h, sizeof h) != 0)
     return fail(PIC_E_INVALID,
-                "checkpoint header does not match this context (version, runs, precision, tile, interval, current)");
+                "checkpoint header does not match this context (version, runs, precision, tile, interval, current, "
+                "deterministic mode)");
   // validate every run before any device copy
   const unsigned char *q = p + sizeof h;
   for (const RunHost &R : ctx->runs) {

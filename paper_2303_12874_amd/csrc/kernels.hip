@@ -46,6 +46,14 @@ __device__ __forceinline__ int wrap_any(int c, int n) {
 }
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// Element i of a particle array as a uniform base plus a 32-bit byte offset,
+// so that a load or store needs no 64-bit address arithmetic per lane
+// (pic_init keeps every particle array under 2^32 bytes).
+template <typename T>
+__device__ __forceinline__ T &elem(void *base, int i) {
+  return *(T *)((char *)base + (unsigned)i * (unsigned)sizeof(T));
+}
+
 // Electrons of a tile are stored transposed: with n electrons in (cell, id)
 // order L[0..n) and chunk = ceil(n / 256), thread t of the tile's workgroup
 // handles L[t chunk + it] for it = 0, 1, ..., and round `it` of the 256
@@ -102,6 +110,28 @@ __device__ __forceinline__ void lds_add(R *a, R v) {  // LDS
   [[clang::atomic(ignore_denormal_mode)]] {
     __hip_atomic_fetch_add(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
+}
+
+// Deterministic mode: a scaled contribution v (|v| < 2^30) as the exact
+// integer pair a = rint(v), b = rint((v - a) 2^31), added to a pair of 64-bit
+// integer sums (two's complement, so that negative parts wrap correctly).
+// Integer addition is associative: the sums do not depend on the order the
+// atomics run in.
+__device__ __forceinline__ void fix_split(double v, unsigned long long &a, unsigned long long &b) {
+  const double ra = rint(v);
+  const double rb = rint((v - ra) * 2147483648.0);  // v - ra is exact, |.| <= 1/2
+  a = (unsigned long long)(long long)(int)ra;
+  b = (unsigned long long)(long long)(int)rb;
+}
+__device__ __forceinline__ void fix_add_lds(unsigned long long *p, double v) {
+  unsigned long long a, b;
+  fix_split(v, a, b);
+  __hip_atomic_fetch_add(p, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  __hip_atomic_fetch_add(p + 1, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void fix_add_global(unsigned long long *p, unsigned long long a, unsigned long long b) {
+  if (a) __hip_atomic_fetch_add(p, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (b) __hip_atomic_fetch_add(p + 1, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---- node records -----------------------------------------------------------
@@ -199,33 +229,40 @@ __device__ __forceinline__ int batch_run(const Batch &b, long long g) {
 //    Bbar_z, each NM planes) and one pad;
 //  * the current of the whole tile over the node window [z0-1, z0+Tz+2) x
 //    [r0-1, r0+Tr+2) (every move of less than one cell from a cell of the
-//    tile stays inside it), records of 3 NM sums in the run's real type,
-//    added to the global arrays once.
+//    tile stays inside it), records of 3 NM FP64 sums, added to the global
+//    arrays once.
 // An electron that drifted out of either window since the last sort gathers
 // from, or deposits to, global memory directly.
-template <typename R, int M>
+// DET (FP64 only): the deterministic mode, whose window and device sums are
+// integer pairs (fix_split) instead of FP64 values.
+template <typename R, int M, bool DET>
 __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
   constexpr int NM = 2 * M + 1;       // planes per component
   constexpr int NMP = 2 * (M + 1);    // reals per field record in registers
   constexpr int FS = 6 * NM + 1;      // reals per field-window node, odd: lanes in
                                       // consecutive nodes hit distinct LDS banks
-  constexpr int JS = 3 * NM;          // sums per current-window node
+  constexpr int JS = 3 * NM;          // FP64 sums per current-window node
   constexpr bool F64 = std::is_same<R, double>::value;
   constexpr int PREC = F64 ? PIC_PREC_FP64 : PIC_PREC_FP32;
-  // the tile current is summed in the run's real type (ds_add_f64 or
-  // ds_add_f32): a tile's node sums a few hundred contributions, far fewer
-  // than would let FP32 rounding approach the FP32 form's current bound
+  // The tile current is summed in FP64 for both precisions: the LDS FP64
+  // atomic add is the fast one on gfx950 (FP32 sums in LDS made the FP32
+  // push several times slower).  In the FP32 form each contribution is the
+  // FP64 product of an FP32 node weight and an FP32 mode coefficient, which
+  // is exact, so the FP64 arithmetic adds no precision to the FP32 inputs;
+  // it only keeps the sums from rounding.
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  R *lds = (R *)lds_raw;
+  double *lds = (double *)lds_raw;
   const int par = bt.par;
   const int TZ = bt.run[0].Tz, TR = bt.run[0].Tr;  // one sort tile for every run of a batch
   const int WZ = TZ + 3, WR = TR + 3;
   const long long TT = (long long)TZ * TR;
-  const int RJ = current_window_row(M, TZ, PREC);  // sums per current-window row (padded)
+  static_assert(!DET || F64, "the deterministic mode is FP64 only");
+  constexpr int JW = DET ? 2 : 1;             // 8-byte words per current sum
+  const int RJ = current_window_row(M, TZ, DET);  // words per current-window row (padded)
   const int nlds = RJ * WR;
   const int FZ = field_window_z(TZ), FR = field_window_r(TR);
   const int RF = field_window_row(M, TZ, PREC);  // reals per field-window row
-  R *fw = (R *)(lds_raw + current_window_bytes(M, TZ, TR, PREC));
+  R *fw = (R *)(lds + nlds);
 
   // Persistent: each workgroup takes tiles (of all runs of the batch) from a
   // ticket counter, zero before the launch, until none are left; the dealing
@@ -268,7 +305,7 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
   };
 
   // the current window starts at zero; each flush clears what it adds
-  for (int e = threadIdx.x; e < nlds; e += blockDim.x) lds[e] = R(0);
+  for (int e = threadIdx.x; e < nlds; e += blockDim.x) lds[e] = 0.0;
   if (gt < t_hi)
     for (int e = threadIdx.x; e < FZ * FR; e += blockDim.x) {
       R v[FS];
@@ -309,19 +346,19 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
   int niz = 0;
   uint32_t nid = 0;
   auto fetch = [&](int pp) {
-    nw = ((const R *)k.pw)[pp];
-    nid = k.pid[pp];
+    nw = elem<R>(k.pw, pp);
+    nid = elem<uint32_t>(k.pid, pp);
     if constexpr (F64) {
-      nz = ((const double *)k.pz)[pp];
+      nz = elem<double>(k.pz, pp);
     } else {
-      niz = ((const int *)k.pz)[pp];
-      nfz = ((const float *)k.pfz)[pp];
+      niz = elem<int>(k.pz, pp);
+      nfz = elem<float>(k.pfz, pp);
     }
-    nx = X[pp];
-    ny = Y[pp];
-    nux = UX[pp];
-    nuy = UY[pp];
-    nuz = UZ[pp];
+    nx = elem<R>(X, pp);
+    ny = elem<R>(Y, pp);
+    nux = elem<R>(UX, pp);
+    nuy = elem<R>(UY, pp);
+    nuz = elem<R>(UZ, pp);
   };
   int base = 0;
   int cnt = round_count(n, chunk, 0);
@@ -438,13 +475,15 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
       Ecyl[0][1] = ep[0];
       Ecyl[0][2] = ez[0];
       R Er = er[0], Ep = ep[0], Ez = ez[0], Br = br[0], Bp = bp[0], Bz = bz[0];
-      R ere = 1, eim = 0;
+      R ere = c0, eim = s0;  // e^{i m phi}, m = 1, then by recurrence
 #pragma unroll
       for (int m = 1; m <= M; ++m) {
-        const R nre = ere * c0 - eim * s0;
-        const R nim = ere * s0 + eim * c0;
-        ere = nre;
-        eim = nim;
+        if (m > 1) {
+          const R nre = ere * c0 - eim * s0;
+          const R nim = ere * s0 + eim * c0;
+          ere = nre;
+          eim = nim;
+        }
         const int a = 2 * m, b = 2 * m + 1;
         Ecyl[m][0] = er[a] * ere - er[b] * eim;
         Ecyl[m][1] = ep[a] * ere - ep[b] * eim;
@@ -589,11 +628,18 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
       // cq (i/m)(e1 - e0) (its factor r_j and the node volume cancel into the
       // row factor of the E update), which is zero on the axis row, where
       // m = 1 takes cq v_phi e_mid instead (cq = c_m q).
+      // (the deterministic mode scales every coefficient by the run's 2^K)
+      const double qs = DET ? k.qscale : 1.0;
       auto for_modes = [&](bool axis_row, auto &&body) {
         R e0r = 1, e0i = 0, e1r = 1, e1i = 0;
 #pragma unroll
         for (int m = 0; m <= M; ++m) {
-          if (m > 0) {
+          if (m == 1) {
+            e0r = c0;
+            e0i = -s0;
+            e1r = c1;
+            e1i = -s1;
+          } else if (m > 1) {
             R t = e0r * c0 + e0i * s0;
             e0i = e0i * c0 - e0r * s0;
             e0r = t;
@@ -613,7 +659,8 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
             pa0 = axis_row ? (m == 1 ? cq * vphi * cmid : R(0)) : pa;
             pb0 = axis_row ? (m == 1 ? -cq * vphi * smid : R(0)) : pb;
           }
-          body(m, m == 0 ? 0 : 2 * m - 1, 2 * m, fa, fb, pa, pb, pa0, pb0);
+          body(m, m == 0 ? 0 : 2 * m - 1, 2 * m, (double)fa * qs, (double)fb * qs, (double)pa * qs, (double)pb * qs,
+               (double)pa0 * qs, (double)pb0 * qs);
         }
       };
       if (!__any(di != 0 || dj != 0)) {
@@ -625,12 +672,13 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
         // weights of a move inside one cell).
         const R df = f1 - f0, dg = g1 - g0;
         const R sz0 = R(1) - f0, sz1 = R(1) - f1, sr0 = R(1) - g0, sr1 = R(1) - g1;
-        const R wz0 = df * (R(0.5) * (sr0 + sr1)), wz1 = df * (R(0.5) * (g0 + g1));
-        const R wr0 = dg * (R(0.5) * (sz0 + sz1)), wr1 = dg * (R(0.5) * (f0 + f1));
-        const R w00 = R(0.5) * (sz0 * sr0 + sz1 * sr1), w10 = R(0.5) * (f0 * sr0 + f1 * sr1);
-        const R w01 = R(0.5) * (sz0 * g0 + sz1 * g1), w11 = R(0.5) * (f0 * g0 + f1 * g1);
+        const double wz0 = (double)(df * (R(0.5) * (sr0 + sr1))), wz1 = (double)(df * (R(0.5) * (g0 + g1)));
+        const double wr0 = (double)(dg * (R(0.5) * (sz0 + sz1))), wr1 = (double)(dg * (R(0.5) * (f0 + f1)));
+        const double w00 = (double)(R(0.5) * (sz0 * sr0 + sz1 * sr1)), w10 = (double)(R(0.5) * (f0 * sr0 + f1 * sr1));
+        const double w01 = (double)(R(0.5) * (sz0 * g0 + sz1 * g1)), w11 = (double)(R(0.5) * (f0 * g0 + f1 * g1));
         auto deposit = [&](auto &&dep) {
-          for_modes(j0 == 0, [&](int m, int qa, int qb, R fa, R fb, R pa, R pb, R pa0, R pb0) {
+          for_modes(j0 == 0, [&](int m, int qa, int qb, double fa, double fb, double pa, double pb, double pa0,
+                                 double pb0) {
             dep(2, qa, 0, 0, wz0 * fa);
             dep(2, qa, 1, 0, wz1 * fa);
             dep(0, qa, 0, 0, wr0 * fa);
@@ -652,12 +700,23 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
           });
         };
         if ((i0 - zlo >= 0) && (i0 + 1 - zlo < WZ) && (j0 - rlo >= 0) && (j0 + 1 - rlo < WR)) {
-          R *jw = lds + (j0 - rlo) * RJ + (i0 - zlo) * JS;
-          deposit([&](int c, int qq, int b, int a, R v) { lds_add(jw + b * RJ + a * JS + c * NM + qq, v); });
+          double *jw = lds + (j0 - rlo) * RJ + (i0 - zlo) * (JW * JS);
+          deposit([&](int c, int qq, int b, int a, double v) {
+            double *p = jw + b * RJ + a * (JW * JS) + JW * (c * NM + qq);
+            if constexpr (DET) fix_add_lds((unsigned long long *)p, v);
+            else lds_add(p, v);
+          });
         } else {
           const int col1 = wrap_once(i0 + 1, Nz);
-          deposit([&](int c, int qq, int b, int a, R v) {
-            atomic_add(J + (c * NM + qq) * plane + (long long)(j0 + b) * Nz + (a ? col1 : i0), v);
+          deposit([&](int c, int qq, int b, int a, double v) {
+            const long long at = (c * NM + qq) * plane + (long long)(j0 + b) * Nz + (a ? col1 : i0);
+            if constexpr (DET) {
+              unsigned long long x, y;
+              fix_split(v, x, y);
+              fix_add_global(k.Jfix + 2 * at, x, y);
+            } else {
+              atomic_add(J + at, (R)v);
+            }
           });
         }
       } else {
@@ -683,14 +742,14 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
         // J_z at face (ib+a+1/2, jb+b): minus the running sum of Wz behind it;
         // J_r at (ib+a, jb+b+1/2): minus the running sum of Wr below it;
         // J_phi at node (ib+a, jb+b): half the summed shape
-        R wz[3][2], wr[3][2], ws[3][3];
+        double wz[3][2], wr[3][2], ws[3][3];
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
           R run = 0;
 #pragma unroll
           for (int a = 0; a < 2; ++a) {
             run += (Sz1[a] - Sz0[a]) * (Sr0[b] + Sr1[b]) * R(0.5);
-            wz[b][a] = -run;
+            wz[b][a] = -(double)run;
           }
         }
 #pragma unroll
@@ -699,10 +758,10 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
 #pragma unroll
           for (int b = 0; b < 2; ++b) {
             run += (Sr1[b] - Sr0[b]) * (Sz0[a] + Sz1[a]) * R(0.5);
-            wr[a][b] = -run;
+            wr[a][b] = -(double)run;
           }
 #pragma unroll
-          for (int b = 0; b < 3; ++b) ws[a][b] = R(0.5) * (Sz0[a] * Sr0[b] + Sz1[a] * Sr1[b]);
+          for (int b = 0; b < 3; ++b) ws[a][b] = (double)(R(0.5) * (Sz0[a] * Sr0[b] + Sz1[a] * Sr1[b]));
         }
         // the whole deposit, into `dep(c, plane, b, a, v)`: component c (0 r,
         // 1 phi, 2 z), window node (ib + a, jb + b).  A node past the first
@@ -710,7 +769,8 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
         // crossed a z (r) face: the wave skips it when no lane did, and each
         // other lane masks itself off.
         auto deposit = [&](auto &&dep) {
-          for_modes(jb == 0, [&](int m, int qa, int qb, R fa, R fb, R pa, R pb, R pa0, R pb0) {
+          for_modes(jb == 0, [&](int m, int qa, int qb, double fa, double fb, double pa, double pb, double pa0,
+                                 double pb0) {
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
               if (b == 2 && !rx) continue;
@@ -747,14 +807,25 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
           });
         };
         if ((ib - zlo >= 0) && (ib + 2 - zlo < WZ) && (jb - rlo >= 0) && (jb + 2 - rlo < WR)) {
-          R *jw = lds + (jb - rlo) * RJ + (ib - zlo) * JS;
-          deposit([&](int c, int qq, int b, int a, R v) { lds_add(jw + b * RJ + a * JS + c * NM + qq, v); });
+          double *jw = lds + (jb - rlo) * RJ + (ib - zlo) * (JW * JS);
+          deposit([&](int c, int qq, int b, int a, double v) {
+            double *p = jw + b * RJ + a * (JW * JS) + JW * (c * NM + qq);
+            if constexpr (DET) fix_add_lds((unsigned long long *)p, v);
+            else lds_add(p, v);
+          });
         } else {
           int col[3];
 #pragma unroll
           for (int a = 0; a < 3; ++a) col[a] = wrap_once(ib + a, Nz);
-          deposit([&](int c, int qq, int b, int a, R v) {
-            atomic_add(J + (c * NM + qq) * plane + (long long)(jb + b) * Nz + col[a], v);
+          deposit([&](int c, int qq, int b, int a, double v) {
+            const long long at = (c * NM + qq) * plane + (long long)(jb + b) * Nz + col[a];
+            if constexpr (DET) {
+              unsigned long long x, y;
+              fix_split(v, x, y);
+              fix_add_global(k.Jfix + 2 * at, x, y);
+            } else {
+              atomic_add(J + at, (R)v);
+            }
           });
         }
       }
@@ -764,16 +835,16 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
     if constexpr (F64) {
       if (z1 < R(0)) z1 += (R)Nz;
       if (z1 >= (R)Nz) z1 -= (R)Nz;
-      ((double *)k.pz)[p] = z1;
+      elem<double>(k.pz, p) = z1;
     } else {
-      ((int *)k.pz)[p] = wrap_once(i1, Nz);
-      ((float *)k.pfz)[p] = f1;
+      elem<int>(k.pz, p) = wrap_once(i1, Nz);
+      elem<float>(k.pfz, p) = f1;
     }
-    X[p] = x1;
-    Y[p] = y1;
-    UX[p] = un[0];
-    UY[p] = un[1];
-    UZ[p] = un[2];
+    elem<R>(X, p) = x1;
+    elem<R>(Y, p) = y1;
+    elem<R>(UX, p) = un[0];
+    elem<R>(UY, p) = un[1];
+    elem<R>(UZ, p) = un[2];
   }
 
   // ---- flush the tile's current (each thread a window node, all its
@@ -795,11 +866,11 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
           if (row < 0 || row > Nr) continue;  // never deposited to
           // a node that takes current lies in [-1, Nz + 1]; the others hold zero
           const unsigned off = (unsigned)(row * Nz + wrap_once(zlo + lc, Nz));
-          R *src = lds + lr * RJ + lc * JS;
+          double *src = lds + lr * RJ + lc * (JW * JS);
 #pragma unroll
           for (int cq = 0; cq < JS; ++cq) {
-            const R v = src[cq];
-            src[cq] = R(0);
+            const R v = (R)src[cq];
+            src[cq] = 0.0;
             if (v != R(0)) atomic_add(J + cq * plane + off, v);
           }
         }
@@ -820,12 +891,22 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
         if (row < 0 || row > Nr) continue;  // never deposited to
         // a node that takes current lies in [-1, Nz + 1]; the others hold zero
         const unsigned off = (unsigned)(row * Nz + wrap_once(zlo + lc, Nz));
-        R *src = lds + lr * RJ + lc * JS;
+        double *src = lds + lr * RJ + lc * (JW * JS);
+        if constexpr (DET) {
+          unsigned long long *s2 = (unsigned long long *)src;
 #pragma unroll
-        for (int cq = 0; cq < JS; ++cq) {
-          const R v = src[cq];
-          src[cq] = R(0);
-          if (v != R(0)) atomic_add(J + cq * plane + off, v);
+          for (int cq = 0; cq < JS; ++cq) {
+            const unsigned long long a = s2[2 * cq], b = s2[2 * cq + 1];
+            s2[2 * cq] = s2[2 * cq + 1] = 0;
+            fix_add_global(k.Jfix + 2 * ((long long)cq * plane + off), a, b);
+          }
+        } else {
+#pragma unroll
+          for (int cq = 0; cq < JS; ++cq) {
+            const R v = (R)src[cq];
+            src[cq] = 0.0;
+            if (v != R(0)) atomic_add(J + cq * plane + off, v);
+          }
         }
       }
     if (nt < t_hi)
@@ -1169,6 +1250,22 @@ __global__ __launch_bounds__(kFieldTile) void bfield_kernel(const Batch bt) {
   store_node<R, NMP>(Bout + 0 * cstride, plane, row + i, nbr);
   store_node<R, NMP>(Bout + 1 * cstride, plane, row + i, nbp);
   store_node<R, NMP>(Bout + 2 * cstride, plane, row + i, nbz);
+}
+
+// Deterministic mode, between the push and the E update: each value of the
+// step's current J[par] from its integer pair, J = a 2^-K + b 2^-(K+31),
+// and the pair cleared for the next step.  One thread per value.
+__global__ __launch_bounds__(256) void fix_convert_kernel(const Batch bt) {
+  const int rn = batch_run(bt, blockIdx.x);
+  const KRun &k = bt.run[rn];
+  const long long i = (long long)(blockIdx.x - bt.off[rn]) * 256 + threadIdx.x;
+  const long long n = 3 * (2 * k.M + 1) * k.plane;
+  if (i >= n) return;
+  unsigned long long *p = k.Jfix + 2 * i;
+  const long long a = (long long)p[0], b = (long long)p[1];
+  p[0] = p[1] = 0;
+  const double s = 1.0 / k.qscale;  // a power of two: exact
+  ((double *)k.J[bt.par])[i] = (double)a * s + (double)b * (s * 0x1p-31);
 }
 
 // ---------------------------------------------------------------------------
@@ -1662,12 +1759,14 @@ constexpr int prec_of() {
 
 template <typename R, int M>
 struct PrepL {
-  static int run(int Tz, int Tr) {
+  static int run(int Tz, int Tr, bool det) {
     // dynamic LDS above 64 KB must be allowed per kernel, once, outside any capture
-    const size_t lds = push_lds_bytes(M, Tz, Tr, prec_of<R>());
+    const size_t lds = push_lds_bytes(M, Tz, Tr, prec_of<R>(), det);
     if (lds <= 65536) return PIC_OK;
-    return check(hipFuncSetAttribute((const void *)push_kernel<R, M>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds),
+    const void *f = (const void *)push_kernel<R, M, false>;
+    if constexpr (std::is_same<R, double>::value)
+      if (det) f = (const void *)push_kernel<R, M, true>;
+    return check(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
                  "hipFuncSetAttribute(push_kernel)");
   }
 };
@@ -1676,18 +1775,24 @@ struct PushL {
   static int run(Batch &b, hipStream_t s) {
     if (!set_offsets(b, [](const KRun &k) { return k.np > 0 ? (long long)k.ntz * k.ntr : 0LL; })) return PIC_OK;
     const KRun &k0 = b.run[0];
-    const size_t lds = push_lds_bytes(M, k0.Tz, k0.Tr, prec_of<R>());
+    const bool det = b.det != 0;
+    if (det && !std::is_same<R, double>::value) return PIC_E_INVALID;
+    const size_t lds = push_lds_bytes(M, k0.Tz, k0.Tr, prec_of<R>(), det);
     // persistent grid: as many workgroups as are resident at once (a multiple
     // of 8, one share per XCD), each walking its tiles; the occupancy query
     // is cached per thread for the last (device, LDS size)
     static thread_local size_t lds_seen = 0;
     static thread_local int dev_seen = -1;
+    static thread_local bool det_seen = false;
     static thread_local long long resident = 0;
     int dev = 0;
     if (int rc = check(hipGetDevice(&dev), "hipGetDevice")) return rc;
-    if (lds != lds_seen || dev != dev_seen) {
+    if (lds != lds_seen || dev != dev_seen || det != det_seen) {
       int per_cu = 0, cus = 0;
-      int rc = check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, push_kernel<R, M>, 256, lds),
+      auto *f = push_kernel<R, M, false>;
+      if constexpr (std::is_same<R, double>::value)
+        if (det) f = push_kernel<R, M, true>;
+      int rc = check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 256, lds),
                      "hipOccupancyMaxActiveBlocksPerMultiprocessor");
       if (!rc) rc = check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
       if (rc) return rc;
@@ -1695,11 +1800,17 @@ struct PushL {
       resident = resident >= 8 ? resident & ~7LL : resident;
       lds_seen = lds;
       dev_seen = dev;
+      det_seen = det;
     }
     const long long grid = b.off[b.n] < resident ? b.off[b.n] : resident;
     zero_kernel<<<1, 64, 0, s>>>((uint4 *)b.run[0].work, 1, nullptr, 0);  // tickets from 0
     if (int rc = check(hipGetLastError(), "zero_kernel")) return rc;
-    push_kernel<R, M><<<(unsigned)grid, 256, lds, s>>>(b);
+    if constexpr (std::is_same<R, double>::value) {
+      if (det) push_kernel<R, M, true><<<(unsigned)grid, 256, lds, s>>>(b);
+      else push_kernel<R, M, false><<<(unsigned)grid, 256, lds, s>>>(b);
+    } else {
+      push_kernel<R, M, false><<<(unsigned)grid, 256, lds, s>>>(b);
+    }
     return check(hipGetLastError(), "push_kernel");
   }
 };
@@ -1759,7 +1870,12 @@ int launch_efield(Batch &b, int prec, void *stream) {
 int launch_bfield(Batch &b, int prec, void *stream) {
   return dispatch_M<BL>(prec, b.run[0].M, b, (hipStream_t)stream);
 }
-int prepare_kernels(int prec, int M, int Tz, int Tr) { return dispatch_M<PrepL>(prec, M, Tz, Tr); }
+int prepare_kernels(int prec, int M, int Tz, int Tr, bool det) { return dispatch_M<PrepL>(prec, M, Tz, Tr, det); }
+int launch_fix_convert(Batch &b, void *stream) {
+  if (!set_offsets(b, [](const KRun &k) { return (3 * (2 * k.M + 1) * k.plane + 255) / 256; })) return PIC_OK;
+  fix_convert_kernel<<<(unsigned)b.off[b.n], 256, 0, (hipStream_t)stream>>>(b);
+  return check(hipGetLastError(), "fix_convert_kernel");
+}
 int launch_rho(const KRun &k, int prec, void *stream) {
   return dispatch_M<RhoL>(prec, k.M, k, (hipStream_t)stream);
 }

@@ -88,11 +88,15 @@ struct KRun {
   double *red;            // reduction partials
   int32_t *work;          // tile ticket counter of the persistent push (run 0's serves a batch)
   uint32_t *flags;        // cell-sort integrity bits (kSort*), sticky
+  // deterministic mode: the deposit's integer sums, pairs (a, b) per value
+  // of the J layout (interleaved), zero between steps, and the scale 2^K
+  unsigned long long *Jfix;
+  double qscale;
 };
 
 // ---- push workgroup LDS ---------------------------------------------------------
 // One push workgroup per sort tile of Tz x Tr cells.  Its LDS holds
-//  * the tile's current window in the run's real type, 3 components x NM
+//  * the tile's current window, FP64 for both precisions, 3 components x NM
 //    planes x (Tz+3) x (Tr+3) nodes from cell (z0-1, r0-1): every move of
 //    less than a cell from a cell of the tile deposits inside it;
 //  * the field window of E and Bbar, records of 6 components x NM planes
@@ -112,11 +116,14 @@ constexpr int kBankBytes = 256;  // 64 LDS banks of 4 bytes
 constexpr int field_window_z(int Tz) { return Tz + 2 + 2 * kFieldMarginZ; }
 constexpr int field_window_r(int Tr) { return Tr + 2 + 2 * kFieldMarginR; }
 constexpr int pos_mod(int a, int m) { return ((a % m) + m) % m; }
-// Sums per current-window row: (Tz + 3) nodes of 3 NM, plus the pad.  The
-// tile current is summed in the run's real type (FP64 or FP32 LDS atomics).
-constexpr int current_window_row(int M, int Tz, int precision) {
-  return 3 * (2 * M + 1) * (Tz + 3) +
-         pos_mod(-3 * 3 * (2 * M + 1), kBankBytes / (precision == PIC_PREC_FP64 ? 8 : 4));
+// 8-byte words per current-window row: (Tz + 3) nodes of 3 NM sums, plus the
+// pad; a sum is one word (FP64), or two (the integer pair of the
+// deterministic mode, det).  The tile current is summed in FP64 for both
+// precisions: on gfx950 the LDS FP32 atomic add (ds_add_f32) is far slower
+// than the FP64 one (an FP32 tile current made the FP32 push of the
+// 8192 x 512 run 6.8x slower).
+constexpr int current_window_row(int M, int Tz, bool det = false) {
+  return (det ? 2 : 1) * 3 * (2 * M + 1) * (Tz + 3) + pos_mod(-3 * (det ? 2 : 1) * 3 * (2 * M + 1), kBankBytes / 8);
 }
 // reals per field-window row: field_window_z nodes of 6 NM + 1, plus the pad
 constexpr int field_window_row(int M, int Tz, int precision) {
@@ -124,17 +131,12 @@ constexpr int field_window_row(int M, int Tz, int precision) {
          pos_mod(-(field_window_z(Tz) - Tz) * (6 * (2 * M + 1) + 1),
                  kBankBytes / (precision == PIC_PREC_FP64 ? 8 : 4));
 }
-constexpr size_t current_window_words(int M, int Tz, int Tr, int precision) {
-  return (size_t)current_window_row(M, Tz, precision) * (Tr + 3);
+constexpr size_t current_window_words(int M, int Tz, int Tr, bool det = false) {
+  return (size_t)current_window_row(M, Tz, det) * (Tr + 3);
 }
-// bytes of the current window, rounded up to 16 so that the field window after it is aligned
-constexpr size_t current_window_bytes(int M, int Tz, int Tr, int precision) {
+inline size_t push_lds_bytes(int M, int Tz, int Tr, int precision, bool det = false) {
   const size_t w = precision == PIC_PREC_FP64 ? 8 : 4;
-  return (current_window_words(M, Tz, Tr, precision) * w + 15) / 16 * 16;
-}
-inline size_t push_lds_bytes(int M, int Tz, int Tr, int precision) {
-  const size_t w = precision == PIC_PREC_FP64 ? 8 : 4;
-  return current_window_bytes(M, Tz, Tr, precision) + (size_t)field_window_row(M, Tz, precision) * field_window_r(Tr) * w;
+  return current_window_words(M, Tz, Tr, det) * 8 + (size_t)field_window_row(M, Tz, precision) * field_window_r(Tr) * w;
 }
 
 // ---- batched launches ---------------------------------------------------------
@@ -146,6 +148,7 @@ constexpr int kMaxBatch = 8;
 struct Batch {
   int n;                            // runs in the batch
   int par;                          // step parity: deposit into J[par], B^{n+1/2} in B[par ^ 1]
+  int det;                          // deterministic mode (integer deposit sums, FP64 only)
   long long off[kMaxBatch + 1];     // first block of each run in the launch (set by the launcher)
   KRun run[kMaxBatch];
   // B update operands per run: Bout = Bin - tau curl_E E, and avg = (Bin + Bout)/2 when not NULL
@@ -155,12 +158,16 @@ struct Batch {
   double tau[kMaxBatch];
 };
 
+// kernel arguments are at most 4 KB
+static_assert(sizeof(Batch) <= 4096, "a Batch is passed by value as the kernel argument");
+
 // ---- kernel launchers (kernels.hip); all enqueue on `stream` -----------------
 int launch_push(Batch &b, int prec, void *stream);
 int launch_efield(Batch &b, int prec, void *stream);
 int launch_bfield(Batch &b, int prec, void *stream);
 int launch_sort(Batch &b, int prec, void *stream);  // swaps the runs' particle buffers in b
-int prepare_kernels(int prec, int M, int Tz, int Tr);  // per-kernel attributes, before any capture
+int prepare_kernels(int prec, int M, int Tz, int Tr, bool det);  // per-kernel attributes, before any capture
+int launch_fix_convert(Batch &b, void *stream);  // deterministic mode: integer sums -> J[par], sums cleared
 int launch_zero(void *ptr, size_t bytes, void *stream);
 int launch_rho(const KRun &k, int prec, void *stream);
 int launch_energy(const KRun &k, int prec, int par, int nblocks_max, int *nblocks, void *stream);

@@ -82,6 +82,14 @@ def test_per_run_options_are_checked():
     assert e.value.code == pic.PIC_E_INVALID
 
 
+def test_deterministic_mode_is_fp64_only():
+    d = _desc()
+    assert pic.workspace_bytes([d], deterministic=True) > pic.workspace_bytes([d])  # the integer sums of J
+    with pytest.raises(pic.PicError) as e:
+        pic.workspace_bytes([d], precision=pic.PREC_FP32, deterministic=True)
+    assert e.value.code == pic.PIC_E_INVALID
+
+
 def test_runs_must_share_modes():
     with pytest.raises(pic.PicError) as e:
         pic.workspace_bytes([_desc(M=1), _desc(M=2)])
