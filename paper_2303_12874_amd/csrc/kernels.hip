@@ -112,20 +112,22 @@ __device__ __forceinline__ void lds_add(R *a, R v) {  // LDS
   }
 }
 
-// Deterministic mode: a scaled contribution v (|v| < 2^30) as the exact
-// integer pair a = rint(v), b = rint((v - a) 2^31), added to a pair of 64-bit
-// integer sums (two's complement, so that negative parts wrap correctly).
-// Integer addition is associative: the sums do not depend on the order the
-// atomics run in.
-__device__ __forceinline__ void fix_split(double v, unsigned long long &a, unsigned long long &b) {
-  const double ra = rint(v);
-  const double rb = rint((v - ra) * 2147483648.0);  // v - ra is exact, |.| <= 1/2
+// Deterministic mode: a scaled contribution w c (|w c| < 2^30) as the integer
+// pair a = rint(w c), b = rint((w c - a) 2^31), the remainder taken from the
+// exact product by an explicit fma (an expression the compiler may contract
+// differently in each place it is inlined would round differently), added to
+// a pair of 64-bit integer sums (two's complement, so that negative parts
+// wrap correctly).  Integer addition is associative: the sums do not depend
+// on the order the atomics run in.
+__device__ __forceinline__ void fix_split(double w, double c, unsigned long long &a, unsigned long long &b) {
+  const double ra = rint(w * c);
+  const double rb = rint(fma(w, c, -ra) * 2147483648.0);  // |w c - ra| <= 1/2 + ulp
   a = (unsigned long long)(long long)(int)ra;
   b = (unsigned long long)(long long)(int)rb;
 }
-__device__ __forceinline__ void fix_add_lds(unsigned long long *p, double v) {
+__device__ __forceinline__ void fix_add_lds(unsigned long long *p, double w, double c) {
   unsigned long long a, b;
-  fix_split(v, a, b);
+  fix_split(w, c, a, b);
   __hip_atomic_fetch_add(p, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   __hip_atomic_fetch_add(p + 1, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
@@ -640,11 +642,14 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
             e1r = c1;
             e1i = -s1;
           } else if (m > 1) {
-            R t = e0r * c0 + e0i * s0;
-            e0i = e0i * c0 - e0r * s0;
+            // written with explicit fma, so that the old and new phases are
+            // rounded alike: an electron whose x, y did not change gets
+            // e1 == e0 bit for bit, and no closure current
+            R t = fma(e0r, c0, e0i * s0);
+            e0i = fma(e0i, c0, -(e0r * s0));
             e0r = t;
-            t = e1r * c1 + e1i * s1;
-            e1i = e1i * c1 - e1r * s1;
+            t = fma(e1r, c1, e1i * s1);
+            e1i = fma(e1i, c1, -(e1r * s1));
             e1r = t;
           }
           const R cq = (m == 0 ? R(1) : R(2)) * q;
@@ -663,7 +668,10 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
                (double)pa0 * qs, (double)pb0 * qs);
         }
       };
-      if (!__any(di != 0 || dj != 0)) {
+      // (not in the deterministic mode: which path an electron takes would
+      // depend on the other electrons of its wavefront, and the two paths
+      // round differently)
+      if (!DET && !__any(di != 0 || dj != 0)) {
         // No electron of the wavefront left its cell: each deposits on the
         // 2 x 2 nodes (i0 + a, j0 + b) of its cell.  J_z at (i0+1/2, j0+b)
         // carries (f1 - f0) times the mean radial shape of row b, J_r at
@@ -679,43 +687,43 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
         auto deposit = [&](auto &&dep) {
           for_modes(j0 == 0, [&](int m, int qa, int qb, double fa, double fb, double pa, double pb, double pa0,
                                  double pb0) {
-            dep(2, qa, 0, 0, wz0 * fa);
-            dep(2, qa, 1, 0, wz1 * fa);
-            dep(0, qa, 0, 0, wr0 * fa);
-            dep(0, qa, 0, 1, wr1 * fa);
-            dep(1, qa, 0, 0, w00 * pa0);
-            dep(1, qa, 0, 1, w10 * pa0);
-            dep(1, qa, 1, 0, w01 * pa);
-            dep(1, qa, 1, 1, w11 * pa);
+            dep(2, qa, 0, 0, wz0, fa);
+            dep(2, qa, 1, 0, wz1, fa);
+            dep(0, qa, 0, 0, wr0, fa);
+            dep(0, qa, 0, 1, wr1, fa);
+            dep(1, qa, 0, 0, w00, pa0);
+            dep(1, qa, 0, 1, w10, pa0);
+            dep(1, qa, 1, 0, w01, pa);
+            dep(1, qa, 1, 1, w11, pa);
             if (m > 0) {
-              dep(2, qb, 0, 0, wz0 * fb);
-              dep(2, qb, 1, 0, wz1 * fb);
-              dep(0, qb, 0, 0, wr0 * fb);
-              dep(0, qb, 0, 1, wr1 * fb);
-              dep(1, qb, 0, 0, w00 * pb0);
-              dep(1, qb, 0, 1, w10 * pb0);
-              dep(1, qb, 1, 0, w01 * pb);
-              dep(1, qb, 1, 1, w11 * pb);
+              dep(2, qb, 0, 0, wz0, fb);
+              dep(2, qb, 1, 0, wz1, fb);
+              dep(0, qb, 0, 0, wr0, fb);
+              dep(0, qb, 0, 1, wr1, fb);
+              dep(1, qb, 0, 0, w00, pb0);
+              dep(1, qb, 0, 1, w10, pb0);
+              dep(1, qb, 1, 0, w01, pb);
+              dep(1, qb, 1, 1, w11, pb);
             }
           });
         };
         if ((i0 - zlo >= 0) && (i0 + 1 - zlo < WZ) && (j0 - rlo >= 0) && (j0 + 1 - rlo < WR)) {
           double *jw = lds + (j0 - rlo) * RJ + (i0 - zlo) * (JW * JS);
-          deposit([&](int c, int qq, int b, int a, double v) {
+          deposit([&](int c, int qq, int b, int a, double w, double cf) {
             double *p = jw + b * RJ + a * (JW * JS) + JW * (c * NM + qq);
-            if constexpr (DET) fix_add_lds((unsigned long long *)p, v);
-            else lds_add(p, v);
+            if constexpr (DET) fix_add_lds((unsigned long long *)p, w, cf);
+            else lds_add(p, w * cf);
           });
         } else {
           const int col1 = wrap_once(i0 + 1, Nz);
-          deposit([&](int c, int qq, int b, int a, double v) {
+          deposit([&](int c, int qq, int b, int a, double w, double cf) {
             const long long at = (c * NM + qq) * plane + (long long)(j0 + b) * Nz + (a ? col1 : i0);
             if constexpr (DET) {
               unsigned long long x, y;
-              fix_split(v, x, y);
+              fix_split(w, cf, x, y);
               fix_add_global(k.Jfix + 2 * at, x, y);
             } else {
-              atomic_add(J + at, (R)v);
+              atomic_add(J + at, (R)(w * cf));
             }
           });
         }
@@ -763,7 +771,7 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
 #pragma unroll
           for (int b = 0; b < 3; ++b) ws[a][b] = (double)(R(0.5) * (Sz0[a] * Sr0[b] + Sz1[a] * Sr1[b]));
         }
-        // the whole deposit, into `dep(c, plane, b, a, v)`: component c (0 r,
+        // the whole deposit, into `dep(c, plane, b, a, w, cf)` (the value w cf): component c (0 r,
         // 1 phi, 2 z), window node (ib + a, jb + b).  A node past the first
         // two columns (rows) takes current only from a lane whose electron
         // crossed a z (r) face: the wave skips it when no lane did, and each
@@ -778,8 +786,8 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
               for (int a = 0; a < 2; ++a) {
                 if (a == 1 && !zx) continue;
                 if ((a == 1 && di == 0) || (b == 2 && dj == 0)) continue;
-                dep(2, qa, b, a, wz[b][a] * fa);
-                if (m > 0) dep(2, qb, b, a, wz[b][a] * fb);
+                dep(2, qa, b, a, wz[b][a], fa);
+                if (m > 0) dep(2, qb, b, a, wz[b][a], fb);
               }
             }
 #pragma unroll
@@ -789,8 +797,8 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
               for (int b = 0; b < 2; ++b) {
                 if (b == 1 && !rx) continue;
                 if ((a == 2 && di == 0) || (b == 1 && dj == 0)) continue;
-                dep(0, qa, b, a, wr[a][b] * fa);
-                if (m > 0) dep(0, qb, b, a, wr[a][b] * fb);
+                dep(0, qa, b, a, wr[a][b], fa);
+                if (m > 0) dep(0, qb, b, a, wr[a][b], fb);
               }
             }
 #pragma unroll
@@ -800,31 +808,31 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
               for (int b = 0; b < 3; ++b) {
                 if (b == 2 && !rx) continue;
                 if ((a == 2 && di == 0) || (b == 2 && dj == 0)) continue;
-                dep(1, qa, b, a, ws[a][b] * (b == 0 ? pa0 : pa));
-                if (m > 0) dep(1, qb, b, a, ws[a][b] * (b == 0 ? pb0 : pb));
+                dep(1, qa, b, a, ws[a][b], (b == 0 ? pa0 : pa));
+                if (m > 0) dep(1, qb, b, a, ws[a][b], (b == 0 ? pb0 : pb));
               }
             }
           });
         };
         if ((ib - zlo >= 0) && (ib + 2 - zlo < WZ) && (jb - rlo >= 0) && (jb + 2 - rlo < WR)) {
           double *jw = lds + (jb - rlo) * RJ + (ib - zlo) * (JW * JS);
-          deposit([&](int c, int qq, int b, int a, double v) {
+          deposit([&](int c, int qq, int b, int a, double w, double cf) {
             double *p = jw + b * RJ + a * (JW * JS) + JW * (c * NM + qq);
-            if constexpr (DET) fix_add_lds((unsigned long long *)p, v);
-            else lds_add(p, v);
+            if constexpr (DET) fix_add_lds((unsigned long long *)p, w, cf);
+            else lds_add(p, w * cf);
           });
         } else {
           int col[3];
 #pragma unroll
           for (int a = 0; a < 3; ++a) col[a] = wrap_once(ib + a, Nz);
-          deposit([&](int c, int qq, int b, int a, double v) {
+          deposit([&](int c, int qq, int b, int a, double w, double cf) {
             const long long at = (c * NM + qq) * plane + (long long)(jb + b) * Nz + col[a];
             if constexpr (DET) {
               unsigned long long x, y;
-              fix_split(v, x, y);
+              fix_split(w, cf, x, y);
               fix_add_global(k.Jfix + 2 * at, x, y);
             } else {
-              atomic_add(J + at, (R)v);
+              atomic_add(J + at, (R)(w * cf));
             }
           });
         }
