@@ -411,6 +411,26 @@ typedef struct pic_tune_report {
 int pic_autotune(const pic_run_desc *runs, int32_t n_runs, pic_opts *opts, void *device_workspace,
                  size_t *workspace_bytes, void *hip_stream, int32_t trial_steps, pic_tune_report *report);
 
+/* ---- allocation-free variant ---------------------------------------------- */
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid allocation): the reduction of
+ * pic_divergence over n electrons in caller-owned device arrays, with no
+ * context and no workspace.  ux, uy, uz (momentum per mass, units of c) and w
+ * (macro-particle charge weight) hold n values each, FP64 (precision
+ * PIC_PREC_FP64) or FP32 (PIC_PREC_FP32); out[6] (host, caller owned)
+ * receives what pic_divergence's out does, over the electrons with Lorentz
+ * factor >= gamma_min and u_z > 0.  The per-block partial sums live in a
+ * fixed device array of 2048 x 4 doubles (64 KiB) that the library holds on
+ * each GPU it runs on until the process ends: the call allocates nothing,
+ * enqueues one kernel and one copy on hip_stream and synchronises it.  One
+ * call takes at most 2048 x 256 x 64 = 33554432 electrons (PIC_E_NOMEM above
+ * that, before any device work).  Calls that overlap on one GPU share that
+ * array and race.  PIC_E_INVALID on a bad precision, NULL arrays with n > 0,
+ * n < 0 or gamma_min < 1; PIC_E_NUMERIC if a sum is not finite.            */
+int pic_divergence_arrays(int32_t precision, int64_t n, const void *ux, const void *uy, const void *uz,
+                          const void *w, double gamma_min, double *out, void *hip_stream);
+
 /* Free host objects of the context (not the workspace).                     */
 int pic_destroy(pic_ctx *ctx);
 

@@ -111,6 +111,7 @@ def _load():
         "pic_profile_read": [p, p, p],
         "pic_autotune": [C.POINTER(_RunDesc), i32, C.POINTER(_Opts), p, C.POINTER(C.c_size_t), p, i32,
                          C.POINTER(_TuneReport)],
+        "pic_divergence_arrays": [i32, i64, p, p, p, p, d, p, p],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)
@@ -125,7 +126,7 @@ _lib = _load()
 EXPORTED = ("pic_solver_setup", "pic_courant_limit", "pic_jz_inverse_taps", "pic_load_host", "pic_init", "pic_step",
             "pic_mode_work", "pic_cartesian_work", "pic_divergence", "pic_dla_integrate", "pic_checkpoint",
             "pic_restore", "pic_fields", "pic_particles", "pic_coefficients", "pic_run_info_get", "pic_destroy",
-            "pic_last_error", "pic_profile", "pic_profile_read", "pic_autotune")
+            "pic_last_error", "pic_profile", "pic_profile_read", "pic_autotune", "pic_divergence_arrays")
 PHASES = ("sort", "push", "efield", "bfield", "step")  # "step": a whole step replayed from a graph
 
 
@@ -274,6 +275,30 @@ def dla_integrate(t0, x, zeta, xd, zetad, t_end: float, h: float, a0=2.8, kz=12.
     stream = torch.cuda.current_stream(t0.device)
     _check(_lib.pic_dla_integrate(C.byref(m), n, *[C.c_void_p(a.data_ptr()) for a in arrs], float(t_end), float(h),
                                   C.c_void_p(stream.cuda_stream)))
+
+
+def divergence_arrays(ux, uy, uz, w, gamma_min=1.0):
+    """pic_divergence_arrays: the divergence sums of pic_divergence over
+    electrons in caller device arrays (contiguous torch tensors of one length
+    and dtype, float64 or float32, on one device), with no allocation (the
+    library's fixed per-GPU scratch).  Synchronises torch's current stream of
+    that device.  {"w", "rms_x", "rms_y", "count", "sum_wtx2", "sum_wty2"}."""
+    import torch  # device memory and streams only
+
+    arrs = (ux, uy, uz, w)
+    n = ux.numel()
+    dt = ux.dtype
+    for a in arrs:
+        if not (isinstance(a, torch.Tensor) and a.is_cuda and a.dtype == dt and a.is_contiguous()
+                and a.numel() == n and a.device == ux.device and dt in (torch.float64, torch.float32)):
+            raise ValueError("divergence_arrays takes contiguous float64 or float32 device tensors of one length")
+    out = np.zeros(6)
+    stream = torch.cuda.current_stream(ux.device)
+    _check(_lib.pic_divergence_arrays(PREC_FP64 if dt == torch.float64 else PREC_FP32, n,
+                                      *[C.c_void_p(a.data_ptr()) for a in arrs], float(gamma_min), _ptr(out),
+                                      C.c_void_p(stream.cuda_stream)))
+    return {"w": out[0], "rms_x": float(out[4]), "rms_y": float(out[5]), "count": int(out[3]), "sum_wtx2": out[1],
+            "sum_wty2": out[2]}
 
 
 def autotune(runs: Sequence[RunDesc], precision=PREC_FP64, solver=SOLVER_DUAL, n_coef=16, device="cuda:0",

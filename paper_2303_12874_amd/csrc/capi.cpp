@@ -29,6 +29,19 @@ int fail(int code, const char *fmt, ...) {
   return code;
 }
 
+}  // namespace
+
+// the message of pic_last_error, for entry points outside this file
+int pic::set_error(int code, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_msg, sizeof g_msg, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+namespace {
+
 int hip_ok(hipError_t e, const char *what) {
   if (e != hipSuccess) return fail(PIC_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
   return PIC_OK;

@@ -161,6 +161,9 @@ struct Batch {
 // kernel arguments are at most 4 KB
 static_assert(sizeof(Batch) <= 4096, "a Batch is passed by value as the kernel argument");
 
+// the message pic_last_error returns (capi.cpp); returns code ("" clears it)
+int set_error(int code, const char *fmt, ...);
+
 // ---- kernel launchers (kernels.hip); all enqueue on `stream` -----------------
 int launch_push(Batch &b, int prec, void *stream);
 int launch_efield(Batch &b, int prec, void *stream);

@@ -90,6 +90,23 @@ def test_deterministic_mode_is_fp64_only():
     assert e.value.code == pic.PIC_E_INVALID
 
 
+def test_allocation_free_divergence_checks_its_arguments_first():
+    """pic_divergence_arrays refuses bad arguments and counts beyond its fixed
+    scratch (2048 x 256 x 64 electrons) before any device call."""
+    out = np.zeros(6)
+    dummy = ctypes.c_void_p(16)  # never dereferenced: the checks come first
+    f = pic._lib.pic_divergence_arrays
+    assert f(64, 2048 * 256 * 64 + 1, dummy, dummy, dummy, dummy, 1.0, pic._ptr(out), None) == pic.PIC_E_NOMEM
+    assert "33554432" in pic._lib.pic_last_error().decode()
+    assert f(16, 10, dummy, dummy, dummy, dummy, 1.0, pic._ptr(out), None) == pic.PIC_E_INVALID
+    assert f(64, -1, dummy, dummy, dummy, dummy, 1.0, pic._ptr(out), None) == pic.PIC_E_INVALID
+    assert f(64, 10, None, dummy, dummy, dummy, 1.0, pic._ptr(out), None) == pic.PIC_E_INVALID
+    assert f(64, 10, dummy, dummy, dummy, dummy, 0.5, pic._ptr(out), None) == pic.PIC_E_INVALID
+    out[:] = 7.0
+    assert f(32, 0, None, None, None, None, 1.0, pic._ptr(out), None) == pic.PIC_OK  # nothing to reduce
+    assert np.all(out == 0.0)
+
+
 def test_runs_must_share_modes():
     with pytest.raises(pic.PicError) as e:
         pic.workspace_bytes([_desc(M=1), _desc(M=2)])
