@@ -217,6 +217,91 @@ def work_split(sim, M: int) -> dict:
             "identity_max_err": float(np.abs(w["gamma_acc"] - g).max())}
 
 
+def work_compare(sim, run: dict) -> dict:
+    """The three estimates of the LWFA / DLA split that Sec. IV.C compares
+    (Fig. 4), on the tracked electrons of run 0: the per-mode work of the
+    quasi-3D decomposition (Eq. (16); m = 0 the wake, m = 1 the laser), the
+    work of the longitudinal and transverse fields (Eq. (17)), and that work
+    corrected for the laser's longitudinal field with the Pukhov ratio
+    (Eqs. (20)-(21)).  Means over all tracked electrons and over the 1% with
+    the largest gamma (the "highest-energy electrons" of the figure)."""
+    import numpy as np
+
+    mw = sim.mode_work(0)
+    cw = sim.cartesian_work(0, corrected=True)
+    g = mw["gamma"]
+    top = np.argsort(g)[-max(1, g.size // 100):]
+
+    def means(sel):
+        return {"modal_lwfa_W0": float(mw["W"][sel, 0].mean()), "modal_dla_W1": float(mw["W"][sel, 1].mean()),
+                "modal_other_modes": float(mw["W"][sel, 2:].sum(axis=1).mean()) if run["M"] >= 2 else 0.0,
+                "component_lwfa_Wz": float(cw["Wz"][sel].mean()), "component_dla_Wperp": float(cw["Wperp"][sel].mean()),
+                "corrected_lwfa_W*": float(cw["W_lwfa"][sel].mean()), "corrected_dla_W*": float(cw["W_dla"][sel].mean()),
+                "pukhov_f": float(cw["f"][sel].mean()), "gamma_mean": float(g[sel].mean()),
+                "gamma_minus_1": float((g[sel] - 1).mean())}
+    return {"tracked": int(g.size), "steps": int(sim.info(0)["steps_done"]), "all": means(np.arange(g.size)),
+            "top1pct": means(top), "top1pct_gamma_min": float(g[top].min())}
+
+
+def convergence_scan(pic, torch, dev, args) -> dict:
+    """The resolution scan of Sec. IV.B (Fig. 3) on the six-run workload
+    (12..64 points per wavelength, equal physical time), once with the dual
+    solver and once with Yee, each batch in one context: per run, the
+    charge-weighted RMS divergence theta_x = atan(u_x / u_z) of the electrons
+    above a Lorentz-factor cut (the 99th percentile of gamma in the finest
+    dual run, the same cut for every run) and the cost (ms per step, steps
+    taken, ms for the whole run)."""
+    import numpy as np
+
+    cfg = workloads.config("c4")
+    runs = cfg["runs"]
+    scale = max(1, args.convergence_scale)
+    # equal physical time: the dual runs take the workload's steps (times the
+    # scale), the Yee runs (whose Courant-limited dt is longer) as many as
+    # cover the same time
+    dts = {name: [pic.solver_setup(r["M"], r["dz"], r["dr"], solver=sv, n_coef=nc)[0] for r in runs]
+           for name, sv, nc in (("dual", pic.SOLVER_DUAL, 16), ("yee", pic.SOLVER_YEE, 1))}
+    nsteps = {"dual": [n * scale for n in cfg["steps"]]}
+    nsteps["yee"] = [int(round(n * dd / dy)) for n, dd, dy in zip(nsteps["dual"], dts["dual"], dts["yee"])]
+    out = {"runs": [f"{r['Nz']}x{r['Nr']} ({round(2 * np.pi / r['dz'])} points per wavelength)" for r in runs],
+           "physical_time": [n * dd for n, dd in zip(nsteps["dual"], dts["dual"])], "scale": scale}
+    sims = {}
+    for name, solver, n_coef in (("dual", pic.SOLVER_DUAL, 16), ("yee", pic.SOLVER_YEE, 1)):
+        steps = nsteps[name]
+        sim = pic.Simulation([workloads.to_rundesc(r, n_steps=n) for r, n in zip(runs, steps)],
+                             precision=cfg["precision"], solver=solver, n_coef=n_coef, tile_z=24, tile_r=8,
+                             sort_interval=16, device="cuda:0")
+        sim.profile(True)
+        stream = torch.cuda.current_stream(dev)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        sim.step(max(steps))
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out[name] = {"ms_whole_scan": e0.elapsed_time(e1), "dt": [sim.info(i)["dt"] for i in range(len(runs))],
+                     "steps": steps}
+        sims[name] = sim
+        print(f"# convergence: {name} scan {out[name]['ms_whole_scan']:.1f} ms", file=sys.stderr, flush=True)
+    finest = sims["dual"].particles(len(runs) - 1)
+    gam = np.sqrt(1 + finest["ux"] ** 2 + finest["uy"] ** 2 + finest["uz"] ** 2)
+    cut = float(np.percentile(gam, 99))
+    out["gamma_cut"] = cut
+    for name, sim in sims.items():
+        rows = []
+        for i, r in enumerate(runs):
+            d = sim.divergence(cut, i)
+            # cost of the run alone: its share of the batch, by particle-steps
+            rows.append({"rms_theta_x": d["rms_x"], "rms_theta_y": d["rms_y"], "count": d["count"],
+                         "particle_steps": int(sim.info(i)["n_particles"]) * nsteps[name][i]})
+        tot = sum(x["particle_steps"] for x in rows)
+        for x in rows:
+            x["ms_share"] = out[name]["ms_whole_scan"] * x["particle_steps"] / tot
+        out[name]["per_run"] = rows
+        sim.close()
+    return out
+
+
 def copy_bandwidth(torch, dev, nbytes: int = 1 << 30, reps: int = 10) -> float:
     """Achievable HBM bandwidth on this device (GB/s): a device-to-device copy
     of nbytes (read + write counted), timed with events over `reps` copies
@@ -341,6 +426,14 @@ def main(argv=None):
                     help="charge conservation with D_B: z filter on J_r, J_phi (default) or P^-1 on J_z")
     ap.add_argument("--work-split", action="store_true",
                     help="after the timed steps, report the tracked electrons' energy gain split by mode (Eq. (16))")
+    ap.add_argument("--work-compare", action="store_true",
+                    help="after the timed steps, report the modal, component and corrected LWFA/DLA work estimates "
+                         "of the tracked electrons (Eqs. (16), (17), (20)-(21); Sec. IV.C)")
+    ap.add_argument("--convergence-scale", type=int, default=1,
+                    help="--convergence: run each resolution this many times the workload's steps")
+    ap.add_argument("--convergence", action="store_true",
+                    help="the six-run resolution scan with the dual and the Yee solver: RMS divergence of the "
+                         "energetic electrons and cost per run (Sec. IV.B); prints that table's JSON line only")
     args = ap.parse_args(argv)
     if args.oracle_sample:  # a child process of the all-core CPU baseline: no GPU is touched
         tot, el = _oracle_sample(args.oracle_sample, args.n_coef)
@@ -357,6 +450,11 @@ def main(argv=None):
 
     if args.workload == "dla":
         return bench_dla(args, torch, pic)
+    if args.convergence:
+        dev = torch.device("cuda:0")
+        torch.cuda.set_device(dev)
+        print(json.dumps({"convergence_scan": convergence_scan(pic, torch, dev, args)}), flush=True)
+        return 0
     cfg = workloads.config(args.workload)
     runs = cfg["runs"]
     multi = len(runs) > 1
@@ -498,6 +596,8 @@ def main(argv=None):
     }
     if args.work_split:
         out["work_split"] = work_split(sim, run["M"])
+    if args.work_compare:
+        out["work_compare"] = work_compare(sim, run)
     if args.fp64_beside if args.fp64_beside is not None else prec == 32:
         # the plain FP64 path on the same workload (library default tile and
         # sort interval), timed the same way, after the FP32 timed region; then
