@@ -181,17 +181,45 @@ __device__ __forceinline__ void store_node(R *__restrict__ F, long long plane, l
   for (int s = 2; s < NMP; ++s) F[(s - 1) * plane + node] = in[s];
 }
 
+// the NMP reals of one component of an LDS field-window record (Re, Im of
+// each mode; Im of m = 0 is stored as zero), read as vectors of VB bytes
+template <typename R, int NMP, int VB>
+__device__ __forceinline__ void load_rec(const R *__restrict__ p, R out[NMP]) {
+  constexpr int VR = VB / (int)sizeof(R);
+  typedef R V __attribute__((ext_vector_type(VR)));
+  static_assert(VR >= 2 && NMP % VR == 0, "record vectors");
+#pragma unroll
+  for (int k = 0; k < NMP / VR; ++k) {
+    const V x = *(const V *)(p + k * VR);
+#pragma unroll
+    for (int j = 0; j < VR; ++j) out[k * VR + j] = x[j];
+  }
+}
+template <typename R, int N, int VB>
+__device__ __forceinline__ void store_rec(R *__restrict__ p, const R in[N]) {
+  constexpr int VR = VB / (int)sizeof(R);
+  typedef R V __attribute__((ext_vector_type(VR)));
+  static_assert(VR >= 2 && N % VR == 0, "record vectors");
+#pragma unroll
+  for (int k = 0; k < N / VR; ++k) {
+    V x;
+#pragma unroll
+    for (int j = 0; j < VR; ++j) x[j] = in[k * VR + j];
+    *(V *)(p + k * VR) = x;
+  }
+}
+
 // mirror sign of mode m at r_{-1/2}: (-1)^{m+1} for r and phi components,
 // (-1)^m for z components (the point (-r, phi) is (r, phi + pi)).
 __host__ __device__ constexpr int mirror_sign_m(int m, bool zcomp) { return ((m % 2 == 0) == zcomp) ? 1 : -1; }
 
-// Bilinear interpolation of one component (all modes) from the records of
-// four nodes: pa, pb on the lower row (columns ca, cb), pc, pd on the upper
-// row; plane q of a record sits at offset q * pstride (the plane stride in
-// device memory, 1 inside an LDS node record).  With `mirror` the lower row
-// is the image of r_{-1/2} (pa, pb point at row r_{1/2}) and each mode takes
-// its mirror sign.
-template <typename R, int NMP, bool HALF_R, bool ZCOMP, typename I>
+// Bilinear interpolation of one component (all modes) from four nodes: pa,
+// pb on the lower row (columns ca, cb), pc, pd on the upper row.  VB = 0:
+// device memory, plane q of the component at offset q * pstride (Im of m = 0
+// not stored); VB > 0: an LDS field-window record component (load_rec).
+// With `mirror` the lower row is the image of r_{-1/2} (pa, pb point at row
+// r_{1/2}) and each mode takes its mirror sign.
+template <typename R, int NMP, bool HALF_R, bool ZCOMP, typename I, int VB = 0>
 __device__ __forceinline__ void interp4(const R *pa, const R *pb, const R *pc, const R *pd, I pstride,
                                         bool mirror, R fz, R fr, R out[NMP]) {
   const R w00 = (R(1) - fz) * (R(1) - fr), w10 = fz * (R(1) - fr);
@@ -199,10 +227,17 @@ __device__ __forceinline__ void interp4(const R *pa, const R *pb, const R *pc, c
   // lower-row weights of the modes whose mirror sign is -1
   const R n00 = (HALF_R && mirror) ? -w00 : w00, n10 = (HALF_R && mirror) ? -w10 : w10;
   R a[NMP], b[NMP], c[NMP], d[NMP];
-  load_node<R, NMP, I>(pa, pstride, 0, a);
-  load_node<R, NMP, I>(pb, pstride, 0, b);
-  load_node<R, NMP, I>(pc, pstride, 0, c);
-  load_node<R, NMP, I>(pd, pstride, 0, d);
+  if constexpr (VB > 0) {
+    load_rec<R, NMP, VB>(pa, a);
+    load_rec<R, NMP, VB>(pb, b);
+    load_rec<R, NMP, VB>(pc, c);
+    load_rec<R, NMP, VB>(pd, d);
+  } else {
+    load_node<R, NMP, I>(pa, pstride, 0, a);
+    load_node<R, NMP, I>(pb, pstride, 0, b);
+    load_node<R, NMP, I>(pc, pstride, 0, c);
+    load_node<R, NMP, I>(pd, pstride, 0, d);
+  }
   out[1] = R(0);  // Im of m = 0
 #pragma unroll
   for (int s = 0; s < NMP; ++s) {
@@ -227,8 +262,8 @@ __device__ __forceinline__ int batch_run(const Batch &b, long long g) {
 // node-major (all planes of a node contiguous, so that every component and
 // mode offset is an immediate):
 //  * E and Bbar over the tile's field window, staged once, which the gather
-//    reads: records of 6 NM reals (E_r, E_phi, E_z, Bbar_r, Bbar_phi,
-//    Bbar_z, each NM planes) and one pad;
+//    reads: one record per node of 6 components (E_r, E_phi, E_z, Bbar_r,
+//    Bbar_phi, Bbar_z) of NMP reals each, read as vectors, and a pad;
 //  * the current of the whole tile over the node window [z0-1, z0+Tz+2) x
 //    [r0-1, r0+Tr+2) (every move of less than one cell from a cell of the
 //    tile stays inside it), records of 3 NM FP64 sums, added to the global
@@ -238,20 +273,23 @@ __device__ __forceinline__ int batch_run(const Batch &b, long long g) {
 // DET (FP64 only): the deterministic mode, whose window and device sums are
 // integer pairs (fix_split) instead of FP64 values.
 template <typename R, int M, bool DET>
-__global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void push_kernel(const Batch bt) {
   constexpr int NM = 2 * M + 1;       // planes per component
   constexpr int NMP = 2 * (M + 1);    // reals per field record in registers
-  constexpr int FS = 6 * NM + 1;      // reals per field-window node, odd: lanes in
-                                      // consecutive nodes hit distinct LDS banks
   constexpr int JS = 3 * NM;          // FP64 sums per current-window node
   constexpr bool F64 = std::is_same<R, double>::value;
   constexpr int PREC = F64 ? PIC_PREC_FP64 : PIC_PREC_FP32;
+  constexpr int FS = field_node_reals(M, PREC);  // reals per field-window record
+  constexpr int VB = field_vec_bytes(M, PREC);   // bytes per vector load of a record, 0: one real at a time
+  constexpr int CR = field_comp_reals(M, PREC);  // reals per component of a record
+  static_assert(CR == (VB ? NMP : NM), "record component");
   // The tile current is summed in FP64 for both precisions: the LDS FP64
-  // atomic add is the fast one on gfx950 (FP32 sums in LDS made the FP32
-  // push several times slower).  In the FP32 form each contribution is the
-  // FP64 product of an FP32 node weight and an FP32 mode coefficient, which
-  // is exact, so the FP64 arithmetic adds no precision to the FP32 inputs;
-  // it only keeps the sums from rounding.
+  // atomic add is the fast one on gfx950 (ds_add_f32 costs about 20 times
+  // ds_add_f64, and FP32 sums in LDS made the FP32 push several times
+  // slower).  In the FP32 form a contribution is the FP64 product of an FP32
+  // node weight and an FP32 mode coefficient, which is exact, so the FP64
+  // arithmetic adds no precision to the FP32 inputs; it only keeps the sums
+  // from rounding (the global current they are added to is FP32).
   extern __shared__ __align__(16) unsigned char lds_raw[];
   double *lds = (double *)lds_raw;
   const int par = bt.par;
@@ -264,7 +302,7 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
   const int nlds = RJ * WR;
   const int FZ = field_window_z(TZ), FR = field_window_r(TR);
   const int RF = field_window_row(M, TZ, PREC);  // reals per field-window row
-  R *fw = (R *)(lds + nlds);
+  R *fw = (R *)(lds + field_window_offset_words(M, TZ, TR, DET));  // 16-byte aligned
 
   // Persistent: each workgroup takes tiles (of all runs of the batch) from a
   // ticket counter, zero before the launch, until none are left; the dealing
@@ -292,18 +330,23 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
     const unsigned gg = (unsigned)((ok ? grow : 0) * kg.Nz + wrap_any(fz0g + col, kg.Nz));
     const R *Eg = (const R *)kg.E, *Bg = (const R *)kg.Bbar;
 #pragma unroll
+    for (int i = 0; i < FS; ++i) v[i] = R(0);  // the pad (and Im of m = 0 in the vector records)
+#pragma unroll
     for (int cq = 0; cq < 6 * NM; ++cq) {
       const int c = cq / NM, q = cq % NM;
       const R t = ((c < 3 ? Eg : Bg) + ((c % 3) * NM + q) * pl)[gg];
-      v[cq] = ok ? t : R(0);
+      v[c * CR + ((VB && q > 0) ? q + 1 : q)] = ok ? t : R(0);
     }
-    v[6 * NM] = R(0);
   };
   auto stage_store = [&](int e, const R v[FS]) {
     const int row = e / FZ;
     R *dst = fw + row * RF + (e - row * FZ) * FS;
+    if constexpr (VB > 0) {
+      store_rec<R, FS, VB>(dst, v);
+    } else {
 #pragma unroll
-    for (int cq = 0; cq < FS; ++cq) dst[cq] = v[cq];
+      for (int i = 0; i < FS; ++i) dst[i] = v[i];
+    }
   };
 
   // the current window starts at zero; each flush clears what it adds
@@ -436,17 +479,17 @@ __global__ __launch_bounds__(256) void push_kernel(const Batch bt) {
       const R *li0 = fw + ri0 * RF, *li1 = li0 + RF;  // rows of j0, j0 + 1
       const R *lh0 = fw + rh0 * RF, *lh1 = fw + rh1 * RF;  // half-r rows
       const int A0 = a0 * FS, A1 = A0 + FS, H0 = h0 * FS, H1 = H0 + FS;
-      interp4<R, NMP, true, false, int>(lh0 + A0, lh0 + A1, lh1 + A0, lh1 + A1, 1, mir, f0, frh, er);
-      interp4<R, NMP, false, false, int>(li0 + A0 + NM, li0 + A1 + NM, li1 + A0 + NM, li1 + A1 + NM, 1, false, f0,
-                                         fr, ep);
-      interp4<R, NMP, false, true, int>(li0 + H0 + 2 * NM, li0 + H1 + 2 * NM, li1 + H0 + 2 * NM, li1 + H1 + 2 * NM,
-                                        1, false, fh, fr, ez);
-      interp4<R, NMP, false, false, int>(li0 + H0 + 3 * NM, li0 + H1 + 3 * NM, li1 + H0 + 3 * NM,
-                                         li1 + H1 + 3 * NM, 1, false, fh, fr, br);
-      interp4<R, NMP, true, false, int>(lh0 + H0 + 4 * NM, lh0 + H1 + 4 * NM, lh1 + H0 + 4 * NM, lh1 + H1 + 4 * NM,
-                                        1, mir, fh, frh, bp);
-      interp4<R, NMP, true, true, int>(lh0 + A0 + 5 * NM, lh0 + A1 + 5 * NM, lh1 + A0 + 5 * NM, lh1 + A1 + 5 * NM,
-                                       1, mir, f0, frh, bz);
+      interp4<R, NMP, true, false, int, VB>(lh0 + A0, lh0 + A1, lh1 + A0, lh1 + A1, 1, mir, f0, frh, er);
+      interp4<R, NMP, false, false, int, VB>(li0 + A0 + CR, li0 + A1 + CR, li1 + A0 + CR, li1 + A1 + CR, 1, false,
+                                             f0, fr, ep);
+      interp4<R, NMP, false, true, int, VB>(li0 + H0 + 2 * CR, li0 + H1 + 2 * CR, li1 + H0 + 2 * CR,
+                                            li1 + H1 + 2 * CR, 1, false, fh, fr, ez);
+      interp4<R, NMP, false, false, int, VB>(li0 + H0 + 3 * CR, li0 + H1 + 3 * CR, li1 + H0 + 3 * CR,
+                                             li1 + H1 + 3 * CR, 1, false, fh, fr, br);
+      interp4<R, NMP, true, false, int, VB>(lh0 + H0 + 4 * CR, lh0 + H1 + 4 * CR, lh1 + H0 + 4 * CR,
+                                            lh1 + H1 + 4 * CR, 1, mir, fh, frh, bp);
+      interp4<R, NMP, true, true, int, VB>(lh0 + A0 + 5 * CR, lh0 + A1 + 5 * CR, lh1 + A0 + 5 * CR,
+                                           lh1 + A1 + 5 * CR, 1, mir, f0, frh, bz);
     } else {
       const long long gi0 = (long long)j0 * Nz, gi1 = gi0 + Nz;
       const long long gh0 = (long long)(mir ? 0 : jh) * Nz, gh1 = (long long)(jh + 1) * Nz;

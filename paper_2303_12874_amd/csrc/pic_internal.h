@@ -99,44 +99,80 @@ struct KRun {
 //  * the tile's current window, FP64 for both precisions, 3 components x NM
 //    planes x (Tz+3) x (Tr+3) nodes from cell (z0-1, r0-1): every move of
 //    less than a cell from a cell of the tile deposits inside it;
-//  * the field window of E and Bbar, records of 6 components x NM planes
-//    (+1 pad) for (Tz+2+2 kFieldMarginZ) x (Tr+2+2 kFieldMarginR) nodes from
-//    column z0-1-kFieldMarginZ and row r0-1-kFieldMarginR: the gather stencil
-//    of every electron within the margins of the tile.
+//  * the field window of E and Bbar, one record per node for
+//    (Tz+2+2 kFieldMarginZ) x (Tr+2+2 kFieldMarginR) nodes from column
+//    z0-1-kFieldMarginZ and row r0-1-kFieldMarginR (the gather stencil of
+//    every electron within the margins of the tile): 6 components of 2 (M+1)
+//    reals each (Re and Im of every mode, Im of m = 0 held as zero), padded
+//    so that a component is read with 16-byte (or 8-byte) vector loads.
 constexpr int kFieldMarginZ = 1;  // columns for electrons that drifted since the sort
 constexpr int kFieldMarginR = 0;
 constexpr size_t kPushLdsDefault = 81920;  // default tile choice: two workgroups per CU
 constexpr size_t kPushLdsMax = 163840;     // gfx950 LDS per workgroup
 
-// Both windows are row-padded: the wavefront's lanes work on consecutive cells
-// of the tile (z fastest, then the next row), and a row stride congruent to
-// Tz nodes modulo the 256-byte bank width keeps those lanes on distinct banks
-// when a wavefront spans two rows.
-constexpr int kBankBytes = 256;  // 64 LDS banks of 4 bytes
+// LDS banks as measured on gfx950: an access of 4 bytes per lane costs the
+// largest number of lanes that fall on one of 32 four-byte banks, one of 8
+// bytes the same with 32 eight-byte banks; lanes on one address share it.
+// The current window is row-padded: the wavefront's lanes work on
+// consecutive cells of the tile (z fastest, then the next row), and a row
+// stride congruent to Tz nodes modulo 256 bytes keeps those lanes on distinct
+// banks when a wavefront spans two rows.
+constexpr int kBankBytes = 256;
 constexpr int field_window_z(int Tz) { return Tz + 2 + 2 * kFieldMarginZ; }
 constexpr int field_window_r(int Tr) { return Tr + 2 + 2 * kFieldMarginR; }
 constexpr int pos_mod(int a, int m) { return ((a % m) + m) % m; }
 // 8-byte words per current-window row: (Tz + 3) nodes of 3 NM sums, plus the
 // pad; a sum is one word (FP64), or two (the integer pair of the
 // deterministic mode, det).  The tile current is summed in FP64 for both
-// precisions: on gfx950 the LDS FP32 atomic add (ds_add_f32) is far slower
-// than the FP64 one (an FP32 tile current made the FP32 push of the
-// 8192 x 512 run 6.8x slower).
+// precisions: on gfx950 the LDS FP32 atomic add (ds_add_f32) costs about 20
+// times the FP64 one (measured: 193 against 8.8 cycles per wavefront
+// instruction without bank conflicts), and an FP32 tile current made the
+// FP32 push of the 8192 x 512 run 6.8x slower.
 constexpr int current_window_row(int M, int Tz, bool det = false) {
   return (det ? 2 : 1) * 3 * (2 * M + 1) * (Tz + 3) + pos_mod(-3 * (det ? 2 : 1) * 3 * (2 * M + 1), kBankBytes / 8);
 }
-// reals per field-window row: field_window_z nodes of 6 NM + 1, plus the pad
+// Field-window records.  FP32 with 2 (M+1) a multiple of 4 (M odd): a
+// component holds its 2 (M+1) reals (Re and Im of every mode, Im of m = 0 as
+// zero) and is read with 16-byte vector loads; the record stride is an odd
+// number of 16-byte vectors, so that lanes reading the same component of
+// different nodes fall on distinct banks, also when the half-cell stencils
+// of neighbouring lanes start one node apart (measured on the gather pattern
+// of a 16 x 4 tile: 4.1 cycles per 8 bytes, against 6.0 for records of
+// 4-byte planes).  Otherwise (FP64, or M even): a component holds its NM
+// planes (no Im of m = 0), read one real at a time, and the record is
+// 6 NM + 1 reals, odd (16-byte vectors measured slower there, and the larger
+// records shrink the default tiles).
+constexpr int field_vec_bytes(int M, int precision) {
+  return (precision == PIC_PREC_FP32 && (2 * (M + 1)) % 4 == 0) ? 16 : 0;
+}
+constexpr int field_comp_reals(int M, int precision) {
+  return field_vec_bytes(M, precision) ? 2 * (M + 1) : 2 * M + 1;
+}
+constexpr int field_node_reals(int M, int precision) {
+  return field_vec_bytes(M, precision) ? (6 * (2 * (M + 1)) / 4 % 2 ? 6 * (2 * (M + 1)) : 6 * (2 * (M + 1)) + 4)
+                                       : 6 * (2 * M + 1) + 1;
+}
+// reals per field-window row (record layout: a whole number of vectors;
+// plane layout: padded so that the row stride is congruent to Tz records
+// modulo 256 bytes, like the current window)
 constexpr int field_window_row(int M, int Tz, int precision) {
-  return (6 * (2 * M + 1) + 1) * field_window_z(Tz) +
-         pos_mod(-(field_window_z(Tz) - Tz) * (6 * (2 * M + 1) + 1),
-                 kBankBytes / (precision == PIC_PREC_FP64 ? 8 : 4));
+  return field_vec_bytes(M, precision)
+             ? field_node_reals(M, precision) * field_window_z(Tz)
+             : field_node_reals(M, precision) * field_window_z(Tz) +
+                   pos_mod(-(field_window_z(Tz) - Tz) * field_node_reals(M, precision),
+                           kBankBytes / (precision == PIC_PREC_FP64 ? 8 : 4));
 }
 constexpr size_t current_window_words(int M, int Tz, int Tr, bool det = false) {
   return (size_t)current_window_row(M, Tz, det) * (Tr + 3);
 }
+// 8-byte words before the field window (the current window, rounded up to 16 bytes)
+constexpr size_t field_window_offset_words(int M, int Tz, int Tr, bool det = false) {
+  return (current_window_words(M, Tz, Tr, det) + 1) / 2 * 2;
+}
 inline size_t push_lds_bytes(int M, int Tz, int Tr, int precision, bool det = false) {
   const size_t w = precision == PIC_PREC_FP64 ? 8 : 4;
-  return current_window_words(M, Tz, Tr, det) * 8 + (size_t)field_window_row(M, Tz, precision) * field_window_r(Tr) * w;
+  return field_window_offset_words(M, Tz, Tr, det) * 8 +
+         (size_t)field_window_row(M, Tz, precision) * field_window_r(Tr) * w;
 }
 
 // ---- batched launches ---------------------------------------------------------
