@@ -74,6 +74,8 @@ def lib():
             "orc_filter_taps": (dp, [p]),
             "orc_set_exact_jz": (None, [p, i]),
             "orc_inverse_filter": (i, [p, p, p]),
+            "orc_set_window": (None, [p, i, d, i]),
+            "orc_window_cells": (l, [p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(_lib, name)
@@ -174,6 +176,18 @@ class Oracle:
     def set_particles(self, z, x, y, ux, uy, uz, w, track_all=True):
         arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (z, x, y, ux, uy, uz, w)]
         lib().orc_set_particles(self._h, arrs[0].size, *[_ptr(a) for a in arrs], int(track_all))
+
+    def set_window(self, interval, speed=1.0, guard=0):
+        """Moving window (App. A): before a step whose count of steps taken is
+        a positive multiple of `interval`, the box advances by the whole cells
+        a front moving at `speed` c has crossed since the start; `guard`
+        columns at the back are cleared at each move.  interval 0: off."""
+        lib().orc_set_window(self._h, int(interval), float(speed), int(guard))
+
+    @property
+    def window_cells(self):
+        """Cells the window has moved: box column i is absolute column i + this."""
+        return int(lib().orc_window_cells(self._h))
 
     def particles(self):
         n = self.np

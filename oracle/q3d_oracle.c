@@ -72,10 +72,20 @@ typedef struct orc {
   double *W;          /* [ntr][M+1] per-mode work */
   double *Wc;         /* [ntr][2] work of E_z and of E_perp, Eq. (17) */
   double *gam0;       /* [ntr] gamma when tracking started */
+  int64_t *tr_id;     /* [ntr] id of each tracked slot */
   long nstep;
   int freeze_fields;  /* 1: Maxwell update skipped (prescribed fields) */
   int deposit_rho;    /* 1: deposit rho after every step */
   int exact_jz;       /* 1: J_z <- P^{-1} J_z, J_r and J_phi unfiltered */
+  /* plasma of the last orc_load_plasma, for the fresh columns of the window */
+  int ppc;
+  uint64_t seed;
+  double n0, ramp_start, ramp_len, down_start, down_len;
+  /* moving window: every win_K steps the box advances by the whole cells
+   * the light front has crossed since the start (speed win_speed c)       */
+  int win_K, win_guard;
+  double win_speed;
+  long win_S;         /* cells moved so far: box column i is absolute column i + win_S */
 } orc;
 
 /* ------------------------------------------------------------------------ */
@@ -149,9 +159,9 @@ orc *orc_create(int Nz, int Nr, int M, double dz, double dr, double dt, int N,
 
 static void free_particles(orc *o) {
   free(o->z); free(o->x); free(o->y); free(o->ux); free(o->uy); free(o->uz);
-  free(o->w); free(o->id); free(o->slot); free(o->W); free(o->Wc); free(o->gam0);
+  free(o->w); free(o->id); free(o->slot); free(o->W); free(o->Wc); free(o->gam0); free(o->tr_id);
   o->z = o->x = o->y = o->ux = o->uy = o->uz = o->w = NULL;
-  o->id = NULL; o->slot = NULL; o->W = o->Wc = o->gam0 = NULL;
+  o->id = NULL; o->slot = NULL; o->W = o->Wc = o->gam0 = NULL; o->tr_id = NULL;
   o->np = 0; o->ntr = 0;
 }
 
@@ -751,9 +761,15 @@ static void push_and_deposit(orc *o) {
     }
     deposit_particle(o, -o->w[p], z0, r0, j0, c0, s0, z1, r1, j1, c1, s1, vphi, cmid, smid);
 
-    /* periodic in z */
-    if (z1 < 0.0) z1 += o->Nz;
-    if (z1 >= o->Nz) z1 -= o->Nz;
+    if (o->win_K > 0) {
+      /* moving window: an electron that left the box through either end
+       * carries no charge from the next step on and is dropped at the next
+       * window move (its position is kept as it is, outside [0, Nz))       */
+      if (z1 < 0.0 || z1 >= o->Nz) o->w[p] = 0.0;
+    } else { /* periodic in z */
+      if (z1 < 0.0) z1 += o->Nz;
+      if (z1 >= o->Nz) z1 -= o->Nz;
+    }
     o->z[p] = z1; o->x[p] = x1; o->y[p] = y1;
     o->ux[p] = un[0]; o->uy[p] = un[1]; o->uz[p] = un[2];
   }
@@ -775,8 +791,78 @@ static void field_update(orc *o) {
   swap_b(o);
 }
 
+static void load_electron(orc *o, long p, int64_t pid, long S);
+
+/* Moving window (App. A: the box follows the pulse through the plasma).
+ * Done before a step when the steps taken are a positive multiple of win_K:
+ * the box advances by the s = floor(v n dt / dz) - S whole cells the front,
+ * moving at v = win_speed c, crossed since the last move.  E^n, B^{n-1/2}
+ * and B^{n+1/2} move back by s columns with zeros entering at the front and
+ * the win_guard columns at the back are cleared (what the z-periodic
+ * stencils carry round from the back would otherwise reach the front); the
+ * electrons move back by s cells, those outside [0, Nz) are dropped (left
+ * through the back, or earlier through either end), and the plasma of the
+ * s new absolute columns is loaded as orc_load_plasma loads it.            */
+static void window_move(orc *o) {
+  const long target = (long)floor(o->win_speed * (double)o->nstep * o->dt / o->dz);
+  long s = target - o->win_S;
+  if (s <= 0) return;
+  const int Nz = o->Nz;
+  for (int c = 0; c < 3; ++c) {
+    cplx *arr[3] = {o->E[c], o->Bo[c], o->Bn[c]};
+    for (int a = 0; a < 3; ++a)
+      for (int m = 0; m <= o->M; ++m)
+        for (int j = 0; j <= o->Nr; ++j) {
+          cplx *row = arr[a] + ((size_t)m * (size_t)(o->Nr + 1) + (size_t)j) * (size_t)Nz;
+          for (int i = 0; i < Nz; ++i) row[i] = (i + s < Nz) ? row[i + s] : 0.0;
+          for (int i = 0; i < o->win_guard && i < Nz; ++i) row[i] = 0.0;
+        }
+  }
+  long keep = 0;
+  for (long p = 0; p < o->np; ++p) {
+    const double z = o->z[p] - (double)s;
+    if (z < 0.0 || z >= Nz) continue;
+    o->z[keep] = z; o->x[keep] = o->x[p]; o->y[keep] = o->y[p];
+    o->ux[keep] = o->ux[p]; o->uy[keep] = o->uy[p]; o->uz[keep] = o->uz[p];
+    o->w[keep] = o->w[p]; o->id[keep] = o->id[p]; o->slot[keep] = o->slot[p];
+    ++keep;
+  }
+  const int nrc = o->Nr - 1;
+  const long fresh = (s < Nz ? s : Nz) * (long)nrc * o->ppc;
+  const long np = keep + fresh;
+  o->z = (double *)realloc(o->z, sizeof(double) * (np > 0 ? np : 1));
+  o->x = (double *)realloc(o->x, sizeof(double) * (np > 0 ? np : 1));
+  o->y = (double *)realloc(o->y, sizeof(double) * (np > 0 ? np : 1));
+  o->ux = (double *)realloc(o->ux, sizeof(double) * (np > 0 ? np : 1));
+  o->uy = (double *)realloc(o->uy, sizeof(double) * (np > 0 ? np : 1));
+  o->uz = (double *)realloc(o->uz, sizeof(double) * (np > 0 ? np : 1));
+  o->w = (double *)realloc(o->w, sizeof(double) * (np > 0 ? np : 1));
+  o->id = (int64_t *)realloc(o->id, sizeof(int64_t) * (np > 0 ? np : 1));
+  o->slot = (int32_t *)realloc(o->slot, sizeof(int32_t) * (np > 0 ? np : 1));
+  /* the new columns are absolute columns [target + Nz - s', target + Nz) */
+  const long a0 = target + Nz - (s < Nz ? s : Nz);
+  long p = keep;
+  for (long a = a0; a < target + Nz; ++a)
+    for (int ir = 0; ir < nrc; ++ir)
+      for (int k = 0; k < o->ppc; ++k, ++p) {
+        const int64_t pid = ((int64_t)a * nrc + ir) * o->ppc + k;
+        load_electron(o, p, pid, target);
+        o->slot[p] = -1;
+      }
+  o->np = np;
+  o->win_S = target;
+}
+
+void orc_set_window(orc *o, int K, double speed, int guard) {
+  o->win_K = K > 0 ? K : 0;
+  o->win_speed = speed;
+  o->win_guard = guard > 0 ? guard : 0;
+}
+long orc_window_cells(const orc *o) { return o->win_S; }
+
 void orc_step(orc *o, int nsteps) {
   for (int s = 0; s < nsteps; ++s) {
+    if (o->win_K > 0 && o->nstep > 0 && o->nstep % o->win_K == 0) window_move(o);
     push_and_deposit(o);
     if (!o->freeze_fields) field_update(o);
     if (o->deposit_rho) deposit_rho_all(o);
@@ -823,6 +909,36 @@ static int cmp_track(const void *a, const void *b) {
   return (x[1] < y[1]) ? -1 : (x[1] > y[1]);
 }
 
+/* Electron pid of the plasma (pid = (a (Nr-1) + ir) ppc + s for absolute
+ * column a, radial cell ir, sample s) into particle slot p, in the
+ * coordinates of a box whose column 0 is absolute column S.                 */
+static void load_electron(orc *o, long p, int64_t pid, long S) {
+  const int nrc = o->Nr - 1, ppc = o->ppc;
+  const int64_t a = pid / ((int64_t)nrc * ppc), ir = (pid / ppc) % nrc;
+  double U0 = uniform_draw(o->seed, pid, 0), U1 = uniform_draw(o->seed, pid, 1);
+  double U2 = uniform_draw(o->seed, pid, 2);
+  double zc = (double)a + U0, rc = (double)ir + U1, phi = 2.0 * ORC_PI * U2;
+  double n = o->n0;
+  if (o->ramp_len > 0.0) {
+    double f = (zc * o->dz - o->ramp_start) / o->ramp_len;
+    if (f < 0.0) f = 0.0;
+    if (f > 1.0) f = 1.0;
+    n = o->n0 * f;
+  }
+  if (o->down_len > 0.0) {
+    double g = 1.0 - (zc * o->dz - o->down_start) / o->down_len;
+    if (g < 0.0) g = 0.0;
+    if (g > 1.0) g = 1.0;
+    n *= g;
+  }
+  o->z[p] = zc - (double)S;
+  o->x[p] = rc * cos(phi);
+  o->y[p] = rc * sin(phi);
+  o->ux[p] = o->uy[p] = o->uz[p] = 0.0;
+  o->w[p] = n * (2.0 * ORC_PI) * (rc * o->dr) * o->dr * o->dz / ppc;
+  o->id[p] = pid;
+}
+
 /* Cold electrons, ppc per cell in cells iz = 0..Nz-1, ir = 0..Nr-2, at
  * uniform-random (z, r, phi) in the cell; density n(z) = n0 times a linear
  * up-ramp over [ramp_start, ramp_start + ramp_len] and a linear down-ramp
@@ -847,37 +963,22 @@ int orc_load_plasma(orc *o, int ppc, double n0, double ramp_start, double ramp_l
   o->w = (double *)malloc(sizeof(double) * np);
   o->id = (int64_t *)malloc(sizeof(int64_t) * np);
   o->slot = (int32_t *)malloc(sizeof(int32_t) * np);
+  o->ppc = ppc; o->seed = seed; o->n0 = n0;
+  o->ramp_start = ramp_start; o->ramp_len = ramp_len;
+  o->down_start = down_start; o->down_len = down_len;
+  o->win_S = 0;
   for (int iz = 0; iz < Nz; ++iz)
     for (int ir = 0; ir < nrc; ++ir)
       for (int s = 0; s < ppc; ++s) {
         int64_t pid = ((int64_t)iz * nrc + ir) * ppc + s;
-        double U0 = uniform_draw(seed, pid, 0), U1 = uniform_draw(seed, pid, 1);
-        double U2 = uniform_draw(seed, pid, 2);
-        double zc = iz + U0, rc = ir + U1, phi = 2.0 * ORC_PI * U2;
-        double n = n0;
-        if (ramp_len > 0.0) {
-          double f = (zc * o->dz - ramp_start) / ramp_len;
-          if (f < 0.0) f = 0.0;
-          if (f > 1.0) f = 1.0;
-          n = n0 * f;
-        }
-        if (down_len > 0.0) {
-          double g = 1.0 - (zc * o->dz - down_start) / down_len;
-          if (g < 0.0) g = 0.0;
-          if (g > 1.0) g = 1.0;
-          n *= g;
-        }
-        o->z[pid] = zc;
-        o->x[pid] = rc * cos(phi);
-        o->y[pid] = rc * sin(phi);
-        o->w[pid] = n * (2.0 * ORC_PI) * (rc * o->dr) * o->dr * o->dz / ppc;
-        o->id[pid] = pid;
+        load_electron(o, pid, pid, 0);
         o->slot[pid] = -1;
       }
   o->ntr = n_tracked;
   o->W = (double *)calloc((size_t)(n_tracked > 0 ? n_tracked : 1) * (o->M + 1), sizeof(double));
   o->Wc = (double *)calloc((size_t)(n_tracked > 0 ? n_tracked : 1) * 2, sizeof(double));
   o->gam0 = (double *)calloc((size_t)(n_tracked > 0 ? n_tracked : 1), sizeof(double));
+  o->tr_id = (int64_t *)calloc((size_t)(n_tracked > 0 ? n_tracked : 1), sizeof(int64_t));
   if (n_tracked > 0) {
     double *key = (double *)malloc(sizeof(double) * 2 * np);
     for (long p = 0; p < np; ++p) { key[2 * p] = uniform_draw(seed, p, 3); key[2 * p + 1] = (double)p; }
@@ -891,7 +992,7 @@ int orc_load_plasma(orc *o, int ppc, double n0, double ramp_start, double ramp_l
       while (b >= 0 && sel[b] > v) { sel[b + 1] = sel[b]; --b; }
       sel[b + 1] = v;
     }
-    for (int k = 0; k < n_tracked; ++k) { o->slot[sel[k]] = k; o->gam0[k] = 1.0; }
+    for (int k = 0; k < n_tracked; ++k) { o->slot[sel[k]] = k; o->gam0[k] = 1.0; o->tr_id[k] = sel[k]; }
     free(sel);
     free(key);
   }
@@ -923,8 +1024,11 @@ int orc_set_particles(orc *o, long np, const double *z, const double *x, const d
   o->W = (double *)calloc((size_t)(o->ntr > 0 ? o->ntr : 1) * (o->M + 1), sizeof(double));
   o->Wc = (double *)calloc((size_t)(o->ntr > 0 ? o->ntr : 1) * 2, sizeof(double));
   o->gam0 = (double *)calloc((size_t)(o->ntr > 0 ? o->ntr : 1), sizeof(double));
-  for (int k = 0; k < o->ntr; ++k)
+  o->tr_id = (int64_t *)malloc(sizeof(int64_t) * (o->ntr > 0 ? o->ntr : 1));
+  for (int k = 0; k < o->ntr; ++k) {
     o->gam0[k] = sqrt(1.0 + ux[k] * ux[k] + uy[k] * uy[k] + uz[k] * uz[k]);
+    o->tr_id[k] = k;
+  }
   return 0;
 }
 
@@ -955,18 +1059,23 @@ void orc_put_particles(orc *o, const double *z, const double *x, const double *y
 /* Tracked output, slot order: ids, W [ntr][M+1], gamma from u, and the FP64
  * accumulated gamma0 + sum_m W_m.                                           */
 int orc_tracked(orc *o, int64_t *ids, double *W, double *gamma, double *gamma_acc) {
-  for (long p = 0; p < o->np; ++p) {
-    int k = o->slot[p];
-    if (k < 0) continue;
-    if (ids) ids[k] = o->id[p];
+  /* every slot reports its id, work and gamma_acc; gamma is NaN for a
+   * tracked electron no longer in the box (dropped by the moving window)   */
+  for (int k = 0; k < o->ntr; ++k) {
+    if (ids) ids[k] = o->tr_id[k];
     double s = o->gam0[k];
     for (int m = 0; m <= o->M; ++m) {
       if (W) W[(size_t)k * (o->M + 1) + m] = o->W[(size_t)k * (o->M + 1) + m];
       s += o->W[(size_t)k * (o->M + 1) + m];
     }
-    if (gamma) gamma[k] = sqrt(1.0 + o->ux[p] * o->ux[p] + o->uy[p] * o->uy[p] + o->uz[p] * o->uz[p]);
+    if (gamma) gamma[k] = NAN;
     if (gamma_acc) gamma_acc[k] = s;
   }
+  if (gamma)
+    for (long p = 0; p < o->np; ++p) {
+      int k = o->slot[p];
+      if (k >= 0) gamma[k] = sqrt(1.0 + o->ux[p] * o->ux[p] + o->uy[p] * o->uy[p] + o->uz[p] * o->uz[p]);
+    }
   return o->ntr;
 }
 
