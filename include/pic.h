@@ -169,6 +169,26 @@ typedef struct pic_opts {
    * interval, and with or without captured graphs; the deposit costs more
    * (about twice the LDS and more arithmetic).  PIC_E_INVALID in FP32.      */
   int32_t deterministic;
+  /* Moving window (App. A: the box follows the pulse through a plasma longer
+   * than the box).  window_interval K > 0: before a step whose count of
+   * steps taken n is a positive multiple of K, every run's box advances by
+   * s = floor(v n dt / dz) - S whole cells (v = window_speed c, 0 -> c; S
+   * the cells moved so far, box column i is absolute column i + S): E^n,
+   * B^{n-1/2}, B^{n+1/2} move back s columns with zeros entering at the
+   * front, the window_guard columns at the back are cleared, electrons move
+   * back s cells and those outside the box are dropped, and the plasma of
+   * the s new absolute columns is loaded as pic_init loads the run's plasma
+   * (same draws, ids pid = (a (Nr-1) + ir) ppc + k, density profile at the
+   * absolute position; none tracked).  An electron leaving the box through
+   * either end keeps its position outside the box and zero weight until the
+   * next move drops it.  The electron count then varies
+   * (pic_run_info.n_particles); the arrays hold the initial count plus four
+   * moves' worth of fresh columns and 1 %, and a move beyond that fails with
+   * PIC_E_NOMEM.  Not with use_graph, deterministic or pic_checkpoint
+   * (PIC_E_INVALID).  0: the static z-periodic box.                         */
+  int32_t window_interval;
+  int32_t window_guard;
+  double window_speed;
 } pic_opts;
 
 typedef struct pic_ctx pic_ctx;
@@ -177,13 +197,15 @@ typedef struct pic_ctx pic_ctx;
 typedef struct pic_run_info {
   double dt;             /* time step in use                                 */
   double courant_limit;  /* largest stable c dt / dz for these coefficients  */
-  int64_t n_particles;   /* electrons in the run                             */
+  int64_t n_particles;   /* electrons in the run (varies with a moving window) */
   int64_t steps_done;    /* steps taken (those of a restored checkpoint
                             included)                                        */
   int32_t n_coef;        /* coefficients per operator                        */
   int32_t n_tracked;
   int32_t tile_z;        /* sort tile in use (cells along z and r)           */
   int32_t tile_r;
+  int64_t window_cells;  /* moving window: cells moved (box column i is
+                            absolute column i + window_cells); else 0        */
 } pic_run_info;
 
 /* ---- host-only setup (no GPU needed) ----------------------------------- */

@@ -57,13 +57,14 @@ class _Opts(C.Structure):
         ("use_graph", C.c_int32), ("current", C.c_int32),
         ("run_dt", C.POINTER(C.c_double)), ("run_coef_E", C.POINTER(C.c_double)),
         ("run_coef_B", C.POINTER(C.c_double)), ("deterministic", C.c_int32),
+        ("window_interval", C.c_int32), ("window_guard", C.c_int32), ("window_speed", C.c_double),
     ]
 
 
 class _RunInfo(C.Structure):
     _fields_ = [("dt", C.c_double), ("courant_limit", C.c_double), ("n_particles", C.c_int64),
                 ("steps_done", C.c_int64), ("n_coef", C.c_int32), ("n_tracked", C.c_int32),
-                ("tile_z", C.c_int32), ("tile_r", C.c_int32)]
+                ("tile_z", C.c_int32), ("tile_r", C.c_int32), ("window_cells", C.c_int64)]
 
 
 MAX_TUNE = 16
@@ -237,9 +238,11 @@ def workspace_bytes(runs: Sequence[RunDesc], precision=PREC_FP64, solver=SOLVER_
 
 def _make_opts(precision, solver, n_coef, dt=0.0, coef_E=None, coef_B=None, cfl_fraction=0.0, fit_band=0.0,
                sort_interval=0, tile_z=0, tile_r=0, use_graph=False, current=CURRENT_FILTER, run_dt=None,
-               run_coef_E=None, run_coef_B=None, deterministic=False):
+               run_coef_E=None, run_coef_B=None, deterministic=False, window_interval=0, window_guard=0,
+               window_speed=0.0):
     """pic_opts.  run_dt: one dt per run; run_coef_E / run_coef_B: one
-    coefficient vector per run (sequences over the runs)."""
+    coefficient vector per run (sequences over the runs); window_*: the
+    moving window (0: static box)."""
     o = _Opts()
     o.precision, o.solver, o.n_coef = precision, solver, n_coef
     o.fit_band, o.cfl_fraction, o.dt = fit_band, cfl_fraction, dt
@@ -254,6 +257,7 @@ def _make_opts(precision, solver, n_coef, dt=0.0, coef_E=None, coef_B=None, cfl_
     o.sort_interval, o.tile_z, o.tile_r, o.use_graph = sort_interval, tile_z, tile_r, int(use_graph)
     o.current = current
     o.deterministic = int(bool(deterministic))
+    o.window_interval, o.window_guard, o.window_speed = int(window_interval), int(window_guard), float(window_speed)
     return o, keep
 
 
@@ -375,7 +379,7 @@ class Simulation:
         _check(_lib.pic_run_info_get(self._h, run, C.byref(inf)))
         return {"dt": inf.dt, "courant_limit": inf.courant_limit, "n_particles": inf.n_particles,
                 "steps_done": inf.steps_done, "n_coef": inf.n_coef, "n_tracked": inf.n_tracked,
-                "tile": (inf.tile_z, inf.tile_r)}
+                "tile": (inf.tile_z, inf.tile_r), "window_cells": inf.window_cells}
 
     def coefficients(self, run=0):
         N = self.info(run)["n_coef"]

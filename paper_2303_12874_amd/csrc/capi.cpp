@@ -73,6 +73,9 @@ struct RunHost {
   std::vector<double> H;  // taps of P^{-1} (exact J_z correction), else empty
   std::vector<double> gam0;
   int64_t steps = 0;
+  int64_t win_S = 0;    // moving window: cells moved (box column i is absolute column i + win_S)
+  int64_t cap = 0;      // particle slots of the run's arrays
+  std::vector<int64_t> tr_ids;  // tracked ids, ascending
   size_t offset = 0, bytes = 0;
   double *dev_gamma = nullptr;  // scratch for pic_mode_work
   int64_t *dev_ids = nullptr;
@@ -85,11 +88,22 @@ struct Layout {
   size_t W, Wc, tracked, CE, CB, P, H, red, gam, ids, work, Jfix, total;
 };
 
-Layout layout_of(const pic_run_desc &d, int prec, int N, int Tz, int Tr, long long n_keys, bool det) {
+// Particle slots of a run: its electrons, and with a moving window of
+// interval K four moves' worth of fresh columns (a move crosses at most
+// ceil(K v) + 1 columns, c dt < dz) and 1 %.
+int64_t particle_capacity(const pic_run_desc &d, const pic_opts &o) {
+  const int64_t np = run_particle_count(d);
+  if (o.window_interval <= 0) return np;
+  const double v = o.window_speed > 0 ? o.window_speed : 1.0;
+  const int64_t cols = (int64_t)std::ceil(o.window_interval * v) + 1;
+  return np + 4 * cols * (int64_t)(d.Nr - 1) * d.ppc + np / 100 + 1024;
+}
+
+Layout layout_of(const pic_run_desc &d, int prec, int N, int Tz, int Tr, long long n_keys, bool det, int64_t cap) {
   const size_t rs = prec == PIC_PREC_FP64 ? 8 : 4;
   const int NM = 2 * d.M + 1;  // mode planes per component
   const size_t plane = (size_t)(d.Nr + 1) * d.Nz;
-  const size_t np = (size_t)run_particle_count(d);
+  const size_t np = (size_t)cap;
   Layout L{};
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -156,6 +170,8 @@ struct pic_ctx {
   int sort_interval = 0;
   int current = PIC_CURRENT_FILTER;
   bool det = false;  // deterministic mode: integer deposit sums
+  int win_K = 0, win_guard = 0;  // moving window: steps between moves (0: static box), guard columns
+  double win_speed = 1.0;        // the window's speed (c)
   std::vector<RunHost> runs;
   // per-phase event timing
   bool profiling = false;
@@ -368,8 +384,16 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
   if (o.deterministic != 0 && o.deterministic != 1) return fail(PIC_E_INVALID, "deterministic must be 0 or 1");
   if (o.deterministic && o.precision != PIC_PREC_FP64)
     return fail(PIC_E_INVALID, "the deterministic mode is for PIC_PREC_FP64 runs");
+  if (o.window_interval < 0 || o.window_guard < 0 || !(o.window_speed >= 0) || !std::isfinite(o.window_speed))
+    return fail(PIC_E_INVALID, "window_interval, window_guard and window_speed must be >= 0");
+  if (o.window_interval > 0 && (o.use_graph || o.deterministic))
+    return fail(PIC_E_INVALID, "the moving window does not run with use_graph or the deterministic mode");
   for (int i = 0; i < n_runs; ++i) {
     TRY(validate_run(runs[i], i, N));
+    if (particle_capacity(runs[i], o) * 8 > (int64_t)UINT32_MAX)
+      return fail(PIC_E_INVALID, "run %d: the moving window's particle slots exceed the 2^29 a run may hold", i);
+    if (o.window_interval > 0 && o.window_guard >= runs[i].Nz)
+      return fail(PIC_E_INVALID, "run %d: window_guard must be below Nz", i);
     if (runs[i].M != runs[0].M) return fail(PIC_E_INVALID, "all runs of one context must share M");
   }
   int Tz, Tr;
@@ -380,7 +404,8 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
   std::vector<size_t> offs;
   size_t total = 0;
   for (int i = 0; i < n_runs; ++i) {
-    lays.push_back(layout_of(runs[i], o.precision, N, Tz, Tr, keys_of(runs[i], Tz, Tr), o.deterministic != 0));
+    lays.push_back(layout_of(runs[i], o.precision, N, Tz, Tr, keys_of(runs[i], Tz, Tr), o.deterministic != 0,
+                             particle_capacity(runs[i], o)));
     offs.push_back(total);
     total = align_up(total + lays.back().total);
   }
@@ -402,6 +427,9 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
   ctx->use_graph = o.use_graph != 0;
   ctx->current = o.current;
   ctx->det = o.deterministic != 0;
+  ctx->win_K = o.window_interval;
+  ctx->win_guard = o.window_guard;
+  ctx->win_speed = o.window_speed > 0 ? o.window_speed : 1.0;
   ctx->runs.resize((size_t)n_runs);
   const hipStream_t s = ctx->stream;
   const bool f64 = o.precision == PIC_PREC_FP64;
@@ -475,6 +503,8 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
     k.dr = d.dr;
     k.dt = R.dt;
     k.np = run_particle_count(d);
+    R.cap = particle_capacity(d, o);
+    k.window = ctx->win_K > 0 ? 1 : 0;
     k.plane = (long long)(d.Nr + 1) * d.Nz;
     k.E = base + L.E;
     k.B[0] = base + L.B0;
@@ -561,6 +591,7 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
     }
     for (size_t t = 0; t < tr.size(); ++t) pid[(size_t)tr[t]] |= kTrackedBit;
     std::vector<int32_t> tr32(tr.begin(), tr.end());
+    R.tr_ids = tr;
     R.gam0.assign(tr.size(), 1.0);  // cold start
     if (f64) {
       std::vector<double> zero(np, 0.0);
@@ -645,6 +676,8 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
 
 }  // extern "C"
 
+extern "C" int check_sort_flags(pic_ctx *ctx);
+
 namespace {
 
 hipEvent_t take_event(pic_ctx *ctx) {
@@ -671,6 +704,84 @@ int timed(pic_ctx *ctx, int phase, F &&launch) {
   return rc;
 }
 
+// Moving window, before a step whose count of steps taken n is a positive
+// multiple of K: the run's box advances by s = floor(v n dt / dz) - S cells.
+// The fresh plasma of the s new absolute columns is appended to the particle
+// arrays in the box's current coordinates, the fields move back (E, B, Bbar;
+// J is zero between steps), and k.shift = s makes the step's sort move every
+// electron back s cells and drop those outside the box.  *moved: a move was
+// enqueued (the step must sort and then read back the electron count).
+int window_move(pic_ctx *ctx, RunHost &R, hipStream_t s, bool *moved) {
+  *moved = false;
+  const int64_t n = R.steps;
+  if (ctx->win_K <= 0 || n <= 0 || n % ctx->win_K != 0) return PIC_OK;
+  const int64_t target = (int64_t)std::floor(ctx->win_speed * (double)n * R.dt / R.d.dz);
+  const int64_t sft = target - R.win_S;
+  if (sft <= 0) return PIC_OK;
+  const pic_run_desc &d = R.d;
+  KRun &k = R.k;
+  const int64_t cols = std::min<int64_t>(sft, d.Nz), a1 = target + d.Nz;
+  const int64_t nf = cols * (int64_t)(d.Nr - 1) * d.ppc;
+  if (k.np + nf > R.cap)
+    return fail(PIC_E_NOMEM, "moving window: %lld electrons after the move exceed the %lld slots",
+                (long long)(k.np + nf), (long long)R.cap);
+  if (nf > 0 && a1 * (int64_t)(d.Nr - 1) * d.ppc - 1 > (int64_t)kIdMask)
+    return fail(PIC_E_INVALID, "moving window: the plasma ids of absolute column %lld exceed the id range",
+                (long long)(a1 - 1));
+  if (nf > 0) {
+    std::vector<double> z((size_t)nf), x((size_t)nf), y((size_t)nf), w((size_t)nf);
+    std::vector<int64_t> id((size_t)nf);
+    load_columns(d, a1 - cols, a1, R.win_S, z.data(), x.data(), y.data(), w.data(), id.data());
+    std::vector<uint32_t> pid(id.begin(), id.end());
+    const size_t at = (size_t)k.np;
+    if (ctx->prec == PIC_PREC_FP64) {
+      std::vector<double> zero((size_t)nf, 0.0);
+      TRY(upload((double *)k.pz + at, z, s));
+      TRY(upload((double *)k.px + at, x, s));
+      TRY(upload((double *)k.py + at, y, s));
+      TRY(upload((double *)k.pux + at, zero, s));
+      TRY(upload((double *)k.puy + at, zero, s));
+      TRY(upload((double *)k.puz + at, zero, s));
+      TRY(upload((double *)k.pw + at, w, s));
+      TRY(upload(k.pid + at, pid, s));
+      TRY(hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize"));
+    } else {
+      // int32 cell + FP32 offset, as pic_init converts (the cell is not wrapped)
+      std::vector<int32_t> iz((size_t)nf);
+      std::vector<float> fz((size_t)nf), xf((size_t)nf), yf((size_t)nf), wf((size_t)nf), zero((size_t)nf, 0.0f);
+      for (size_t p = 0; p < (size_t)nf; ++p) {
+        double c = std::floor(z[p]);
+        float f = (float)(z[p] - c);
+        if (f >= 1.0f) {
+          f = 0.0f;
+          c += 1.0;
+        }
+        iz[p] = (int32_t)c;
+        fz[p] = f;
+        xf[p] = (float)x[p];
+        yf[p] = (float)y[p];
+        wf[p] = (float)w[p];
+      }
+      TRY(upload((int32_t *)k.pz + at, iz, s));
+      TRY(upload((float *)k.pfz + at, fz, s));
+      TRY(upload((float *)k.px + at, xf, s));
+      TRY(upload((float *)k.py + at, yf, s));
+      TRY(upload((float *)k.pux + at, zero, s));
+      TRY(upload((float *)k.puy + at, zero, s));
+      TRY(upload((float *)k.puz + at, zero, s));
+      TRY(upload((float *)k.pw + at, wf, s));
+      TRY(upload(k.pid + at, pid, s));
+      TRY(hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize"));
+    }
+    k.np += nf;
+  }
+  k.shift = (int)std::min<int64_t>(sft, (int64_t)d.Nz + 1);  // beyond Nz every electron is dropped alike
+  TRY(launch_window_shift(k, ctx->prec, ctx->win_guard, s));
+  R.win_S = target;
+  *moved = true;
+  return PIC_OK;
+}
+
 // Enqueue one step of the runs `ids` (at most kMaxBatch, all at the same step
 // count): sort when due, then push, E update and B update, one launch per
 // phase for all of them -- or the replay of that step's captured graph.
@@ -679,7 +790,12 @@ int step_batch(pic_ctx *ctx, const std::vector<int> &ids) {
   const int prec = ctx->prec;
   const int64_t step = ctx->runs[(size_t)ids[0]].steps;
   const int par = (int)(step & 1);
-  const bool sort = step > 0 && step % ctx->sort_interval == 0;
+  bool sort = step > 0 && step % ctx->sort_interval == 0;
+  bool moved[kMaxBatch] = {};
+  for (size_t i = 0; i < ids.size(); ++i) {
+    TRY(window_move(ctx, ctx->runs[(size_t)ids[i]], s, &moved[i]));
+    if (moved[i]) sort = true;
+  }
   Batch b;
   std::memset(&b, 0, sizeof b);  // every byte defined: the batch is a capture key
   b.n = (int)ids.size();
@@ -738,6 +854,15 @@ int step_batch(pic_ctx *ctx, const std::vector<int> &ids) {
     RunHost &R = ctx->runs[(size_t)ids[(size_t)i]];
     R.k = b.run[i];
     R.steps++;
+    if (moved[i]) {  // the sort kept the electrons in the box: cell_start[n_keys] of them
+      int32_t alive = 0;
+      TRY(hip_ok(hipMemcpyAsync(&alive, R.k.cell_start + R.k.n_keys, 4, hipMemcpyDeviceToHost, s), "D2H"));
+      TRY(hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize"));
+      TRY(check_sort_flags(ctx));
+      if (alive < 0 || alive > R.k.np) return fail(PIC_E_DEVICE, "moving window: bad electron count %d", alive);
+      R.k.np = alive;
+      R.k.shift = 0;
+    }
   }
   return PIC_OK;
 }
@@ -966,6 +1091,7 @@ int pic_run_info_get(pic_ctx *ctx, int32_t run, pic_run_info *info) {
   info->n_tracked = R->d.n_tracked;
   info->tile_z = R->k.Tz;
   info->tile_r = R->k.Tr;
+  info->window_cells = R->win_S;
   return PIC_OK;
 }
 
@@ -1112,6 +1238,8 @@ int pic_mode_work(pic_ctx *ctx, int32_t run, double *work, double *gamma, double
   bool finite = true;
   std::vector<double> W((size_t)nt * (M + 1));
   if (nt > 0) {
+    // ids of tracked electrons not in the box (dropped by a moving window) stay -1
+    TRY(hip_ok(hipMemsetAsync(R->dev_ids, 0xff, (size_t)nt * 8, s), "hipMemsetAsync"));
     TRY(launch_tracked_gamma(k, ctx->prec, R->dev_gamma, R->dev_ids, s));
     TRY(hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize"));
     TRY(hip_ok(hipMemcpy(W.data(), k.W, W.size() * 8, hipMemcpyDeviceToHost), "D2H"));
@@ -1122,10 +1250,11 @@ int pic_mode_work(pic_ctx *ctx, int32_t run, double *work, double *gamma, double
     for (int t = 0; t < nt; ++t) {
       double acc = R->gam0[(size_t)t];
       for (int m = 0; m <= M; ++m) acc += W[(size_t)t * (M + 1) + m];
-      if (!std::isfinite(acc) || !std::isfinite(g[(size_t)t])) finite = false;
+      const bool present = id[(size_t)t] >= 0;
+      if (!std::isfinite(acc) || (present && !std::isfinite(g[(size_t)t]))) finite = false;
       if (gamma_acc) gamma_acc[t] = acc;
-      if (gamma) gamma[t] = g[(size_t)t];
-      if (ids) ids[t] = id[(size_t)t];
+      if (gamma) gamma[t] = present ? g[(size_t)t] : std::nan("");
+      if (ids) ids[t] = R->tr_ids[(size_t)t];
     }
     if (work) std::memcpy(work, W.data(), W.size() * 8);
   }
@@ -1312,6 +1441,7 @@ extern "C" {
 int pic_checkpoint(pic_ctx *ctx, void *host_buf, size_t *bytes) {
   g_msg[0] = 0;
   if (!ctx_ok(ctx)) return fail(PIC_E_STATE, "invalid or destroyed context");
+  if (ctx->win_K > 0) return fail(PIC_E_INVALID, "no checkpoint of a moving-window context");
   TRY(check_sort_flags(ctx));
   if (!bytes) return fail(PIC_E_INVALID, "bytes is NULL");
   const size_t need = checkpoint_bytes(ctx);
@@ -1346,6 +1476,7 @@ int pic_checkpoint(pic_ctx *ctx, void *host_buf, size_t *bytes) {
 int pic_restore(pic_ctx *ctx, const void *host_buf, size_t bytes) {
   g_msg[0] = 0;
   if (!ctx_ok(ctx)) return fail(PIC_E_STATE, "invalid or destroyed context");
+  if (ctx->win_K > 0) return fail(PIC_E_INVALID, "no restore into a moving-window context");
   if (!host_buf) return fail(PIC_E_INVALID, "buffer is NULL");
   const size_t need = checkpoint_bytes(ctx);
   if (bytes != need) return fail(PIC_E_INVALID, "checkpoint of %zu bytes, this context takes %zu", bytes, need);

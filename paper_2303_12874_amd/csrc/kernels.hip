@@ -882,13 +882,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void p
       }
     }
 
-    // ---- store (periodic in z) ----
+    // ---- store (periodic in z; with a moving window unwrapped, and an
+    // electron that left the box keeps zero weight until the next move) ----
     if constexpr (F64) {
-      if (z1 < R(0)) z1 += (R)Nz;
-      if (z1 >= (R)Nz) z1 -= (R)Nz;
+      if (k.window) {
+        if (z1 < R(0) || z1 >= (R)Nz) elem<R>(k.pw, p) = R(0);
+      } else {
+        if (z1 < R(0)) z1 += (R)Nz;
+        if (z1 >= (R)Nz) z1 -= (R)Nz;
+      }
       elem<double>(k.pz, p) = z1;
     } else {
-      elem<int>(k.pz, p) = wrap_once(i1, Nz);
+      if (k.window) {
+        const int i1raw = ciz + (i1 - i0);  // the cell before wrapping
+        if (i1raw < 0 || i1raw >= Nz) elem<R>(k.pw, p) = R(0);
+        elem<int>(k.pz, p) = i1raw;
+      } else {
+        elem<int>(k.pz, p) = wrap_once(i1, Nz);
+      }
       elem<float>(k.pfz, p) = f1;
     }
     elem<R>(X, p) = x1;
@@ -1499,6 +1510,10 @@ __device__ __forceinline__ int cell_order(const KRun &k, long long p) {
   } else {
     iz = ((const int *)k.pz)[p];
   }
+  if (k.shift > 0) {  // a window move: back by `shift` cells, outside the box -> the drop key n_keys
+    iz -= k.shift;
+    if (iz < 0 || iz >= k.Nz) return (int)k.n_keys;
+  }
   iz = wrap_any(iz, k.Nz);
   const R x = ((const R *)k.px)[p], y = ((const R *)k.py)[p];
   const R r2 = fma(x, x, y * y);
@@ -1513,8 +1528,9 @@ __device__ __forceinline__ int cell_order(const KRun &k, long long p) {
 // one or two tiles, so keys inside a window of two tiles' cells, starting at
 // the tile of the block's first electron, are counted and ranked in LDS, with
 // one device-memory atomic per cell and block; other keys (the first sort of
-// the loading order, electrons that changed tiles) take a device-memory atomic
-// each.  The keys go to the run's spid buffer, free until the gather writes it.
+// the loading order, electrons that changed tiles, the drop key n_keys of a
+// window move) take a device-memory atomic each.  The keys go to the run's
+// spid buffer, free until the gather writes it.
 constexpr int kSortPer = 8;
 constexpr int kSortBlock = 256 * kSortPer;
 
@@ -1536,7 +1552,7 @@ __global__ __launch_bounds__(256) void sort_key_kernel(const Batch bt) {
     const int key = cell_order<R>(k, p);
     keys[p] = key;
     const int d = key - kb;
-    if (d >= 0 && d < HW) atomicAdd(&hist[d], 1);
+    if (d >= 0 && d < HW && key < k.n_keys) atomicAdd(&hist[d], 1);
     else atomicAdd(&k.cell_count[key], 1);
   }
   __syncthreads();
@@ -1604,7 +1620,7 @@ __global__ __launch_bounds__(256) void sort_scatter_kernel(const Batch bt) {
     const long long p = p0 + q * 256 + threadIdx.x;
     key[q] = p < k.np ? keys[p] : -1;
     const int d = key[q] - kb;
-    rank[q] = (p < k.np && d >= 0 && d < HW) ? atomicAdd(&hist[d], 1) : -1;
+    rank[q] = (p < k.np && d >= 0 && d < HW && key[q] < k.n_keys) ? atomicAdd(&hist[d], 1) : -1;
   }
   __syncthreads();
   for (int d = threadIdx.x; d < HW; d += blockDim.x)
@@ -1705,7 +1721,7 @@ __device__ __forceinline__ void sort_tile(const KRun &k, uint64_t *ent, long lon
     for (int g = 0; g < kG; ++g) {
       if (!ok[g]) continue;
       const int d = dd[g];
-      SZ[d] = vz[g];
+      SZ[d] = vz[g] - (Zw)k.shift;  // a window move: back by `shift` cells (exact)
       if constexpr (!F64) SF[d] = vf[g];
       SX[d] = vx[g];
       SY[d] = vy[g];
@@ -1731,7 +1747,8 @@ __global__ __launch_bounds__(256) void sort_tile_kernel(const Batch bt) {
   const int n = end - beg;
   if (threadIdx.x == 0) {
     uint32_t f = sort_tile_flags(beg, end, k.np);
-    if (blockIdx.x == bt.off[rn]) f |= sort_count_flags(k.cell_start[k.n_keys], k.np);  // one block per run
+    if (blockIdx.x == bt.off[rn])  // one block per run
+      f |= sort_count_flags(k.cell_start[k.n_keys], k.np, k.shift > 0);
     if (f) atomicOr(k.flags, f);
   }
   if (n <= 0 || beg < 0 || end > k.np) return;
@@ -1970,6 +1987,48 @@ int launch_tracked_gamma(const KRun &k, int prec, double *gamma, int64_t *ids, v
   if (prec == PIC_PREC_FP64) tracked_gamma_kernel<double><<<blocks, 256, 0, (hipStream_t)stream>>>(k, gamma, ids);
   else tracked_gamma_kernel<float><<<blocks, 256, 0, (hipStream_t)stream>>>(k, gamma, ids);
   return check(hipGetLastError(), "tracked_gamma_kernel");
+}
+
+// ---------------------------------------------------------------------------
+// moving window: each of E, B[0], B[1], Bbar back by s columns in place, row
+// by row (one workgroup per row of (Nr+1) Nz reals); a chunk's reads
+// (columns [c0+s, c0+s+C)) all land before its writes ([c0, c0+C)), and no
+// chunk reads what an earlier one wrote
+constexpr int kShiftPer = 4;
+template <typename R>
+__global__ __launch_bounds__(256) void window_shift_kernel(R *a0, R *a1, R *a2, R *a3, long long rows, int Nz, int s,
+                                                           int guard) {
+  const long long b = blockIdx.x;
+  R *base = b < rows ? a0 : (b < 2 * rows ? a1 : (b < 3 * rows ? a2 : a3));
+  R *row = base + (b % rows) * (long long)Nz;
+  for (int c0 = 0; c0 < Nz; c0 += 256 * kShiftPer) {
+    R v[kShiftPer];
+#pragma unroll
+    for (int j = 0; j < kShiftPer; ++j) {
+      const int i = c0 + j * 256 + (int)threadIdx.x;
+      v[j] = (i < Nz && s < Nz - i) ? row[i + s] : R(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kShiftPer; ++j) {
+      const int i = c0 + j * 256 + (int)threadIdx.x;
+      if (i < Nz) row[i] = i < guard ? R(0) : v[j];
+    }
+  }
+}
+
+int launch_window_shift(const KRun &k, int prec, int guard, void *stream) {
+  if (k.shift <= 0) return PIC_OK;
+  const long long rows = 3LL * (2 * k.M + 1) * (k.Nr + 1);
+  const unsigned blocks = (unsigned)(4 * rows);
+  const hipStream_t s = (hipStream_t)stream;
+  if (prec == PIC_PREC_FP64)
+    window_shift_kernel<double><<<blocks, 256, 0, s>>>((double *)k.E, (double *)k.B[0], (double *)k.B[1],
+                                                       (double *)k.Bbar, rows, k.Nz, k.shift, guard);
+  else
+    window_shift_kernel<float><<<blocks, 256, 0, s>>>((float *)k.E, (float *)k.B[0], (float *)k.B[1],
+                                                      (float *)k.Bbar, rows, k.Nz, k.shift, guard);
+  return check(hipGetLastError(), "window_shift_kernel");
 }
 
 int launch_sort(Batch &b, int prec, void *stream) {

@@ -26,6 +26,10 @@ double courant_limit_of(const double *CE, const double *CB, int N, int M, double
 int jz_inverse_taps(const double *CB, int N, double eps, int max_taps, double *h, int *nh);
 double courant_limit_fitted(int solver, int N, int M, double dz, double dr, double band);
 int64_t run_particle_count(const pic_run_desc &r);
+// moving window: the plasma of absolute columns [a0, a1), z in a box whose
+// column 0 is absolute column S, (a1 - a0) (Nr-1) ppc electrons in pid order
+void load_columns(const pic_run_desc &r, int64_t a0, int64_t a1, int64_t S, double *z, double *x, double *y,
+                  double *w, int64_t *id);
 void load_electrons(const pic_run_desc &r, double *z, double *x, double *y, double *w, int64_t *id,
                     int64_t *tracked);
 void laser_fields(const pic_run_desc &r, double *E, double *B);
@@ -40,7 +44,10 @@ constexpr uint32_t kSortBadTile = 2u;    // a tile's electron range is not insid
 constexpr uint32_t kSortBadSlot = 4u;    // a ranked entry's slot is outside [0, np)
 constexpr uint32_t kSortBadSource = 8u;  // an entry names an electron outside [0, np)
 // (constexpr functions are host and device functions alike)
-constexpr uint32_t sort_count_flags(long long total, long long np) { return total != np ? kSortBadCount : 0u; }
+// (a sort that drops electrons, a window move, keeps at most np)
+constexpr uint32_t sort_count_flags(long long total, long long np, bool drops = false) {
+  return (drops ? total > np || total < 0 : total != np) ? kSortBadCount : 0u;
+}
 constexpr uint32_t sort_tile_flags(long long beg, long long end, long long np) {
   return (beg < 0 || end < beg || end > np) ? kSortBadTile : 0u;
 }
@@ -92,6 +99,10 @@ struct KRun {
   // of the J layout (interleaved), zero between steps, and the scale 2^K
   unsigned long long *Jfix;
   double qscale;
+  // moving window: positions are kept unwrapped in z and an electron that
+  // leaves the box gets zero weight (window); at a window move the sort
+  // shifts every electron back `shift` cells and drops those outside the box
+  int window, shift;
 };
 
 // ---- push workgroup LDS ---------------------------------------------------------
@@ -205,6 +216,9 @@ int launch_push(Batch &b, int prec, void *stream);
 int launch_efield(Batch &b, int prec, void *stream);
 int launch_bfield(Batch &b, int prec, void *stream);
 int launch_sort(Batch &b, int prec, void *stream);  // swaps the runs' particle buffers in b
+// moving window: E, B[0], B[1], Bbar of run k back by k.shift columns (zeros
+// entering at the front), then the first `guard` columns cleared
+int launch_window_shift(const KRun &k, int prec, int guard, void *stream);
 int prepare_kernels(int prec, int M, int Tz, int Tr, bool det);  // per-kernel attributes, before any capture
 int launch_fix_convert(Batch &b, void *stream);  // deterministic mode: integer sums -> J[par], sums cleared
 int launch_zero(void *ptr, size_t bytes, void *stream);

@@ -317,6 +317,48 @@ static inline double draw(uint64_t seed, int64_t pid, int d) {
 
 int64_t run_particle_count(const pic_run_desc &r) { return (int64_t)r.Nz * (r.Nr - 1) * r.ppc; }
 
+// Electron pid of the plasma, in absolute column a and radial cell ir:
+// absolute z (cells), x, y (cells) and weight.
+static inline void plasma_electron(const pic_run_desc &r, int64_t pid, int64_t a, int ir, double *zc, double *x,
+                                   double *y, double *w) {
+#pragma clang fp contract(off)  // each operation rounded on its own, so that every loader gets these bits
+  const double z = (double)a + draw(r.seed, pid, 0);
+  const double rc = ir + draw(r.seed, pid, 1);
+  const double phi = 2.0 * kPi * draw(r.seed, pid, 2);
+  double n = r.n0;
+  if (r.ramp_len > 0.0) {
+    double f = (z * r.dz - r.ramp_start) / r.ramp_len;
+    f = f < 0.0 ? 0.0 : (f > 1.0 ? 1.0 : f);
+    n = r.n0 * f;
+  }
+  if (r.down_len > 0.0) {
+    double g = 1.0 - (z * r.dz - r.down_start) / r.down_len;
+    g = g < 0.0 ? 0.0 : (g > 1.0 ? 1.0 : g);
+    n *= g;
+  }
+  *zc = z;
+  *x = rc * std::cos(phi);
+  *y = rc * std::sin(phi);
+  *w = n * (2.0 * kPi) * (rc * r.dr) * r.dr * r.dz / r.ppc;
+}
+
+// The plasma of absolute columns [a0, a1) (all radial cells, ppc each, pid
+// order), z in the cells of a box whose column 0 is absolute column S.
+void load_columns(const pic_run_desc &r, int64_t a0, int64_t a1, int64_t S, double *z, double *x, double *y,
+                  double *w, int64_t *id) {
+  const int nrc = r.Nr - 1;
+  int64_t p = 0;
+  for (int64_t a = a0; a < a1; ++a)
+    for (int ir = 0; ir < nrc; ++ir)
+      for (int k = 0; k < r.ppc; ++k, ++p) {
+        const int64_t pid = (a * nrc + ir) * r.ppc + k;
+        double zc;
+        plasma_electron(r, pid, a, ir, &zc, x + p, y + p, w + p);
+        z[p] = zc - (double)S;
+        id[p] = pid;
+      }
+}
+
 // Cold electrons: ppc per cell for r < (Nr-1) dr at uniform-random (z, r, phi)
 // in the cell; the density n(z) (with its linear up- and down-ramps) and the annulus
 // volume enter the weight w = n 2 pi r dr dr dz / ppc, so the density is
@@ -343,24 +385,12 @@ void load_electrons(const pic_run_desc &r, double *z, double *x, double *y, doub
       for (int ir = 0; ir < nrc; ++ir)
         for (int s = 0; s < r.ppc; ++s) {
           int64_t pid = ((int64_t)iz * nrc + ir) * r.ppc + s;
-          double zc = iz + draw(r.seed, pid, 0);
-          double rc = ir + draw(r.seed, pid, 1);
-          double phi = 2.0 * kPi * draw(r.seed, pid, 2);
-          double n = r.n0;
-          if (r.ramp_len > 0.0) {
-            double f = (zc * r.dz - r.ramp_start) / r.ramp_len;
-            f = f < 0.0 ? 0.0 : (f > 1.0 ? 1.0 : f);
-            n = r.n0 * f;
-          }
-          if (r.down_len > 0.0) {
-            double g = 1.0 - (zc * r.dz - r.down_start) / r.down_len;
-            g = g < 0.0 ? 0.0 : (g > 1.0 ? 1.0 : g);
-            n *= g;
-          }
+          double zc, xc, yc, wc;
+          plasma_electron(r, pid, iz, ir, &zc, &xc, &yc, &wc);
           if (z) z[pid] = zc;
-          if (x) x[pid] = rc * std::cos(phi);
-          if (y) y[pid] = rc * std::sin(phi);
-          if (w) w[pid] = n * (2.0 * kPi) * (rc * r.dr) * r.dr * r.dz / r.ppc;
+          if (x) x[pid] = xc;
+          if (y) y[pid] = yc;
+          if (w) w[pid] = wc;
           if (id) id[pid] = pid;
           if (nt_want) {
             cand.push_back({draw(r.seed, pid, 3), pid});

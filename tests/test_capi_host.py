@@ -90,6 +90,22 @@ def test_deterministic_mode_is_fp64_only():
     assert e.value.code == pic.PIC_E_INVALID
 
 
+def test_moving_window_options_are_checked():
+    """The moving window sizes the particle arrays for four moves' worth of
+    fresh columns and refuses bad values, captured graphs, the deterministic
+    mode and a guard band as long as the box."""
+    d = _desc()
+    plain = pic.workspace_bytes([d])
+    assert pic.workspace_bytes([d], window_interval=8) > plain
+    assert pic.workspace_bytes([d], window_interval=8, window_speed=2.0) > pic.workspace_bytes([d], window_interval=8)
+    for kw in (dict(window_interval=-1), dict(window_interval=4, window_guard=-2),
+               dict(window_interval=4, window_speed=-1.0), dict(window_interval=4, use_graph=True),
+               dict(window_interval=4, deterministic=True), dict(window_interval=4, window_guard=d.Nz)):
+        with pytest.raises(pic.PicError) as e:
+            pic.workspace_bytes([d], **kw)
+        assert e.value.code == pic.PIC_E_INVALID, kw
+
+
 def test_allocation_free_divergence_checks_its_arguments_first():
     """pic_divergence_arrays refuses bad arguments and counts beyond its fixed
     scratch (2048 x 256 x 64 electrons) before any device call."""
