@@ -416,6 +416,9 @@ def main(argv=None):
     ap.add_argument("--tile-z", type=int, default=0, help="sort tile extent in z (0: library default)")
     ap.add_argument("--tile-r", type=int, default=0, help="sort tile extent in r (0: library default)")
     ap.add_argument("--graph", action="store_true", help="replay captured steps (per-phase timing then unavailable)")
+    ap.add_argument("--window", type=int, default=0,
+                    help="moving window (App. A): a move every K steps (0: the static box of the workload)")
+    ap.add_argument("--window-guard", type=int, default=16, help="moving window: guard columns cleared at a move")
     ap.add_argument("--autotune", type=int, default=None,
                     help="1: tile and sort interval from the library's autotuner (default: on for c4 and c5)")
     ap.add_argument("--precision", type=int, default=0, choices=[0, 32, 64],
@@ -489,6 +492,7 @@ def main(argv=None):
             return pic.Simulation([workloads.to_rundesc(r, n_steps=n) for r, n in zip(runs, limits)],
                                   precision=prec_, solver=solver, n_coef=n_coef, sort_interval=sort_interval,
                                   tile_z=tile_z, tile_r=tile_r, use_graph=args.graph, current=current,
+                                  window_interval=args.window, window_guard=args.window_guard if args.window else 0,
                                   device="cuda:0")
 
         if multi:
@@ -556,7 +560,8 @@ def main(argv=None):
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
     ach = kernels[dom]["GBs"]
     traffic = (measured_traffic(args.workload, dom, "%dx%d" % infos[0]["tile"], sort_k, prec)
-               if args.solver == "dual" and args.current == "filter" else None)  # the counters' settings
+               if args.solver == "dual" and args.current == "filter" and not args.window
+               else None)  # the counters' settings
     particle_steps = sum(n * s for n, s in zip(nps, per_run))
     value = particle_steps / (elapsed_ms * 1e-3)
     run = runs[0]
@@ -570,6 +575,11 @@ def main(argv=None):
               "sort_interval": sort_k, "tile": "%dx%d" % infos[0]["tile"], "graph": bool(args.graph)}
     if multi:
         config["steps_per_run"] = per_run
+    if args.window:
+        # electrons counted at the start of the timed region (the count varies by the fresh columns' share)
+        config["window"] = {"interval": args.window, "guard": args.window_guard,
+                            "cells_moved": [sim.info(i)["window_cells"] for i in range(len(runs))],
+                            "electrons_after": sum(sim.info(i)["n_particles"] for i in range(len(runs)))}
     if tune is not None:
         config["autotune"] = {"seconds": round(tune["seconds"], 1),
                               "candidates": [list(c[:3]) + [round(c[3], 4)] for c in tune["candidates"]]}

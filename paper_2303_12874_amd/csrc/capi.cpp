@@ -2,6 +2,7 @@
 // set-up and upload of runs, the step loop and FP64 read-back.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -732,6 +733,30 @@ int window_move(pic_ctx *ctx, RunHost &R, hipStream_t s, bool *moved) {
     std::vector<double> z((size_t)nf), x((size_t)nf), y((size_t)nf), w((size_t)nf);
     std::vector<int64_t> id((size_t)nf);
     load_columns(d, a1 - cols, a1, R.win_S, z.data(), x.data(), y.data(), w.data(), id.data());
+    // in the cell order the sort will give them (near enough: the cell of
+    // r is taken without the sort's rounding care), so that the sort's
+    // blocks count them in LDS; the slots they land in are the sort's choice
+    {
+      std::vector<int64_t> key((size_t)nf);
+      const int64_t TT = (int64_t)k.Tz * k.Tr;
+      for (size_t p = 0; p < (size_t)nf; ++p) {
+        const int64_t iz = std::min<int64_t>(std::max<int64_t>((int64_t)std::floor(z[p]) - sft, 0), d.Nz - 1);
+        const int64_t ir = std::min<int64_t>((int64_t)std::sqrt(x[p] * x[p] + y[p] * y[p]), d.Nr - 1);
+        key[p] = ((ir / k.Tr) * k.ntz + iz / k.Tz) * TT + (ir % k.Tr) * k.Tz + iz % k.Tz;
+      }
+      std::vector<size_t> ord((size_t)nf);
+      for (size_t p = 0; p < ord.size(); ++p) ord[p] = p;
+      std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return key[a] < key[b]; });
+      auto permute = [&](auto &v) {
+        auto t = v;
+        for (size_t p = 0; p < ord.size(); ++p) v[p] = t[ord[p]];
+      };
+      permute(z);
+      permute(x);
+      permute(y);
+      permute(w);
+      permute(id);
+    }
     std::vector<uint32_t> pid(id.begin(), id.end());
     const size_t at = (size_t)k.np;
     if (ctx->prec == PIC_PREC_FP64) {

@@ -1527,22 +1527,23 @@ __device__ __forceinline__ int cell_order(const KRun &k, long long p) {
 // (kSortPer per thread).  In the order of the previous sort such a block spans
 // one or two tiles, so keys inside a window of two tiles' cells, starting at
 // the tile of the block's first electron, are counted and ranked in LDS, with
-// one device-memory atomic per cell and block; other keys (the first sort of
-// the loading order, electrons that changed tiles, the drop key n_keys of a
-// window move) take a device-memory atomic each.  The keys go to the run's
-// spid buffer, free until the gather writes it.
+// one device-memory atomic per cell and block; the drop key n_keys of a
+// window move has a counter of its own after the window; other keys (the
+// first sort of the loading order, electrons that changed tiles) take a
+// device-memory atomic each.  The keys go to the run's spid buffer, free
+// until the gather writes it.
 constexpr int kSortPer = 8;
 constexpr int kSortBlock = 256 * kSortPer;
 
 template <typename R>
 __global__ __launch_bounds__(256) void sort_key_kernel(const Batch bt) {
-  extern __shared__ int32_t hist[];  // 2 TT counters
+  extern __shared__ int32_t hist[];  // 2 TT counters, then the drop key's
   const int rn = batch_run(bt, blockIdx.x);
   const KRun &k = bt.run[rn];
   const int TT = k.Tz * k.Tr, HW = 2 * TT;
   const long long p0 = (long long)(blockIdx.x - bt.off[rn]) * kSortBlock;
   const int kb = cell_order<R>(k, p0) / TT * TT;  // window start (p0 < np: blocks cover np)
-  for (int d = threadIdx.x; d < HW; d += blockDim.x) hist[d] = 0;
+  for (int d = threadIdx.x; d <= HW; d += blockDim.x) hist[d] = 0;
   __syncthreads();
   int32_t *keys = (int32_t *)k.spid;
 #pragma unroll
@@ -1552,12 +1553,14 @@ __global__ __launch_bounds__(256) void sort_key_kernel(const Batch bt) {
     const int key = cell_order<R>(k, p);
     keys[p] = key;
     const int d = key - kb;
-    if (d >= 0 && d < HW && key < k.n_keys) atomicAdd(&hist[d], 1);
+    if (key >= k.n_keys) atomicAdd(&hist[HW], 1);
+    else if (d >= 0 && d < HW) atomicAdd(&hist[d], 1);
     else atomicAdd(&k.cell_count[key], 1);
   }
   __syncthreads();
   for (int d = threadIdx.x; d < HW; d += blockDim.x)
     if (hist[d] > 0 && kb + d < k.n_keys) atomicAdd(&k.cell_count[kb + d], hist[d]);
+  if (threadIdx.x == 0 && hist[HW] > 0) atomicAdd(&k.cell_count[k.n_keys], hist[HW]);
 }
 
 // exclusive scan of 1024-element blocks; block totals to bsum
@@ -1604,33 +1607,37 @@ __global__ __launch_bounds__(256) void copy_i32_kernel(int32_t *dst, const int32
 // then one device-memory atomic per cell of the window reserves the block's
 // share of the cell (cell_count holds a copy of cell_start, the fill cursor)
 __global__ __launch_bounds__(256) void sort_scatter_kernel(const Batch bt) {
-  extern __shared__ int32_t hist[];  // 2 TT counters, then 2 TT bases
+  extern __shared__ int32_t hist[];  // 2 TT + 1 counters (the last the drop key's), then 2 TT + 1 bases
   const int rn = batch_run(bt, blockIdx.x);
   const KRun &k = bt.run[rn];
   const int TT = k.Tz * k.Tr, HW = 2 * TT;
-  int32_t *base = hist + HW;
+  int32_t *base = hist + HW + 1;
   const long long p0 = (long long)(blockIdx.x - bt.off[rn]) * kSortBlock;
   const int32_t *keys = (const int32_t *)k.spid;
   const int kb = keys[p0] / TT * TT;  // the window of the key kernel
-  for (int d = threadIdx.x; d < HW; d += blockDim.x) hist[d] = 0;
+  for (int d = threadIdx.x; d <= HW; d += blockDim.x) hist[d] = 0;
   __syncthreads();
   int key[kSortPer], rank[kSortPer];
 #pragma unroll
   for (int q = 0; q < kSortPer; ++q) {
     const long long p = p0 + q * 256 + threadIdx.x;
     key[q] = p < k.np ? keys[p] : -1;
-    const int d = key[q] - kb;
-    rank[q] = (p < k.np && d >= 0 && d < HW && key[q] < k.n_keys) ? atomicAdd(&hist[d], 1) : -1;
+    const bool drop = key[q] >= k.n_keys;  // the drop key: its own counter
+    const int d = drop ? HW : key[q] - kb;
+    rank[q] = (p < k.np && (drop || (d >= 0 && d < HW))) ? atomicAdd(&hist[d], 1) : -1;
   }
   __syncthreads();
-  for (int d = threadIdx.x; d < HW; d += blockDim.x)
-    base[d] = (hist[d] > 0 && kb + d < k.n_keys) ? atomicAdd(&k.cell_count[kb + d], hist[d]) : 0;
+  for (int d = threadIdx.x; d <= HW; d += blockDim.x) {
+    const long long c = d == HW ? k.n_keys : kb + d;
+    base[d] = (hist[d] > 0 && (d == HW || c < k.n_keys)) ? atomicAdd(&k.cell_count[c], hist[d]) : 0;
+  }
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < kSortPer; ++q) {
     const long long p = p0 + q * 256 + threadIdx.x;
     if (p >= k.np) break;
-    const int pos = rank[q] >= 0 ? base[key[q] - kb] + rank[q] : atomicAdd(&k.cell_count[key[q]], 1);
+    const int dq = key[q] >= k.n_keys ? HW : key[q] - kb;
+    const int pos = rank[q] >= 0 ? base[dq] + rank[q] : atomicAdd(&k.cell_count[key[q]], 1);
     if (const uint32_t f = sort_index_flags(pos, k.np, kSortBadSlot)) {
       atomicOr(k.flags, f);
       continue;
@@ -2037,7 +2044,7 @@ int launch_sort(Batch &b, int prec, void *stream) {
   for (int i = 0; i < b.n; ++i)
     if ((rc = launch_zero(b.run[i].cell_count, (size_t)(b.run[i].n_keys + 1) * 4, stream))) return rc;
   const auto pblocks = [](const KRun &k) { return (k.np + kSortBlock - 1) / kSortBlock; };
-  const size_t hw = (size_t)2 * b.run[0].Tz * b.run[0].Tr * sizeof(int32_t);  // one 2-tile window
+  const size_t hw = ((size_t)2 * b.run[0].Tz * b.run[0].Tr + 1) * sizeof(int32_t);  // a 2-tile window + the drop key
   if (set_offsets(b, pblocks)) {
     if (prec == PIC_PREC_FP64) sort_key_kernel<double><<<(unsigned)b.off[b.n], 256, hw, s>>>(b);
     else sort_key_kernel<float><<<(unsigned)b.off[b.n], 256, hw, s>>>(b);
