@@ -76,6 +76,80 @@ def measured_traffic(workload: str, kernel: str, tile: str, sort_interval: int, 
     return None if e is None else e["read_bytes"] + e["write_bytes"]
 
 
+# kernel name -> bench phase of the rocprofv3 summaries
+_PHASE_OF = (("push_kernel", "push"), ("efield_kernel", "efield"), ("bfield_kernel", "bfield"),
+             ("sort_tile_kernel", "sort_tile"), ("sort_key_kernel", "sort_key"), ("sort_scatter_kernel", "sort_scatter"),
+             ("scan_block_kernel", "scan_block"), ("scan_add_kernel", "scan_add"), ("copy_i32_kernel", "copy_i32"),
+             ("window_shift_kernel", "window_shift"))
+
+
+def _csv_rows(directory: str, suffix: str) -> list:
+    import csv
+    import glob
+
+    rows = []
+    for f in sorted(glob.glob(os.path.join(directory, "**", "*" + suffix), recursive=True)):
+        with open(f) as fh:
+            rows += list(csv.DictReader(fh))
+    return rows
+
+
+def summarize_counters(workload: str, fetch_dir: str, write_dir: str, tile: str, sort_interval: int,
+                       precision: int) -> dict:
+    """Per-launch HBM bytes of each kernel from a FETCH_SIZE pass and a
+    WRITE_SIZE pass (rocprofv3 --pmc, csv) of the benchmark's command, scaled
+    by what the same counters read for the benchmark's own 1 GiB device copy
+    (the largest copyBuffer dispatch); written into profiles/hbm_traffic.json
+    under the workload with the kernels' source hash, so that bench lines of
+    the same settings report it as roofline.traffic."""
+    vals = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        for r in _csv_rows(d, "counter_collection.csv"):
+            if r["Counter_Name"] == counter:
+                vals.setdefault(counter, []).append((r["Kernel_Name"], float(r["Counter_Value"])))
+    gib_kib = (1 << 30) / 1024.0
+    copies = {c: max(v for n, v in vals[c] if "copyBuffer" in n) for c in ("FETCH_SIZE", "WRITE_SIZE")}
+    ff, wf = gib_kib / copies["FETCH_SIZE"], gib_kib / copies["WRITE_SIZE"]
+    entry = {"settings": {"tile": tile, "sort_interval": sort_interval, "precision": precision}}
+    for key, phase in _PHASE_OF:
+        f = [v for n, v in vals["FETCH_SIZE"] if key in n]
+        w = [v for n, v in vals["WRITE_SIZE"] if key in n]
+        if f and w:
+            fk, wk = sum(f) / len(f), sum(w) / len(w)
+            entry[phase] = {"read_bytes": fk * 1024 * ff, "write_bytes": wk * 1024 * wf, "fetch_kib": fk,
+                            "write_kib": wk, "launches": len(f)}
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        t = {}
+    with open(os.path.join(ROOT, "paper_2303_12874_amd", "csrc", "kernels.hip"), "rb") as fh:
+        h = hashlib.sha256(fh.read()).hexdigest()
+    if t.get("kernels_sha256") != h:
+        t = {"workloads": {}}
+    t["kernels_sha256"] = h
+    t["fetch_factor"], t["write_factor"] = ff, wf
+    t["calibration"] = (f"1 GiB device copy: FETCH_SIZE {copies['FETCH_SIZE']:.0f} KiB, "
+                        f"WRITE_SIZE {copies['WRITE_SIZE']:.0f} KiB")
+    t.setdefault("workloads", {})[workload] = entry
+    with open(path, "w") as fh:
+        json.dump(t, fh, indent=1)
+    return entry
+
+
+def summarize_trace(trace_dir: str) -> str:
+    """Markdown table of a rocprofv3 --kernel-trace --stats run (kernel_stats.csv)."""
+    rows = _csv_rows(trace_dir, "kernel_stats.csv")
+    tot = sum(float(r["TotalDurationNs"]) for r in rows) or 1.0
+    out = ["| Kernel | Calls | Average (us) | Min (us) | Max (us) | Share |", "|---|---:|---:|---:|---:|---:|"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        name = r["Name"] if len(r["Name"]) < 72 else r["Name"][:69] + "..."
+        out.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
+                   f"{float(r['MaxNs']) / 1e3:.1f} | {100 * float(r['TotalDurationNs']) / tot:.1f}% |")
+    return "\n".join(out)
+
+
 WORKLOADS = ("c1", "c2", "c3", "c4", "c5", "cv32", "cv128", "dla")
 
 
@@ -437,7 +511,22 @@ def main(argv=None):
     ap.add_argument("--convergence", action="store_true",
                     help="the six-run resolution scan with the dual and the Yee solver: RMS divergence of the "
                          "energetic electrons and cost per run (Sec. IV.B); prints that table's JSON line only")
+    ap.add_argument("--summarize-trace", default=None, metavar="DIR",
+                    help="print the markdown table of a rocprofv3 --kernel-trace --stats csv run and exit")
+    ap.add_argument("--summarize-counters", nargs=2, default=None, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the per-launch HBM bytes of a FETCH_SIZE and a WRITE_SIZE pass of this workload's "
+                         "bench command into profiles/hbm_traffic.json (with --tile-z, --tile-r, --sort-interval, "
+                         "--precision as the bench line ran) and exit")
     args = ap.parse_args(argv)
+    if args.summarize_trace:
+        print(summarize_trace(args.summarize_trace))
+        return 0
+    if args.summarize_counters:
+        prec = args.precision or workloads.config(args.workload)["precision"]
+        e = summarize_counters(args.workload, *args.summarize_counters, "%dx%d" % (args.tile_z, args.tile_r),
+                               args.sort_interval, prec)
+        print(json.dumps(e, indent=1))
+        return 0
     if args.oracle_sample:  # a child process of the all-core CPU baseline: no GPU is touched
         tot, el = _oracle_sample(args.oracle_sample, args.n_coef)
         print(json.dumps({"particle_steps": tot, "seconds": el}), flush=True)
