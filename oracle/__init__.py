@@ -75,6 +75,7 @@ def lib():
             "orc_set_exact_jz": (None, [p, i]),
             "orc_inverse_filter": (i, [p, p, p]),
             "orc_set_window": (None, [p, i, d, i]),
+            "orc_set_shape": (i, [p, i]),
             "orc_window_cells": (l, [p]),
         }
         for name, (res, args) in sig.items():
@@ -176,6 +177,12 @@ class Oracle:
     def set_particles(self, z, x, y, ux, uy, uz, w, track_all=True):
         arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (z, x, y, ux, uy, uz, w)]
         lib().orc_set_particles(self._h, arrs[0].size, *[_ptr(a) for a in arrs], int(track_all))
+
+    def set_shape(self, order):
+        """Particle shape order of the gather and the deposit: 1 linear (the
+        default), 2 quadratic."""
+        if lib().orc_set_shape(self._h, int(order)) != 0:
+            raise ValueError("shape order must be 1 or 2")
 
     def set_window(self, interval, speed=1.0, guard=0):
         """Moving window (App. A): before a step whose count of steps taken is

@@ -77,6 +77,7 @@ typedef struct orc {
   int freeze_fields;  /* 1: Maxwell update skipped (prescribed fields) */
   int deposit_rho;    /* 1: deposit rho after every step */
   int exact_jz;       /* 1: J_z <- P^{-1} J_z, J_r and J_phi unfiltered */
+  int shape;          /* particle shape order: 1 linear (default), 2 quadratic */
   /* plasma of the last orc_load_plasma, for the fresh columns of the window */
   int ppc;
   uint64_t seed;
@@ -129,6 +130,7 @@ orc *orc_create(int Nz, int Nr, int M, double dz, double dr, double dt, int N,
   orc *o = (orc *)calloc(1, sizeof(orc));
   o->Nz = Nz; o->Nr = Nr; o->M = M; o->N = N;
   o->dz = dz; o->dr = dr; o->dt = dt;
+  o->shape = 1;
   o->CE = (double *)malloc(sizeof(double) * N);
   o->CB = (double *)malloc(sizeof(double) * N);
   memcpy(o->CE, CE, sizeof(double) * N);
@@ -179,6 +181,11 @@ void orc_set_flags(orc *o, int freeze_fields, int deposit_rho) {
 }
 
 void orc_set_exact_jz(orc *o, int on) { o->exact_jz = on; }
+int orc_set_shape(orc *o, int order) {
+  if (order != 1 && order != 2) return -1;
+  o->shape = order;
+  return 0;
+}
 
 long orc_num_particles(const orc *o) { return o->np; }
 long orc_num_steps(const orc *o) { return o->nstep; }
@@ -468,12 +475,55 @@ static cplx interp(const orc *o, const cplx *f, int m, double zc, double rc, int
   return (1.0 - fz) * (1.0 - fr) * v00 + fz * (1.0 - fr) * v10 + (1.0 - fz) * fr * v01 + fz * fr * v11;
 }
 
+/* Quadratic shapes: the weights of the quadratic B-spline centred on x (cell
+ * units) at the three nodes nearest x, i-1, i, i+1 with i the nearest node:
+ * with d = x - i in [-1/2, 1/2), (1/2 - d)^2 / 2, 3/4 - d^2, (1/2 + d)^2 / 2. */
+static int qweights(double x, double w[3]) {
+  int i = (int)floor(x + 0.5);
+  double d = x - i;
+  w[0] = 0.5 * (0.5 - d) * (0.5 - d);
+  w[1] = 0.75 - d * d;
+  w[2] = 0.5 * (0.5 + d) * (0.5 + d);
+  return i;
+}
+
+/* Quadratic interpolation of one component of mode m at (zc, rc): 3 x 3
+ * nodes of its staggered grid.  A row below the axis is the mirror image of
+ * the row above it (integer grid: r_{-1} of r_1; half grid: r_{-1/2} of
+ * r_{1/2}) times the component's mirror sign.                               */
+static cplx interp2(const orc *o, const cplx *f, int m, double zc, double rc, int zhalf, int rhalf,
+                    double mirror) {
+  double wz[3], wr[3];
+  int i = qweights(zhalf ? zc - 0.5 : zc, wz);
+  int j = qweights(rhalf ? rc - 0.5 : rc, wr);
+  cplx acc = 0.0;
+  for (int b = 0; b < 3; ++b) {
+    int row = j - 1 + b;
+    double sg = 1.0;
+    if (row < 0) {
+      row = rhalf ? -row - 1 : -row;
+      sg = mirror;
+    }
+    for (int a = 0; a < 3; ++a) acc += wz[a] * wr[b] * sg * f[ix(o, m, row, i - 1 + a)];
+  }
+  return acc;
+}
+
 /* All six components of every mode at one position.  out[c][m], c = E_r,
  * E_phi, E_z, B_r, B_phi, B_z; B is the time average of Eq. (12).          */
 static void gather_modes(const orc *o, double zc, double rc, int jr, cplx out[6][8]) {
   for (int m = 0; m <= o->M; ++m) {
     double s_rp = (m % 2 == 0) ? -1.0 : 1.0; /* (-1)^{m+1} */
     double s_z = -s_rp;                        /* (-1)^m */
+    if (o->shape == 2) {
+      out[0][m] = interp2(o, o->E[CR], m, zc, rc, 0, 1, s_rp);
+      out[1][m] = interp2(o, o->E[CP], m, zc, rc, 0, 0, s_rp);
+      out[2][m] = interp2(o, o->E[CZ], m, zc, rc, 1, 0, s_z);
+      out[3][m] = 0.5 * (interp2(o, o->Bo[CR], m, zc, rc, 1, 0, s_rp) + interp2(o, o->Bn[CR], m, zc, rc, 1, 0, s_rp));
+      out[4][m] = 0.5 * (interp2(o, o->Bo[CP], m, zc, rc, 1, 1, s_rp) + interp2(o, o->Bn[CP], m, zc, rc, 1, 1, s_rp));
+      out[5][m] = 0.5 * (interp2(o, o->Bo[CZ], m, zc, rc, 0, 1, s_z) + interp2(o, o->Bn[CZ], m, zc, rc, 0, 1, s_z));
+      continue;
+    }
     out[0][m] = interp(o, o->E[CR], m, zc, rc, jr, 0, 1, s_rp);
     out[1][m] = interp(o, o->E[CP], m, zc, rc, jr, 0, 0, 0.0);
     out[2][m] = interp(o, o->E[CZ], m, zc, rc, jr, 1, 0, 0.0);
@@ -625,6 +675,88 @@ static void deposit_particle(orc *o, double q, double z0, double r0, int j0, dou
   }
 }
 
+/* Quadratic shapes: the same charge-conserving deposit on the 4 x 4 nodes
+ * that hold both positions' 3 x 3 supports (a move of less than a cell),
+ * S = Sz Sr with quadratic B-splines.  A particle within half a cell of the
+ * axis has shape on row r_{-1}; the point (-r, phi) is (r, phi + pi), so
+ * that charge belongs to row r_1 with the mode's sign (-1)^m, and the
+ * z-flux of row r_{-1}, the r-flux through r_{-1/2} and the phi-current of
+ * row r_{-1} belong to row r_1, face r_{1/2} and row r_1 with the signs of a
+ * z, an r and a phi component ((-1)^m, (-1)^{m+1}, (-1)^{m+1}).  Folded so,
+ * the node charges of rows r >= dr (every m) and of the axis row (m = 0)
+ * change by exactly minus the divergence of the folded fluxes.  The phi
+ * closure of a folded row is (-1)^m times its value at r_1, the m = 0 direct
+ * term (-1) times it.                                                        */
+static void deposit_particle2(orc *o, double q, double z0, double r0, double c0, double s0,
+                              double z1, double r1, double c1, double s1,
+                              double vphi, double cmid, double smid) {
+  const double dt = o->dt, dr = o->dr;
+  double wz0[3], wz1[3], wr0[3], wr1[3];
+  int i0 = qweights(z0, wz0), i1 = qweights(z1, wz1);
+  int j0 = qweights(r0, wr0), j1 = qweights(r1, wr1);
+  int ib = (i0 < i1 ? i0 : i1) - 1, jb = (j0 < j1 ? j0 : j1) - 1;
+  double Sz0[4] = {0, 0, 0, 0}, Sz1[4] = {0, 0, 0, 0}, Sr0[4] = {0, 0, 0, 0}, Sr1[4] = {0, 0, 0, 0};
+  for (int k = 0; k < 3; ++k) {
+    Sz0[i0 - 1 - ib + k] += wz0[k];
+    Sz1[i1 - 1 - ib + k] += wz1[k];
+    Sr0[j0 - 1 - jb + k] += wr0[k];
+    Sr1[j1 - 1 - jb + k] += wr1[k];
+  }
+  double Wz[4][4], Wr[4][4], Ssum[4][4];
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) {
+      Wz[a][b] = (Sz1[a] - Sz0[a]) * (Sr0[b] + Sr1[b]) * 0.5;
+      Wr[a][b] = (Sr1[b] - Sr0[b]) * (Sz0[a] + Sz1[a]) * 0.5;
+      Ssum[a][b] = Sz0[a] * Sr0[b] + Sz1[a] * Sr1[b];
+    }
+  for (int m = 0; m <= o->M; ++m) {
+    double cm = m == 0 ? 1.0 : 2.0;
+    double s_z = (m % 2 == 0) ? 1.0 : -1.0, s_rp = -s_z;
+    cplx e0 = ipow(c0 - I * s0, m), e1 = ipow(c1 - I * s1, m);
+    cplx xi = 0.5 * (e0 + e1);
+    /* J_z at (ib+a+1/2, jb+b), a = 0..2; a row past r_Nr has zero weight
+     * (both positions nearest r_{Nr-1}) and is skipped */
+    for (int b = 0; b < 4; ++b) {
+      int j = jb + b;
+      double sg = 1.0;
+      if (j > o->Nr) continue;
+      if (j < 0) { j = -j; sg = s_z; }
+      double run = 0.0;
+      for (int a = 0; a < 3; ++a) {
+        run += Wz[a][b];
+        o->J[CZ][ix(o, m, j, ib + a)] += sg * (-cm * q * xi * run) / (dt * area_z(o, j));
+      }
+    }
+    /* J_r at (ib+a, jb+b+1/2), b = 0..2 (face index jb+b) */
+    for (int a = 0; a < 4; ++a) {
+      double run = 0.0;
+      for (int b = 0; b < 3; ++b) {
+        run += Wr[a][b];
+        int j = jb + b;
+        double sg = 1.0;
+        if (j < 0) { j = -j - 1; sg = s_rp; }
+        o->J[CR][ix(o, m, j, ib + a)] += sg * (-cm * q * xi * run) / (dt * area_r(o, j));
+      }
+    }
+    /* J_phi at (ib+a, jb+b) */
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) {
+        int j = jb + b;
+        double sg = 1.0;
+        if (j > o->Nr) continue;
+        if (j < 0) { j = -j; sg = -1.0; }
+        cplx v;
+        if (m == 0 || (m == 1 && j == 0 && sg > 0)) {
+          cplx emid = ipow(cmid - I * smid, m);
+          v = sg * cm * q * vphi * emid * Ssum[a][b] / (2.0 * vol_node(o, j));
+        } else {
+          v = (sg < 0 ? s_z : 1.0) * cm * q * (I * (j * dr) / m) * (e1 - e0) * Ssum[a][b] / (2.0 * dt * vol_node(o, j));
+        }
+        o->J[CP][ix(o, m, j, ib + a)] += v;
+      }
+  }
+}
+
 /* rho^m = c_m q e^{-i m phi} S / V_j of every particle at its position.    */
 static void deposit_rho_all(orc *o) {
   memset(o->rho, 0, o->nf * sizeof(cplx));
@@ -640,6 +772,18 @@ static void deposit_rho_all(orc *o) {
     for (int m = 0; m <= o->M; ++m) {
       double cm = m == 0 ? 1.0 : 2.0;
       cplx e = ipow(c - I * s, m);
+      if (o->shape == 2) { /* rows below the axis folded with (-1)^m, as in the deposit */
+        double wz[3], wr[3];
+        int i = qweights(zc, wz), j = qweights(rc, wr);
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) {
+            int row = j - 1 + b;
+            double sg = 1.0;
+            if (row < 0) { row = -row; sg = (m % 2 == 0) ? 1.0 : -1.0; }
+            o->rho[ix(o, m, row, i - 1 + a)] += sg * cm * q * e * wz[a] * wr[b] / vol_node(o, row);
+          }
+        continue;
+      }
       for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) {
           double S = (a ? fz : 1.0 - fz) * (b ? fr : 1.0 - fr);
@@ -670,7 +814,8 @@ void orc_deposit_add(orc *o, double q, double z0, double x0, double y0, double z
   double xm = 0.5 * (x0 + x1), ym = 0.5 * (y0 + y1), rm = sqrt(xm * xm + ym * ym);
   double cm = 1, sm = 0;
   if (rm > 0) { cm = xm / rm; sm = ym / rm; }
-  deposit_particle(o, q, z0, r0, j0, c0, s0, z1, r1, j1, c1, s1, vphi, cm, sm);
+  if (o->shape == 2) deposit_particle2(o, q, z0, r0, c0, s0, z1, r1, c1, s1, vphi, cm, sm);
+  else deposit_particle(o, q, z0, r0, j0, c0, s0, z1, r1, j1, c1, s1, vphi, cm, sm);
 }
 
 void orc_deposit_one(orc *o, double q, double z0, double x0, double y0, double z1, double x1,
@@ -759,7 +904,10 @@ static void push_and_deposit(orc *o) {
       cmid = xm / rm; smid = ym / rm;
       vphi = (cmid * un[1] - smid * un[0]) / g_new;
     }
-    deposit_particle(o, -o->w[p], z0, r0, j0, c0, s0, z1, r1, j1, c1, s1, vphi, cmid, smid);
+    if (o->shape == 2)
+      deposit_particle2(o, -o->w[p], z0, r0, c0, s0, z1, r1, c1, s1, vphi, cmid, smid);
+    else
+      deposit_particle(o, -o->w[p], z0, r0, j0, c0, s0, z1, r1, j1, c1, s1, vphi, cmid, smid);
 
     if (o->win_K > 0) {
       /* moving window: an electron that left the box through either end
