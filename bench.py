@@ -153,9 +153,10 @@ def summarize_trace(trace_dir: str) -> str:
 WORKLOADS = ("c1", "c2", "c3", "c4", "c5", "cv32", "cv128", "dla")
 
 
-def _oracle_sample(workload: str, n_coef: int) -> tuple:
+def _oracle_sample(workload: str, n_coef: int, shape: int = 1) -> tuple:
     """The serial FP64 oracle over the workload's bounded CPU sample
-    (workloads.cpu_sample): (particle-steps, seconds of stepping)."""
+    (workloads.cpu_sample), with the given particle shape order:
+    (particle-steps, seconds of stepping)."""
     import oracle  # noqa: F401  (test infrastructure: the CPU baseline only)
     from oracle import coef
 
@@ -164,6 +165,7 @@ def _oracle_sample(workload: str, n_coef: int) -> tuple:
     for run in smp["runs"]:
         dt, CE, CB, _ = coef.solver_setup(n_coef, run["M"], run["dz"], run["dr"])
         o = workloads.to_oracle(run, dt, CE, CB)
+        o.set_shape(shape)
         t0 = time.perf_counter()
         o.step(smp["steps"])
         el += time.perf_counter() - t0
@@ -190,14 +192,14 @@ def host_cpu() -> tuple:
     return cores, model
 
 
-def cpu_baseline(workload: str, n_coef: int = 16, max_procs: int = 16) -> dict:
+def cpu_baseline(workload: str, n_coef: int = 16, max_procs: int = 16, shape: int = 1) -> dict:
     """The FP64 oracle as it stands (serial C) on the workload's bounded
     sample: once on one core, then as one process per usable host core (at
     most max_procs), all running the same sample at once; the all-core value
     is their summed particle-steps over the wall time of the slowest."""
     cores, model = host_cpu()
     smp = workloads.cpu_sample(workload)
-    tot1, el1 = _oracle_sample(workload, n_coef)
+    tot1, el1 = _oracle_sample(workload, n_coef, shape)
     one = {"value": tot1 / el1, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
            "sample": f"{smp['desc']}: {tot1} particle-steps, serial C oracle, setup excluded, {el1:.1f} s",
            "cpu": model}
@@ -206,7 +208,8 @@ def cpu_baseline(workload: str, n_coef: int = 16, max_procs: int = 16) -> dict:
         return dict(one, all_cores=dict(one))
     import subprocess
 
-    cmd = [sys.executable, os.path.abspath(__file__), "--oracle-sample", workload, "--n-coef", str(n_coef)]
+    cmd = [sys.executable, os.path.abspath(__file__), "--oracle-sample", workload, "--n-coef", str(n_coef),
+           "--shape", str(shape)]
     procs = [subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, text=True,
                               env=dict(os.environ, OMP_NUM_THREADS="1")) for _ in range(nproc)]
     res = []
@@ -493,6 +496,8 @@ def main(argv=None):
     ap.add_argument("--window", type=int, default=0,
                     help="moving window (App. A): a move every K steps (0: the static box of the workload)")
     ap.add_argument("--window-guard", type=int, default=16, help="moving window: guard columns cleared at a move")
+    ap.add_argument("--shape", type=int, default=1, choices=[1, 2],
+                    help="particle shape order of the gather and deposit: 1 linear, 2 quadratic")
     ap.add_argument("--autotune", type=int, default=None,
                     help="1: tile and sort interval from the library's autotuner (default: on for c4 and c5)")
     ap.add_argument("--precision", type=int, default=0, choices=[0, 32, 64],
@@ -528,7 +533,7 @@ def main(argv=None):
         print(json.dumps(e, indent=1))
         return 0
     if args.oracle_sample:  # a child process of the all-core CPU baseline: no GPU is touched
-        tot, el = _oracle_sample(args.oracle_sample, args.n_coef)
+        tot, el = _oracle_sample(args.oracle_sample, args.n_coef, args.shape)
         print(json.dumps({"particle_steps": tot, "seconds": el}), flush=True)
         return 0
     if args.gpus != 1:
@@ -564,7 +569,7 @@ def main(argv=None):
         t0 = time.perf_counter()
         tune = pic.autotune([workloads.to_rundesc(r) for r in runs], precision=prec, solver=solver, n_coef=n_coef,
                             current=current, tile_z=args.tile_z,
-                            tile_r=args.tile_r, device="cuda:0")
+                            tile_r=args.tile_r, shape=args.shape, device="cuda:0")
         torch.cuda.empty_cache()
         args.tile_z, args.tile_r = tune["tile_z"], tune["tile_r"]
         args.sort_interval = args.sort_interval or tune["sort_interval"]
@@ -582,7 +587,7 @@ def main(argv=None):
                                   precision=prec_, solver=solver, n_coef=n_coef, sort_interval=sort_interval,
                                   tile_z=tile_z, tile_r=tile_r, use_graph=args.graph, current=current,
                                   window_interval=args.window, window_guard=args.window_guard if args.window else 0,
-                                  device="cuda:0")
+                                  shape=args.shape, device="cuda:0")
 
         if multi:
             warm = make([0] * len(runs))
@@ -649,7 +654,7 @@ def main(argv=None):
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
     ach = kernels[dom]["GBs"]
     traffic = (measured_traffic(args.workload, dom, "%dx%d" % infos[0]["tile"], sort_k, prec)
-               if args.solver == "dual" and args.current == "filter" and not args.window
+               if args.solver == "dual" and args.current == "filter" and not args.window and args.shape == 1
                else None)  # the counters' settings
     particle_steps = sum(n * s for n, s in zip(nps, per_run))
     value = particle_steps / (elapsed_ms * 1e-3)
@@ -661,7 +666,8 @@ def main(argv=None):
               else "dual, 16 coefficients per operator",
               "current": "P^-1 on J_z" if args.current == "exact" else "z filter on J_r, J_phi",
               "dt": [i["dt"] for i in infos] if multi else infos[0]["dt"],
-              "sort_interval": sort_k, "tile": "%dx%d" % infos[0]["tile"], "graph": bool(args.graph)}
+              "sort_interval": sort_k, "tile": "%dx%d" % infos[0]["tile"], "graph": bool(args.graph),
+              "shape": "quadratic" if args.shape == 2 else "linear"}
     if multi:
         config["steps_per_run"] = per_run
     if args.window:
@@ -719,7 +725,7 @@ def main(argv=None):
     out["roofline"]["frac_of_measured_peak"] = ach / copy_bw
     if args.cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(args.workload, n_coef)
+        out["cpu_baseline"] = cpu_baseline(args.workload, n_coef, shape=args.shape)
     print(json.dumps(out), flush=True)
     return 0
 

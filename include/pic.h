@@ -189,6 +189,19 @@ typedef struct pic_opts {
   int32_t window_interval;
   int32_t window_guard;
   double window_speed;
+  /* Particle shape order of the gather and the deposit (the order the paper
+   * leaves open, Sec. III): 0 or 1 linear (cloud in cell: 2 x 2 nodes), 2
+   * quadratic B-splines (3 x 3 nodes round the nearest node; the
+   * charge-conserving deposit on the 4 x 4 nodes holding both positions'
+   * supports, with the continuity of the dual D_B kept exact).  A stencil
+   * row below the axis, r_{-1} (or r_{-1/2}), is the row r_1 (or r_{1/2})
+   * seen from the other side: the gather reads it as that row times the
+   * component's mirror sign per mode ((-1)^m for z components and the
+   * charge, (-1)^(m+1) for r and phi components) and the deposit folds onto
+   * it with the same signs (the phi closure current, whose factor r changes
+   * sign with the row, with (-1)^m; the m = 0 phi current with -1).  Not
+   * with deterministic (PIC_E_INVALID).                                      */
+  int32_t shape;
 } pic_opts;
 
 typedef struct pic_ctx pic_ctx;

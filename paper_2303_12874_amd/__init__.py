@@ -58,6 +58,7 @@ class _Opts(C.Structure):
         ("run_dt", C.POINTER(C.c_double)), ("run_coef_E", C.POINTER(C.c_double)),
         ("run_coef_B", C.POINTER(C.c_double)), ("deterministic", C.c_int32),
         ("window_interval", C.c_int32), ("window_guard", C.c_int32), ("window_speed", C.c_double),
+        ("shape", C.c_int32),
     ]
 
 
@@ -239,10 +240,11 @@ def workspace_bytes(runs: Sequence[RunDesc], precision=PREC_FP64, solver=SOLVER_
 def _make_opts(precision, solver, n_coef, dt=0.0, coef_E=None, coef_B=None, cfl_fraction=0.0, fit_band=0.0,
                sort_interval=0, tile_z=0, tile_r=0, use_graph=False, current=CURRENT_FILTER, run_dt=None,
                run_coef_E=None, run_coef_B=None, deterministic=False, window_interval=0, window_guard=0,
-               window_speed=0.0):
+               window_speed=0.0, shape=1):
     """pic_opts.  run_dt: one dt per run; run_coef_E / run_coef_B: one
     coefficient vector per run (sequences over the runs); window_*: the
-    moving window (0: static box)."""
+    moving window (0: static box); shape: particle shape order (1 linear,
+    2 quadratic)."""
     o = _Opts()
     o.precision, o.solver, o.n_coef = precision, solver, n_coef
     o.fit_band, o.cfl_fraction, o.dt = fit_band, cfl_fraction, dt
@@ -258,6 +260,7 @@ def _make_opts(precision, solver, n_coef, dt=0.0, coef_E=None, coef_B=None, cfl_
     o.current = current
     o.deterministic = int(bool(deterministic))
     o.window_interval, o.window_guard, o.window_speed = int(window_interval), int(window_guard), float(window_speed)
+    o.shape = int(shape)
     return o, keep
 
 

@@ -173,6 +173,7 @@ struct pic_ctx {
   bool det = false;  // deterministic mode: integer deposit sums
   int win_K = 0, win_guard = 0;  // moving window: steps between moves (0: static box), guard columns
   double win_speed = 1.0;        // the window's speed (c)
+  int shape = 1;                 // particle shape order: 1 linear, 2 quadratic
   std::vector<RunHost> runs;
   // per-phase event timing
   bool profiling = false;
@@ -235,6 +236,9 @@ int validate_run(const pic_run_desc &r, int i, int N) {
   return PIC_OK;
 }
 
+// particle shape order of the options: 1 linear (0 or 1), 2 quadratic
+int shape_of(const pic_opts &o) { return o.shape == 2 ? 2 : 1; }
+
 // Sort tile: 32 x 8 cells unless given.  A default extent shrinks until the
 // push workgroup's LDS (current and field windows) fits the budget of two
 // workgroups per CU: the radial extent halves down to 4, then the axial one
@@ -243,16 +247,17 @@ int choose_tiles(const pic_opts &o, int M, int *Tz, int *Tr) {
   *Tz = o.tile_z > 0 ? o.tile_z : 32;
   *Tr = o.tile_r > 0 ? o.tile_r : 8;
   const bool det = o.deterministic != 0;
-  auto over = [&] { return push_lds_bytes(M, *Tz, *Tr, o.precision, det) > kPushLdsDefault; };
+  const int sh = shape_of(o);
+  auto over = [&] { return push_lds_bytes(M, *Tz, *Tr, o.precision, det, sh) > kPushLdsDefault; };
   while (over()) {
     if (o.tile_r <= 0 && *Tr > 4) *Tr /= 2;
     else if (o.tile_z <= 0 && *Tz > 16) *Tz -= 2;
     else if (o.tile_r <= 0 && *Tr > 1) *Tr /= 2;
     else break;
   }
-  if (push_lds_bytes(M, *Tz, *Tr, o.precision, det) > kPushLdsMax)
+  if (push_lds_bytes(M, *Tz, *Tr, o.precision, det, sh) > kPushLdsMax)
     return fail(PIC_E_INVALID, "tile %dx%d needs %zu bytes of LDS (limit %zu)", *Tz, *Tr,
-                push_lds_bytes(M, *Tz, *Tr, o.precision, det), kPushLdsMax);
+                push_lds_bytes(M, *Tz, *Tr, o.precision, det, sh), kPushLdsMax);
   return PIC_OK;
 }
 
@@ -389,6 +394,9 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
     return fail(PIC_E_INVALID, "window_interval, window_guard and window_speed must be >= 0");
   if (o.window_interval > 0 && (o.use_graph || o.deterministic))
     return fail(PIC_E_INVALID, "the moving window does not run with use_graph or the deterministic mode");
+  if (o.shape < 0 || o.shape > 2) return fail(PIC_E_INVALID, "shape must be 0, 1 (linear) or 2 (quadratic)");
+  if (o.shape == 2 && o.deterministic)
+    return fail(PIC_E_INVALID, "quadratic shapes do not run in the deterministic mode");
   for (int i = 0; i < n_runs; ++i) {
     TRY(validate_run(runs[i], i, N));
     if (particle_capacity(runs[i], o) * 8 > (int64_t)UINT32_MAX)
@@ -431,13 +439,14 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
   ctx->win_K = o.window_interval;
   ctx->win_guard = o.window_guard;
   ctx->win_speed = o.window_speed > 0 ? o.window_speed : 1.0;
+  ctx->shape = shape_of(o);
   ctx->runs.resize((size_t)n_runs);
   const hipStream_t s = ctx->stream;
   const bool f64 = o.precision == PIC_PREC_FP64;
   const double band = o.fit_band > 0 ? o.fit_band : 2.0 * kPi / 3.0;
   const double frac = o.cfl_fraction > 0 ? o.cfl_fraction : 0.95;
 
-  int rc = prepare_kernels(o.precision, runs[0].M, Tz, Tr, ctx->det);
+  int rc = prepare_kernels(o.precision, runs[0].M, Tz, Tr, ctx->det, shape_of(o));
   for (int i = 0; i < n_runs && rc == PIC_OK; ++i) {
     RunHost &R = ctx->runs[(size_t)i];
     R.d = runs[i];
@@ -506,6 +515,7 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
     k.np = run_particle_count(d);
     R.cap = particle_capacity(d, o);
     k.window = ctx->win_K > 0 ? 1 : 0;
+    k.shape = ctx->shape;
     k.plane = (long long)(d.Nr + 1) * d.Nz;
     k.E = base + L.E;
     k.B[0] = base + L.B0;
@@ -970,7 +980,8 @@ int pic_autotune(const pic_run_desc *runs, int32_t n_runs, pic_opts *opts, void 
     cand.push_back({Tz, Tr});
   } else {
     for (const auto &t : kTuneTiles)
-      if (push_lds_bytes(rd[0].M, t[0], t[1], opts->precision, opts->deterministic != 0) <= kPushLdsMax &&
+      if (push_lds_bytes(rd[0].M, t[0], t[1], opts->precision, opts->deterministic != 0, shape_of(*opts)) <=
+              kPushLdsMax &&
           cand.size() < PIC_MAX_TUNE)
         cand.push_back({t[0], t[1]});
   }
@@ -1404,7 +1415,7 @@ namespace {
 
 struct CkptHeader {
   char magic[8];
-  int32_t version, n_runs, precision, tile_z, tile_r, sort_interval, current, deterministic;
+  int32_t version, n_runs, precision, tile_z, tile_r, sort_interval, current, deterministic, shape;
 };
 
 struct Seg {
@@ -1448,7 +1459,7 @@ CkptHeader header_of(pic_ctx *ctx) {
   CkptHeader h;
   std::memset(&h, 0, sizeof h);
   std::memcpy(h.magic, "PICCKPT1", 8);
-  h.version = 3;
+  h.version = 4;
   h.n_runs = (int32_t)ctx->runs.size();
   h.precision = ctx->prec;
   h.tile_z = ctx->runs.empty() ? 0 : ctx->runs[0].k.Tz;
@@ -1456,6 +1467,7 @@ CkptHeader header_of(pic_ctx *ctx) {
   h.sort_interval = ctx->sort_interval;
   h.current = ctx->current;
   h.deterministic = ctx->det ? 1 : 0;
+  h.shape = ctx->shape;
   return h;
 }
 
@@ -1510,7 +1522,7 @@ int pic_restore(pic_ctx *ctx, const void *host_buf, size_t bytes) {
   if (std::memcmp(p, &h, sizeof h) != 0)
     return fail(PIC_E_INVALID,
                 "checkpoint header does not match this context (version, runs, precision, tile, interval, current, "
-                "deterministic mode)");
+                "deterministic mode, shape order)");
   // validate every run before any device copy
   const unsigned char *q = p + sizeof h;
   for (const RunHost &R : ctx->runs) {

@@ -247,6 +247,78 @@ __device__ __forceinline__ void interp4(const R *pa, const R *pb, const R *pc, c
   }
 }
 
+// Quadratic B-spline weights of the three nodes round the nearest node, d
+// the offset from that node in cells (in [-1/2, 1/2]).
+template <typename R>
+__device__ __forceinline__ void qspline(R d, R w[3]) {
+  const R lo = R(0.5) - d, hi = R(0.5) + d;
+  w[0] = R(0.5) * lo * lo;
+  w[1] = R(0.75) - d * d;
+  w[2] = R(0.5) * hi * hi;
+}
+
+// Quadratic interpolation of one component (all modes) from the 3 x 3
+// records of an LDS field window: node (a, b) of the stencil at
+// p + b rstride + a nstride (p points at the component in the first node).
+// Rows below the axis were staged as mirror images, so no axis rule applies.
+template <typename R, int NMP, int VB>
+__device__ __forceinline__ void interp9(const R *p, int rstride, int nstride, const R wz[3], const R wr[3],
+                                        R out[NMP]) {
+#pragma unroll
+  for (int s = 0; s < NMP; ++s) out[s] = R(0);
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    R t[NMP];
+#pragma unroll
+    for (int s = 0; s < NMP; ++s) t[s] = R(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      R v[NMP];
+      if constexpr (VB > 0) load_rec<R, NMP, VB>(p + b * rstride + a * nstride, v);
+      else load_node<R, NMP, int>(p + b * rstride + a * nstride, 1, 0, v);
+#pragma unroll
+      for (int s = 0; s < NMP; ++s) t[s] += wz[a] * v[s];
+    }
+#pragma unroll
+    for (int s = 0; s < NMP; ++s) out[s] += wr[b] * t[s];
+  }
+  out[1] = R(0);  // Im of m = 0
+}
+
+// The same from device memory (mode planes of stride `plane`): columns c0 ..
+// c0+2 (periodic), rows r0 .. r0+2 of the component's radial grid; a row
+// below the axis reads its mirror image (integer grid r_{-j} -> r_j, half
+// grid r_{-j-1/2} -> r_{j-1/2}) times each mode's mirror sign.
+template <typename R, int NMP, bool HALF_R, bool ZCOMP>
+__device__ __forceinline__ void interp9_global(const R *F, long long plane, int Nz, int Nr, int c0, int r0,
+                                               const R wz[3], const R wr[3], R out[NMP]) {
+  int col[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) col[a] = wrap_any(c0 + a, Nz);
+#pragma unroll
+  for (int s = 0; s < NMP; ++s) out[s] = R(0);
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    int row = r0 + b;
+    const bool mir = row < 0;
+    if (mir) row = HALF_R ? -row - 1 : -row;
+    row = clampi(row, 0, Nr);
+    R t[NMP];
+#pragma unroll
+    for (int s = 0; s < NMP; ++s) t[s] = R(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      R v[NMP];
+      load_node<R, NMP>(F, plane, (long long)row * Nz + col[a], v);
+#pragma unroll
+      for (int s = 0; s < NMP; ++s) t[s] += wz[a] * v[s];
+    }
+#pragma unroll
+    for (int s = 0; s < NMP; ++s) out[s] += ((mir && mirror_sign_m(s / 2, ZCOMP) < 0) ? -wr[b] : wr[b]) * t[s];
+  }
+  out[1] = R(0);
+}
+
 // run of a batch that owns block g of the launch
 __device__ __forceinline__ int batch_run(const Batch &b, long long g) {
   int r = 0;
@@ -272,7 +344,8 @@ __device__ __forceinline__ int batch_run(const Batch &b, long long g) {
 // from, or deposits to, global memory directly.
 // DET (FP64 only): the deterministic mode, whose window and device sums are
 // integer pairs (fix_split) instead of FP64 values.
-template <typename R, int M, bool DET>
+// SH: the particle shape order, 1 linear (CIC) or 2 quadratic (not with DET).
+template <typename R, int M, bool DET, int SH>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void push_kernel(const Batch bt) {
   constexpr int NM = 2 * M + 1;       // planes per component
   constexpr int NMP = 2 * (M + 1);    // reals per field record in registers
@@ -294,15 +367,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void p
   double *lds = (double *)lds_raw;
   const int par = bt.par;
   const int TZ = bt.run[0].Tz, TR = bt.run[0].Tr;  // one sort tile for every run of a batch
-  const int WZ = TZ + 3, WR = TR + 3;
+  const int WZ = current_window_z(TZ, SH), WR = current_window_r(TR, SH);
   const long long TT = (long long)TZ * TR;
   static_assert(!DET || F64, "the deterministic mode is FP64 only");
+  static_assert(SH == 1 || (SH == 2 && !DET), "shape order 1, or 2 without the deterministic mode");
   constexpr int JW = DET ? 2 : 1;             // 8-byte words per current sum
-  const int RJ = current_window_row(M, TZ, DET);  // words per current-window row (padded)
+  const int RJ = current_window_row(M, TZ, DET, SH);  // words per current-window row (padded)
   const int nlds = RJ * WR;
-  const int FZ = field_window_z(TZ), FR = field_window_r(TR);
-  const int RF = field_window_row(M, TZ, PREC);  // reals per field-window row
-  R *fw = (R *)(lds + field_window_offset_words(M, TZ, TR, DET));  // 16-byte aligned
+  const int FZ = field_window_z(TZ, SH), FR = field_window_r(TR, SH);
+  const int RF = field_window_row(M, TZ, PREC, SH);  // reals per field-window row
+  R *fw = (R *)(lds + field_window_offset_words(M, TZ, TR, DET, SH));  // 16-byte aligned
 
   // Persistent: each workgroup takes tiles (of all runs of the batch) from a
   // ticket counter, zero before the launch, until none are left; the dealing
@@ -327,15 +401,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void p
     // offset inside a plane (32-bit, so that each load is a uniform plane
     // base plus a per-lane offset); every address is valid (row clamped), so
     // the loads need no branch
-    const unsigned gg = (unsigned)((ok ? grow : 0) * kg.Nz + wrap_any(fz0g + col, kg.Nz));
+    const int colw = wrap_any(fz0g + col, kg.Nz);
+    const unsigned gg = (unsigned)((ok ? grow : 0) * kg.Nz + colw);
+    // quadratic: row r_{-1} (the only row below the axis in the window) is
+    // the image of r_1 for a component on the integer radial grid and r_{-1/2}
+    // that of r_{1/2} for one on the half grid, times the mirror sign
+    const bool mirror = SH == 2 && grow == -1;
     const R *Eg = (const R *)kg.E, *Bg = (const R *)kg.Bbar;
 #pragma unroll
     for (int i = 0; i < FS; ++i) v[i] = R(0);  // the pad (and Im of m = 0 in the vector records)
 #pragma unroll
     for (int cq = 0; cq < 6 * NM; ++cq) {
       const int c = cq / NM, q = cq % NM;
-      const R t = ((c < 3 ? Eg : Bg) + ((c % 3) * NM + q) * pl)[gg];
-      v[c * CR + ((VB && q > 0) ? q + 1 : q)] = ok ? t : R(0);
+      if constexpr (SH == 2) {
+        const bool half_r = c == 0 || c == 4 || c == 5;  // E_r, B_phi, B_z
+        const bool zcomp = c == 2 || c == 5;
+        const unsigned at = mirror ? (unsigned)((half_r ? 0 : kg.Nz) + colw) : gg;
+        const R t = ((c < 3 ? Eg : Bg) + ((c % 3) * NM + q) * pl)[at];
+        const R sg = mirror && mirror_sign_m((q + 1) / 2, zcomp) < 0 ? R(-1) : R(1);
+        v[c * CR + ((VB && q > 0) ? q + 1 : q)] = (ok || mirror) ? sg * t : R(0);
+      } else {
+        const R t = ((c < 3 ? Eg : Bg) + ((c % 3) * NM + q) * pl)[gg];
+        v[c * CR + ((VB && q > 0) ? q + 1 : q)] = ok ? t : R(0);
+      }
     }
   };
   auto stage_store = [&](int e, const R v[FS]) {
@@ -364,7 +452,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void p
   const KRun &k = bt.run[rn];
   const int tile = gt - (int)bt.off[rn];
   const int tz = tile % k.ntz, tr = tile / k.ntz;
-  const int zlo = tz * TZ - 1, rlo = tr * TR - 1;
+  const int zlo = tz * TZ - SH, rlo = tr * TR - SH;  // current-window origin
   const int beg = k.cell_start[tile * TT], end = k.cell_start[(tile + 1) * TT];
   const int Nz = k.Nz, Nr = k.Nr;
   const long long plane = k.plane;
@@ -473,40 +561,71 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void p
     int fc = i0 - fz0;
     fc += (fc < 0) ? Nz : 0;
     fc -= (fc >= Nz) ? Nz : 0;
-    const int a0 = fc, h0 = fc + dh;
-    const int ri0 = j0 - fr0, rh0 = (mir ? 0 : jh) - fr0, rh1 = jh + 1 - fr0;
-    if (h0 >= 0 && a0 + 1 <= FZ - 1 && ri0 >= 0 && rh0 >= 0 && ri0 + 1 <= FR - 1 && rh1 <= FR - 1) {
-      const R *li0 = fw + ri0 * RF, *li1 = li0 + RF;  // rows of j0, j0 + 1
-      const R *lh0 = fw + rh0 * RF, *lh1 = fw + rh1 * RF;  // half-r rows
-      const int A0 = a0 * FS, A1 = A0 + FS, H0 = h0 * FS, H1 = H0 + FS;
-      interp4<R, NMP, true, false, int, VB>(lh0 + A0, lh0 + A1, lh1 + A0, lh1 + A1, 1, mir, f0, frh, er);
-      interp4<R, NMP, false, false, int, VB>(li0 + A0 + CR, li0 + A1 + CR, li1 + A0 + CR, li1 + A1 + CR, 1, false,
-                                             f0, fr, ep);
-      interp4<R, NMP, false, true, int, VB>(li0 + H0 + 2 * CR, li0 + H1 + 2 * CR, li1 + H0 + 2 * CR,
-                                            li1 + H1 + 2 * CR, 1, false, fh, fr, ez);
-      interp4<R, NMP, false, false, int, VB>(li0 + H0 + 3 * CR, li0 + H1 + 3 * CR, li1 + H0 + 3 * CR,
-                                             li1 + H1 + 3 * CR, 1, false, fh, fr, br);
-      interp4<R, NMP, true, false, int, VB>(lh0 + H0 + 4 * CR, lh0 + H1 + 4 * CR, lh1 + H0 + 4 * CR,
-                                            lh1 + H1 + 4 * CR, 1, mir, fh, frh, bp);
-      interp4<R, NMP, true, true, int, VB>(lh0 + A0 + 5 * CR, lh0 + A1 + 5 * CR, lh1 + A0 + 5 * CR,
-                                           lh1 + A1 + 5 * CR, 1, mir, f0, frh, bz);
+    if constexpr (SH == 2) {
+      // Quadratic: 3 x 3 nodes round the nearest node of each component's
+      // grid.  Along z the nearest integer node is i0 + zn and the nearest
+      // half node (z_{i+1/2}, column i) is i0; along r likewise j0 + rn and
+      // j0.  Weights at offsets f0 - zn, f0 - 1/2, fr - rn, fr - 1/2.
+      const int zn = f0 >= R(0.5) ? 1 : 0, rn_ = fr >= R(0.5) ? 1 : 0;
+      R wzn[3], wzh[3], wrn[3], wrh[3];
+      qspline(f0 - (R)zn, wzn);
+      qspline(f0 - R(0.5), wzh);
+      qspline(fr - (R)rn_, wrn);
+      qspline(fr - R(0.5), wrh);
+      const int cn = fc + zn - 1, chh = fc - 1;                // first window column: integer, half z
+      const int rnn = j0 + rn_ - 1 - fr0, rhh = j0 - 1 - fr0;  // first window row: integer, half r
+      if (chh >= 0 && cn + 2 <= FZ - 1 && rhh >= 0 && rnn + 2 <= FR - 1) {
+        interp9<R, NMP, VB>(fw + rhh * RF + cn * FS, RF, FS, wzn, wrh, er);
+        interp9<R, NMP, VB>(fw + rnn * RF + cn * FS + CR, RF, FS, wzn, wrn, ep);
+        interp9<R, NMP, VB>(fw + rnn * RF + chh * FS + 2 * CR, RF, FS, wzh, wrn, ez);
+        interp9<R, NMP, VB>(fw + rnn * RF + chh * FS + 3 * CR, RF, FS, wzh, wrn, br);
+        interp9<R, NMP, VB>(fw + rhh * RF + chh * FS + 4 * CR, RF, FS, wzh, wrh, bp);
+        interp9<R, NMP, VB>(fw + rhh * RF + cn * FS + 5 * CR, RF, FS, wzn, wrh, bz);
+      } else {
+        const int gn = i0 + zn - 1, gh = i0 - 1, qn = j0 + rn_ - 1, qh = j0 - 1;
+        interp9_global<R, NMP, true, false>(E, plane, Nz, Nr, gn, qh, wzn, wrh, er);
+        interp9_global<R, NMP, false, false>(E + cstride, plane, Nz, Nr, gn, qn, wzn, wrn, ep);
+        interp9_global<R, NMP, false, true>(E + 2 * cstride, plane, Nz, Nr, gh, qn, wzh, wrn, ez);
+        interp9_global<R, NMP, false, false>(Bb, plane, Nz, Nr, gh, qn, wzh, wrn, br);
+        interp9_global<R, NMP, true, false>(Bb + cstride, plane, Nz, Nr, gh, qh, wzh, wrh, bp);
+        interp9_global<R, NMP, true, true>(Bb + 2 * cstride, plane, Nz, Nr, gn, qh, wzn, wrh, bz);
+      }
     } else {
-      const long long gi0 = (long long)j0 * Nz, gi1 = gi0 + Nz;
-      const long long gh0 = (long long)(mir ? 0 : jh) * Nz, gh1 = (long long)(jh + 1) * Nz;
-      const R *er_ = E, *ep_ = E + cstride, *ez_ = E + 2 * cstride;
-      const R *br_ = Bb, *bp_ = Bb + cstride, *bz_ = Bb + 2 * cstride;
-      interp4<R, NMP, true, false, long long>(er_ + gh0 + ci0, er_ + gh0 + ci1, er_ + gh1 + ci0, er_ + gh1 + ci1,
-                                              plane, mir, f0, frh, er);
-      interp4<R, NMP, false, false, long long>(ep_ + gi0 + ci0, ep_ + gi0 + ci1, ep_ + gi1 + ci0, ep_ + gi1 + ci1,
-                                               plane, false, f0, fr, ep);
-      interp4<R, NMP, false, true, long long>(ez_ + gi0 + ch0, ez_ + gi0 + ch1, ez_ + gi1 + ch0, ez_ + gi1 + ch1,
-                                              plane, false, fh, fr, ez);
-      interp4<R, NMP, false, false, long long>(br_ + gi0 + ch0, br_ + gi0 + ch1, br_ + gi1 + ch0, br_ + gi1 + ch1,
-                                               plane, false, fh, fr, br);
-      interp4<R, NMP, true, false, long long>(bp_ + gh0 + ch0, bp_ + gh0 + ch1, bp_ + gh1 + ch0, bp_ + gh1 + ch1,
-                                              plane, mir, fh, frh, bp);
-      interp4<R, NMP, true, true, long long>(bz_ + gh0 + ci0, bz_ + gh0 + ci1, bz_ + gh1 + ci0, bz_ + gh1 + ci1,
-                                             plane, mir, f0, frh, bz);
+      const int a0 = fc, h0 = fc + dh;
+      const int ri0 = j0 - fr0, rh0 = (mir ? 0 : jh) - fr0, rh1 = jh + 1 - fr0;
+      if (h0 >= 0 && a0 + 1 <= FZ - 1 && ri0 >= 0 && rh0 >= 0 && ri0 + 1 <= FR - 1 && rh1 <= FR - 1) {
+        const R *li0 = fw + ri0 * RF, *li1 = li0 + RF;  // rows of j0, j0 + 1
+        const R *lh0 = fw + rh0 * RF, *lh1 = fw + rh1 * RF;  // half-r rows
+        const int A0 = a0 * FS, A1 = A0 + FS, H0 = h0 * FS, H1 = H0 + FS;
+        interp4<R, NMP, true, false, int, VB>(lh0 + A0, lh0 + A1, lh1 + A0, lh1 + A1, 1, mir, f0, frh, er);
+        interp4<R, NMP, false, false, int, VB>(li0 + A0 + CR, li0 + A1 + CR, li1 + A0 + CR, li1 + A1 + CR, 1, false,
+                                               f0, fr, ep);
+        interp4<R, NMP, false, true, int, VB>(li0 + H0 + 2 * CR, li0 + H1 + 2 * CR, li1 + H0 + 2 * CR,
+                                              li1 + H1 + 2 * CR, 1, false, fh, fr, ez);
+        interp4<R, NMP, false, false, int, VB>(li0 + H0 + 3 * CR, li0 + H1 + 3 * CR, li1 + H0 + 3 * CR,
+                                               li1 + H1 + 3 * CR, 1, false, fh, fr, br);
+        interp4<R, NMP, true, false, int, VB>(lh0 + H0 + 4 * CR, lh0 + H1 + 4 * CR, lh1 + H0 + 4 * CR,
+                                              lh1 + H1 + 4 * CR, 1, mir, fh, frh, bp);
+        interp4<R, NMP, true, true, int, VB>(lh0 + A0 + 5 * CR, lh0 + A1 + 5 * CR, lh1 + A0 + 5 * CR,
+                                             lh1 + A1 + 5 * CR, 1, mir, f0, frh, bz);
+      } else {
+        const long long gi0 = (long long)j0 * Nz, gi1 = gi0 + Nz;
+        const long long gh0 = (long long)(mir ? 0 : jh) * Nz, gh1 = (long long)(jh + 1) * Nz;
+        const R *er_ = E, *ep_ = E + cstride, *ez_ = E + 2 * cstride;
+        const R *br_ = Bb, *bp_ = Bb + cstride, *bz_ = Bb + 2 * cstride;
+        interp4<R, NMP, true, false, long long>(er_ + gh0 + ci0, er_ + gh0 + ci1, er_ + gh1 + ci0, er_ + gh1 + ci1,
+                                                plane, mir, f0, frh, er);
+        interp4<R, NMP, false, false, long long>(ep_ + gi0 + ci0, ep_ + gi0 + ci1, ep_ + gi1 + ci0, ep_ + gi1 + ci1,
+                                                 plane, false, f0, fr, ep);
+        interp4<R, NMP, false, true, long long>(ez_ + gi0 + ch0, ez_ + gi0 + ch1, ez_ + gi1 + ch0, ez_ + gi1 + ch1,
+                                                plane, false, fh, fr, ez);
+        interp4<R, NMP, false, false, long long>(br_ + gi0 + ch0, br_ + gi0 + ch1, br_ + gi1 + ch0, br_ + gi1 + ch1,
+                                                 plane, false, fh, fr, br);
+        interp4<R, NMP, true, false, long long>(bp_ + gh0 + ch0, bp_ + gh0 + ch1, bp_ + gh1 + ch0, bp_ + gh1 + ch1,
+                                                plane, mir, fh, frh, bp);
+        interp4<R, NMP, true, true, long long>(bz_ + gh0 + ci0, bz_ + gh0 + ci1, bz_ + gh1 + ci0, bz_ + gh1 + ci1,
+                                               plane, mir, f0, frh, bz);
+      }
     }
 
     // ---- reconstruct Re sum_m F^m e^{i m phi}, rotate to Cartesian ----
@@ -711,10 +830,129 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void p
                (double)pa0 * qs, (double)pb0 * qs);
         }
       };
-      // (not in the deterministic mode: which path an electron takes would
-      // depend on the other electrons of its wavefront, and the two paths
-      // round differently)
-      if (!DET && !__any(di != 0 || dj != 0)) {
+      if constexpr (SH == 2) {
+        // Quadratic: the 4 x 4 node window [ib, ib+3] x [jb, jb+3] that holds
+        // the 3 x 3 supports round the nearest nodes of both positions (a
+        // move of less than a cell changes each nearest node by at most one),
+        // quadratic B-spline shapes S0, S1 on it, and the same Esirkepov
+        // weights and running sums as the linear deposit.  Nodes on row
+        // r_{-1} (within half a cell of the axis) are summed there in the
+        // tile window and folded onto r_1 (J_r: face r_{-1/2} onto r_{1/2})
+        // with the mirror sign when the window is flushed; the device-memory
+        // path folds them at once.
+        const int n0z = f0 >= R(0.5) ? 1 : 0, n1z = f1 >= R(0.5) ? 1 : 0;
+        const int n0r = g0 >= R(0.5) ? 1 : 0, n1r = g1 >= R(0.5) ? 1 : 0;
+        const int dn = clampi(di + n1z - n0z, -1, 1), dm = clampi(dj + n1r - n0r, -1, 1);
+        const int oz0 = dn < 0 ? 1 : 0, oz1 = oz0 + dn;  // first support node of each position in the window
+        const int or0 = dm < 0 ? 1 : 0, or1 = or0 + dm;
+        const int ib = i0 + n0z - 1 - oz0, jb = j0 + n0r - 1 - or0;
+        const bool zx = __any(dn != 0), rx = __any(dm != 0);
+        R q0z[3], q1z[3], q0r[3], q1r[3];
+        qspline(f0 - (R)n0z, q0z);
+        qspline(f1 - (R)n1z, q1z);
+        qspline(g0 - (R)n0r, q0r);
+        qspline(g1 - (R)n1r, q1r);
+        R Sz0[4], Sz1[4], Sr0[4], Sr1[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          Sz0[a] = a == oz0 ? q0z[0] : (a == oz0 + 1 ? q0z[1] : (a == oz0 + 2 ? q0z[2] : R(0)));
+          Sz1[a] = a == oz1 ? q1z[0] : (a == oz1 + 1 ? q1z[1] : (a == oz1 + 2 ? q1z[2] : R(0)));
+          Sr0[a] = a == or0 ? q0r[0] : (a == or0 + 1 ? q0r[1] : (a == or0 + 2 ? q0r[2] : R(0)));
+          Sr1[a] = a == or1 ? q1r[0] : (a == or1 + 1 ? q1r[1] : (a == or1 + 2 ? q1r[2] : R(0)));
+        }
+        // J_z at (ib+a+1/2, jb+b), a = 0..2; J_r at (ib+a, jb+b+1/2), b = 0..2;
+        // J_phi at (ib+a, jb+b)
+        double wz[4][3], wr[4][3], ws[4][4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          R run = 0;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            run += (Sz1[a] - Sz0[a]) * (Sr0[b] + Sr1[b]) * R(0.5);
+            wz[b][a] = -(double)run;
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          R run = 0;
+#pragma unroll
+          for (int b = 0; b < 3; ++b) {
+            run += (Sr1[b] - Sr0[b]) * (Sz0[a] + Sz1[a]) * R(0.5);
+            wr[a][b] = -(double)run;
+          }
+#pragma unroll
+          for (int b = 0; b < 4; ++b) ws[a][b] = (double)(R(0.5) * (Sz0[a] * Sr0[b] + Sz1[a] * Sr1[b]));
+        }
+        // a node past the first three columns (rows) holds shape only for an
+        // electron whose nearest node moved along z (r), and the last flux
+        // of a line is the whole line's sum, zero, when it did not
+        auto deposit = [&](auto &&dep) {
+          for_modes(true, [&](int m, int qa, int qb, double fa, double fb, double pa, double pb, double pa0,
+                              double pb0) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+              if (b == 3 && !rx) continue;
+#pragma unroll
+              for (int a = 0; a < 3; ++a) {
+                if (a == 2 && !zx) continue;
+                if ((a == 2 && dn == 0) || (b == 3 && dm == 0)) continue;
+                dep(2, qa, b, a, wz[b][a], fa);
+                if (m > 0) dep(2, qb, b, a, wz[b][a], fb);
+              }
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+              if (a == 3 && !zx) continue;
+#pragma unroll
+              for (int b = 0; b < 3; ++b) {
+                if (b == 2 && !rx) continue;
+                if ((a == 3 && dn == 0) || (b == 2 && dm == 0)) continue;
+                dep(0, qa, b, a, wr[a][b], fa);
+                if (m > 0) dep(0, qb, b, a, wr[a][b], fb);
+              }
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+              if (a == 3 && !zx) continue;
+#pragma unroll
+              for (int b = 0; b < 4; ++b) {
+                if (b == 3 && !rx) continue;
+                if ((a == 3 && dn == 0) || (b == 3 && dm == 0)) continue;
+                const bool axis = jb + b == 0;  // the axis row takes the axis coefficients
+                dep(1, qa, b, a, ws[a][b], axis ? pa0 : pa);
+                if (m > 0) dep(1, qb, b, a, ws[a][b], axis ? pb0 : pb);
+              }
+            }
+          });
+        };
+        if ((ib - zlo >= 0) && (ib + 3 - zlo < WZ) && (jb - rlo >= 0) && (jb + 3 - rlo < WR)) {
+          double *jw = lds + (jb - rlo) * RJ + (ib - zlo) * JS;
+          deposit([&](int c, int qq, int b, int a, double w, double cf) {
+            lds_add(jw + b * RJ + a * JS + (c * NM + qq), w * cf);
+          });
+        } else {
+          int col[4];
+#pragma unroll
+          for (int a = 0; a < 4; ++a) col[a] = wrap_any(ib + a, Nz);
+          deposit([&](int c, int qq, int b, int a, double w, double cf) {
+            // row r_{-1} onto r_1, face r_{-1/2} onto r_{1/2}, with the
+            // mirror sign of the component and mode
+            int row = jb + b;
+            double sg = 1.0;
+            if (row < 0) {
+              const int m = (qq + 1) / 2;
+              row = c == 0 ? -row - 1 : -row;
+              sg = (c == 0 ? mirror_sign_m(m, false) : (c == 1 && m == 0 ? -1 : mirror_sign_m(m, true))) < 0 ? -1.0
+                                                                                                                : 1.0;
+            }
+            const long long at = (c * NM + qq) * plane + (long long)row * Nz + col[a];
+            atomic_add(J + at, (R)(sg * w * cf));
+          });
+        }
+      } else if (!DET && !__any(di != 0 || dj != 0)) {
+        // (this path not in the deterministic mode: which path an electron
+        // takes would depend on the other electrons of its wavefront, and the
+        // two paths round differently)
         // No electron of the wavefront left its cell: each deposits on the
         // 2 x 2 nodes (i0 + a, j0 + b) of its cell.  J_z at (i0+1/2, j0+b)
         // carries (f1 - f0) times the mean radial shape of row b, J_r at
@@ -915,6 +1153,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void p
   if (threadIdx.x == 0) ticket = atomicAdd(bt.run[0].work, 1);  // read after the barrier
   __syncthreads();
   const int nt = ticket;
+  // quadratic: one window node, row r_{-1} folded onto r_1 (J_r: face
+  // r_{-1/2} onto r_{1/2}) with the mirror sign: (-1)^m for J_z, (-1)^(m+1)
+  // for J_r, and for J_phi (-1)^m of the closure (its factor r changes sign
+  // with the row) and -1 of the m = 0 current
+  auto flush_quadratic = [&](int e) {
+    const int lr = e / WZ, lc = e - lr * WZ;
+    const int row = rlo + lr;
+    if (row < -1 || row > Nr) return;  // never deposited to
+    const int col = wrap_any(zlo + lc, Nz);
+    double *src = lds + lr * RJ + lc * JS;
+#pragma unroll
+    for (int cq = 0; cq < JS; ++cq) {
+      const int c = cq / NM, m = (cq % NM + 1) / 2;
+      int trow = row;
+      R sg = R(1);
+      if (row < 0) {
+        trow = c == 0 ? 0 : 1;
+        sg = (c == 0 ? mirror_sign_m(m, false) : (c == 1 && m == 0 ? -1 : mirror_sign_m(m, true))) < 0 ? R(-1) : R(1);
+      }
+      const R v = sg * (R)src[cq];
+      src[cq] = 0.0;
+      if (v != R(0)) atomic_add(J + cq * plane + (unsigned)(trow * Nz + col), v);
+    }
+  };
   if constexpr (!F64) {
     // FP32: the first half of the wavefronts flush the current window while
     // the other half stage the next tile's field window (separate LDS
@@ -923,6 +1185,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void p
     if ((int)threadIdx.x < split) {
       if (n > 0)
         for (int e = threadIdx.x; e < WZ * WR; e += split) {
+          if constexpr (SH == 2) {
+            flush_quadratic(e);
+            continue;
+          }
           const int lr = e / WZ, lc = e - lr * WZ;
           const int row = rlo + lr;
           if (row < 0 || row > Nr) continue;  // never deposited to
@@ -948,6 +1214,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void p
     // then stages
     if (n > 0)
       for (int e = threadIdx.x; e < WZ * WR; e += blockDim.x) {
+        if constexpr (SH == 2) {
+          flush_quadratic(e);
+          continue;
+        }
         const int lr = e / WZ, lc = e - lr * WZ;
         const int row = rlo + lr;
         if (row < 0 || row > Nr) continue;  // never deposited to
@@ -1371,6 +1641,12 @@ __global__ __launch_bounds__(256) void rho_kernel(KRun k) {
   const double q = -(double)((const R *)k.pw)[p];
   double *rho = (double *)k.rho;
   const double dzd = k.dz, drd = k.dr;
+  // quadratic: 3 x 3 nodes round the nearest node, row r_{-1} onto r_1
+  // with the sign (-1)^m of a scalar's mode m
+  const int zn = (k.shape == 2 && f0 >= R(0.5)) ? 1 : 0, rn = (k.shape == 2 && fr >= R(0.5)) ? 1 : 0;
+  double wz[3], wr[3];
+  qspline((double)f0 - zn, wz);
+  qspline((double)fr - rn, wr);
   double er = 1, ei = 0;
   for (int m = 0; m <= M; ++m) {
     if (m > 0) {
@@ -1379,6 +1655,26 @@ __global__ __launch_bounds__(256) void rho_kernel(KRun k) {
       ei = ti;
     }
     const double cm = m == 0 ? 1.0 : 2.0;
+    const int qa = m == 0 ? 0 : 2 * m - 1;
+    if (k.shape == 2) {
+      for (int b = 0; b < 3; ++b) {
+        int j = j0 + rn - 1 + b;
+        double sg = 1.0;
+        if (j < 0) {
+          j = -j;
+          sg = m % 2 ? -1.0 : 1.0;
+        }
+        if ((m > 0 && j == 0) || j > Nr) continue;  // the m >= 1 density vanishes on the axis
+        const double V = j == 0 ? kPi * drd * drd * dzd / 4.0 : 2.0 * kPi * (j * drd) * drd * dzd;
+        for (int a = 0; a < 3; ++a) {
+          const long long node = (long long)j * Nz + wrap_any(i0 + zn - 1 + a, Nz);
+          const double S = sg * wz[a] * wr[b];
+          atomic_add(rho + qa * k.plane + node, cm * q * er * S / V);
+          if (m > 0) atomic_add(rho + (qa + 1) * k.plane + node, cm * q * ei * S / V);
+        }
+      }
+      continue;
+    }
     for (int a = 0; a < 2; ++a)
       for (int b = 0; b < 2; ++b) {
         const int j = j0 + b;
@@ -1386,7 +1682,6 @@ __global__ __launch_bounds__(256) void rho_kernel(KRun k) {
         const double V = j == 0 ? kPi * drd * drd * dzd / 4.0 : 2.0 * kPi * (j * drd) * drd * dzd;
         const double S = (a ? (double)f0 : 1.0 - (double)f0) * (b ? (double)fr : 1.0 - (double)fr);
         const long long node = (long long)j * Nz + wrap_once(i0 + a, Nz);
-        const int qa = m == 0 ? 0 : 2 * m - 1;
         atomic_add(rho + qa * k.plane + node, cm * q * er * S / V);
         if (m > 0) atomic_add(rho + (qa + 1) * k.plane + node, cm * q * ei * S / V);
       }
@@ -1832,16 +2127,25 @@ constexpr int prec_of() {
   return std::is_same<R, double>::value ? PIC_PREC_FP64 : PIC_PREC_FP32;
 }
 
+// the push kernel of (deterministic mode, shape order); the deterministic
+// mode is FP64 and linear only (nullptr otherwise)
+template <typename R, int M>
+auto push_kernel_of(bool det, int sh) -> decltype(&push_kernel<R, M, false, 1>) {
+  if (sh == 2) return det ? nullptr : push_kernel<R, M, false, 2>;
+  if (!det) return push_kernel<R, M, false, 1>;
+  if constexpr (std::is_same<R, double>::value) return push_kernel<R, M, true, 1>;
+  return nullptr;
+}
+
 template <typename R, int M>
 struct PrepL {
-  static int run(int Tz, int Tr, bool det) {
+  static int run(int Tz, int Tr, bool det, int sh) {
     // dynamic LDS above 64 KB must be allowed per kernel, once, outside any capture
-    const size_t lds = push_lds_bytes(M, Tz, Tr, prec_of<R>(), det);
+    const auto f = push_kernel_of<R, M>(det, sh);
+    if (!f) return PIC_E_INVALID;
+    const size_t lds = push_lds_bytes(M, Tz, Tr, prec_of<R>(), det, sh);
     if (lds <= 65536) return PIC_OK;
-    const void *f = (const void *)push_kernel<R, M, false>;
-    if constexpr (std::is_same<R, double>::value)
-      if (det) f = (const void *)push_kernel<R, M, true>;
-    return check(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+    return check(hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
                  "hipFuncSetAttribute(push_kernel)");
   }
 };
@@ -1851,22 +2155,21 @@ struct PushL {
     if (!set_offsets(b, [](const KRun &k) { return k.np > 0 ? (long long)k.ntz * k.ntr : 0LL; })) return PIC_OK;
     const KRun &k0 = b.run[0];
     const bool det = b.det != 0;
-    if (det && !std::is_same<R, double>::value) return PIC_E_INVALID;
-    const size_t lds = push_lds_bytes(M, k0.Tz, k0.Tr, prec_of<R>(), det);
+    const int sh = k0.shape;
+    const auto f = push_kernel_of<R, M>(det, sh);
+    if (!f) return PIC_E_INVALID;
+    const size_t lds = push_lds_bytes(M, k0.Tz, k0.Tr, prec_of<R>(), det, sh);
     // persistent grid: as many workgroups as are resident at once (a multiple
     // of 8, one share per XCD), each walking its tiles; the occupancy query
-    // is cached per thread for the last (device, LDS size)
+    // is cached per thread for the last (device, kernel, LDS size)
     static thread_local size_t lds_seen = 0;
     static thread_local int dev_seen = -1;
-    static thread_local bool det_seen = false;
+    static thread_local const void *f_seen = nullptr;
     static thread_local long long resident = 0;
     int dev = 0;
     if (int rc = check(hipGetDevice(&dev), "hipGetDevice")) return rc;
-    if (lds != lds_seen || dev != dev_seen || det != det_seen) {
+    if (lds != lds_seen || dev != dev_seen || (const void *)f != f_seen) {
       int per_cu = 0, cus = 0;
-      auto *f = push_kernel<R, M, false>;
-      if constexpr (std::is_same<R, double>::value)
-        if (det) f = push_kernel<R, M, true>;
       int rc = check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 256, lds),
                      "hipOccupancyMaxActiveBlocksPerMultiprocessor");
       if (!rc) rc = check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
@@ -1875,18 +2178,13 @@ struct PushL {
       resident = resident >= 8 ? resident & ~7LL : resident;
       lds_seen = lds;
       dev_seen = dev;
-      det_seen = det;
+      f_seen = (const void *)f;
     }
     const long long grid = b.off[b.n] < resident ? b.off[b.n] : resident;
     zero_kernel<<<1, 64, 0, s>>>((uint4 *)b.run[0].work, 1, nullptr, 0);  // tickets from 0
     if (int rc = check(hipGetLastError(), "zero_kernel")) return rc;
-    if constexpr (std::is_same<R, double>::value) {
-      if (det) push_kernel<R, M, true><<<(unsigned)grid, 256, lds, s>>>(b);
-      else push_kernel<R, M, false><<<(unsigned)grid, 256, lds, s>>>(b);
-    } else {
-      push_kernel<R, M, false><<<(unsigned)grid, 256, lds, s>>>(b);
-    }
-    return check(hipGetLastError(), "push_kernel");
+    void *args[] = {&b};
+    return check(hipLaunchKernel((const void *)f, dim3((unsigned)grid), dim3(256), args, lds, s), "push_kernel");
   }
 };
 template <typename R, int M>
@@ -1945,7 +2243,9 @@ int launch_efield(Batch &b, int prec, void *stream) {
 int launch_bfield(Batch &b, int prec, void *stream) {
   return dispatch_M<BL>(prec, b.run[0].M, b, (hipStream_t)stream);
 }
-int prepare_kernels(int prec, int M, int Tz, int Tr, bool det) { return dispatch_M<PrepL>(prec, M, Tz, Tr, det); }
+int prepare_kernels(int prec, int M, int Tz, int Tr, bool det, int sh) {
+  return dispatch_M<PrepL>(prec, M, Tz, Tr, det, sh);
+}
 int launch_fix_convert(Batch &b, void *stream) {
   if (!set_offsets(b, [](const KRun &k) { return (3 * (2 * k.M + 1) * k.plane + 255) / 256; })) return PIC_OK;
   fix_convert_kernel<<<(unsigned)b.off[b.n], 256, 0, (hipStream_t)stream>>>(b);

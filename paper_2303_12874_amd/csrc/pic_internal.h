@@ -103,19 +103,26 @@ struct KRun {
   // leaves the box gets zero weight (window); at a window move the sort
   // shifts every electron back `shift` cells and drops those outside the box
   int window, shift;
+  int shape;              // particle shape order: 1 linear, 2 quadratic (every run of a batch alike)
 };
 
 // ---- push workgroup LDS ---------------------------------------------------------
 // One push workgroup per sort tile of Tz x Tr cells.  Its LDS holds
 //  * the tile's current window, FP64 for both precisions, 3 components x NM
-//    planes x (Tz+3) x (Tr+3) nodes from cell (z0-1, r0-1): every move of
-//    less than a cell from a cell of the tile deposits inside it;
+//    planes x (Tz+1+2 sh) x (Tr+1+2 sh) nodes from node (z0-sh, r0-sh), sh
+//    the shape order (1 linear, 2 quadratic): every move of less than a cell
+//    from a cell of the tile deposits inside it (linear: the 3 x 3 nodes
+//    round both cells; quadratic: the 4 x 4 nodes round both nearest nodes);
 //  * the field window of E and Bbar, one record per node for
-//    (Tz+2+2 kFieldMarginZ) x (Tr+2+2 kFieldMarginR) nodes from column
-//    z0-1-kFieldMarginZ and row r0-1-kFieldMarginR (the gather stencil of
-//    every electron within the margins of the tile): 6 components of 2 (M+1)
-//    reals each (Re and Im of every mode, Im of m = 0 held as zero), padded
-//    so that a component is read with 16-byte (or 8-byte) vector loads.
+//    (Tz+2+2 kFieldMarginZ+sh-1) x (Tr+2+2 kFieldMarginR+sh-1) nodes from
+//    column z0-1-kFieldMarginZ and row r0-1-kFieldMarginR (the gather stencil
+//    of every electron within the margins of the tile: linear 2 x 2 nodes,
+//    quadratic 3 x 3 round the nearest node), 6 components of 2 (M+1) reals
+//    each (Re and Im of every mode, Im of m = 0 held as zero), padded so that
+//    a component is read with 16-byte (or 8-byte) vector loads.  For the
+//    quadratic shape a row below the axis holds the mirror image of the row
+//    above (each mode times its mirror sign), so that the gather needs no
+//    axis rule.
 constexpr int kFieldMarginZ = 1;  // columns for electrons that drifted since the sort
 constexpr int kFieldMarginR = 0;
 constexpr size_t kPushLdsDefault = 81920;  // default tile choice: two workgroups per CU
@@ -129,18 +136,21 @@ constexpr size_t kPushLdsMax = 163840;     // gfx950 LDS per workgroup
 // stride congruent to Tz nodes modulo 256 bytes keeps those lanes on distinct
 // banks when a wavefront spans two rows.
 constexpr int kBankBytes = 256;
-constexpr int field_window_z(int Tz) { return Tz + 2 + 2 * kFieldMarginZ; }
-constexpr int field_window_r(int Tr) { return Tr + 2 + 2 * kFieldMarginR; }
+constexpr int field_window_z(int Tz, int sh = 1) { return Tz + 2 + 2 * kFieldMarginZ + sh - 1; }
+constexpr int field_window_r(int Tr, int sh = 1) { return Tr + 2 + 2 * kFieldMarginR + sh - 1; }
+constexpr int current_window_z(int Tz, int sh = 1) { return Tz + 1 + 2 * sh; }
+constexpr int current_window_r(int Tr, int sh = 1) { return Tr + 1 + 2 * sh; }
 constexpr int pos_mod(int a, int m) { return ((a % m) + m) % m; }
-// 8-byte words per current-window row: (Tz + 3) nodes of 3 NM sums, plus the
-// pad; a sum is one word (FP64), or two (the integer pair of the
+// 8-byte words per current-window row: current_window_z nodes of 3 NM sums,
+// plus the pad; a sum is one word (FP64), or two (the integer pair of the
 // deterministic mode, det).  The tile current is summed in FP64 for both
 // precisions: on gfx950 the LDS FP32 atomic add (ds_add_f32) costs about 20
 // times the FP64 one (measured: 193 against 8.8 cycles per wavefront
 // instruction without bank conflicts), and an FP32 tile current made the
 // FP32 push of the 8192 x 512 run 6.8x slower.
-constexpr int current_window_row(int M, int Tz, bool det = false) {
-  return (det ? 2 : 1) * 3 * (2 * M + 1) * (Tz + 3) + pos_mod(-3 * (det ? 2 : 1) * 3 * (2 * M + 1), kBankBytes / 8);
+constexpr int current_window_row(int M, int Tz, bool det = false, int sh = 1) {
+  return (det ? 2 : 1) * 3 * (2 * M + 1) * current_window_z(Tz, sh) +
+         pos_mod(-(1 + 2 * sh) * (det ? 2 : 1) * 3 * (2 * M + 1), kBankBytes / 8);
 }
 // Field-window records.  FP32 with 2 (M+1) a multiple of 4 (M odd): a
 // component holds its 2 (M+1) reals (Re and Im of every mode, Im of m = 0 as
@@ -166,24 +176,24 @@ constexpr int field_node_reals(int M, int precision) {
 // reals per field-window row (record layout: a whole number of vectors;
 // plane layout: padded so that the row stride is congruent to Tz records
 // modulo 256 bytes, like the current window)
-constexpr int field_window_row(int M, int Tz, int precision) {
+constexpr int field_window_row(int M, int Tz, int precision, int sh = 1) {
   return field_vec_bytes(M, precision)
-             ? field_node_reals(M, precision) * field_window_z(Tz)
-             : field_node_reals(M, precision) * field_window_z(Tz) +
-                   pos_mod(-(field_window_z(Tz) - Tz) * field_node_reals(M, precision),
+             ? field_node_reals(M, precision) * field_window_z(Tz, sh)
+             : field_node_reals(M, precision) * field_window_z(Tz, sh) +
+                   pos_mod(-(field_window_z(Tz, sh) - Tz) * field_node_reals(M, precision),
                            kBankBytes / (precision == PIC_PREC_FP64 ? 8 : 4));
 }
-constexpr size_t current_window_words(int M, int Tz, int Tr, bool det = false) {
-  return (size_t)current_window_row(M, Tz, det) * (Tr + 3);
+constexpr size_t current_window_words(int M, int Tz, int Tr, bool det = false, int sh = 1) {
+  return (size_t)current_window_row(M, Tz, det, sh) * current_window_r(Tr, sh);
 }
 // 8-byte words before the field window (the current window, rounded up to 16 bytes)
-constexpr size_t field_window_offset_words(int M, int Tz, int Tr, bool det = false) {
-  return (current_window_words(M, Tz, Tr, det) + 1) / 2 * 2;
+constexpr size_t field_window_offset_words(int M, int Tz, int Tr, bool det = false, int sh = 1) {
+  return (current_window_words(M, Tz, Tr, det, sh) + 1) / 2 * 2;
 }
-inline size_t push_lds_bytes(int M, int Tz, int Tr, int precision, bool det = false) {
+inline size_t push_lds_bytes(int M, int Tz, int Tr, int precision, bool det = false, int sh = 1) {
   const size_t w = precision == PIC_PREC_FP64 ? 8 : 4;
-  return field_window_offset_words(M, Tz, Tr, det) * 8 +
-         (size_t)field_window_row(M, Tz, precision) * field_window_r(Tr) * w;
+  return field_window_offset_words(M, Tz, Tr, det, sh) * 8 +
+         (size_t)field_window_row(M, Tz, precision, sh) * field_window_r(Tr, sh) * w;
 }
 
 // ---- batched launches ---------------------------------------------------------
@@ -219,7 +229,7 @@ int launch_sort(Batch &b, int prec, void *stream);  // swaps the runs' particle 
 // moving window: E, B[0], B[1], Bbar of run k back by k.shift columns (zeros
 // entering at the front), then the first `guard` columns cleared
 int launch_window_shift(const KRun &k, int prec, int guard, void *stream);
-int prepare_kernels(int prec, int M, int Tz, int Tr, bool det);  // per-kernel attributes, before any capture
+int prepare_kernels(int prec, int M, int Tz, int Tr, bool det, int sh);  // per-kernel attributes, before any capture
 int launch_fix_convert(Batch &b, void *stream);  // deterministic mode: integer sums -> J[par], sums cleared
 int launch_zero(void *ptr, size_t bytes, void *stream);
 int launch_rho(const KRun &k, int prec, void *stream);

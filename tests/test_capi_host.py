@@ -106,6 +106,18 @@ def test_moving_window_options_are_checked():
         assert e.value.code == pic.PIC_E_INVALID, kw
 
 
+def test_shape_order_option_is_checked():
+    """Shape order 0 or 1 (linear) and 2 (quadratic) are taken; other values
+    and quadratic shapes with the deterministic mode are refused."""
+    d = _desc()
+    for sh in (0, 1, 2):
+        assert pic.workspace_bytes([d], shape=sh) > 0
+    for kw in (dict(shape=3), dict(shape=-1), dict(shape=2, deterministic=True)):
+        with pytest.raises(pic.PicError) as e:
+            pic.workspace_bytes([d], **kw)
+        assert e.value.code == pic.PIC_E_INVALID, kw
+
+
 def test_allocation_free_divergence_checks_its_arguments_first():
     """pic_divergence_arrays refuses bad arguments and counts beyond its fixed
     scratch (2048 x 256 x 64 electrons) before any device call."""
