@@ -831,22 +831,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void p
         }
       };
       if constexpr (SH == 2) {
-        // Quadratic: the 4 x 4 node window [ib, ib+3] x [jb, jb+3] that holds
+        // Quadratic: a 4 x 4 node window [ib, ib+3] x [jb, jb+3] that holds
         // the 3 x 3 supports round the nearest nodes of both positions (a
         // move of less than a cell changes each nearest node by at most one),
         // quadratic B-spline shapes S0, S1 on it, and the same Esirkepov
-        // weights and running sums as the linear deposit.  Nodes on row
-        // r_{-1} (within half a cell of the axis) are summed there in the
-        // tile window and folded onto r_1 (J_r: face r_{-1/2} onto r_{1/2})
-        // with the mirror sign when the window is flushed; the device-memory
-        // path folds them at once.
+        // weights and running sums as the linear deposit.  The window starts
+        // at node (i0 - 1, j0 - 1), one before the cell, whenever it holds
+        // both supports (each nearest node is the cell's first or second
+        // node): then lanes in distinct cells never add to one LDS address in
+        // the same instruction (a window started at the nearest node minus
+        // one gives two lanes in neighbouring cells the same window in a
+        // quarter of the cases).  Otherwise it starts one before the lower
+        // nearest node.  Nodes on row r_{-1} (within half a cell of the axis)
+        // are summed there in the tile window and folded onto r_1 (J_r: face
+        // r_{-1/2} onto r_{1/2}) with the mirror sign when the window is
+        // flushed; the device-memory path folds them at once.
         const int n0z = f0 >= R(0.5) ? 1 : 0, n1z = f1 >= R(0.5) ? 1 : 0;
         const int n0r = g0 >= R(0.5) ? 1 : 0, n1r = g1 >= R(0.5) ? 1 : 0;
+        // nearest nodes relative to the cell: old n0, new n0 + dn
         const int dn = clampi(di + n1z - n0z, -1, 1), dm = clampi(dj + n1r - n0r, -1, 1);
-        const int oz0 = dn < 0 ? 1 : 0, oz1 = oz0 + dn;  // first support node of each position in the window
-        const int or0 = dm < 0 ? 1 : 0, or1 = or0 + dm;
-        const int ib = i0 + n0z - 1 - oz0, jb = j0 + n0r - 1 - or0;
-        const bool zx = __any(dn != 0), rx = __any(dm != 0);
+        const int zlo_ = n0z + (dn < 0 ? dn : 0), zhi_ = n0z + (dn > 0 ? dn : 0);
+        const int rlo_ = n0r + (dm < 0 ? dm : 0), rhi_ = n0r + (dm > 0 ? dm : 0);
+        const int bz = (zlo_ >= 0 && zhi_ <= 1) ? -1 : zlo_ - 1;  // window start relative to the cell
+        const int br = (rlo_ >= 0 && rhi_ <= 1) ? -1 : rlo_ - 1;
+        const int oz0 = n0z - 1 - bz, oz1 = oz0 + dn;  // first support node of each position in the window
+        const int or0 = n0r - 1 - br, or1 = or0 + dm;
+        const int lz = zlo_ - 1 - bz, hz = zhi_ - 1 - bz;  // lower and upper of oz0, oz1 (0 or 1)
+        const int lr = rlo_ - 1 - br, hr = rhi_ - 1 - br;
+        const int ib = i0 + bz, jb = j0 + br;
+        // the first (last) window column or row carries current only from a
+        // lane whose lower (upper) support starts there: the wave skips it when
+        // no lane's does
+        const bool zf = __any(lz == 0), zl = __any(hz == 1), rf = __any(lr == 0), rl = __any(hr == 1);
         R q0z[3], q1z[3], q0r[3], q1r[3];
         qspline(f0 - (R)n0z, q0z);
         qspline(f1 - (R)n1z, q1z);
@@ -883,41 +899,42 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void p
 #pragma unroll
           for (int b = 0; b < 4; ++b) ws[a][b] = (double)(R(0.5) * (Sz0[a] * Sr0[b] + Sz1[a] * Sr1[b]));
         }
-        // a node past the first three columns (rows) holds shape only for an
-        // electron whose nearest node moved along z (r), and the last flux
-        // of a line is the whole line's sum, zero, when it did not
+        // a lane's shapes cover window columns lz .. hz + 2 and rows
+        // lr .. hr + 2; its z fluxes faces lz .. hz + 1, its r fluxes faces
+        // lr .. hr + 1 (past those a line's running sum is the whole line's,
+        // zero).  Each lane masks itself off the others.
         auto deposit = [&](auto &&dep) {
           for_modes(true, [&](int m, int qa, int qb, double fa, double fb, double pa, double pb, double pa0,
                               double pb0) {
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-              if (b == 3 && !rx) continue;
+              if ((b == 0 && !rf) || (b == 3 && !rl)) continue;
 #pragma unroll
               for (int a = 0; a < 3; ++a) {
-                if (a == 2 && !zx) continue;
-                if ((a == 2 && dn == 0) || (b == 3 && dm == 0)) continue;
+                if ((a == 0 && !zf) || (a == 2 && !zl)) continue;
+                if (a < lz || a > hz + 1 || b < lr || b > hr + 2) continue;
                 dep(2, qa, b, a, wz[b][a], fa);
                 if (m > 0) dep(2, qb, b, a, wz[b][a], fb);
               }
             }
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
-              if (a == 3 && !zx) continue;
+              if ((a == 0 && !zf) || (a == 3 && !zl)) continue;
 #pragma unroll
               for (int b = 0; b < 3; ++b) {
-                if (b == 2 && !rx) continue;
-                if ((a == 3 && dn == 0) || (b == 2 && dm == 0)) continue;
+                if ((b == 0 && !rf) || (b == 2 && !rl)) continue;
+                if (a < lz || a > hz + 2 || b < lr || b > hr + 1) continue;
                 dep(0, qa, b, a, wr[a][b], fa);
                 if (m > 0) dep(0, qb, b, a, wr[a][b], fb);
               }
             }
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
-              if (a == 3 && !zx) continue;
+              if ((a == 0 && !zf) || (a == 3 && !zl)) continue;
 #pragma unroll
               for (int b = 0; b < 4; ++b) {
-                if (b == 3 && !rx) continue;
-                if ((a == 3 && dn == 0) || (b == 3 && dm == 0)) continue;
+                if ((b == 0 && !rf) || (b == 3 && !rl)) continue;
+                if (a < lz || a > hz + 2 || b < lr || b > hr + 2) continue;
                 const bool axis = jb + b == 0;  // the axis row takes the axis coefficients
                 dep(1, qa, b, a, ws[a][b], axis ? pa0 : pa);
                 if (m > 0) dep(1, qb, b, a, ws[a][b], axis ? pb0 : pb);
