@@ -11,7 +11,8 @@
   from the FP32 arithmetic of the E update and of the push's radius, and the
   tracked work sums over modes to the change of gamma (Eq. (16)).
   Sampled outputs the oracle computes one by one: the gather and push of
-  3600 electrons from the library's own field and electron state.
+  3600 electrons from the library's own field and electron state.  Both
+  checks run with linear and with quadratic particle shapes.
 * the six-run FP32 scan (34 M electrons, 24 x 8 tiles, sort every 16 steps,
   captured-graph steps): the smallest run against the oracle at the FP32
   bounds, every run against the same Gauss-law and work-identity checks.
@@ -52,8 +53,9 @@ def test_fp64_4096x256_two_steps_match_oracle():
     sim.close()
 
 
-def test_fp32_8192x512_invariants():
-    """Three steps.  Bound on the change of the Gauss residual, per step, from
+@pytest.mark.parametrize("shape", [1, 2])
+def test_fp32_8192x512_invariants(shape):
+    """Three steps, linear or quadratic shapes.  Bound on the change of the Gauss residual, per step, from
     the FP32 arithmetic (u = 2^-24, a factor 2 sqrt(2) for complex parts and
     margin):
       * each E update rounds E, and takes an FP32 J: errors u (|E| + dt |J|)
@@ -64,12 +66,12 @@ def test_fp32_8192x512_invariants():
         current's radial weights differ from rho's by u j at row j, so
         continuity holds to u max_j (j |rho_j|), times sum|P| after the
         filter."""
-    _say("[gpu] full size 8192x512 fp32, invariants")
+    _say(f"[gpu] full size 8192x512 fp32, invariants, shape order {shape}")
     pic = _pic()
     cfg = workloads.config("c5")
     run = cfg["runs"][0]
     sim = pic.Simulation([workloads.to_rundesc(run)], precision=pic.PREC_FP32, tile_z=16, tile_r=4,
-                         sort_interval=16)
+                         sort_interval=16, shape=shape)
     CE, CB, taps = sim.coefficients()
     dt = sim.info(0)["dt"]
     M, dz, dr = run["M"], run["dz"], run["dr"]
@@ -172,8 +174,10 @@ def _gauss_run(sim, pic, run, CB, taps, m, i):
     return G, max(np.abs(Er).max(), np.abs(Ep).max(), np.abs(Ez).max())
 
 
-def test_fp32_8192x512_sampled_step_matches_oracle():
-    """Sampled parity at full size, gather + push and deposit: after two steps of the 8192 x 512 FP32 run
+@pytest.mark.parametrize("shape", [1, 2])
+def test_fp32_8192x512_sampled_step_matches_oracle(shape):
+    """Sampled parity at full size, gather + push and deposit, with linear or
+    quadratic shapes (the oracle takes the same shape order): after two steps of the 8192 x 512 FP32 run
     (67 M electrons, the benchmark's 16 x 4 tiles), the library's E^n and
     time-averaged B^n are loaded into an FP64 oracle grid, and for 3600
     sampled electrons (random ones, the closest to the axis, the most
@@ -186,19 +190,20 @@ def test_fp32_8192x512_sampled_step_matches_oracle():
     patches (below) within 1e-5 of the largest current there: each
     electron's FP32 offset difference is exact to ~2^-24 cells, and a node
     sums a few hundred of them."""
-    _say("[gpu] full size 8192x512 fp32, sampled push against the oracle")
+    _say(f"[gpu] full size 8192x512 fp32, sampled push against the oracle, shape order {shape}")
     import oracle
 
     pic = _pic()
     run = workloads.config("c5")["runs"][0]
     sim = pic.Simulation([workloads.to_rundesc(run)], precision=pic.PREC_FP32, tile_z=16, tile_r=4,
-                         sort_interval=16)
+                         sort_interval=16, shape=shape)
     sim.step(2)  # the next step sorts nothing: the storage order is kept
     P0 = sim.particles()
     Nz, Nr, M, dz, dr = run["Nz"], run["Nr"], run["M"], run["dz"], run["dr"]
     CE, CB, _ = sim.coefficients()
     dt = sim.info()["dt"]
     o = oracle.Oracle(Nz, Nr, M, dz, dr, dt, CE, CB)
+    o.set_shape(shape)
     for m in range(M + 1):
         for gc, oc in ((pic.ER, oracle.ER), (pic.EPHI, oracle.EP), (pic.EZ, oracle.EZ)):
             o.set_field(oc, m, sim.fields(gc, m))
@@ -236,7 +241,9 @@ def test_fp32_8192x512_sampled_step_matches_oracle():
     assert max(worst.values()) <= 1.0, worst
 
     # the deposit of that step on 12 patches of 8 x 6 nodes (two on the axis):
-    # every electron whose old cell is within reach of a patch is deposited
+    # every electron whose old cell is within reach of a patch (two cells
+    # below and three above it with quadratic shapes, one and two with
+    # linear ones, plus a cell of move) is deposited
     # by the oracle from the library's own old and new states, and the current
     # on the patch is compared with the library's J of the step
     z0, z1 = P0["z"], P1["z"].copy()

@@ -176,3 +176,64 @@ def test_fp64_quadratic_moving_window():
     assert np.array_equal(P["id"][a], Q["id"][b])
     assert max(np.abs(P[k][a] - Q[k][b]).max() for k in ("z", "x", "y")) < TOL64
     sim.close()
+
+
+def test_fp64_quadratic_batched_graph_exact_jz():
+    """Two runs of different grids and cells in one context with quadratic
+    shapes, the exact J_z correction and captured-graph steps (sorts every 4
+    steps, advanced in chunks with reads in between), each run against its
+    own oracle with the same switches at the FP64 bar."""
+    _say("[gpu] fp64 quadratic shapes, batched runs, graph replay, exact J_z")
+    from test_gpu_batch import _runs
+
+    pic = _pic()
+    runs = _runs()[:2]
+    dt, CE, CB, _ = _setup(16, 2, runs[-1]["dz"], runs[-1]["dr"])
+    sim = pic.Simulation([workloads.to_rundesc(r) for r in runs], dt=dt, coef_E=CE, coef_B=CB, sort_interval=4,
+                         use_graph=True, current=pic.CURRENT_EXACT_JZ, shape=2)
+    done = 0
+    for chunk in (3, 5, 6):
+        sim.step(chunk)
+        done += chunk
+        sim.fields(pic.EZ, 0, 0)  # a read between replays
+    for i, run in enumerate(runs):
+        o = oracle_of(run, dt, CE, CB)
+        o.set_shape(2)
+        o.set_exact_jz(True)
+        o.step(done)
+        worst = compare_fields(sim, o, run["M"], TOL64, run=i)
+        bad = {k: v for k, v in worst.items() if v > TOL64}
+        assert not bad, (i, bad)
+        dzmax, dxy, du, _ = compare_particles(sim, o, run["Nz"], run=i)
+        assert dzmax < TOL64 and dxy < TOL64 and du < TOL64, (i, dzmax, dxy, du)
+    sim.close()
+
+
+def test_quadratic_checkpoint_restore_and_shape_mismatch():
+    """A quadratic-shape context restores its own checkpoint and continues like
+    the original (to 1e-12); a linear-shape context of the same runs refuses
+    it (the header records the shape order)."""
+    _say("[gpu] quadratic shapes, checkpoint and restore")
+    pic = _pic()
+    run = workloads.small(M=2, Nz=64, Nr=12, ppc=2, n_tracked=10)["runs"][0]
+    dt, CE, CB, _ = _setup(16, 2, run["dz"], run["dr"])
+
+    def make(shape):
+        return pic.Simulation([workloads.to_rundesc(run)], dt=dt, coef_E=CE, coef_B=CB, sort_interval=4, shape=shape)
+
+    a = make(2)
+    a.step(9)
+    blob = a.checkpoint()
+    a.step(6)
+    b = make(2)
+    b.restore(blob)
+    b.step(6)
+    for comp in (0, 1, 2, 6, 7, 8, 13, 14, 15):
+        for m in range(run["M"] + 1):
+            x, y = a.fields(comp, m), b.fields(comp, m)
+            assert np.abs(x - y).max() <= 1e-12 * max(np.abs(x).max(), 1e-300), (comp, m)
+    c = make(1)
+    with pytest.raises(pic.PicError):
+        c.restore(blob)
+    for s in (a, b, c):
+        s.close()
