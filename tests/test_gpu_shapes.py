@@ -94,6 +94,25 @@ def test_fp64_quadratic_electrons_outside_their_tile_windows():
     sim.close()
 
 
+def test_fp64_quadratic_smallest_grid_all_tracked_and_many_per_cell():
+    """Edge cases with quadratic shapes: the smallest grid accepted (32 x 4:
+    the stencils wrap the whole periodic line, every electron within reach of
+    both the axis fold and the wall row) with every electron tracked, and 24
+    electrons per cell (a wavefront's lanes share cells, so their LDS atomics
+    collide), each against the oracle at the FP64 bar."""
+    _say("[gpu] fp64 quadratic shapes, smallest grid and 24 ppc")
+    run = workloads.small(M=1, Nz=32, Nr=4, ppc=3, n_tracked=0)["runs"][0]
+    run["n_tracked"] = 32 * 3 * 3
+    sim, o = _pair(run, 25)
+    _check_fp64(sim, o, run)
+    assert sim.mode_work()["id"].size == run["n_tracked"]
+    sim.close()
+    run = workloads.small(M=2, Nz=64, Nr=12, ppc=24, n_tracked=50)["runs"][0]
+    sim, o = _pair(run, 10)
+    _check_fp64(sim, o, run)
+    sim.close()
+
+
 def test_fp32_quadratic_within_fp32_bounds():
     """The FP32 form (int32 cell + FP32 offset) with quadratic shapes, from the
     FP32-rounded start, 20 steps, modes 0..3, to the FP32 bounds."""
