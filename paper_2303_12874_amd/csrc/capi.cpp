@@ -150,7 +150,7 @@ Layout layout_of(const pic_run_desc &d, int prec, int N, int Tz, int Tr, long lo
   L.P = take((size_t)(2 * N - 1) * rs);
   L.H = take((size_t)PIC_MAX_JZ_TAPS * rs);
   L.red = take((size_t)kRedBlocks * (PIC_MAX_MODES + 1) * 8);
-  L.work = take(32);  // tile ticket (16 bytes), then the sort's flag word
+  L.work = take(64);  // the push's 8 tile ticket counters (32 bytes), then the sort's flag word
   L.gam = take((size_t)(d.n_tracked > 0 ? d.n_tracked : 1) * 8);
   L.ids = take((size_t)(d.n_tracked > 0 ? d.n_tracked : 1) * 8);
   // deterministic mode: an integer pair (2 x 8 bytes) per value of J
@@ -562,7 +562,7 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
     k.NH = (int)R.H.size();
     k.red = (double *)(base + L.red);
     k.work = (int32_t *)(base + L.work);
-    k.flags = (uint32_t *)(base + L.work + 16);
+    k.flags = (uint32_t *)(base + L.work + 32);
     k.Jfix = ctx->det ? (unsigned long long *)(base + L.Jfix) : nullptr;
     k.qscale = 1.0;
     R.dev_gamma = (double *)(base + L.gam);
@@ -656,7 +656,7 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
     }
     const size_t rs = f64 ? 8 : 4;
     const size_t vecb = (size_t)3 * (2 * d.M + 1) * (size_t)k.plane * rs;
-    if ((rc = launch_zero(k.work, 32, s)) || (rc = launch_zero(k.J[0], vecb, s)) || (rc = launch_zero(k.J[1], vecb, s)) ||
+    if ((rc = launch_zero(k.work, 64, s)) || (rc = launch_zero(k.J[0], vecb, s)) || (rc = launch_zero(k.J[1], vecb, s)) ||
         (rc = launch_zero(k.W, (size_t)(d.n_tracked > 0 ? d.n_tracked : 1) * (d.M + 1) * 8, s)) ||
         (rc = launch_zero(k.Wc, (size_t)(d.n_tracked > 0 ? d.n_tracked : 1) * 2 * 8, s)))
       break;

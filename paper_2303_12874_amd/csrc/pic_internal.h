@@ -93,7 +93,7 @@ struct KRun {
   int ntz, ntr;           // tiles along z and r
   long long n_keys;       // tiles * Tz * Tr
   double *red;            // reduction partials
-  int32_t *work;          // tile ticket counter of the persistent push (run 0's serves a batch)
+  int32_t *work;          // the persistent push's 8 tile ticket counters, one per XCD (run 0's serve a batch)
   uint32_t *flags;        // cell-sort integrity bits (kSort*), sticky
   // deterministic mode: the deposit's integer sums, pairs (a, b) per value
   // of the J layout (interleaved), zero between steps, and the scale 2^K
@@ -206,6 +206,7 @@ struct Batch {
   int n;                            // runs in the batch
   int par;                          // step parity: deposit into J[par], B^{n+1/2} in B[par ^ 1]
   int det;                          // deterministic mode (integer deposit sums, FP64 only)
+  int deal_xcd;                     // push: tiles dealt per XCD (set by the launcher), else in one order
   long long off[kMaxBatch + 1];     // first block of each run in the launch (set by the launcher)
   KRun run[kMaxBatch];
   // B update operands per run: Bout = Bin - tau curl_E E, and avg = (Bin + Bout)/2 when not NULL
