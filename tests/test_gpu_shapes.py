@@ -27,11 +27,12 @@ from test_gpu_parity import (TOL64, _pic, _say, _setup, compare_cartesian_work, 
 pytestmark = pytest.mark.gpu
 
 
-def _pair(run, nsteps, precision=64, **kw):
+def _pair(run, nsteps, precision=64, N=16, **kw):
     pic = _pic()
-    dt, CE, CB, _ = _setup(16, run["M"], run["dz"], run["dr"])
-    sim = pic.Simulation([workloads.to_rundesc(run)], precision=precision, dt=dt, coef_E=CE, coef_B=CB, shape=2,
-                         **kw)
+    dt, CE, CB, _ = _setup(N, run["M"], run["dz"], run["dr"])
+    solver = pic.SOLVER_YEE if N == 1 else pic.SOLVER_DUAL
+    sim = pic.Simulation([workloads.to_rundesc(run)], precision=precision, solver=solver, n_coef=N, dt=dt, coef_E=CE,
+                         coef_B=CB, shape=2, **kw)
     o = oracle_of(run, dt, CE, CB, fp32_start=(precision == 32))
     o.set_shape(2)
     if kw.get("window_interval"):
@@ -126,6 +127,17 @@ def test_fp32_quadratic_within_fp32_bounds():
     sim.close()
 
 
+def test_fp64_quadratic_yee_solver():
+    """Quadratic shapes with the Yee solver (one coefficient per operator, no
+    filter) through the same kernels, against the oracle run with
+    C^E = C^B = (1), to the FP64 bar."""
+    _say("[gpu] fp64 quadratic shapes, Yee solver")
+    run = workloads.small(M=2, Nz=64, Nr=12, ppc=2, n_tracked=40)["runs"][0]
+    sim, o = _pair(run, 30, N=1)
+    _check_fp64(sim, o, run)
+    sim.close()
+
+
 def test_fp64_quadratic_charge_density_and_gauss_law():
     """The quadratic charge density diagnostic equals the oracle's, and
     div_B E - P rho stays constant through 15 steps on the library's own
@@ -194,6 +206,27 @@ def test_fp64_quadratic_moving_window():
     a, b = np.argsort(P["id"]), np.argsort(Q["id"])
     assert np.array_equal(P["id"][a], Q["id"][b])
     assert max(np.abs(P[k][a] - Q[k][b]).max() for k in ("z", "x", "y")) < TOL64
+    sim.close()
+
+
+def test_fp32_quadratic_moving_window():
+    """The FP32 form with quadratic shapes and the moving window (positions
+    unwrapped, electrons dropped and fresh columns loaded), 40 steps, a move
+    every 4, to the FP32 bounds by electron id."""
+    _say("[gpu] fp32 quadratic shapes with the moving window")
+    run = workloads.small(M=1, Nz=128, Nr=12, ppc=2, n_tracked=40)["runs"][0]
+    run["pulses"][0]["zc"] = 3.5 * workloads.LAMBDA0
+    L = run["Nz"] * run["dz"]
+    run.update(ramp_start=0.2 * L, ramp_len=0.3 * L)
+    sim, o = _pair(run, 40, precision=32, window_interval=4, window_guard=8, sort_interval=6)
+    assert sim.info()["window_cells"] == o.window_cells > 20
+    assert sim.info()["n_particles"] == o.np
+    for (name, m), v in compare_fields(sim, o, run["M"], 0).items():
+        assert v <= (JTOL if name.startswith("J") else EBTOL), (name, m, v)
+    P, Q = sim.particles(), o.particles()
+    a, b = np.argsort(P["id"]), np.argsort(Q["id"])
+    assert np.array_equal(P["id"][a], Q["id"][b])
+    assert np.abs(P["z"][a] - Q["z"][b]).max() < 1e-3
     sim.close()
 
 
