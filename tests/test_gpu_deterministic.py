@@ -78,10 +78,10 @@ def test_deterministic_is_bitwise_reproducible():
     run = _run()
     dt, CE, CB, _ = _setup(16, run["M"], run["dz"], run["dr"])
     n = 24
-    configs = [dict(), dict(tile_z=8, tile_r=1, sort_interval=1000), dict(tile_z=16, tile_r=4, sort_interval=3),
+    settings = [dict(), dict(tile_z=8, tile_r=1, sort_interval=1000), dict(tile_z=16, tile_r=4, sort_interval=3),
                dict(tile_z=24, tile_r=2, sort_interval=5, use_graph=True)]
     ref = None
-    for kw in configs:
+    for kw in settings:
         sim = _sim(pic, run, dt, CE, CB, deterministic=True, **kw)
         sim.step(n)
         st = _state(sim, run)
@@ -102,7 +102,7 @@ def test_deterministic_is_bitwise_reproducible():
     b.close()
     # the plain FP64 mode, for the record: the same two tilings
     plain = []
-    for kw in configs[:2]:
+    for kw in settings[:2]:
         sim = _sim(pic, run, dt, CE, CB, **kw)
         sim.step(n)
         plain.append(_state(sim, run))
