@@ -79,7 +79,7 @@ def test_deterministic_is_bitwise_reproducible():
     dt, CE, CB, _ = _setup(16, run["M"], run["dz"], run["dr"])
     n = 24
     settings = [dict(), dict(tile_z=8, tile_r=1, sort_interval=1000), dict(tile_z=16, tile_r=4, sort_interval=3),
-               dict(tile_z=24, tile_r=2, sort_interval=5, use_graph=True)]
+                dict(tile_z=24, tile_r=2, sort_interval=5, use_graph=True)]
     ref = None
     for kw in settings:
         sim = _sim(pic, run, dt, CE, CB, deterministic=True, **kw)
