@@ -199,8 +199,7 @@ typedef struct pic_opts {
    * component's mirror sign per mode ((-1)^m for z components and the
    * charge, (-1)^(m+1) for r and phi components) and the deposit folds onto
    * it with the same signs (the phi closure current, whose factor r changes
-   * sign with the row, with (-1)^m; the m = 0 phi current with -1).  Not
-   * with deterministic (PIC_E_INVALID).                                      */
+   * sign with the row, with (-1)^m; the m = 0 phi current with -1).         */
   int32_t shape;
 } pic_opts;
 

@@ -395,8 +395,6 @@ int pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_opts *opts, voi
   if (o.window_interval > 0 && (o.use_graph || o.deterministic))
     return fail(PIC_E_INVALID, "the moving window does not run with use_graph or the deterministic mode");
   if (o.shape < 0 || o.shape > 2) return fail(PIC_E_INVALID, "shape must be 0, 1 (linear) or 2 (quadratic)");
-  if (o.shape == 2 && o.deterministic)
-    return fail(PIC_E_INVALID, "quadratic shapes do not run in the deterministic mode");
   for (int i = 0; i < n_runs; ++i) {
     TRY(validate_run(runs[i], i, N));
     if (particle_capacity(runs[i], o) * 8 > (int64_t)UINT32_MAX)

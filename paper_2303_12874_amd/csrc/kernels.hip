@@ -346,7 +346,7 @@ __device__ __forceinline__ int batch_run(const Batch &b, long long g) {
 // from, or deposits to, global memory directly.
 // DET (FP64 only): the deterministic mode, whose window and device sums are
 // integer pairs (fix_split) instead of FP64 values.
-// SH: the particle shape order, 1 linear (CIC) or 2 quadratic (not with DET).
+// SH: the particle shape order, 1 linear (CIC) or 2 quadratic.
 template <typename R, int M, bool DET, int SH>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void push_kernel(const Batch bt) {
   constexpr int NM = 2 * M + 1;       // planes per component
@@ -372,7 +372,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void p
   const int WZ = current_window_z(TZ, SH), WR = current_window_r(TR, SH);
   const long long TT = (long long)TZ * TR;
   static_assert(!DET || F64, "the deterministic mode is FP64 only");
-  static_assert(SH == 1 || (SH == 2 && !DET), "shape order 1, or 2 without the deterministic mode");
+  static_assert(SH == 1 || SH == 2, "shape order 1 or 2");
   constexpr int JW = DET ? 2 : 1;             // 8-byte words per current sum
   const int RJ = current_window_row(M, TZ, DET, SH);  // words per current-window row (padded)
   const int nlds = RJ * WR;
@@ -967,9 +967,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void p
           });
         };
         if ((ib - zlo >= 0) && (ib + 3 - zlo < WZ) && (jb - rlo >= 0) && (jb + 3 - rlo < WR)) {
-          double *jw = lds + (jb - rlo) * RJ + (ib - zlo) * JS;
+          double *jw = lds + (jb - rlo) * RJ + (ib - zlo) * (JW * JS);
           deposit([&](int c, int qq, int b, int a, double w, double cf) {
-            lds_add(jw + b * RJ + a * JS + (c * NM + qq), w * cf);
+            double *p = jw + b * RJ + a * (JW * JS) + JW * (c * NM + qq);
+            if constexpr (DET) fix_add_lds((unsigned long long *)p, w, cf);
+            else lds_add(p, w * cf);
           });
         } else {
           int col[4];
@@ -987,7 +989,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void p
                                                                                                                 : 1.0;
             }
             const long long at = (c * NM + qq) * plane + (long long)row * Nz + col[a];
-            atomic_add(J + at, (R)(sg * w * cf));
+            if constexpr (DET) {
+              unsigned long long x, y;
+              fix_split(sg * w, cf, x, y);  // sg w is exact
+              fix_add_global(k.Jfix + 2 * at, x, y);
+            } else {
+              atomic_add(J + at, (R)(sg * w * cf));
+            }
           });
         }
       } else if (!DET && !__any(di != 0 || dj != 0)) {
@@ -1203,19 +1211,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void p
     const int row = rlo + lr;
     if (row < -1 || row > Nr) return;  // never deposited to
     const int col = wrap_any(zlo + lc, Nz);
-    double *src = lds + lr * RJ + lc * JS;
+    double *src = lds + lr * RJ + lc * (JW * JS);
 #pragma unroll
     for (int cq = 0; cq < JS; ++cq) {
       const int c = cq / NM, m = (cq % NM + 1) / 2;
       int trow = row;
-      R sg = R(1);
+      bool neg = false;
       if (row < 0) {
         trow = c == 0 ? 0 : 1;
-        sg = (c == 0 ? mirror_sign_m(m, false) : (c == 1 && m == 0 ? -1 : mirror_sign_m(m, true))) < 0 ? R(-1) : R(1);
+        neg = (c == 0 ? mirror_sign_m(m, false) : (c == 1 && m == 0 ? -1 : mirror_sign_m(m, true))) < 0;
       }
-      const R v = sg * (R)src[cq];
-      src[cq] = 0.0;
-      if (v != R(0)) atomic_add(J + cq * plane + (unsigned)(trow * Nz + col), v);
+      const unsigned off = (unsigned)(trow * Nz + col);
+      if constexpr (DET) {
+        // the integer pair negated word by word (two's complement) is the
+        // pair of the negated value
+        unsigned long long *s2 = (unsigned long long *)src;
+        const unsigned long long a = s2[2 * cq], b = s2[2 * cq + 1];
+        s2[2 * cq] = s2[2 * cq + 1] = 0;
+        fix_add_global(k.Jfix + 2 * ((long long)cq * plane + off), neg ? 0ull - a : a, neg ? 0ull - b : b);
+      } else {
+        const R v = (neg ? R(-1) : R(1)) * (R)src[cq];
+        src[cq] = 0.0;
+        if (v != R(0)) atomic_add(J + cq * plane + off, v);
+      }
     }
   };
   if constexpr (!F64) {
@@ -2169,12 +2187,12 @@ constexpr int prec_of() {
 }
 
 // the push kernel of (deterministic mode, shape order); the deterministic
-// mode is FP64 and linear only (nullptr otherwise)
+// mode is FP64 only (nullptr otherwise)
 template <typename R, int M>
 auto push_kernel_of(bool det, int sh) -> decltype(&push_kernel<R, M, false, 1>) {
-  if (sh == 2) return det ? nullptr : push_kernel<R, M, false, 2>;
-  if (!det) return push_kernel<R, M, false, 1>;
-  if constexpr (std::is_same<R, double>::value) return push_kernel<R, M, true, 1>;
+  if (!det) return sh == 2 ? push_kernel<R, M, false, 2> : push_kernel<R, M, false, 1>;
+  if constexpr (std::is_same<R, double>::value)
+    return sh == 2 ? push_kernel<R, M, true, 2> : push_kernel<R, M, true, 1>;
   return nullptr;
 }
 

@@ -107,12 +107,13 @@ def test_moving_window_options_are_checked():
 
 
 def test_shape_order_option_is_checked():
-    """Shape order 0 or 1 (linear) and 2 (quadratic) are taken; other values
-    and quadratic shapes with the deterministic mode are refused."""
+    """Shape order 0 or 1 (linear) and 2 (quadratic) are taken, quadratic also
+    with the deterministic mode; other values are refused."""
     d = _desc()
     for sh in (0, 1, 2):
         assert pic.workspace_bytes([d], shape=sh) > 0
-    for kw in (dict(shape=3), dict(shape=-1), dict(shape=2, deterministic=True)):
+    assert pic.workspace_bytes([d], shape=2, deterministic=True) > pic.workspace_bytes([d], shape=2)
+    for kw in (dict(shape=3), dict(shape=-1)):
         with pytest.raises(pic.PicError) as e:
             pic.workspace_bytes([d], **kw)
         assert e.value.code == pic.PIC_E_INVALID, kw

@@ -109,3 +109,43 @@ def test_deterministic_is_bitwise_reproducible():
         sim.close()
     diff = max(np.abs(plain[0][k] - plain[1][k]).max() for k in plain[0])
     _say(f"  plain FP64, two tilings: largest difference {diff:.3e} (deterministic: 0)")
+
+
+def test_deterministic_quadratic_shapes():
+    """The deterministic mode with quadratic shapes (the fold of row r_{-1}
+    done on the integer pairs): against the oracle's quadratic shapes at the
+    FP64 bar, and bitwise the same across sort tiles, sort intervals (8 x 1
+    tiles never re-sorted: most electrons on the device-memory path), graph
+    replay and a checkpoint."""
+    _say("[gpu] deterministic fp64 with quadratic shapes")
+    pic = _pic()
+    run = _run()
+    dt, CE, CB, _ = _setup(16, run["M"], run["dz"], run["dr"])
+    n = 24
+    sim = _sim(pic, run, dt, CE, CB, deterministic=True, shape=2)
+    o = oracle_of(run, dt, CE, CB)
+    o.set_shape(2)
+    sim.step(n)
+    o.step(n)
+    worst = compare_fields(sim, o, run["M"], TOL64)
+    bad = {k: v for k, v in worst.items() if v > TOL64}
+    assert not bad, bad
+    dzmax, dxy, du, _ = compare_particles(sim, o, run["Nz"])
+    assert dzmax < TOL64 and dxy < TOL64 and du < TOL64, (dzmax, dxy, du)
+    ref = _state(sim, run)
+    sim.close()
+    for kw in (dict(tile_z=8, tile_r=1, sort_interval=1000), dict(tile_z=16, tile_r=4, sort_interval=3),
+               dict(tile_z=24, tile_r=2, sort_interval=5, use_graph=True)):
+        sim = _sim(pic, run, dt, CE, CB, deterministic=True, shape=2, **kw)
+        sim.step(n)
+        assert _same_bits(ref, _state(sim, run)), kw
+        sim.close()
+    a = _sim(pic, run, dt, CE, CB, deterministic=True, shape=2)
+    a.step(10)
+    blob = a.checkpoint()
+    a.close()
+    b = _sim(pic, run, dt, CE, CB, deterministic=True, shape=2)
+    b.restore(blob)
+    b.step(n - 10)
+    assert _same_bits(ref, _state(b, run))
+    b.close()
