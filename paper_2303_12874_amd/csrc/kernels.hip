@@ -57,13 +57,35 @@ __device__ __forceinline__ T &elem(void *base, int i) {
 }
 
 // Electrons of a tile are stored transposed: with n electrons in (cell, id)
-// order L[0..n) and chunk = ceil(n / 256), thread t of the tile's workgroup
-// handles L[t chunk + it] for it = 0, 1, ..., and round `it` of the 256
-// threads reads consecutive slots.  round_count = threads active in round it.
+// order L[0..n) and chunk = ceil(n / 256), list column c holds L[c chunk +
+// it] for it = 0, 1, ..., and round `it` of the tile's workgroup takes the
+// round_count(n, chunk, it) electrons of its columns from consecutive slots,
+// thread t the slot t.  round_count = electrons (active threads) of round it.
 __device__ __forceinline__ int round_count(int n, int chunk, int it) {
   if (it >= n) return 0;
   const int c = (n - 1 - it) / chunk + 1;
   return c < 256 ? c : 256;
+}
+
+// The slots of a round do not hold the columns in their order: slot o holds
+// column round_column(o, cnt, S), the columns c = S l + w (w < S) grouped by
+// w, l rising.  With S at least the number of columns per cell, the 64 lanes
+// of a wavefront (64 consecutive slots, one w) are in distinct cells, so
+// that their LDS atomics do not collide on one address, and every particle
+// load and store of a wavefront is one contiguous run of slots.
+__device__ __forceinline__ int round_spread(int n, int chunk, long long TT) {
+  int S = 1;
+  while (S < 4 && (long long)S * chunk * TT < n) S *= 2;
+  return S;
+}
+__device__ __forceinline__ int round_column(int o, int cnt, int S) {
+  int w = 0, pre = 0;
+  for (; w < S - 1; ++w) {
+    const int cw = (cnt - w + S - 1) / S;  // columns S l + w below cnt
+    if (o < pre + cw) break;
+    pre += cw;
+  }
+  return S * (o - pre) + w;
 }
 
 // largest integer j with j^2 <= r2 (r = sqrt(r2) rounded)
@@ -490,13 +512,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void p
 
   const int n = end - beg;
   const int chunk = (n + 255) / 256;
-  // Thread t takes list column S (t mod 256/S) + t / (256/S): with S at least
-  // the number of columns per cell, the 64 lanes of a wavefront work in
-  // distinct cells and their LDS atomics do not collide on one address.
-  int S = 1;
-  while (S < 4 && (long long)S * chunk * TT < n) S *= 2;
-  const int per = 256 / S;
-  const int colm = S * ((int)threadIdx.x % per) + (int)threadIdx.x / per;
+  // thread t takes slot t of each round (the sort has spread the slots'
+  // electrons over the tile's cells, round_column)
+  const int slot = threadIdx.x;
   const R dt_dz = (R)(k.dt / k.dz), dt_dr = (R)(k.dt / k.dr);
   // the electron of the next round is loaded while this round's is pushed
   R nw = 0, nz = 0, nfz = 0, nx = 0, ny = 0, nux = 0, nuy = 0, nuz = 0;
@@ -519,16 +537,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void p
   };
   int base = 0;
   int cnt = round_count(n, chunk, 0);
-  if (colm < cnt) fetch(beg + colm);
+  if (slot < cnt) fetch(beg + slot);
   for (int it = 0; it < chunk; ++it) {
-    const int p = beg + base + colm;
-    const bool act = colm < cnt;
+    const int p = beg + base + slot;
+    const bool act = slot < cnt;
     const R cw = nw, cz = nz, cfz = nfz, cx = nx, cy = ny, cux = nux, cuy = nuy, cuz = nuz;
     const int ciz = niz;
     const uint32_t cid = nid;
     base += cnt;
     cnt = (it + 1 < chunk) ? round_count(n, chunk, it + 1) : 0;
-    if (colm < cnt) fetch(beg + base + colm);
+    if (slot < cnt) fetch(beg + base + slot);
     if (!act) continue;
     const R q = -cw;
     const uint32_t pidw = cid;
@@ -2027,6 +2045,7 @@ __device__ __forceinline__ void sort_tile(const KRun &k, uint64_t *ent, long lon
   }
   __syncthreads();
   const int chunk = (n + 255) / 256;
+  const int S = round_spread(n, chunk, TT);
   const int t = threadIdx.x;
   // the gather, kG rounds at a time: every load of the group is issued
   // before its stores, so that the rounds' memory latencies overlap (the
@@ -2056,7 +2075,7 @@ __device__ __forceinline__ void sort_tile(const KRun &k, uint64_t *ent, long lon
       const int cnt = it < chunk ? round_count(n, chunk, it) : 0;
       dd[g] = beg + base + t;
       base += cnt;
-      ss[g] = t < cnt ? (long long)(ent[t * chunk + it] & 0xffffffffu) : -1;
+      ss[g] = t < cnt ? (long long)(ent[round_column(t, cnt, S) * chunk + it] & 0xffffffffu) : -1;
       ok[g] = ss[g] >= 0 && ss[g] < k.np;
       if (t < cnt && !ok[g]) atomicOr(k.flags, sort_index_flags(ss[g], k.np, kSortBadSource));
     }

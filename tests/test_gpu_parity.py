@@ -286,7 +286,9 @@ def _oracle_order(o, Tz, Tr, threads=256):
     """ids in (tile, cell, id) order from the oracle's own positions, each
     tile's list then stored transposed as the library's workgroup reads it:
     with n electrons and chunk = ceil(n / threads), round `it` holds
-    L[t chunk + it] for t = 0, 1, ... while t chunk + it < n."""
+    L[c chunk + it] for the columns c with c chunk + it < n, ordered by
+    (c mod S, c div S), where S (1, 2 or 4) is the smallest with
+    S chunk Tz Tr >= n, or 4."""
     P = o.particles()
     ords = o.cell_order(Tz, Tr)
     order = np.lexsort((P["id"], ords))
@@ -296,10 +298,14 @@ def _oracle_order(o, Tz, Tr, threads=256):
         L = ids[tiles == tile]
         n = L.size
         chunk = -(-n // threads)
+        S = 1
+        while S < 4 and S * chunk * Tz * Tr < n:
+            S *= 2
         for it in range(chunk):
-            t = np.arange(threads)
-            t = t[t * chunk + it < n]
-            out.append(L[t * chunk + it])
+            c = np.arange(threads)
+            c = c[c * chunk + it < n]
+            c = c[np.lexsort((c // S, c % S))]
+            out.append(L[c * chunk + it])
     return np.concatenate(out)
 
 
