@@ -324,12 +324,15 @@ def test_initial_cell_sort_bit_exact(precision):
     sim.close()
 
 
-def test_cell_sort_after_steps_bit_exact():
+@pytest.mark.parametrize("ppc", [2, 3])
+def test_cell_sort_after_steps_bit_exact(ppc):
     """FP64 run with a sort every 4 steps: after 9 steps the order is the one
-    the oracle's key gives for its state after 8 steps."""
-    _say("[gpu] sort after 8 steps")
+    the oracle's key gives for its state after 8 steps (16 x 4 tiles: with 2
+    electrons per cell most tiles store their rounds with S = 2, with 3 with
+    S = 4, in partly filled rounds)."""
+    _say(f"[gpu] sort after 8 steps, {ppc} ppc")
     pic = _pic()
-    run = workloads.small(M=2, Nz=96, Nr=20, ppc=3, n_tracked=10)["runs"][0]
+    run = workloads.small(M=2, Nz=96, Nr=20, ppc=ppc, n_tracked=10)["runs"][0]
     dt, CE, CB, _ = _setup(16, run["M"], run["dz"], run["dr"])
     sim = pic.Simulation([workloads.to_rundesc(run)], dt=dt, coef_E=CE, coef_B=CB, sort_interval=4,
                          tile_z=16, tile_r=4)
