@@ -33,7 +33,8 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kFieldTile = 128;  // z-columns per field-update workgroup
-constexpr int kSortLdsEntries = 6144;  // sort entries of a tile held in LDS (48 KB)
+constexpr int kSortLdsEntries = 4608;  // sort entries of a tile held in LDS (36 KB, with their 9 KB of ranks)
+constexpr int kSortRankPerCell = 8;    // mean entries per cell above which a tile's cells are ranked in parallel
 constexpr int kDealBlock = 64;         // consecutive tiles dealt to one XCD's ticket counter
 constexpr int kDealMinPerGroup = 32;   // tiles per resident workgroup from which tiles are dealt per XCD
 
@@ -2034,16 +2035,22 @@ __device__ __forceinline__ void sort_cell(uint64_t *ent, int b, int e) {
 // Order a tile's n entries `ent` by (cell, id), then gather its electrons into
 // the transposed order the push kernel reads (see round_count).  Inlined with
 // `ent` either in LDS or in device memory, so that every access has a known
-// address space.  Cell bounds are clamped to the tile and a source index out
-// of range is skipped, so that no data can drive an access out of bounds.
-template <typename R>
-__device__ __forceinline__ void sort_tile(const KRun &k, uint64_t *ent, long long c0, int beg, int n) {
+// address space.  In LDS (kRank) the entries stay where they are and `pos`
+// lists them in (cell, id) order (their ranks, rank_cells); in device memory
+// each cell is sorted in place by one thread.  Cell bounds are clamped to the
+// tile and a source index out of range is skipped, so that no data can drive
+// an access out of bounds.
+template <typename R, bool kRank>
+__device__ __forceinline__ void sort_tile(const KRun &k, uint64_t *ent, const uint16_t *pos, long long c0, int beg,
+                                          int n) {
   const long long TT = (long long)k.Tz * k.Tr;
-  for (long long c = threadIdx.x; c < TT; c += blockDim.x) {
-    const int b = clampi(k.cell_start[c0 + c] - beg, 0, n), e = clampi(k.cell_start[c0 + c + 1] - beg, 0, n);
-    sort_cell(ent, b, e);
+  if constexpr (!kRank) {
+    for (long long c = threadIdx.x; c < TT; c += blockDim.x) {
+      const int b = clampi(k.cell_start[c0 + c] - beg, 0, n), e = clampi(k.cell_start[c0 + c + 1] - beg, 0, n);
+      sort_cell(ent, b, e);
+    }
+    __syncthreads();
   }
-  __syncthreads();
   const int chunk = (n + 255) / 256;
   const int S = round_spread(n, chunk, TT);
   const int t = threadIdx.x;
@@ -2075,7 +2082,9 @@ __device__ __forceinline__ void sort_tile(const KRun &k, uint64_t *ent, long lon
       const int cnt = it < chunk ? round_count(n, chunk, it) : 0;
       dd[g] = beg + base + t;
       base += cnt;
-      ss[g] = t < cnt ? (long long)(ent[round_column(t, cnt, S) * chunk + it] & 0xffffffffu) : -1;
+      int L = t < cnt ? round_column(t, cnt, S) * chunk + it : 0;  // list position
+      if constexpr (kRank) L = pos[L];
+      ss[g] = t < cnt ? (long long)(ent[L] & 0xffffffffu) : -1;
       ok[g] = ss[g] >= 0 && ss[g] < k.np;
       if (t < cnt && !ok[g]) atomicOr(k.flags, sort_index_flags(ss[g], k.np, kSortBadSource));
     }
@@ -2114,8 +2123,33 @@ __device__ __forceinline__ void sort_tile(const KRun &k, uint64_t *ent, long lon
   }
 }
 
-// One workgroup per tile: its entries, ordered in LDS, or in place in device
-// memory for a tile too dense for the LDS budget.
+// (cell, id) order of a tile's n entries held in LDS, all threads at once:
+// entry a of the cell range [b, e) (the last cell starting at or before a,
+// from the tile's clamped cell starts cs) has the rank r = #{x in [b, e):
+// ent[x] < ent[a]} (ids are unique, so the entry order is the id order), and
+// pos[b + r] = a.  pos starts as the identity, so that inconsistent data can
+// leave it stale but never out of range.
+__device__ __forceinline__ void rank_cells(const uint64_t *ent, uint16_t *pos, const int32_t *cs, int TT, int n) {
+  for (int a = threadIdx.x; a < n; a += blockDim.x) {
+    int lo = 0, hi = TT - 1;  // cs[lo] <= a
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (cs[mid] <= a) lo = mid;
+      else hi = mid - 1;
+    }
+    const int b = cs[lo], e = cs[lo + 1];
+    const uint64_t v = ent[a];
+    int r = 0;
+    for (int x = b; x < e; ++x) r += ent[x] < v ? 1 : 0;
+    if (b + r < n) pos[b + r] = (uint16_t)a;
+  }
+}
+
+// One workgroup per tile: its entries in LDS, ranked (measured faster with
+// 16 electrons per cell: sort 2.60 -> 2.26 ms on the 8192 x 512 run) or, with
+// a few per cell, each cell sorted by one thread (faster there: ranking took
+// the six-run scan's sort, 4 per cell, from 1.26 to 1.32 ms); in device
+// memory, sorted in place, for a tile too dense for the LDS budget.
 template <typename R>
 __global__ __launch_bounds__(256) void sort_tile_kernel(const Batch bt) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -2135,10 +2169,21 @@ __global__ __launch_bounds__(256) void sort_tile_kernel(const Batch bt) {
   if (n <= kSortLdsEntries) {
     uint64_t *ent = (uint64_t *)lds_raw;
     for (int a = threadIdx.x; a < n; a += blockDim.x) ent[a] = k.perm[beg + a];
-    __syncthreads();
-    sort_tile<R>(k, ent, c0, beg, n);
+    if (n > kSortRankPerCell * TT) {  // dense cells: ranks, all threads at once
+      uint16_t *pos = (uint16_t *)(lds_raw + (size_t)kSortLdsEntries * sizeof(uint64_t));
+      int32_t *cs = (int32_t *)(lds_raw + (size_t)kSortLdsEntries * (sizeof(uint64_t) + sizeof(uint16_t)));
+      for (int a = threadIdx.x; a < n; a += blockDim.x) pos[a] = (uint16_t)a;
+      for (long long c = threadIdx.x; c <= TT; c += blockDim.x) cs[c] = clampi(k.cell_start[c0 + c] - beg, 0, n);
+      __syncthreads();
+      rank_cells(ent, pos, cs, (int)TT, n);
+      __syncthreads();
+      sort_tile<R, true>(k, ent, pos, c0, beg, n);
+    } else {  // a few entries per cell: each cell sorted in place by one thread
+      __syncthreads();
+      sort_tile<R, false>(k, ent, nullptr, c0, beg, n);
+    }
   } else {
-    sort_tile<R>(k, k.perm + beg, c0, beg, n);
+    sort_tile<R, false>(k, k.perm + beg, nullptr, c0, beg, n);
   }
 }
 
@@ -2444,7 +2489,15 @@ int launch_sort(Batch &b, int prec, void *stream) {
   sort_scatter_kernel<<<(unsigned)b.off[b.n], 256, 2 * hw, s>>>(b);
   if ((rc = check(hipGetLastError(), "sort_scatter_kernel"))) return rc;
   set_offsets(b, [](const KRun &k) { return k.np > 0 ? (long long)k.ntz * k.ntr : 0LL; });
-  const size_t lds = (size_t)kSortLdsEntries * sizeof(uint64_t);
+  // entries, their ranks and the tile's cell starts (the runs of a batch share the tile)
+  const size_t lds = (size_t)kSortLdsEntries * (sizeof(uint64_t) + sizeof(uint16_t)) +
+                     ((size_t)b.run[0].Tz * b.run[0].Tr + 1) * sizeof(int32_t);
+  if (lds > 65536) {  // tiles of more than about 4800 cells
+    const void *f = prec == PIC_PREC_FP64 ? (const void *)sort_tile_kernel<double> : (const void *)sort_tile_kernel<float>;
+    if ((rc = check(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+                    "hipFuncSetAttribute(sort_tile_kernel)")))
+      return rc;
+  }
   if (prec == PIC_PREC_FP64) sort_tile_kernel<double><<<(unsigned)b.off[b.n], 256, lds, s>>>(b);
   else sort_tile_kernel<float><<<(unsigned)b.off[b.n], 256, lds, s>>>(b);
   if ((rc = check(hipGetLastError(), "sort_tile_kernel"))) return rc;

@@ -324,12 +324,13 @@ def test_initial_cell_sort_bit_exact(precision):
     sim.close()
 
 
-@pytest.mark.parametrize("ppc", [2, 3])
+@pytest.mark.parametrize("ppc", [2, 3, 10])
 def test_cell_sort_after_steps_bit_exact(ppc):
     """FP64 run with a sort every 4 steps: after 9 steps the order is the one
     the oracle's key gives for its state after 8 steps (16 x 4 tiles: with 2
     electrons per cell most tiles store their rounds with S = 2, with 3 with
-    S = 4, in partly filled rounds)."""
+    S = 4, in partly filled rounds; with 10 the tiles' cells are ranked in
+    parallel instead of sorted one per thread)."""
     _say(f"[gpu] sort after 8 steps, {ppc} ppc")
     pic = _pic()
     run = workloads.small(M=2, Nz=96, Nr=20, ppc=ppc, n_tracked=10)["runs"][0]
@@ -340,6 +341,24 @@ def test_cell_sort_after_steps_bit_exact(ppc):
     sim.step(9)
     o.step(8)
     assert np.array_equal(sim.particles()["id"], _oracle_order(o, 16, 4))
+    sim.close()
+
+
+def test_dense_tile_sort_bit_exact():
+    """Tiles too dense for the sort's LDS budget (64 x 8 cells at 10 electrons
+    per cell: over 5000 entries a tile) are sorted in device memory instead:
+    the same order as the oracle's key, at start-up and after 8 steps."""
+    _say("[gpu] dense-tile sort (device-memory path)")
+    pic = _pic()
+    run = workloads.small(M=0, Nz=128, Nr=17, ppc=10, n_tracked=10)["runs"][0]
+    dt, CE, CB, _ = _setup(16, run["M"], run["dz"], run["dr"])
+    sim = pic.Simulation([workloads.to_rundesc(run)], dt=dt, coef_E=CE, coef_B=CB, sort_interval=4,
+                         tile_z=64, tile_r=8)
+    o = oracle_of(run, dt, CE, CB)
+    assert np.array_equal(sim.particles()["id"], _oracle_order(o, 64, 8))
+    sim.step(9)
+    o.step(8)
+    assert np.array_equal(sim.particles()["id"], _oracle_order(o, 64, 8))
     sim.close()
 
 
