@@ -501,6 +501,8 @@ def main(argv=None):
     ap.add_argument("--window", type=int, default=0,
                     help="moving window (App. A): a move every K steps (0: the static box of the workload)")
     ap.add_argument("--window-guard", type=int, default=16, help="moving window: guard columns cleared at a move")
+    ap.add_argument("--deterministic", action="store_true",
+                    help="FP64 only: the deposit's sums in integers, bitwise independent of the atomics' order")
     ap.add_argument("--shape", type=int, default=1, choices=[1, 2],
                     help="particle shape order of the gather and deposit: 1 linear, 2 quadratic")
     ap.add_argument("--autotune", type=int, default=None,
@@ -564,6 +566,9 @@ def main(argv=None):
     W = args.warmup if args.warmup is not None else (8 if multi else 20)
     per_run = [min(n, K) for n in cfg["steps"]] if multi else [K]
     prec = args.precision or cfg["precision"]
+    if args.deterministic and prec != 64:
+        print("--deterministic needs FP64 (--precision 64 for an FP32 workload)", file=sys.stderr)
+        return 2
     solver = pic.SOLVER_YEE if args.solver == "yee" else pic.SOLVER_DUAL
     n_coef = 1 if args.solver == "yee" else 16
     current = pic.CURRENT_EXACT_JZ if args.current == "exact" else pic.CURRENT_FILTER
@@ -574,7 +579,8 @@ def main(argv=None):
         t0 = time.perf_counter()
         tune = pic.autotune([workloads.to_rundesc(r) for r in runs], precision=prec, solver=solver, n_coef=n_coef,
                             current=current, tile_z=args.tile_z,
-                            tile_r=args.tile_r, shape=args.shape, device="cuda:0")
+                            tile_r=args.tile_r, shape=args.shape, deterministic=args.deterministic,
+                            device="cuda:0")
         torch.cuda.empty_cache()
         args.tile_z, args.tile_r = tune["tile_z"], tune["tile_r"]
         args.sort_interval = args.sort_interval or tune["sort_interval"]
@@ -592,7 +598,7 @@ def main(argv=None):
                                   precision=prec_, solver=solver, n_coef=n_coef, sort_interval=sort_interval,
                                   tile_z=tile_z, tile_r=tile_r, use_graph=args.graph, current=current,
                                   window_interval=args.window, window_guard=args.window_guard if args.window else 0,
-                                  shape=args.shape, device="cuda:0")
+                                  shape=args.shape, deterministic=args.deterministic, device="cuda:0")
 
         if multi:
             warm = make([0] * len(runs))
@@ -660,7 +666,7 @@ def main(argv=None):
     ach = kernels[dom]["GBs"]
     traffic = (measured_traffic(args.workload, dom, "%dx%d" % infos[0]["tile"], sort_k, prec)
                if args.solver == "dual" and args.current == "filter" and not args.window and args.shape == 1
-               else None)  # the counters' settings
+               and not args.deterministic else None)  # the counters' settings
     particle_steps = sum(n * s for n, s in zip(nps, per_run))
     value = particle_steps / (elapsed_ms * 1e-3)
     run = runs[0]
@@ -672,7 +678,7 @@ def main(argv=None):
               "current": "P^-1 on J_z" if args.current == "exact" else "z filter on J_r, J_phi",
               "dt": [i["dt"] for i in infos] if multi else infos[0]["dt"],
               "sort_interval": sort_k, "tile": "%dx%d" % infos[0]["tile"], "graph": bool(args.graph),
-              "shape": "quadratic" if args.shape == 2 else "linear"}
+              "shape": "quadratic" if args.shape == 2 else "linear", "deterministic": bool(args.deterministic)}
     if multi:
         config["steps_per_run"] = per_run
     if args.window:
