@@ -71,9 +71,10 @@ __device__ __forceinline__ int round_count(int n, int chunk, int it) {
 // The slots of a round do not hold the columns in their order: slot o holds
 // column round_column(o, cnt, S), the columns c = S l + w (w < S) grouped by
 // w, l rising.  With S at least the number of columns per cell, the 64 lanes
-// of a wavefront (64 consecutive slots, one w) are in distinct cells, so
-// that their LDS atomics do not collide on one address, and every particle
-// load and store of a wavefront is one contiguous run of slots.
+// of a wavefront (64 consecutive slots, of one w in a full round; a partly
+// filled round's wavefront can span two) are in distinct cells, so that
+// their LDS atomics do not collide on one address, and every particle load
+// and store of a wavefront is one contiguous run of slots.
 __device__ __forceinline__ int round_spread(int n, int chunk, long long TT) {
   int S = 1;
   while (S < 4 && (long long)S * chunk * TT < n) S *= 2;
